@@ -1,0 +1,90 @@
+"""Seeded synthetic workloads: model parameters and job lists.
+
+This module only draws and lists inputs; it holds none of the method's
+arithmetic and imports nothing from the solver or from the oracle, so both
+sides (and the tests) can take their inputs from here.
+
+Base model: the generalized two-state model of Sec. II.C with
+w_g = 0.15, w_u = 0.10 eV, k_1 = -0.1, k_2 = +0.1, lam = lam_1 = lam_2 = 0.05,
+E_1 = 1.0 eV, gap E_2 - E_1 = 0.5 eV, all four widths A = 0.2, B = 1.0 with
+l = 0 for the even and l = 1 for the odd partial wave (the l pattern of
+Table II), level shift on a 4096-node square-root grid up to 40 eV.
+"""
+import numpy as np
+
+PARAM_NAMES = ("omega_g", "omega_u", "kappa1", "kappa2", "lam", "lam1", "lam2", "gap",
+               "A1e", "A2e", "A1o", "A2o", "B1e", "B2e", "B1o", "B2o")
+
+SEED = 20230725
+
+
+def base_params():
+    return dict(omega_g=0.15, omega_u=0.10, kappa1=-0.1, kappa2=0.1, lam=0.05,
+                lam1=0.05, lam2=0.05, gap=0.5,
+                A1e=0.2, A2e=0.2, A1o=0.2, A2o=0.2,
+                B1e=1.0, B2e=1.0, B1o=1.0, B2o=1.0,
+                E1=1.0, l_e=0, l_o=1, K=4096, X=40.0)
+
+
+def draw_params(seed, base=None):
+    """Each of the 16 continuous parameters times U(0.8, 1.2), in PARAM_NAMES
+    order, from numpy's default_rng(seed); E1, l and the grid stay fixed."""
+    p = dict(base or base_params())
+    rng = np.random.default_rng(seed)
+    fac = rng.uniform(0.8, 1.2, size=len(PARAM_NAMES))
+    for name, f in zip(PARAM_NAMES, fac):
+        p[name] = p[name] * float(f)
+    return p
+
+
+def params_vector(p):
+    return np.array([p[k] for k in PARAM_NAMES], dtype=np.float64)
+
+
+def params_from_vector(vec, like):
+    p = dict(like)
+    for k, v in zip(PARAM_NAMES, vec):
+        p[k] = float(v)
+    return p
+
+
+# ---- job lists ----------------------------------------------------------
+# A job is (eps_i, (n_g, n_u) of v_i, mu_i) with mu_i in {0: even, 1: odd}.
+# Vibrational labels v = 0, 1, 2, ... denote the tuning-mode progression
+# (n_g = v, n_u = 0).
+
+def single_jobs():
+    """One energy eps_i = 1.0 eV, v_i = 0, both partial waves; 40 x 40 basis."""
+    return dict(params=base_params(), Ng=40, Nu=40,
+                jobs=[(1.0, (0, 0), 0), (1.0, (0, 0), 1)],
+                finals=[(k, 0) for k in range(6)])
+
+
+def batched_jobs(n_energies=512, n_basis=120, seed=SEED):
+    """512 energies on [0.1, 3.0] eV x v_i in {0,1,2} x mu in {e, o}, one
+    parameter draw; 120 x 120 basis per state (28800 unknowns)."""
+    p = draw_params(seed)
+    eps = np.linspace(0.1, 3.0, n_energies)
+    jobs = [(float(e), (v, 0), mu) for e in eps for v in range(3) for mu in range(2)]
+    return dict(params=p, Ng=n_basis, Nu=n_basis, jobs=jobs,
+                finals=[(k, 0) for k in range(6)])
+
+
+def uneven_instances(n_inst=64, seed=SEED + 3, nmin=40, nmax=160):
+    """64 instances, each with its own parameter draw, an n x n basis with
+    n ~ U{40..160} and one energy eps_i ~ U[0.1, 3.0]; v_i = 0, both mu."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_inst):
+        n = int(rng.integers(nmin, nmax + 1))
+        e = float(rng.uniform(0.1, 3.0))
+        out.append(dict(params=draw_params(seed * 1000 + k), Ng=n, Nu=n, eps=e))
+    return out
+
+
+def adjoint_workload(n_energies=256, n_basis=120, seed=SEED):
+    """Model at the base parameters, 256 energies on [0.1, 3.0] eV, v_i = 0,
+    finals v_f = 0..5; the target spectrum comes from a second draw (seed+1)."""
+    return dict(params=base_params(), target_params=draw_params(seed + 1),
+                Ng=n_basis, Nu=n_basis, eps=np.linspace(0.1, 3.0, n_energies),
+                v_i=(0, 0), finals=[(k, 0) for k in range(6)])
