@@ -1,0 +1,190 @@
+/*
+ * vdc.h - C ABI of the MI355X (gfx950) solver for vibronic dynamics of
+ * discrete states in the electron continuum.
+ *
+ * Method: Cosicova, Dvorak & Cizek, "Vibronic dynamics in electron continuum -
+ * iterative solvers", arXiv:2307.13483.  The library builds the generalized
+ * two-state, two-mode model of Sec. II.C and, for each job (incident energy
+ * eps_i, initial vibrational state v_i, incoming partial wave mu_i), solves
+ *     (E - H_ef(E)) Psi = Phi^{v_i mu_i},   E = eps_i + E_{v_i}     (Eqs. (2), (26))
+ * by a Krylov method (restarted GMRES, Sec. III.A) with the diagonal
+ * preconditioner of Sec. III.B, then projects the T-matrix amplitudes
+ * (Eqs. (15), (24)) and cross sections (Eq. (16)).
+ *
+ * Conventions shared by every entry point
+ *  - Energies in eV.  T is dimensionless; sigma is in bohr^2 with eps_i
+ *    converted to hartree (1 hartree = 27.211386245988 eV) in 2 pi^3/eps_i.
+ *  - Complex numbers are interleaved (re, im) pairs of double ("c16") or,
+ *    where stated, float.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory owned by the caller.  The library never
+ *    keeps a caller pointer past the call.
+ *  - Work is ordered on the caller's hipStream_t (passed as void*, NULL = the
+ *    default stream).  Calls that return host results synchronise that stream.
+ *  - Every function returns vdc_status; it never throws or aborts.  On error
+ *    vdc_last_error() returns a thread-local message.  A job that fails to
+ *    converge is not a call error: it is reported in its vdc_job_status.
+ *  - Basis (Sec. II.D): compound index alpha = (d, n_g, n_u), d in {1,2},
+ *    n_g < Ng, n_u < Nu; full vectors are laid out d-major, then n_g, with n_u
+ *    fastest: index (d-1)*Ng*Nu + n_g*Nu + n_u, length N = 2*Ng*Nu.
+ */
+#ifndef VDC_H
+#define VDC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VDC_OK = 0,
+  VDC_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range   */
+  VDC_ERR_WORKSPACE = 2,     /* workspace smaller than vdc_workspace_size()     */
+  VDC_ERR_HIP = 3,           /* a HIP runtime call failed                       */
+  VDC_ERR_UNSUPPORTED = 4    /* a valid request this build does not implement   */
+} vdc_status;
+
+typedef enum {
+  VDC_CONVERGED = 0,         /* ||b - A x||_2 <= tol ||b||_2 (true residual)    */
+  VDC_NOT_CONVERGED = 1,     /* max_iter reached first                          */
+  VDC_BREAKDOWN = 2,         /* Krylov space exhausted without reaching tol     */
+  VDC_NONFINITE = 3          /* a NaN/Inf appeared in the iteration             */
+} vdc_job_status;
+
+/* Parameters of the generalized model, Sec. II.C (Eqs. (18), (21)-(23)).
+ *   H_0   = w_g (n_g + 1/2) + w_u (n_u + 1/2)
+ *   U     = [[E1 + kappa1 q_g, lam q_u], [lam q_u, E1 + gap + kappa2 q_g]]
+ *   V_eps = [[f_1^e (1 + lam1 q_g), f_1^o q_u], [f_2^e q_u, f_2^o (1 + lam2 q_g)]]
+ *   2 pi (f_d^mu)^2 = Gamma_d^mu(eps) = A[d][mu] eps^(l[mu]+1/2) exp(-eps/B[d][mu]),
+ *   f >= 0, Gamma = 0 for eps <= 0.  Index d: 0 -> state 1, 1 -> state 2;
+ *   mu: 0 -> even (e), 1 -> odd (o).
+ * The level shift F[f_d f_d'] (Eq. (19)) has the analytic imaginary part
+ * -sqrt(Gamma_d Gamma_d')/2 and, as real part, the principal-value transform
+ * of the piecewise-linear interpolant of sqrt(Gamma_d Gamma_d') on the nodes
+ * x_k = (k sqrt(hilbert_xmax)/(hilbert_nodes-1))^2, k = 0..hilbert_nodes-1. */
+typedef struct {
+  double omega_g, omega_u;
+  double kappa1, kappa2, lam;
+  double lam1, lam2;
+  double E1, gap;
+  double A[2][2];            /* [d][mu], >= 0                                    */
+  double B[2][2];            /* [d][mu], > 0                                     */
+  int l[2];                  /* [mu], 0..4, the same for both states            */
+  int Ng, Nu;                /* basis sizes, 1..1024 each                       */
+  int hilbert_nodes;         /* 16..65536 (4096 in the reference workloads)     */
+  double hilbert_xmax;       /* > 0 eV (40 in the reference workloads)          */
+} vdc_model2d_desc;
+
+typedef struct vdc_model* vdc_model_t;   /* opaque; owns a few KB of device data */
+
+/* One right-hand side.  v_i = (vi_g, vi_u) must lie in the basis and
+ * eps_i > 0 (an open entrance channel), else the call fails with
+ * VDC_ERR_INVALID_ARG.  model indexes the models[] array of the call.      */
+typedef struct {
+  double eps_i;
+  int vi_g, vi_u;
+  int mu_i;                  /* 0 = e, 1 = o                                    */
+  int model;
+} vdc_job;
+
+typedef enum { VDC_PREC_NONE = 0, VDC_PREC_JACOBI = 1 } vdc_precond;
+typedef enum {
+  VDC_FP64 = 0,              /* restarted GMRES in complex FP64                  */
+  VDC_FP32_INNER = 1         /* FGMRES: FP64 outer (true residual, Givens,
+                                solution, amplitudes), GMRES in FP32 with FP32
+                                accumulation as the variable preconditioner   */
+} vdc_precision;
+
+typedef struct {
+  int restart;               /* GMRES restart length m, 1..128                  */
+  int max_iter;              /* total Arnoldi steps (inner steps for FP32)      */
+  double tol;                /* relative true-residual target, > 0            */
+  int precond;               /* vdc_precond                                     */
+  int precision;             /* vdc_precision                                   */
+  int inner_restart;         /* FP32_INNER: inner GMRES length (1..128)         */
+  double inner_tol;          /* FP32_INNER: inner relative tolerance            */
+  int outer_restart;         /* FP32_INNER: outer FGMRES length (1..32)         */
+} vdc_solve_opts;
+
+/* Per-job results written to host memory by the solve calls. */
+typedef struct {
+  int status;                /* vdc_job_status                                  */
+  int iters;                 /* Arnoldi steps taken (inner steps for FP32)      */
+  int restarts;              /* GMRES cycles (outer steps for FP32)             */
+  int outer_iters;           /* FP32_INNER: outer FGMRES steps, else 0          */
+  double rel_res;            /* final ||b - A x|| / ||b||, FP64 true residual   */
+} vdc_job_info;
+
+/* Build a model (host call; allocates and fills its small device tables:
+ * the transform's nodes and second differences of the interpolated widths). */
+vdc_status vdc_model2d_create(const vdc_model2d_desc* desc, vdc_model_t* out);
+vdc_status vdc_model_destroy(vdc_model_t model);
+
+/* Bytes of device workspace that vdc_solve / vdc_solve_plain need for this job
+ * list.  Host call, no device work. */
+vdc_status vdc_workspace_size(int n_models, const vdc_model_t* models,
+                              const vdc_solve_opts* opts, int n_jobs, const vdc_job* jobs,
+                              size_t* bytes);
+
+/* Solve every job in ONE persistent kernel launch (after one launch that
+ * builds the per-energy level-shift tables).  Each workgroup pops jobs,
+ * longest-first, from a device queue and runs the whole restarted GMRES for
+ * the job on chip, then projects the amplitudes.
+ *   finals   host int[n_final][2]: (n_g, n_u) of each final state v_f
+ *   T_out    device c16 [n_jobs][n_final][2]: T_{mu_f v_f <- mu_i v_i},
+ *            mu_f = e, o; 0 for closed channels (eps_f <= 0)
+ *   sigma_out device double [n_jobs][n_final]: this job's share of
+ *            sigma_{v_f <- v_i}, 2 pi^3/eps_i sum_{mu_f} |T|^2; the cross
+ *            section of Eq. (16) is the sum of the shares of the mu_i = e and
+ *            mu_i = o jobs at the same (eps_i, v_i)
+ *   psi_out  device c16 [n_jobs][N] or NULL: the solution Psi, full layout
+ *   info     host vdc_job_info[n_jobs] or NULL
+ * Requirements: workspace device, >= vdc_workspace_size() bytes, 256-byte
+ * aligned.  Synchronises the stream before returning. */
+vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                     int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                     void* workspace, size_t ws_bytes,
+                     double* T_out, double* sigma_out, double* psi_out,
+                     vdc_job_info* info, void* stream);
+
+/* The plain single-solve path: the same arithmetic, one job after another,
+ * each GMRES step issued from the host as separate grid-wide kernels (matvec,
+ * Gram-Schmidt projections, norm, Givens update) with one status read-back
+ * per restart cycle.  FP64 only (opts->precision must be VDC_FP64).  Same
+ * arguments and outputs as vdc_solve. */
+vdc_status vdc_solve_plain(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                           int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                           void* workspace, size_t ws_bytes,
+                           double* T_out, double* sigma_out, double* psi_out,
+                           vdc_job_info* info, void* stream);
+
+/* Level-shift tables (Eq. (19) with the widths of Eq. (22)): for n_eps
+ * electron energies eps (device double[n_eps]) write the six complex values
+ * F[f_1^e f_1^e], F[f_1^e f_2^e], F[f_2^e f_2^e], F[f_1^o f_1^o],
+ * F[f_1^o f_2^o], F[f_2^o f_2^o] at each energy to out (device c16
+ * [n_eps][6]).  Asynchronous on the stream. */
+vdc_status vdc_level_shift(vdc_model_t model, int n_eps, const double* eps, double* out,
+                           void* stream);
+
+/* y = A x for the matrix A = E - H_ef(E) of Eq. (28) at total energy E, applied
+ * to n_vec full-layout vectors x (device c16 [n_vec][N]) that each lie in one
+ * symmetry block (parity[v] = 0: d=1 on even n_u and d=2 on odd n_u; 1: the
+ * opposite; host int[n_vec]); components outside the block are ignored and
+ * written as 0.  y: device c16 [n_vec][N].  workspace: device, >=
+ * vdc_matvec_workspace_size() bytes.  Asynchronous on the stream. */
+vdc_status vdc_matvec_workspace_size(vdc_model_t model, int n_vec, size_t* bytes);
+vdc_status vdc_matvec(vdc_model_t model, double E, int n_vec, const int* parity,
+                      const double* x, double* y, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* Thread-local text of the last error (never NULL). */
+const char* vdc_last_error(void);
+
+/* Library version string. */
+const char* vdc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VDC_H */

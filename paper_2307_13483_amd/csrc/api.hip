@@ -1,0 +1,479 @@
+// C ABI of libvdc: model build, workspace layout, job ordering and launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+#include "solve_args.h"
+
+namespace vdc {
+hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, hipStream_t s);
+int gmres_fp64_occupancy();
+hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, hipStream_t s);
+int fgmres_mixed_occupancy();
+hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,
+                              int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
+                              c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
+vdc_status solve_plain_impl(const SolveArgs& a, const std::vector<DevJob>& jobs,
+                            const std::vector<DevModel>& models, hipStream_t s,
+                            std::string& err);
+}  // namespace vdc
+
+using namespace vdc;
+
+struct vdc_model {
+  vdc_model2d_desc desc;
+  DevModel dev;
+  double* d_nodes = nullptr;
+  double* d_coef = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+vdc_status fail(vdc_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+vdc_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return VDC_ERR_HIP;
+}
+
+#define HIPCHK(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// sqrt(Gamma_d Gamma_d') on the host, for the transform coefficients.
+double width_pair_host(const vdc_model2d_desc& d, int mu, int d1, int d2, double x) {
+  if (!(x > 0.0)) return 0.0;
+  const double A = std::sqrt(d.A[d1][mu] * d.A[d2][mu]);
+  const double rB = 0.5 / d.B[d1][mu] + 0.5 / d.B[d2][mu];
+  return A * std::pow(x, d.l[mu] + 0.5) * std::exp(-x * rB);
+}
+
+double vib_energy(const vdc_model2d_desc& d, int g, int u) {
+  return d.omega_g * (g + 0.5) + d.omega_u * (u + 0.5);
+}
+
+struct Plan {
+  std::vector<DevModel> models;
+  std::vector<DevJob> jobs;       // sorted, longest first
+  std::vector<DevTable> tabs;
+  int max_nc = 0;
+  size_t table_elems = 0;
+  int n_groups = 0;
+  size_t ncap = 0, slot_elems = 0;
+  // byte offsets
+  size_t off_counter, off_models, off_jobs, off_tabs, off_finals, off_info, off_tables,
+      off_tables32, off_scratch, total;
+};
+
+int cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+  return n > 0 ? n : 256;
+}
+
+vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_opts* o,
+                     int n_jobs, const vdc_job* jobs, int n_final, bool plain, Plan& P) {
+  if (n_models <= 0 || !models) return fail(VDC_ERR_INVALID_ARG, "no models");
+  if (!o) return fail(VDC_ERR_INVALID_ARG, "opts is NULL");
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(VDC_ERR_INVALID_ARG, "bad job list");
+  if (n_final < 0 || n_final > kMaxFinal) return fail(VDC_ERR_INVALID_ARG, "n_final must be 0..64");
+  if (o->restart < 1 || o->restart > kMaxRestart) return fail(VDC_ERR_INVALID_ARG, "restart must be 1..128");
+  if (o->max_iter < 1) return fail(VDC_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (!(o->tol > 0.0)) return fail(VDC_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI)
+    return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->precision != VDC_FP64 && o->precision != VDC_FP32_INNER)
+    return fail(VDC_ERR_INVALID_ARG, "unknown precision");
+  const bool mixed = o->precision == VDC_FP32_INNER;
+  if (mixed) {
+    if (plain) return fail(VDC_ERR_UNSUPPORTED, "the plain path is FP64 only");
+    if (o->inner_restart < 1 || o->inner_restart > kMaxRestart)
+      return fail(VDC_ERR_INVALID_ARG, "inner_restart must be 1..128");
+    if (o->outer_restart < 1 || o->outer_restart > 32)
+      return fail(VDC_ERR_INVALID_ARG, "outer_restart must be 1..32");
+    if (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0))
+      return fail(VDC_ERR_INVALID_ARG, "inner_tol must be in (0, 1)");
+  }
+  P.models.resize(n_models);
+  for (int k = 0; k < n_models; ++k) {
+    if (!models[k]) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+    P.models[k] = models[k]->dev;
+    P.max_nc = std::max(P.max_nc, models[k]->dev.Nc);
+  }
+  std::map<std::pair<int, double>, int> tab_index;
+  P.jobs.resize(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) {
+    const vdc_job& jb = jobs[j];
+    if (jb.model < 0 || jb.model >= n_models) return fail(VDC_ERR_INVALID_ARG, "job model index out of range");
+    const vdc_model2d_desc& d = models[jb.model]->desc;
+    if (!(jb.eps_i > 0.0) || !std::isfinite(jb.eps_i))
+      return fail(VDC_ERR_INVALID_ARG, "eps_i must be > 0 (open entrance channel)");
+    if (jb.vi_g < 0 || jb.vi_g >= d.Ng || jb.vi_u < 0 || jb.vi_u >= d.Nu)
+      return fail(VDC_ERR_INVALID_ARG, "v_i outside the basis");
+    if (jb.mu_i != 0 && jb.mu_i != 1) return fail(VDC_ERR_INVALID_ARG, "mu_i must be 0 or 1");
+    DevJob& o2 = P.jobs[j];
+    o2.eps_i = jb.eps_i;
+    o2.E = jb.eps_i + vib_energy(d, jb.vi_g, jb.vi_u);
+    o2.vi_g = jb.vi_g;
+    o2.vi_u = jb.vi_u;
+    o2.mu = jb.mu_i;
+    o2.parity = (jb.vi_u + jb.mu_i) & 1;
+    o2.model = jb.model;
+    o2.out = j;
+    o2.pad = 0;
+    auto key = std::make_pair(jb.model, o2.E);
+    auto it = tab_index.find(key);
+    if (it == tab_index.end()) {
+      DevTable t;
+      t.E = o2.E;
+      t.model = jb.model;
+      t.pad = 0;
+      t.offset = P.table_elems;
+      P.table_elems += 6 * (size_t)P.models[jb.model].Nc;
+      it = tab_index.emplace(key, (int)P.tabs.size()).first;
+      P.tabs.push_back(t);
+    }
+    o2.table = it->second;
+  }
+  if ((int)P.tabs.size() > 65535) return fail(VDC_ERR_INVALID_ARG, "more than 65535 distinct energies");
+  // longest first: cost ~ unknowns x (iterations grow with the total energy)
+  std::stable_sort(P.jobs.begin(), P.jobs.end(), [&](const DevJob& a, const DevJob& b) {
+    const double ca = P.models[a.model].Nc * (0.5 + a.E);
+    const double cb = P.models[b.model].Nc * (0.5 + b.E);
+    return ca > cb;
+  });
+  const int m = mixed ? o->outer_restart : o->restart;
+  P.ncap = (size_t)((P.max_nc + 63) / 64) * 64;
+  if (mixed) {
+    // FP64: Vout (m+1), Z (m), x, b, wA, wB, R; FP32 (in c64 units): Vin (m_in+1), dinv, wA, wB
+    const int mi = o->inner_restart;
+    P.slot_elems = (size_t)(2 * m + 1 + 4) * P.ncap + (size_t)(m + 1) * m +
+                   ((size_t)(mi + 1 + 3) * P.ncap + 1) / 2 + (size_t)(mi + 1) * mi;
+  } else {
+    // V (m+1), x, b, dinv, w, wA, wB, R
+    P.slot_elems = (size_t)(m + 1 + 6) * P.ncap + (size_t)(m + 1) * m;
+  }
+  P.slot_elems = (P.slot_elems + 31) / 32 * 32;
+  int occ = 1;
+  if (!plain) occ = mixed ? fgmres_mixed_occupancy() : gmres_fp64_occupancy();
+  P.n_groups = plain ? 1 : std::max(1, std::min(n_jobs, cu_count() * occ));
+  size_t off = 0;
+  P.off_counter = off; off += 256;
+  P.off_models = off; off = align256(off + sizeof(DevModel) * n_models);
+  P.off_jobs = off; off = align256(off + sizeof(DevJob) * std::max(1, n_jobs));
+  P.off_tabs = off; off = align256(off + sizeof(DevTable) * std::max<size_t>(1, P.tabs.size()));
+  P.off_finals = off; off = align256(off + sizeof(int) * 2 * std::max(1, n_final));
+  P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
+  P.off_tables = off; off = align256(off + sizeof(c64) * P.table_elems);
+  P.off_tables32 = off; off = align256(off + (mixed ? sizeof(c32) * P.table_elems : 0));
+  P.off_scratch = off; off = align256(off + sizeof(c64) * P.slot_elems * P.n_groups);
+  P.total = off;
+  return VDC_OK;
+}
+
+vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                     int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                     void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                     double* psi_out, vdc_job_info* info, void* stream, bool plain) {
+  Plan P;
+  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, plain, P);
+  if (st != VDC_OK) return st;
+  if (n_jobs == 0) return VDC_OK;
+  if (!workspace) return fail(VDC_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total)
+    return fail(VDC_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) +
+                                       " bytes, got " + std::to_string(ws_bytes));
+  if (n_final > 0 && (!finals || !T_out || !sigma_out))
+    return fail(VDC_ERR_INVALID_ARG, "finals/T_out/sigma_out must be non-NULL when n_final > 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  const bool mixed = opts->precision == VDC_FP32_INNER;
+
+  HIPCHK(hipMemcpyAsync(ws + P.off_models, P.models.data(), sizeof(DevModel) * n_models,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_jobs, P.jobs.data(), sizeof(DevJob) * n_jobs,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_tabs, P.tabs.data(), sizeof(DevTable) * P.tabs.size(),
+                        hipMemcpyHostToDevice, s));
+  if (n_final > 0)
+    HIPCHK(hipMemcpyAsync(ws + P.off_finals, finals, sizeof(int) * 2 * n_final,
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(launch_zero_int(reinterpret_cast<int*>(ws + P.off_counter), 64, s));
+
+  SolveArgs a{};
+  a.models = reinterpret_cast<const DevModel*>(ws + P.off_models);
+  a.jobs = reinterpret_cast<const DevJob*>(ws + P.off_jobs);
+  a.n_jobs = n_jobs;
+  a.tabs = reinterpret_cast<const DevTable*>(ws + P.off_tabs);
+  a.tables = reinterpret_cast<const c64*>(ws + P.off_tables);
+  a.tables32 = mixed ? reinterpret_cast<const c32*>(ws + P.off_tables32) : nullptr;
+  a.counter = reinterpret_cast<int*>(ws + P.off_counter);
+  a.scratch = reinterpret_cast<c64*>(ws + P.off_scratch);
+  a.slot_elems = P.slot_elems;
+  a.ncap = P.ncap;
+  a.m = mixed ? opts->outer_restart : opts->restart;
+  a.max_iter = opts->max_iter;
+  a.tol = opts->tol;
+  a.precond = opts->precond;
+  a.m_in = opts->inner_restart;
+  a.tol_in = opts->inner_tol;
+  a.n_final = n_final;
+  a.finals = reinterpret_cast<const int*>(ws + P.off_finals);
+  a.T_out = reinterpret_cast<c64*>(T_out);
+  a.sigma_out = sigma_out;
+  a.psi_out = reinterpret_cast<c64*>(psi_out);
+  a.psi_ld = 2 * (size_t)P.max_nc;
+  a.info = reinterpret_cast<DevInfo*>(ws + P.off_info);
+
+  HIPCHK(launch_level_shift_tables(a.models, a.tabs, (int)P.tabs.size(), P.max_nc,
+                                   reinterpret_cast<c64*>(ws + P.off_tables),
+                                   mixed ? reinterpret_cast<c32*>(ws + P.off_tables32) : nullptr, s));
+  if (plain) {
+    std::string err;
+    st = solve_plain_impl(a, P.jobs, P.models, s, err);
+    if (st != VDC_OK) return fail(st, err);
+  } else if (mixed) {
+    HIPCHK(launch_fgmres_mixed(a, P.n_groups, s));
+  } else {
+    HIPCHK(launch_gmres_fp64(a, P.n_groups, s));
+  }
+  std::vector<DevInfo> hinfo(n_jobs);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), ws + P.off_info, sizeof(DevInfo) * n_jobs,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    for (int j = 0; j < n_jobs; ++j) {
+      info[j].status = hinfo[j].status;
+      info[j].iters = hinfo[j].iters;
+      info[j].restarts = hinfo[j].restarts;
+      info[j].outer_iters = hinfo[j].outer;
+      info[j].rel_res = hinfo[j].rel_res;
+    }
+  }
+  return VDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vdc_last_error(void) { return g_err.c_str(); }
+
+const char* vdc_version(void) { return "vdc 0.1 gfx950"; }
+
+vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
+  if (!d || !out) return fail(VDC_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (d->Ng < 1 || d->Nu < 1 || d->Ng > kSqMax || d->Nu > kSqMax)
+    return fail(VDC_ERR_INVALID_ARG, "Ng and Nu must be 1..1024");
+  if (d->hilbert_nodes < 16 || d->hilbert_nodes > 65536)
+    return fail(VDC_ERR_INVALID_ARG, "hilbert_nodes must be 16..65536");
+  if (!(d->hilbert_xmax > 0.0) || !std::isfinite(d->hilbert_xmax))
+    return fail(VDC_ERR_INVALID_ARG, "hilbert_xmax must be > 0");
+  for (int mu = 0; mu < 2; ++mu) {
+    if (d->l[mu] < 0 || d->l[mu] > 4) return fail(VDC_ERR_INVALID_ARG, "l must be 0..4");
+    for (int s = 0; s < 2; ++s) {
+      if (!(d->A[s][mu] >= 0.0) || !std::isfinite(d->A[s][mu]))
+        return fail(VDC_ERR_INVALID_ARG, "width amplitudes A must be finite and >= 0");
+      if (!(d->B[s][mu] > 0.0) || !std::isfinite(d->B[s][mu]))
+        return fail(VDC_ERR_INVALID_ARG, "width scales B must be finite and > 0");
+    }
+  }
+  const double scal[] = {d->omega_g, d->omega_u, d->kappa1, d->kappa2, d->lam,
+                         d->lam1,    d->lam2,    d->E1,     d->gap};
+  for (double v : scal)
+    if (!std::isfinite(v)) return fail(VDC_ERR_INVALID_ARG, "non-finite model parameter");
+  if (!(d->omega_g > 0.0) || !(d->omega_u > 0.0))
+    return fail(VDC_ERR_INVALID_ARG, "vibrational frequencies must be > 0");
+  if ((size_t)d->Ng * d->Nu > (size_t)1 << 26) return fail(VDC_ERR_INVALID_ARG, "basis too large");
+
+  vdc_model* m = new vdc_model();
+  m->desc = *d;
+  DevModel& dm = m->dev;
+  dm.Ng = d->Ng;
+  dm.Nu = d->Nu;
+  dm.Nc = d->Ng * d->Nu;
+  dm.K = d->hilbert_nodes;
+  dm.omega_g = d->omega_g;
+  dm.omega_u = d->omega_u;
+  dm.E1 = d->E1;
+  dm.E2 = d->E1 + d->gap;
+  dm.kappa[0] = d->kappa1;
+  dm.kappa[1] = d->kappa2;
+  dm.lam = d->lam;
+  dm.lamd[0] = d->lam1;
+  dm.lamd[1] = d->lam2;
+  for (int s = 0; s < 2; ++s)
+    for (int mu = 0; mu < 2; ++mu) {
+      dm.A[s][mu] = d->A[s][mu];
+      dm.B[s][mu] = d->B[s][mu];
+    }
+  dm.l[0] = d->l[0];
+  dm.l[1] = d->l[1];
+  // transform data: nodes, slope jumps c_k of the interpolated width products
+  const int K = dm.K;
+  std::vector<double> x(K), coef((size_t)K * kNumF, 0.0);
+  for (int k = 0; k < K; ++k) {
+    const double t = k * std::sqrt(d->hilbert_xmax) / (K - 1);
+    x[k] = t * t;
+  }
+  for (int mu = 0; mu < 2; ++mu) {
+    const int pairs[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+    for (int pq = 0; pq < 3; ++pq) {
+      const int f = fidx(mu, pq);
+      std::vector<double> g(K);
+      for (int k = 0; k < K; ++k) g[k] = width_pair_host(*d, mu, pairs[pq][0], pairs[pq][1], x[k]);
+      double sprev = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double s = (k + 1 < K) ? (g[k + 1] - g[k]) / (x[k + 1] - x[k]) : 0.0;
+        coef[(size_t)k * kNumF + f] = s - sprev;
+        sprev = s;
+      }
+      dm.glast[f] = g[K - 1];
+    }
+  }
+  hipError_t e = hipMalloc(&m->d_nodes, sizeof(double) * K);
+  if (e == hipSuccess) e = hipMalloc(&m->d_coef, sizeof(double) * K * kNumF);
+  if (e == hipSuccess) e = hipMemcpy(m->d_nodes, x.data(), sizeof(double) * K, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->d_coef, coef.data(), sizeof(double) * K * kNumF, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (m->d_nodes) (void)hipFree(m->d_nodes);
+    if (m->d_coef) (void)hipFree(m->d_coef);
+    delete m;
+    return hip_fail(e, "model upload");
+  }
+  dm.nodes = m->d_nodes;
+  dm.coef = m->d_coef;
+  *out = m;
+  return VDC_OK;
+}
+
+vdc_status vdc_model_destroy(vdc_model_t m) {
+  if (!m) return VDC_OK;
+  if (m->d_nodes) (void)hipFree(m->d_nodes);
+  if (m->d_coef) (void)hipFree(m->d_coef);
+  delete m;
+  return VDC_OK;
+}
+
+vdc_status vdc_workspace_size(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                              int n_jobs, const vdc_job* jobs, size_t* bytes) {
+  if (!bytes) return fail(VDC_ERR_INVALID_ARG, "bytes is NULL");
+  // size for the larger of the two paths so one workspace serves both
+  Plan P;
+  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, kMaxFinal, false, P);
+  if (st != VDC_OK) return st;
+  size_t total = P.total;
+  if (opts->precision == VDC_FP64) {
+    Plan Q;
+    st = make_plan(n_models, models, opts, n_jobs, jobs, kMaxFinal, true, Q);
+    if (st != VDC_OK) return st;
+    total = std::max(total, Q.total);
+  }
+  *bytes = total;
+  return VDC_OK;
+}
+
+vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                     int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                     void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                     double* psi_out, vdc_job_info* info, void* stream) {
+  return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
+                   T_out, sigma_out, psi_out, info, stream, false);
+}
+
+vdc_status vdc_solve_plain(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                           int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                           void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                           double* psi_out, vdc_job_info* info, void* stream) {
+  return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
+                   T_out, sigma_out, psi_out, info, stream, true);
+}
+
+vdc_status vdc_level_shift(vdc_model_t m, int n_eps, const double* eps, double* out, void* stream) {
+  if (!m) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+  if (n_eps < 0) return fail(VDC_ERR_INVALID_ARG, "n_eps < 0");
+  if (n_eps == 0) return VDC_OK;
+  if (!eps || !out) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  HIPCHK(launch_level_shift_points(m->dev, n_eps, eps, reinterpret_cast<c64*>(out),
+                                   reinterpret_cast<hipStream_t>(stream)));
+  return VDC_OK;
+}
+
+static size_t matvec_ws(const vdc_model* m, int n_vec) {
+  const size_t Nc = (size_t)m->dev.Nc;
+  size_t off = 0;
+  off = align256(off + sizeof(DevModel));
+  off = align256(off + sizeof(DevTable));
+  off = align256(off + sizeof(int) * std::max(1, n_vec));
+  off = align256(off + sizeof(c64) * 6 * Nc);
+  off = align256(off + sizeof(c64) * 4 * Nc * std::max(1, n_vec));
+  return off;
+}
+
+vdc_status vdc_matvec_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
+  if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  *bytes = matvec_ws(m, n_vec);
+  return VDC_OK;
+}
+
+vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, const double* x,
+                      double* y, void* workspace, size_t ws_bytes, void* stream) {
+  if (!m) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+  if (n_vec < 0 || !std::isfinite(E)) return fail(VDC_ERR_INVALID_ARG, "bad n_vec or E");
+  if (n_vec == 0) return VDC_OK;
+  if (!parity || !x || !y || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  for (int v = 0; v < n_vec; ++v)
+    if (parity[v] != 0 && parity[v] != 1) return fail(VDC_ERR_INVALID_ARG, "parity must be 0 or 1");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < matvec_ws(m, n_vec)) return fail(VDC_ERR_WORKSPACE, "workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t Nc = (size_t)m->dev.Nc;
+  char* ws = static_cast<char*>(workspace);
+  size_t off = 0;
+  DevModel* dmod = reinterpret_cast<DevModel*>(ws + off); off = align256(off + sizeof(DevModel));
+  DevTable* dtab = reinterpret_cast<DevTable*>(ws + off); off = align256(off + sizeof(DevTable));
+  int* dpar = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * n_vec);
+  c64* tables = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * 6 * Nc);
+  c64* z = reinterpret_cast<c64*>(ws + off);
+  c64* yc = z + Nc * n_vec;
+  c64* wA = yc + Nc * n_vec;
+  c64* wB = wA + Nc * n_vec;
+  DevTable t;
+  t.E = E;
+  t.model = 0;
+  t.pad = 0;
+  t.offset = 0;
+  HIPCHK(hipMemcpyAsync(dmod, &m->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dtab, &t, sizeof(DevTable), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dpar, parity, sizeof(int) * n_vec, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_level_shift_tables(dmod, dtab, 1, m->dev.Nc, tables, nullptr, s));
+  HIPCHK(launch_matvec_full(dmod, dtab, tables, n_vec, dpar, reinterpret_cast<const c64*>(x),
+                            reinterpret_cast<c64*>(y), z, yc, wA, wB, m->dev.Nc, s));
+  // the host-side staging buffers above are read by the copies before return
+  HIPCHK(hipStreamSynchronize(s));
+  return VDC_OK;
+}
+
+}  // extern "C"

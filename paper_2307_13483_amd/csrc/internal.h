@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP translation units of libvdc.
+// Not part of the C ABI (see include/vdc.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "vdc.h"
+
+namespace vdc {
+
+constexpr double kHartreeEV = 27.211386245988;
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kBlock = 1024;      // threads per workgroup of the persistent solver
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxRestart = 128;
+constexpr int kMaxFinal = 64;
+constexpr int kNumF = 6;          // level-shift functions per energy
+
+// Level-shift function index: mu-major, pairs (11, 12, 22).
+//   0: F[f1e f1e]  1: F[f1e f2e]  2: F[f2e f2e]
+//   3: F[f1o f1o]  4: F[f1o f2o]  5: F[f2o f2o]
+__host__ __device__ constexpr int fidx(int mu, int pair) { return 3 * mu + pair; }
+
+// Model parameters in the form the kernels read them (plain values + device
+// pointers to the transform data owned by the model).
+struct DevModel {
+  int Ng, Nu, Nc;        // Nc = Ng*Nu unknowns per symmetry block
+  int K;                 // transform nodes
+  double omega_g, omega_u;
+  double E1, E2;
+  double kappa[2];       // [d]
+  double lam;            // direct q_u coupling
+  double lamd[2];        // continuum-coupling slopes lam_1, lam_2
+  double A[2][2], B[2][2];
+  int l[2];
+  double glast[kNumF];   // interpolated width product at the last node
+  const double* nodes;   // [K]            device
+  const double* coef;    // [K][kNumF]     device: second differences c_k
+};
+
+// One job as the kernels see it (host-filled, device-resident array).
+struct DevJob {
+  double eps_i;          // incident electron energy
+  double E;              // total energy eps_i + E_{v_i}
+  int vi_g, vi_u, mu;
+  int parity;            // 0: state 1 on even n_u; 1: state 1 on odd n_u
+  int model;             // index into the DevModel array
+  int table;             // index of the per-energy table pair
+  int out;               // index of the job in the caller's arrays
+  int pad;
+};
+
+// Per-energy table set: 2 parities x 3 planes (AA, AB, BB) x Nc complex.
+struct DevTable {
+  double E;
+  int model;
+  int pad;
+  size_t offset;         // in complex elements from the table base
+};
+
+// Per-job results written by the kernels, copied to vdc_job_info on the host.
+struct DevInfo {
+  int status, iters, restarts, outer;
+  double rel_res;
+};
+
+struct c64 { double x, y; };
+struct c32 { float x, y; };
+
+__host__ __device__ inline c64 mk(double a, double b) { return c64{a, b}; }
+__host__ __device__ inline c64 operator+(c64 a, c64 b) { return c64{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline c64 operator-(c64 a, c64 b) { return c64{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline c64 operator*(c64 a, c64 b) {
+  return c64{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline c64 operator*(double s, c64 a) { return c64{s * a.x, s * a.y}; }
+__host__ __device__ inline c64 conjmul(c64 a, c64 b) {  // conj(a) * b
+  return c64{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ inline double norm2(c64 a) { return a.x * a.x + a.y * a.y; }
+
+__host__ __device__ inline c32 operator+(c32 a, c32 b) { return c32{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline c32 operator-(c32 a, c32 b) { return c32{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline c32 operator*(c32 a, c32 b) {
+  return c32{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline c32 operator*(float s, c32 a) { return c32{s * a.x, s * a.y}; }
+__host__ __device__ inline c32 conjmul(c32 a, c32 b) {
+  return c32{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ inline float norm2(c32 a) { return a.x * a.x + a.y * a.y; }
+
+// Launchers (defined in the .hip files).
+hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevTable* tables_dev,
+                                     int n_tables, int max_nc, c64* table_base,
+                                     c32* table32_base, hipStream_t s);
+hipError_t launch_level_shift_points(const DevModel& m, int n_eps, const double* eps,
+                                     c64* out, hipStream_t s);
+
+}  // namespace vdc

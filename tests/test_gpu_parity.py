@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Tolerances:
+  * level-shift tables: 64 ulp of the sum of magnitudes of the transform's
+    terms (both sides sum the same terms in a different order and lose
+    digits by cancellation near threshold);
+  * matvec: FP64 in a different order, 1e-13 of the largest entry;
+  * solves: the oracle recomputes ||b - A psi_gpu|| / ||b|| with its own
+    assembled A and requires <= tol (1e-10) + 1e-13 rounding slack; the
+    amplitudes agree with the oracle's LU solution within cond * tol, checked
+    as a relative 1e-8 (cond(A) is O(10^2) for these models).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import levelshift as ls
+from oracle import model2d as m2
+from oracle import solvers
+from paper_2307_13483_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_13483_amd import vdc as v
+    v.lib()
+    return v
+
+
+def _oracle_job(p, Ng, Nu, eps_i, vi, mu, finals):
+    E = m2.total_energy(p, eps_i, vi)
+    mdl = m2.Model2D(p, Ng, Nu, E)
+    A = mdl.matrix()
+    b = mdl.phi(vi, m2.MU[mu])
+    psi = solvers.lu_solve(A, b)
+    T = np.array([[mdl.phi(vf, mf) @ psi for mf in m2.MU] for vf in finals])
+    return mdl, A, b, psi, T
+
+
+# ------------------------------------------------------------ level shift
+
+def _shift_error_bound(eps, A1, B1, A2, B2, l, p):
+    """Rounding bound of the principal-value sum: the terms c_k psi(eps - x_k)
+    (slope jumps times t ln|t|) are up to ~1e5 times the result near
+    threshold, so both sides lose digits by cancellation; allow 64 ulp of the
+    sum of magnitudes, plus 1e-13 of the value."""
+    x = ls.grid_nodes(p["K"], p["X"])
+    g = ls.pair_g(x, A1, B1, A2, B2, l)
+    s = np.diff(g) / np.diff(x)
+    c = np.concatenate([[s[0]], np.diff(s), [-s[-1]]])
+    out = []
+    for e in np.atleast_1d(eps):
+        t = e - x
+        psi = np.abs(t * np.log(np.abs(np.where(t == 0, 1.0, t))))
+        out.append(64 * 2.2e-16 * np.sum(np.abs(c) * psi) / (2 * np.pi) + 1e-15)
+    return np.array(out)
+
+
+def _table_bounds(p, eps):
+    """Per-point error bounds of the six level-shift diagonals (oracle-side
+    Model2D 'tables' hook, used to build an error-bound matrix)."""
+    out = {}
+    for mu in ("e", "o"):
+        l = p["l_" + mu]
+        for a, b in ((1, 1), (1, 2), (2, 2)):
+            out[(mu, a, b)] = _shift_error_bound(eps, p["A%d%s" % (a, mu)], p["B%d%s" % (a, mu)],
+                                                 p["A%d%s" % (b, mu)], p["B%d%s" % (b, mu)], l, p) + 0j
+    return out
+
+
+@pytest.mark.parametrize("seed", [None, 4])
+def test_level_shift_tables_match_oracle(vdc, seed):
+    p = inputs.base_params() if seed is None else inputs.draw_params(seed)
+    model = vdc.Model2D(p, 4, 4)
+    eps = np.array([-3.0, -0.5, 0.0, 1e-9, 0.01, 0.37, 1.0, 1.55, 2.999, 4.2, 12.0])
+    got = vdc.level_shift(model, eps).cpu().numpy()
+    ref = m2.default_tables(p, eps)
+    order = [("e", 1, 1), ("e", 1, 2), ("e", 2, 2), ("o", 1, 1), ("o", 1, 2), ("o", 2, 2)]
+    for f, key in enumerate(order):
+        mu = key[0]
+        l = p["l_" + mu]
+        A1, B1 = p["A%d%s" % (key[1], mu)], p["B%d%s" % (key[1], mu)]
+        A2, B2 = p["A%d%s" % (key[2], mu)], p["B%d%s" % (key[2], mu)]
+        assert np.max(np.abs(got[:, f] - ref[key]) / _shift_error_bound(eps, A1, B1, A2, B2, l, p)) <= 1.0, key
+
+
+def test_level_shift_at_grid_nodes(vdc):
+    """eps exactly on a node of the transform: the principal value is finite."""
+    p = inputs.base_params()
+    model = vdc.Model2D(p, 2, 2)
+    x = ls.grid_nodes(p["K"], p["X"])
+    eps = x[[1, 10, 500, 2000]]
+    got = vdc.level_shift(model, eps).cpu().numpy()
+    ref = m2.default_tables(p, eps)
+    assert np.all(np.isfinite(got))
+    bound = _shift_error_bound(eps, p["A1e"], p["B1e"], p["A1e"], p["B1e"], p["l_e"], p)
+    assert np.all(np.abs(got[:, 0] - ref[("e", 1, 1)]) <= bound)
+
+
+# ------------------------------------------------------------ matvec
+
+@pytest.mark.parametrize("Ng,Nu,seed", [(1, 1, 0), (2, 3, 1), (7, 5, 2), (40, 40, 3), (33, 70, 4),
+                                        (120, 9, 5)])
+def test_matvec_matches_assembled_matrix(vdc, Ng, Nu, seed):
+    import torch
+    p = inputs.draw_params(seed)
+    rng = np.random.default_rng(seed)
+    E = 2.3
+    A = m2.Model2D(p, Ng, Nu, E).matrix()
+    lab = m2.parity_of(Ng, Nu)
+    xs, par = [], []
+    for parity in (0, 1):
+        x = rng.standard_normal(2 * Ng * Nu) + 1j * rng.standard_normal(2 * Ng * Nu)
+        x[lab != (1.0 if parity == 0 else -1.0)] = 0.0
+        xs.append(x)
+        par.append(parity)
+    model = vdc.Model2D(p, Ng, Nu)
+    y = vdc.matvec(model, E, torch.tensor(np.array(xs)), par).cpu().numpy()
+    # error bound: rounding of the stencil sums plus the level-shift table
+    # bound pushed through the (nonnegative) sandwich |O| diag(delta) |O|
+    absA = abs(A)
+    mb = m2.Model2D(p, Ng, Nu, E, tables=_table_bounds)
+    Fbound = sp.bmat([[mb.F_block(1, 1), mb.F_block(1, 2)], [mb.F_block(2, 1), mb.F_block(2, 2)]])
+    for k in range(2):
+        ref = A @ xs[k]
+        bound = 1e-14 * (absA @ np.abs(xs[k])) + abs(Fbound) @ np.abs(xs[k]) + 1e-15
+        assert np.all(np.abs(y[k] - ref) <= bound)
+
+
+# ------------------------------------------------------------ solves
+
+def _check_solve(p, Ng, Nu, jobs, finals, T, sigma, psi, infos, tol=1e-10):
+    for k, (eps_i, vi, mu) in enumerate(jobs):
+        mdl, A, b, psi_lu, T_lu = _oracle_job(p, Ng, Nu, eps_i, vi, mu, finals)
+        info = infos[k]
+        assert info["status"] == 0, info
+        res = np.linalg.norm(b - A @ psi[k]) / np.linalg.norm(b)
+        assert res <= tol + 1e-13, (k, res)
+        assert abs(info["rel_res"] - res) <= 1e-12 + 0.05 * res
+        assert np.linalg.norm(psi[k] - psi_lu) <= 1e-8 * np.linalg.norm(psi_lu)
+        scale = np.max(np.abs(T_lu))
+        assert np.max(np.abs(T[k] - T_lu)) <= 1e-8 * scale
+        pref = 2 * math.pi ** 3 / (eps_i / ls.HARTREE_EV)
+        sig = pref * np.sum(np.abs(T[k]) ** 2, axis=1)
+        assert np.allclose(sigma[k], sig, rtol=1e-12, atol=0)
+
+
+def test_single_energy_workload(vdc):
+    """40 x 40 basis, eps_i = 1.0 eV, v_i = 0, both partial waves, GMRES(50)."""
+    cfg = inputs.single_jobs()
+    p = cfg["params"]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    T, sigma, psi, infos = vdc.solve(model, cfg["jobs"], cfg["finals"],
+                                     vdc.Opts(restart=50, tol=1e-10), want_psi=True)
+    _check_solve(p, cfg["Ng"], cfg["Nu"], cfg["jobs"], cfg["finals"], T.cpu().numpy(),
+                 sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+
+
+@pytest.mark.parametrize("Ng,Nu,restart", [(1, 1, 5), (2, 3, 4), (13, 29, 7), (64, 17, 20)])
+def test_ragged_and_tiny_bases(vdc, Ng, Nu, restart):
+    p = inputs.draw_params(21)
+    jobs = [(0.8, (0, 0), 0), (2.1, (min(1, Ng - 1), 0), 1), (1.4, (0, min(1, Nu - 1)), 0)]
+    finals = [(0, 0), (min(2, Ng - 1), 0), (0, min(1, Nu - 1))]
+    model = vdc.Model2D(p, Ng, Nu)
+    T, sigma, psi, infos = vdc.solve(model, jobs, finals, vdc.Opts(restart=restart),
+                                     want_psi=True)
+    _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
+                 psi.cpu().numpy(), infos)
+
+
+def test_iterations_track_textbook_gmres(vdc):
+    """Same restart length and preconditioner as the oracle's textbook GMRES:
+    iteration counts agree closely (CGS2 vs MGS round differently)."""
+    p = inputs.draw_params(8)
+    Ng = Nu = 24
+    jobs = [(0.5, (0, 0), 0), (2.6, (1, 0), 1)]
+    model = vdc.Model2D(p, Ng, Nu)
+    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)], vdc.Opts(restart=15))
+    for k, (e, vi, mu) in enumerate(jobs):
+        mdl, A, b, _, _ = _oracle_job(p, Ng, Nu, e, vi, mu, [(0, 0)])
+        _, info = solvers.gmres(A, b, m=15, tol=1e-10, dinv=1.0 / m2.jacobi_diagonal(A))
+        assert abs(infos[k]["iters"] - info["iters"]) <= 2, (infos[k], info)
+
+
+def test_batched_full_size_sampled(vdc):
+    """The 120 x 120 batched workload's model on a sample of its jobs, all in
+    one launch; every job checked against the oracle."""
+    cfg = inputs.batched_jobs(n_energies=512)
+    p = cfg["params"]
+    sample = [cfg["jobs"][k] for k in (0, 1, 1001, 2000, 3071, 2502)]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    T, sigma, psi, infos = vdc.solve(model, sample, cfg["finals"], vdc.Opts(restart=30),
+                                     want_psi=True)
+    _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
+                 sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+
+
+def test_repeat_runs_bitwise_identical(vdc):
+    cfg = inputs.single_jobs()
+    model = vdc.Model2D(cfg["params"], 30, 30)
+    s = vdc.Solver(model, cfg["jobs"] * 3, cfg["finals"], vdc.Opts(restart=20))
+    a = s.run().T.cpu().numpy().copy()
+    b = s.run().T.cpu().numpy().copy()
+    assert np.array_equal(a, b)
+    # the same job repeated inside the batch gives the same bits
+    assert np.array_equal(a[0], a[2]) and np.array_equal(a[1], a[5])
+
+
+def test_status_not_converged_and_breakdown_free(vdc):
+    cfg = inputs.single_jobs()
+    model = vdc.Model2D(cfg["params"], 20, 20)
+    _, _, _, infos = vdc.solve(model, cfg["jobs"], cfg["finals"],
+                               vdc.Opts(restart=5, max_iter=1))
+    assert all(i["status"] == vdc.NOT_CONVERGED and i["iters"] == 1 for i in infos)
+
+
+def test_closed_final_channels_are_zero(vdc):
+    """eps_f = E - E_{v_f} <= 0: f(eps_f) = 0, so T and sigma are exactly 0."""
+    p = inputs.base_params()
+    model = vdc.Model2D(p, 20, 10)
+    finals = [(0, 0), (10, 0), (19, 9)]
+    T, sigma, _, infos = vdc.solve(model, [(0.2, (0, 0), 0)], finals, vdc.Opts())
+    T = T.cpu().numpy()
+    assert infos[0]["status"] == 0
+    assert np.all(T[0, 1:] == 0) and np.all(sigma.cpu().numpy()[0, 1:] == 0)
+    assert np.all(np.abs(T[0, 0]) > 0) or abs(T[0, 0, 0]) > 0
+
+
+def test_invalid_jobs_rejected(vdc):
+    model = vdc.Model2D(inputs.base_params(), 5, 5)
+    for jobs in ([(0.0, (0, 0), 0)], [(-1.0, (0, 0), 0)], [(1.0, (5, 0), 0)], [(1.0, (0, 0), 2)]):
+        with pytest.raises(vdc.VdcError) as e:
+            vdc.solve(model, jobs, [(0, 0)], vdc.Opts())
+        assert e.value.code == vdc.VDC_ERR_INVALID_ARG
