@@ -1,0 +1,204 @@
+"""Throughput of the batched scattering solve on one MI355X.
+
+Workload (one "step"): the generalized two-state model of Sec. II.C at one
+seeded +-20 % parameter draw, 120 x 120 basis per state (28800 unknowns),
+512 incident energies on [0.1, 3.0] eV x initial states v_i = 0, 1, 2 x
+both partial waves = 3072 right-hand sides, each solved to a relative true
+residual of 1e-10 (restarted GMRES, diagonal preconditioner), followed by the
+amplitudes to v_f = 0..5 and the cross-section shares.  The per-energy
+level-shift tables are built inside the step.  Inputs are synthetic (seeded
+parameters; the paper uses no dataset).
+
+Prints one JSON line (see DESIGN.md for the byte model behind "roofline").
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "converged solves/s at 1e-10 rel. residual; matvec HBM GB/s; batched+FP32 vs plain"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["op2d.h", "blockops.h", "solve_args.h", "gmres.hip", "mixed.hip"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2307_13483_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def fp64_solver_bytes(infos, nc, m, n_final):
+    """Algorithmic HBM bytes of the FP64 persistent solver for the given job
+    results, counted in passes over one block vector of nc complex FP64
+    (16 B) values:
+      setup per job: 3 table planes read, dinv/x/b/v_0 written        -> 7
+      Arnoldi step j (j+1 basis vectors): matvec reads v_j, dinv and 3
+        table planes, writes w (6); CGS2 reads the basis 4 times
+        (two projections, two updates: 4 (j+1)); v_{j+1} written (1)
+      cycle end with k steps: x += M^-1 V y reads k vectors, dinv, x and
+        writes x (k+3); true residual: matvec of x (5), b read (1),
+        v_0 written (1)                                                -> k+10
+    """
+    passes = 0
+    for inf in infos:
+        it = inf["iters"]
+        cyc = max(1, inf["restarts"])
+        passes += 7
+        # distribute the steps over cycles of length m
+        left = it
+        for _ in range(cyc):
+            k = min(m, left)
+            left -= k
+            passes += sum(6 + 4 * (j + 1) + 1 for j in range(k)) + k + 10
+    return passes * 16.0 * nc
+
+
+def load_traffic(kernel, workload):
+    """HBM traffic per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        e = d[kernel][workload]
+        if e.get("kernel_hash") != kernel_hash():
+            return None
+        return e["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(cfg, n_sample):
+    """The oracle as it stands: assemble A, LU-solve, project T, for a bounded
+    sample of the same jobs, one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import model2d as m2
+    from oracle import solvers
+    p, Ng, Nu = cfg["params"], cfg["Ng"], cfg["Nu"]
+    jobs = cfg["jobs"]
+    idx = [int(round(k * (len(jobs) - 1) / max(1, n_sample - 1))) for k in range(n_sample)]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for k in idx:
+            eps_i, vi, mu = jobs[k]
+            mdl = m2.Model2D(p, Ng, Nu, m2.total_energy(p, eps_i, vi))
+            A = mdl.matrix()
+            psi = solvers.lu_solve(A, mdl.phi(vi, m2.MU[mu]))
+            for vf in cfg["finals"]:
+                for mf in m2.MU:
+                    _ = mdl.phi(vf, mf) @ psi
+        dt = time.perf_counter() - t0
+    return dict(value=len(idx) / dt, unit="solves/s", cores=1, kind="oracle",
+                sample=f"{len(idx)} of the {len(jobs)} right-hand sides (evenly spaced), "
+                       f"sparse LU of the assembled {2 * Ng * Nu}-unknown matrix, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--energies", type=int, default=512)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--plain-sample", type=int, default=48,
+                    help="right-hand sides timed on the plain single-solve path (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=4,
+                    help="right-hand sides timed on the CPU oracle (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2307_13483_amd import inputs, vdc
+
+    cfg = inputs.batched_jobs(n_energies=args.energies)
+    p, Ng, Nu = cfg["params"], cfg["Ng"], cfg["Nu"]
+    nc = Ng * Nu
+    model = vdc.Model2D(p, Ng, Nu)
+    prec = vdc.FP64 if args.precision == "fp64" else vdc.FP32_INNER
+    opts = vdc.Opts(restart=args.restart, tol=1e-10, precision=prec)
+    solver = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts)
+    n_jobs = solver.n_jobs
+    for _ in range(args.warmup):
+        solver.run()
+    torch.cuda.synchronize()
+    ms_tables, ms_solver, conv = [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.run()
+        a, b = vdc.last_kernel_times()
+        ms_tables.append(a)
+        ms_solver.append(b)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    infos = solver.infos()
+    conv = sum(1 for i in infos if i["status"] == vdc.CONVERGED)
+    value = conv * args.steps / dt
+    iters = [i["iters"] for i in infos]
+    solver_ms = sum(ms_solver) / len(ms_solver)
+    if prec == vdc.FP64:
+        alg = fp64_solver_bytes(infos, nc, args.restart, len(cfg["finals"]))
+    else:
+        alg = None
+    kernel = "gmres_fp64_kernel" if prec == vdc.FP64 else "fgmres_mixed_kernel"
+    workload = f"batched_{args.energies}x3x2_{Ng}x{Nu}_m{args.restart}"
+    achieved = alg / (solver_ms * 1e-3) / 1e9 if alg else None
+    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=(achieved / HBM_PEAK_GBS) if achieved else None,
+                traffic=load_traffic(kernel, workload), kernel=kernel,
+                algorithmic_bytes=alg, kernel_ms=solver_ms)
+    out = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if prec == vdc.FP64 else "c64-inner/c128-outer",
+        "data": "synthetic (seeded parameter draw, no dataset)",
+        "config": {"workload": "2D generalized model, batched energies x v_i x mu",
+                   "basis": f"{Ng}x{Nu} per state", "unknowns": 2 * nc,
+                   "right_hand_sides": n_jobs, "energies": args.energies,
+                   "solver": f"GMRES({args.restart}) Jacobi, tol 1e-10",
+                   "precision": args.precision},
+        "converged": conv,
+        "iters_mean": sum(iters) / len(iters), "iters_max": max(iters),
+        "ms_tables": sum(ms_tables) / len(ms_tables), "ms_solver": solver_ms,
+        "roofline": roof,
+    }
+    if args.plain_sample > 0 and prec == vdc.FP64:
+        jobs = cfg["jobs"]
+        k = args.plain_sample
+        sub = [jobs[int(round(i * (len(jobs) - 1) / max(1, k - 1)))] for i in range(k)]
+        sp = vdc.Solver(model, sub, cfg["finals"], opts)
+        try:
+            sp.run(plain=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            sp.run(plain=True)
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t1
+            sb = vdc.Solver(model, sub, cfg["finals"], opts)
+            sb.run()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            sb.run()
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t2
+            out["plain"] = dict(sample=k, plain_solves_per_s=k / tp, batched_same_jobs_solves_per_s=k / tb,
+                                speedup_full_batch_vs_plain=value / (k / tp))
+        except vdc.VdcError as e:
+            out["plain"] = dict(error=str(e))
+    if args.cpu_sample > 0:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

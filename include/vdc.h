@@ -178,6 +178,13 @@ vdc_status vdc_matvec(vdc_model_t model, double E, int n_vec, const int* parity,
                       const double* x, double* y, void* workspace, size_t ws_bytes,
                       void* stream);
 
+/* Durations, in milliseconds, of the kernels of the last vdc_solve /
+ * vdc_solve_plain call on this host thread, measured with HIP events recorded
+ * on the call's stream: the level-shift table kernel and the solver (the
+ * persistent kernel, or the whole sequence of plain-path kernels).  Host
+ * pointers, either may be NULL. */
+vdc_status vdc_last_kernel_times(double* ms_tables, double* ms_solver);
+
 /* Thread-local text of the last error (never NULL). */
 const char* vdc_last_error(void);
 

@@ -37,6 +37,21 @@ struct vdc_model {
 namespace {
 
 thread_local std::string g_err = "no error";
+thread_local double g_ms_tables = 0.0, g_ms_solver = 0.0;
+
+// Events bracketing the table kernel and the solver on the call's stream.
+struct EventSet {
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  bool ok = false;
+  EventSet() {
+    ok = true;
+    for (auto& x : e) ok = ok && hipEventCreate(&x) == hipSuccess;
+  }
+  ~EventSet() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
 
 vdc_status fail(vdc_status s, const std::string& msg) {
   g_err = msg;
@@ -72,13 +87,16 @@ struct Plan {
   std::vector<DevModel> models;
   std::vector<DevJob> jobs;       // sorted, longest first
   std::vector<DevTable> tabs;
+  std::vector<DevGroup> groups;
   int max_nc = 0;
+  int max_group_pts = 0;
+  size_t shift_elems = 0;
   size_t table_elems = 0;
   int n_groups = 0;
   size_t ncap = 0, slot_elems = 0;
   // byte offsets
-  size_t off_counter, off_models, off_jobs, off_tabs, off_finals, off_info, off_tables,
-      off_tables32, off_scratch, total;
+  size_t off_counter, off_models, off_jobs, off_tabs, off_groups, off_finals, off_info,
+      off_shift, off_tables, off_tables32, off_scratch, total;
 };
 
 int cu_count() {
@@ -118,6 +136,44 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     P.max_nc = std::max(P.max_nc, models[k]->dev.Nc);
   }
   std::map<std::pair<int, double>, int> tab_index;
+  // jobs sharing (model, eps_i) share one shift table over the offsets they need
+  std::map<std::pair<int, double>, int> grp_index;
+  std::vector<int> gvmin_g, gvmax_g, gvmin_u, gvmax_u;
+  for (int j = 0; j < n_jobs; ++j) {
+    const vdc_job& jb = jobs[j];
+    if (jb.model < 0 || jb.model >= n_models) return fail(VDC_ERR_INVALID_ARG, "job model index out of range");
+    auto key = std::make_pair(jb.model, jb.eps_i);
+    auto it = grp_index.find(key);
+    if (it == grp_index.end()) {
+      it = grp_index.emplace(key, (int)P.groups.size()).first;
+      DevGroup g{};
+      g.eps_i = jb.eps_i;
+      g.model = jb.model;
+      P.groups.push_back(g);
+      gvmin_g.push_back(jb.vi_g);
+      gvmax_g.push_back(jb.vi_g);
+      gvmin_u.push_back(jb.vi_u);
+      gvmax_u.push_back(jb.vi_u);
+    } else {
+      const int g = it->second;
+      gvmin_g[g] = std::min(gvmin_g[g], jb.vi_g);
+      gvmax_g[g] = std::max(gvmax_g[g], jb.vi_g);
+      gvmin_u[g] = std::min(gvmin_u[g], jb.vi_u);
+      gvmax_u[g] = std::max(gvmax_u[g], jb.vi_u);
+    }
+  }
+  for (size_t g = 0; g < P.groups.size(); ++g) {
+    DevGroup& G = P.groups[g];
+    const DevModel& md = P.models[G.model];
+    G.a_min = gvmin_g[g] - (md.Ng - 1);
+    G.na = gvmax_g[g] - G.a_min + 1;
+    G.b_min = gvmin_u[g] - (md.Nu - 1);
+    G.nb = gvmax_u[g] - G.b_min + 1;
+    G.offset = P.shift_elems;
+    P.shift_elems += (size_t)G.na * G.nb * kNumF;
+    P.max_group_pts = std::max(P.max_group_pts, G.na * G.nb);
+  }
+  if (P.groups.size() > 65535) return fail(VDC_ERR_INVALID_ARG, "more than 65535 distinct incident energies");
   P.jobs.resize(n_jobs);
   for (int j = 0; j < n_jobs; ++j) {
     const vdc_job& jb = jobs[j];
@@ -144,7 +200,9 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
       DevTable t;
       t.E = o2.E;
       t.model = jb.model;
-      t.pad = 0;
+      t.group = grp_index.at(std::make_pair(jb.model, jb.eps_i));
+      t.vg = jb.vi_g;
+      t.vu = jb.vi_u;
       t.offset = P.table_elems;
       P.table_elems += 6 * (size_t)P.models[jb.model].Nc;
       it = tab_index.emplace(key, (int)P.tabs.size()).first;
@@ -179,8 +237,10 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   P.off_models = off; off = align256(off + sizeof(DevModel) * n_models);
   P.off_jobs = off; off = align256(off + sizeof(DevJob) * std::max(1, n_jobs));
   P.off_tabs = off; off = align256(off + sizeof(DevTable) * std::max<size_t>(1, P.tabs.size()));
+  P.off_groups = off; off = align256(off + sizeof(DevGroup) * std::max<size_t>(1, P.groups.size()));
   P.off_finals = off; off = align256(off + sizeof(int) * 2 * std::max(1, n_final));
   P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
+  P.off_shift = off; off = align256(off + sizeof(c64) * P.shift_elems);
   P.off_tables = off; off = align256(off + sizeof(c64) * P.table_elems);
   P.off_tables32 = off; off = align256(off + (mixed ? sizeof(c32) * P.table_elems : 0));
   P.off_scratch = off; off = align256(off + sizeof(c64) * P.slot_elems * P.n_groups);
@@ -214,6 +274,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + P.off_tabs, P.tabs.data(), sizeof(DevTable) * P.tabs.size(),
                         hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_groups, P.groups.data(), sizeof(DevGroup) * P.groups.size(),
+                        hipMemcpyHostToDevice, s));
   if (n_final > 0)
     HIPCHK(hipMemcpyAsync(ws + P.off_finals, finals, sizeof(int) * 2 * n_final,
                           hipMemcpyHostToDevice, s));
@@ -244,9 +306,15 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   a.psi_ld = 2 * (size_t)P.max_nc;
   a.info = reinterpret_cast<DevInfo*>(ws + P.off_info);
 
-  HIPCHK(launch_level_shift_tables(a.models, a.tabs, (int)P.tabs.size(), P.max_nc,
+  EventSet ev;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  HIPCHK(launch_level_shift_tables(a.models, reinterpret_cast<const DevGroup*>(ws + P.off_groups),
+                                   (int)P.groups.size(), P.max_group_pts, a.tabs,
+                                   (int)P.tabs.size(), P.max_nc,
+                                   reinterpret_cast<c64*>(ws + P.off_shift),
                                    reinterpret_cast<c64*>(ws + P.off_tables),
                                    mixed ? reinterpret_cast<c32*>(ws + P.off_tables32) : nullptr, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
   if (plain) {
     std::string err;
     st = solve_plain_impl(a, P.jobs, P.models, s, err);
@@ -256,10 +324,18 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   } else {
     HIPCHK(launch_gmres_fp64(a, P.n_groups, s));
   }
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
   std::vector<DevInfo> hinfo(n_jobs);
   HIPCHK(hipMemcpyAsync(hinfo.data(), ws + P.off_info, sizeof(DevInfo) * n_jobs,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t1 = 0.f, t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = t1;
+    g_ms_solver = t2;
+  }
   if (info) {
     for (int j = 0; j < n_jobs; ++j) {
       info[j].status = hinfo[j].status;
@@ -277,6 +353,12 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
 extern "C" {
 
 const char* vdc_last_error(void) { return g_err.c_str(); }
+
+vdc_status vdc_last_kernel_times(double* ms_tables, double* ms_solver) {
+  if (ms_tables) *ms_tables = g_ms_tables;
+  if (ms_solver) *ms_solver = g_ms_solver;
+  return VDC_OK;
+}
 
 const char* vdc_version(void) { return "vdc 0.1 gfx950"; }
 
@@ -425,6 +507,8 @@ static size_t matvec_ws(const vdc_model* m, int n_vec) {
   size_t off = 0;
   off = align256(off + sizeof(DevModel));
   off = align256(off + sizeof(DevTable));
+  off = align256(off + sizeof(DevGroup));
+  off = align256(off + sizeof(c64) * kNumF * Nc);
   off = align256(off + sizeof(int) * std::max(1, n_vec));
   off = align256(off + sizeof(c64) * 6 * Nc);
   off = align256(off + sizeof(c64) * 4 * Nc * std::max(1, n_vec));
@@ -454,21 +538,37 @@ vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, con
   size_t off = 0;
   DevModel* dmod = reinterpret_cast<DevModel*>(ws + off); off = align256(off + sizeof(DevModel));
   DevTable* dtab = reinterpret_cast<DevTable*>(ws + off); off = align256(off + sizeof(DevTable));
+  DevGroup* dgrp = reinterpret_cast<DevGroup*>(ws + off); off = align256(off + sizeof(DevGroup));
+  c64* shift = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * Nc);
   int* dpar = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * n_vec);
   c64* tables = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * 6 * Nc);
   c64* z = reinterpret_cast<c64*>(ws + off);
   c64* yc = z + Nc * n_vec;
   c64* wA = yc + Nc * n_vec;
   c64* wB = wA + Nc * n_vec;
-  DevTable t;
+  // one energy: a shift table over offsets a = -n_g, b = -n_u at
+  // eps = E - (w_g + w_u)/2 + w_g a + w_u b = E - E_nu, read with v = (0, 0)
+  DevGroup g{};
+  g.eps_i = E - 0.5 * (m->dev.omega_g + m->dev.omega_u);
+  g.model = 0;
+  g.a_min = -(m->dev.Ng - 1);
+  g.na = m->dev.Ng;
+  g.b_min = -(m->dev.Nu - 1);
+  g.nb = m->dev.Nu;
+  g.offset = 0;
+  DevTable t{};
   t.E = E;
   t.model = 0;
-  t.pad = 0;
+  t.group = 0;
+  t.vg = 0;
+  t.vu = 0;
   t.offset = 0;
   HIPCHK(hipMemcpyAsync(dmod, &m->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dtab, &t, sizeof(DevTable), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dgrp, &g, sizeof(DevGroup), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dpar, parity, sizeof(int) * n_vec, hipMemcpyHostToDevice, s));
-  HIPCHK(launch_level_shift_tables(dmod, dtab, 1, m->dev.Nc, tables, nullptr, s));
+  HIPCHK(launch_level_shift_tables(dmod, dgrp, 1, m->dev.Nc, dtab, 1, m->dev.Nc, shift, tables,
+                                   nullptr, s));
   HIPCHK(launch_matvec_full(dmod, dtab, tables, n_vec, dpar, reinterpret_cast<const c64*>(x),
                             reinterpret_cast<c64*>(y), z, yc, wA, wB, m->dev.Nc, s));
   // the host-side staging buffers above are read by the copies before return

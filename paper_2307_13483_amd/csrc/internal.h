@@ -55,8 +55,20 @@ struct DevJob {
 struct DevTable {
   double E;
   int model;
-  int pad;
+  int group;             // shift table it is gathered from
+  int vg, vu;            // initial state of a job with this energy
   size_t offset;         // in complex elements from the table base
+};
+
+// Shift table of one (model, eps_i): level shifts at eps_i + w_g a + w_u b for
+// the offsets a = v_g - n_g in [a_min, a_min + na), b = v_u - n_u in
+// [b_min, b_min + nb), stored [point][6] from offset (complex elements).
+struct DevGroup {
+  double eps_i;
+  int model;
+  int a_min, na, b_min, nb;
+  int pad;
+  size_t offset;
 };
 
 // Per-job results written by the kernels, copied to vdc_job_info on the host.
@@ -92,8 +104,9 @@ __host__ __device__ inline c32 conjmul(c32 a, c32 b) {
 __host__ __device__ inline float norm2(c32 a) { return a.x * a.x + a.y * a.y; }
 
 // Launchers (defined in the .hip files).
-hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevTable* tables_dev,
-                                     int n_tables, int max_nc, c64* table_base,
+hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,
+                                     int n_groups, int max_group_pts, const DevTable* tables_dev,
+                                     int n_tables, int max_nc, c64* shift, c64* table_base,
                                      c32* table32_base, hipStream_t s);
 hipError_t launch_level_shift_points(const DevModel& m, int n_eps, const double* eps,
                                      c64* out, hipStream_t s);

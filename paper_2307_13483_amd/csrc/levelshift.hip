@@ -9,11 +9,59 @@
 // (s_{-1} = s_{K-1} = 0; g_0 = 0 because Gamma(0) = 0).  This follows from
 // integrating L(x)/(eps - x) segment by segment and summing by parts.
 // All six functions share the same psi(eps - x_k), so each node costs one
-// logarithm and six fused multiply-adds.
+// logarithm and six fused multiply-adds; nodes and slope jumps are staged
+// through LDS in chunks shared by the workgroup.
 // Imaginary part: -g(eps)/2 = -pi f_d f_d' for eps > 0, else 0 (analytic).
+//
+// Sharing across initial states: eps_nu = eps_i + w_g (v_g - n_g) + w_u (v_u - n_u)
+// depends on (n_g, n_u) only through the offsets (v_g - n_g, v_u - n_u), so
+// the jobs with one incident energy eps_i evaluate the transform once on the
+// rectangle of offsets they need ("shift table"), and a gather pass writes
+// each total energy's block tables from it.
 #include "internal.h"
 
 namespace vdc {
+
+constexpr int kLsThreads = 256;
+constexpr int kLsChunk = 256;      // nodes staged per LDS chunk
+constexpr int kLsStride = 8;       // doubles per staged node: x, c[6], pad
+
+// ln|t| for t != 0, finite: t = m 2^e with m in [1/sqrt2, sqrt2),
+// ln m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, by its odd power series
+// (11 terms: the remainder is below 2^-56 relative), plus e ln 2 with ln 2
+// split into a 32-bit head and a tail so e*ln2_hi is exact.
+__device__ inline double ln_abs(double t) {
+  int e;
+  double m = frexp(fabs(t), &e);            // [0.5, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double num = m - 1.0;               // exact
+  const double den = m + 1.0;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  double s = num * r;
+  s = fma(r, fma(-s, den, num), s);         // one residual correction
+  const double z = s * s;
+  double p = 1.0 / 23.0;
+  p = fma(p, z, 1.0 / 21.0);
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double lnm = fma(2.0 * s * z, p, 2.0 * s);
+  const double ln2_hi = 6.93147180369123816490e-01;   // 32 significant bits
+  const double ln2_lo = 1.90821492927058770002e-10;
+  const double de = (double)e;
+  return fma(de, ln2_hi, fma(de, ln2_lo, lnm));
+}
 
 __device__ inline double width_pair(const DevModel& m, int mu, int d1, int d2, double eps) {
   if (!(eps > 0.0)) return 0.0;
@@ -22,25 +70,42 @@ __device__ inline double width_pair(const DevModel& m, int mu, int d1, int d2, d
   return A * pow(eps, m.l[mu] + 0.5) * exp(-eps * rB);
 }
 
-// The six complex values at one electron energy eps.
-__device__ inline void level_shift6(const DevModel& m, double eps, c64 out[kNumF]) {
+// The six complex values at electron energy eps, for a workgroup of
+// kLsThreads threads that all call it (with `active` false for idle threads)
+// so the LDS staging barriers are uniform.
+__device__ inline void level_shift6_block(const DevModel& m, double eps, bool active,
+                                          double* lds, c64 out[kNumF]) {
   double acc[kNumF];
 #pragma unroll
   for (int f = 0; f < kNumF; ++f) acc[f] = 0.0;
   const double* __restrict__ xk = m.nodes;
   const double* __restrict__ ck = m.coef;
-  for (int k = 0; k < m.K; ++k) {
-    const double t = eps - xk[k];
-    const double psi = (t == 0.0) ? 0.0 : t * log(fabs(t));
+  for (int k0 = 0; k0 < m.K; k0 += kLsChunk) {
+    const int nk = min(kLsChunk, m.K - k0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nk; q += blockDim.x) {
+      double* d = lds + q * kLsStride;
+      d[0] = xk[k0 + q];
 #pragma unroll
-    for (int f = 0; f < kNumF; ++f) acc[f] = fma(ck[k * kNumF + f], psi, acc[f]);
+      for (int f = 0; f < kNumF; ++f) d[1 + f] = ck[(size_t)(k0 + q) * kNumF + f];
+      d[7] = 0.0;
+    }
+    __syncthreads();
+    if (active) {
+      for (int q = 0; q < nk; ++q) {
+        const double* d = lds + q * kLsStride;
+        const double t = eps - d[0];
+        const double psi = (t == 0.0) ? 0.0 : t * ln_abs(t);
+#pragma unroll
+        for (int f = 0; f < kNumF; ++f) acc[f] = fma(d[1 + f], psi, acc[f]);
+      }
+    }
   }
   const double tl = eps - xk[m.K - 1];
-  const double lnl = (tl == 0.0) ? 0.0 : log(fabs(tl));
+  const double lnl = (tl == 0.0) ? 0.0 : ln_abs(tl);
   const double inv2pi = 1.0 / (2.0 * kPi);
 #pragma unroll
   for (int f = 0; f < kNumF; ++f) out[f].x = (acc[f] - m.glast[f] * (lnl + 1.0)) * inv2pi;
-  // imaginary parts, pairs (1,1), (1,2), (2,2) per mu
 #pragma unroll
   for (int mu = 0; mu < 2; ++mu) {
     out[fidx(mu, 0)].y = -0.5 * width_pair(m, mu, 0, 0, eps);
@@ -49,22 +114,49 @@ __device__ inline void level_shift6(const DevModel& m, double eps, c64 out[kNumF
   }
 }
 
-// One thread per (energy, basis point).  Writes both parity tables:
+// Shift tables: one thread per (group, offset point).  Group g covers offsets
+// a in [a_min, a_min + na), b in [b_min, b_min + nb) at eps_i + w_g a + w_u b,
+// stored [point][6] from the group's offset.
+__global__ void __launch_bounds__(kLsThreads)
+shift_table_kernel(const DevModel* __restrict__ models, const DevGroup* __restrict__ groups,
+                   c64* __restrict__ shift) {
+  __shared__ double lds[kLsChunk * kLsStride];
+  const DevGroup gr = groups[blockIdx.y];
+  const DevModel& m = models[gr.model];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npts = gr.na * gr.nb;
+  const bool active = i < npts;
+  double eps = 0.0;
+  if (active) {
+    const int ia = i / gr.nb, ib = i - ia * gr.nb;
+    eps = gr.eps_i + m.omega_g * (gr.a_min + ia) + m.omega_u * (gr.b_min + ib);
+  }
+  // a whole workgroup beyond this group's points has nothing to do
+  if (blockIdx.x * blockDim.x >= npts) return;
+  c64 F[kNumF];
+  level_shift6_block(m, eps, active, lds, F);
+  if (active) {
+#pragma unroll
+    for (int f = 0; f < kNumF; ++f) shift[gr.offset + (size_t)i * kNumF + f] = F[f];
+  }
+}
+
+// Block tables of one total energy from its group's shift table:
 // table[(p*3 + slot)*Nc + i], slots (AA, AB, BB) of the active state at i:
 // state 1 active (n_u + p even): (F[1e1e], F[1e2e], F[2e2e]);
 // state 2 active:               (F[2o2o], F[1o2o], F[1o1o]).
-__global__ void __launch_bounds__(256)
-level_shift_tables_kernel(const DevModel* __restrict__ models, const DevTable* __restrict__ tabs,
-                          int max_nc, c64* __restrict__ base, c32* __restrict__ base32) {
-  const int t = blockIdx.y;
-  const DevTable tb = tabs[t];
+__global__ void __launch_bounds__(kLsThreads)
+gather_tables_kernel(const DevModel* __restrict__ models, const DevGroup* __restrict__ groups,
+                     const DevTable* __restrict__ tabs, const c64* __restrict__ shift,
+                     c64* __restrict__ base, c32* __restrict__ base32) {
+  const DevTable tb = tabs[blockIdx.y];
   const DevModel& m = models[tb.model];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m.Nc) return;
+  const DevGroup gr = groups[tb.group];
   const int ng = i / m.Nu, nu = i - ng * m.Nu;
-  const double Ev = m.omega_g * (ng + 0.5) + m.omega_u * (nu + 0.5);
-  c64 F[kNumF];
-  level_shift6(m, tb.E - Ev, F);
+  const int ia = tb.vg - ng - gr.a_min, ib = tb.vu - nu - gr.b_min;
+  const c64* F = shift + gr.offset + (size_t)(ia * gr.nb + ib) * kNumF;
   for (int p = 0; p < 2; ++p) {
     const bool s1 = ((nu + p) & 1) == 0;
     const c64 aa = s1 ? F[0] : F[5];
@@ -83,31 +175,37 @@ level_shift_tables_kernel(const DevModel* __restrict__ models, const DevTable* _
   }
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kLsThreads)
 level_shift_points_kernel(DevModel m, int n, const double* __restrict__ eps, c64* __restrict__ out) {
+  __shared__ double lds[kLsChunk * kLsStride];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const bool active = i < n;
   c64 F[kNumF];
-  level_shift6(m, eps[i], F);
+  level_shift6_block(m, active ? eps[i] : 0.0, active, lds, F);
+  if (active) {
 #pragma unroll
-  for (int f = 0; f < kNumF; ++f) out[(size_t)i * kNumF + f] = F[f];
+    for (int f = 0; f < kNumF; ++f) out[(size_t)i * kNumF + f] = F[f];
+  }
 }
 
-hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevTable* tables_dev,
-                                     int n_tables, int max_nc, c64* table_base,
+hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,
+                                     int n_groups, int max_group_pts, const DevTable* tables_dev,
+                                     int n_tables, int max_nc, c64* shift, c64* table_base,
                                      c32* table32_base, hipStream_t s) {
   if (n_tables <= 0) return hipSuccess;
-  dim3 grid((max_nc + 255) / 256, n_tables);
-  hipLaunchKernelGGL(level_shift_tables_kernel, grid, dim3(256), 0, s, models_dev, tables_dev,
-                     max_nc, table_base, table32_base);
+  dim3 g1((max_group_pts + kLsThreads - 1) / kLsThreads, n_groups);
+  hipLaunchKernelGGL(shift_table_kernel, g1, dim3(kLsThreads), 0, s, models_dev, groups_dev, shift);
+  dim3 g2((max_nc + kLsThreads - 1) / kLsThreads, n_tables);
+  hipLaunchKernelGGL(gather_tables_kernel, g2, dim3(kLsThreads), 0, s, models_dev, groups_dev,
+                     tables_dev, shift, table_base, table32_base);
   return hipGetLastError();
 }
 
 hipError_t launch_level_shift_points(const DevModel& m, int n_eps, const double* eps, c64* out,
                                      hipStream_t s) {
   if (n_eps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(level_shift_points_kernel, dim3((n_eps + 255) / 256), dim3(256), 0, s, m,
-                     n_eps, eps, out);
+  hipLaunchKernelGGL(level_shift_points_kernel, dim3((n_eps + kLsThreads - 1) / kLsThreads),
+                     dim3(kLsThreads), 0, s, m, n_eps, eps, out);
   return hipGetLastError();
 }
 

@@ -83,6 +83,7 @@ def lib():
         "vdc_level_shift": (I, [P, I, P, P, P]),
         "vdc_matvec_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
         "vdc_matvec": (I, [P, D, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
+        "vdc_last_kernel_times": (I, [ctypes.POINTER(D), ctypes.POINTER(D)]),
         "vdc_last_error": (ctypes.c_char_p, []),
         "vdc_version": (ctypes.c_char_p, []),
     }
@@ -242,6 +243,13 @@ def solve(models, jobs, finals, opts=None, plain=False, want_psi=False):
     """One-shot helper: returns (T, sigma, psi, infos) as torch/python objects."""
     s = Solver(models, jobs, finals, opts, want_psi).run(plain=plain)
     return s.T, s.sigma, s.psi, s.infos()
+
+
+def last_kernel_times():
+    """(ms of the table kernel, ms of the solver) of the last solve call."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().vdc_last_kernel_times(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def version():
