@@ -105,14 +105,27 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--energies", type=int, default=512)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--plain-sample", type=int, default=48,
                     help="right-hand sides timed on the plain single-solve path (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="right-hand sides timed on the CPU oracle (0: skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times "
+                         "(calibrates the HBM byte counters of a profiler)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = 1 << 30
+        x = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "repeats": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
