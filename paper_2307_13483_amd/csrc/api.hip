@@ -20,6 +20,7 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
+size_t plain_extra_elems(size_t ncap, int m);
 vdc_status solve_plain_impl(const SolveArgs& a, const std::vector<DevJob>& jobs,
                             const std::vector<DevModel>& models, hipStream_t s,
                             std::string& err);
@@ -227,6 +228,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   } else {
     // V (m+1), x, b, dinv, w, wA, wB, R
     P.slot_elems = (size_t)(m + 1 + 6) * P.ncap + (size_t)(m + 1) * m;
+    if (plain) P.slot_elems += plain_extra_elems(P.ncap, m);
   }
   P.slot_elems = (P.slot_elems + 31) / 32 * 32;
   int occ = 1;

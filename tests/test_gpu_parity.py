@@ -238,3 +238,21 @@ def test_invalid_jobs_rejected(vdc):
         with pytest.raises(vdc.VdcError) as e:
             vdc.solve(model, jobs, [(0, 0)], vdc.Opts())
         assert e.value.code == vdc.VDC_ERR_INVALID_ARG
+
+
+def test_plain_path_matches_oracle_and_batched(vdc):
+    """The plain single-solve path (one grid-wide kernel per step) solves the
+    same jobs to the same tolerance; its iteration counts match the batched
+    solver's (same algorithm, different reduction order)."""
+    p = inputs.draw_params(31)
+    Ng, Nu = 30, 26
+    jobs = [(0.7, (0, 0), 0), (2.4, (1, 0), 1), (1.6, (0, 1), 0)]
+    finals = [(0, 0), (1, 0), (2, 0)]
+    model = vdc.Model2D(p, Ng, Nu)
+    opts = vdc.Opts(restart=12)
+    T, sigma, psi, infos = vdc.solve(model, jobs, finals, opts, plain=True, want_psi=True)
+    _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
+                 psi.cpu().numpy(), infos)
+    _, _, _, binfos = vdc.solve(model, jobs, finals, opts)
+    for a, b in zip(infos, binfos):
+        assert abs(a["iters"] - b["iters"]) <= 1 and a["status"] == b["status"] == 0
