@@ -221,10 +221,11 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   const int m = mixed ? o->outer_restart : o->restart;
   P.ncap = (size_t)((P.max_nc + 63) / 64) * 64;
   if (mixed) {
-    // FP64: Vout (m+1), Z (m), x, b, wA, wB, R; FP32 (in c64 units): Vin (m_in+1), dinv, wA, wB
+    // FP64: Vout (m+1), Z (m), x, b, w, wA, wB, R_out, R_in;
+    // FP32 (in c64 units): Vin (m_in+1), dinv, w, wA, wB
     const int mi = o->inner_restart;
-    P.slot_elems = (size_t)(2 * m + 1 + 4) * P.ncap + (size_t)(m + 1) * m +
-                   ((size_t)(mi + 1 + 3) * P.ncap + 1) / 2 + (size_t)(mi + 1) * mi;
+    P.slot_elems = (size_t)(2 * m + 6) * P.ncap + (size_t)(m + 1) * m + (size_t)(mi + 1) * mi +
+                   ((size_t)(mi + 5) * P.ncap + 1) / 2;
   } else {
     // V (m+1), x, b, dinv, w, wA, wB, R
     P.slot_elems = (size_t)(m + 1 + 6) * P.ncap + (size_t)(m + 1) * m;

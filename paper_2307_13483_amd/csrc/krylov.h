@@ -1,0 +1,150 @@
+// One restarted-GMRES cycle run by a whole workgroup (Sec. III.A): Arnoldi
+// with classical Gram-Schmidt applied twice, a one-thread Givens update of
+// each Hessenberg column, and the back substitution R y = g at the end.
+// Generic in the precision R of the basis vectors and their dot products; the
+// small Hessenberg least-squares problem is always FP64.
+#pragma once
+#include "blockops.h"
+
+namespace vdc {
+
+template <typename R>
+struct KrylovLds {
+  double cs[kMaxRestart];
+  c64 sn[kMaxRestart];
+  c64 g[kMaxRestart + 1];
+  c64 y[kMaxRestart];
+  R h1[2 * (kMaxRestart + 1)];
+  R h2[2 * (kMaxRestart + 1)];
+  c64 hc[kMaxRestart + 1];
+  double resid;
+};
+
+__device__ inline c64 cdiv(c64 a, c64 b) {
+  const double n = b.x * b.x + b.y * b.y;
+  return c64{(a.x * b.x + a.y * b.y) / n, (a.y * b.x - a.x * b.y) / n};
+}
+
+// Thread-0 Givens update of Hessenberg column j: apply the previous
+// rotations, build rotation j from (h_jj, h_{j+1,j}), store the R column and
+// update the right-hand side g.  Returns |g_{j+1}| (the residual norm of the
+// least-squares problem).
+template <typename R>
+__device__ inline double givens_step(KrylovLds<R>& L, int j, double hnext, c64* Rcol) {
+  c64* col = L.hc;
+  for (int i = 0; i <= j; ++i)
+    col[i] = c64{(double)L.h1[2 * i] + (double)L.h2[2 * i],
+                 (double)L.h1[2 * i + 1] + (double)L.h2[2 * i + 1]};
+  for (int i = 0; i < j; ++i) {
+    const c64 a = col[i], b = col[i + 1];
+    const c64 s = L.sn[i];
+    const double c = L.cs[i];
+    col[i] = c * a + s * b;
+    col[i + 1] = c * b - c64{s.x, -s.y} * a;
+  }
+  const c64 a = col[j];
+  const double aa = sqrt(norm2(a));
+  const double den = hypot(aa, hnext);
+  double c;
+  c64 s;
+  if (den == 0.0) {
+    c = 1.0;
+    s = c64{0.0, 0.0};
+  } else if (aa == 0.0) {
+    c = 0.0;
+    s = c64{1.0, 0.0};
+  } else {
+    c = aa / den;
+    s = c64{a.x / aa * hnext / den, a.y / aa * hnext / den};  // (a/|a|) conj(h)/den, h real
+  }
+  L.cs[j] = c;
+  L.sn[j] = s;
+  col[j] = c * a + hnext * s;
+  for (int i = 0; i <= j; ++i) Rcol[i] = col[i];
+  const c64 gj = L.g[j];
+  L.g[j + 1] = -1.0 * (c64{s.x, -s.y} * gj);
+  L.g[j] = c * gj;
+  return sqrt(norm2(L.g[j + 1]));
+}
+
+// Back substitution R y = g for the k x k upper triangle (columns in Rm,
+// leading dimension ldr).  Thread 0.
+template <typename R>
+__device__ inline void back_substitute(KrylovLds<R>& L, int k, const c64* Rm, int ldr) {
+  for (int i = k - 1; i >= 0; --i) {
+    c64 s = L.g[i];
+    for (int l = i + 1; l < k; ++l) s = s - Rm[(size_t)l * ldr + i] * L.y[l];
+    L.y[i] = cdiv(s, Rm[(size_t)i * ldr + i]);
+  }
+}
+
+struct CycleResult {
+  int k;           // Arnoldi steps taken
+  bool breakdown;  // h_{k,k-1} == 0 (Krylov space exhausted)
+  bool nonfinite;
+};
+
+// Runs up to m Arnoldi steps from V_0 (normalised, L.g[0] = beta already set
+// by thread 0), stopping when the least-squares residual drops to tol_abs or
+// iters reaches max_iter.  apply(j, w) must write the preconditioned operator
+// applied to basis vector j into w (own elements).  On return L.y holds the
+// least-squares coefficients (after a barrier).
+template <typename R, typename Apply>
+__device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<R>::C* V,
+                                           size_t ld, int Nc, int m, double tol_abs,
+                                           int max_iter, int& iters, c64* Rm,
+                                           typename CT<R>::C* w, Apply apply) {
+  using C = typename CT<R>::C;
+  CycleResult res{0, false, false};
+  for (int j = 0; j < m; ++j) {
+    apply(j, w);
+    project<R>(V, ld, j + 1, w, Nc, red, L.h1);
+    subtract<R>(V, ld, j + 1, w, Nc, L.h1);
+    project<R>(V, ld, j + 1, w, Nc, red, L.h2);
+    subtract<R>(V, ld, j + 1, w, Nc, L.h2);
+    const double hn = sqrt((double)norm_sq<R>(w, Nc, red));
+    if (threadIdx.x == 0) L.resid = givens_step<R>(L, j, hn, Rm + (size_t)j * (m + 1));
+    __syncthreads();
+    const double r = L.resid;
+    ++iters;
+    res.k = j + 1;
+    if (!isfinite(r) || !isfinite(hn)) {
+      res.nonfinite = true;
+      break;
+    }
+    if (hn == 0.0) {
+      res.breakdown = true;
+      break;
+    }
+    if (r <= tol_abs || iters >= max_iter) break;
+    if (j + 1 < m) {
+      const R sc = R(1.0 / hn);
+      for (int i = threadIdx.x; i < Nc; i += kBlock) V[(size_t)(j + 1) * ld + i] = sc * w[i];
+    }
+  }
+  if (threadIdx.x == 0) back_substitute<R>(L, res.k, Rm, m + 1);
+  __syncthreads();
+  return res;
+}
+
+// w = -sum_l V_l y_l (own elements), y from L.y (FP64), in precision R.
+template <typename R>
+__device__ inline void combine_neg(const typename CT<R>::C* V, size_t ld, int k, const c64* y,
+                                   typename CT<R>::C* w, int Nc) {
+  using C = typename CT<R>::C;
+  for (int i = threadIdx.x; i < Nc; i += kBlock) {
+    C s = cz<R>();
+    int l = 0;
+    for (; l + kChunk <= k; l += kChunk) {
+      C vv[kChunk];
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) vv[q] = V[(size_t)(l + q) * ld + i];
+#pragma unroll
+      for (int q = 0; q < kChunk; ++q) s = s - vv[q] * C{R(y[l + q].x), R(y[l + q].y)};
+    }
+    for (; l < k; ++l) s = s - V[(size_t)l * ld + i] * C{R(y[l].x), R(y[l].y)};
+    w[i] = s;
+  }
+}
+
+}  // namespace vdc

@@ -1,7 +1,168 @@
-// FGMRES with an FP32 inner GMRES (placeholder until the kernel lands).
+// Mixed precision on chip: flexible GMRES in complex FP64 (outer) whose
+// variable right preconditioner is one cycle of GMRES run entirely in complex
+// FP32 (inner: FP32 basis, FP32 level-shift tables, FP32 stencil, FP32 dot
+// products accumulated in FP32, FP32 Jacobi scaling).  The outer level keeps
+// everything that decides the answer in FP64: the operator applied to the
+// inner results, its Gram-Schmidt, the Hessenberg least squares by Givens, the
+// solution update, the true residual b - A x and the amplitudes.  Because
+// the outer basis Z of preconditioned vectors is stored (A Z_k = V_{k+1} H_k),
+// the inner solve may differ from step to step and the outer residual
+// estimate stays that of the FP64 operator.
+//
+// One job per workgroup, jobs popped from a device queue as in the FP64
+// solver; "iters" counts inner FP32 Arnoldi steps (the bulk of the bytes),
+// "outer" the FP64 outer steps.
+#include "krylov.h"
 #include "solve_args.h"
 
 namespace vdc {
-hipError_t launch_fgmres_mixed(const SolveArgs&, int, hipStream_t) { return hipErrorNotSupported; }
-int fgmres_mixed_occupancy() { return 1; }
+
+struct MixedLds {
+  KrylovLds<double> Ko;
+  KrylovLds<float> Ki;
+  double red[kRedSize];
+  float redf[kRedSize];
+  double sq[kSqMax + 1];
+  float sqf[kSqMax + 1];
+  int job;
+};
+
+__global__ void __launch_bounds__(kBlock)
+fgmres_mixed_kernel(SolveArgs a) {
+  __shared__ MixedLds L;
+  fill_sq<double>(L.sq);
+  fill_sq<float>(L.sqf);
+  const int tid = threadIdx.x;
+  const int m = a.m, mi = a.m_in;
+  const size_t ld = a.ncap;
+  c64* slot = a.scratch + (size_t)blockIdx.x * a.slot_elems;
+  // FP64 part
+  c64* Vo = slot;                                 // (m+1) x ld
+  c64* Z = Vo + (size_t)(m + 1) * ld;             // m x ld
+  c64* x = Z + (size_t)m * ld;
+  c64* b = x + ld;
+  c64* w = b + ld;
+  c64* wA = w + ld;
+  c64* wB = wA + ld;
+  c64* Ro = wB + ld;                              // (m+1) x m
+  c64* Ri = Ro + (size_t)(m + 1) * m;             // (mi+1) x mi
+  // FP32 part
+  c32* Vi = reinterpret_cast<c32*>(Ri + (size_t)(mi + 1) * mi);   // (mi+1) x ld
+  c32* dinv = Vi + (size_t)(mi + 1) * ld;
+  c32* w32 = dinv + ld;
+  c32* wA32 = w32 + ld;
+  c32* wB32 = wA32 + ld;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) L.job = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int js = L.job;
+    if (js >= a.n_jobs) break;
+    const DevJob jb = a.jobs[js];
+    const DevModel& md = a.models[jb.model];
+    const DevTable tb = a.tabs[jb.table];
+    const size_t toff = tb.offset + (size_t)(jb.parity * 3) * md.Nc;
+    const OpJob<double> op = make_op<double>(md, jb, a.tables + toff);
+    const OpJob<float> op32 = make_op<float>(md, jb, a.tables32 + toff);
+    const int Nc = md.Nc;
+
+    for (int i = tid; i < Nc; i += kBlock) {
+      const c64 d = a.precond ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
+      dinv[i] = c32{(float)d.x, (float)d.y};
+      x[i] = c64{0.0, 0.0};
+      b[i] = c64{0.0, 0.0};
+    }
+    __syncthreads();
+    if (tid == 0) {
+      PhiEntry e[6];
+      const int n = phi_entries(md, jb.mu, jb.eps_i, jb.vi_g, jb.vi_u, e);
+      for (int q = 0; q < n; ++q) b[e[q].g * md.Nu + e[q].u] = c64{e[q].val, 0.0};
+    }
+    __syncthreads();
+    const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
+    double beta = bnorm;
+    int iters = 0, outer = 0, cycles = 0, status = VDC_NOT_CONVERGED;
+    if (!(bnorm > 0.0) || !isfinite(bnorm)) {
+      status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
+      beta = 0.0;
+    } else {
+      for (int i = tid; i < Nc; i += kBlock) Vo[i] = (1.0 / beta) * b[i];
+      // inner FP32 operator: A (dinv * v)
+      auto apply_in = [&](int j, c32* out) {
+        matvec_block<float>(op32, L.sqf, Vi + (size_t)j * ld, dinv, wA32, wB32, out);
+      };
+      // outer step j: Z_j = inner(V_j), out = A Z_j in FP64
+      auto apply_out = [&](int j, c64* out) {
+        const c64* v = Vo + (size_t)j * ld;
+        for (int i = tid; i < Nc; i += kBlock) Vi[i] = c32{(float)v[i].x, (float)v[i].y};
+        const double n0 = sqrt((double)norm_sq<float>(Vi, Nc, L.redf));
+        if (n0 > 0.0) {
+          const float sc = (float)(1.0 / n0);
+          for (int i = tid; i < Nc; i += kBlock) Vi[i] = sc * Vi[i];
+          if (tid == 0) L.Ki.g[0] = c64{n0, 0.0};
+          const CycleResult ci = krylov_cycle<float>(L.Ki, L.redf, Vi, ld, Nc, mi,
+                                                     a.tol_in * n0, a.max_iter, iters, Ri,
+                                                     w32, apply_in);
+          combine_neg<float>(Vi, ld, ci.k, L.Ki.y, w32, Nc);
+        } else {
+          for (int i = tid; i < Nc; i += kBlock) w32[i] = c32{0.f, 0.f};
+        }
+        c64* z = Z + (size_t)j * ld;
+        for (int i = tid; i < Nc; i += kBlock) {
+          const c32 t = dinv[i] * w32[i];
+          z[i] = c64{-(double)t.x, -(double)t.y};
+        }
+        matvec_block<double>(op, L.sq, z, nullptr, wA, wB, out);
+        ++outer;
+      };
+      int ocount = 0;
+      for (;;) {
+        if (tid == 0) L.Ko.g[0] = c64{beta, 0.0};
+        const CycleResult cr = krylov_cycle<double>(L.Ko, L.red, Vo, ld, Nc, m, a.tol * bnorm,
+                                                    1 << 30, ocount, Ro, w, apply_out);
+        // x += Z y
+        combine_neg<double>(Z, ld, cr.k, L.Ko.y, w, Nc);
+        for (int i = tid; i < Nc; i += kBlock) x[i] = x[i] - w[i];
+        // FP64 true residual
+        matvec_block<double>(op, L.sq, x, nullptr, wA, wB, w);
+        for (int i = tid; i < Nc; i += kBlock) w[i] = b[i] - w[i];
+        beta = sqrt(norm_sq<double>(w, Nc, L.red));
+        ++cycles;
+        if (!isfinite(beta) || cr.nonfinite) {
+          status = VDC_NONFINITE;
+          break;
+        }
+        if (beta <= a.tol * bnorm) {
+          status = VDC_CONVERGED;
+          break;
+        }
+        if (cr.breakdown) {
+          status = VDC_BREAKDOWN;
+          break;
+        }
+        if (iters >= a.max_iter) {
+          status = VDC_NOT_CONVERGED;
+          break;
+        }
+        for (int i = tid; i < Nc; i += kBlock) Vo[i] = (1.0 / beta) * w[i];
+      }
+    }
+    __syncthreads();
+    finish_job(a, md, jb, x, tid, status, iters, cycles, outer,
+               bnorm > 0.0 ? beta / bnorm : 0.0);
+  }
+}
+
+hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, hipStream_t s) {
+  hipLaunchKernelGGL(fgmres_mixed_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+int fgmres_mixed_occupancy() {
+  int n = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fgmres_mixed_kernel, kBlock, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 }  // namespace vdc

@@ -256,3 +256,46 @@ def test_plain_path_matches_oracle_and_batched(vdc):
     _, _, _, binfos = vdc.solve(model, jobs, finals, opts)
     for a, b in zip(infos, binfos):
         assert abs(a["iters"] - b["iters"]) <= 1 and a["status"] == b["status"] == 0
+
+
+def _uneven(n_inst, nmin, nmax, seed):
+    insts = inputs.uneven_instances(n_inst=n_inst, seed=seed, nmin=nmin, nmax=nmax)
+    jobs = []
+    for k, ins in enumerate(insts):
+        for mu in (0, 1):
+            jobs.append((ins["eps"], (0, 0), mu, k))
+    return insts, jobs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uneven_multi_model_batch(vdc, precision):
+    """Instances with their own parameter draws and basis sizes in one launch
+    (the uneven mixed-precision workload at reduced sizes); every solve meets
+    the FP64 true-residual target against the oracle's own matrix."""
+    insts, jobs = _uneven(6, 8, 36, 99)
+    models = [vdc.Model2D(ins["params"], ins["Ng"], ins["Nu"]) for ins in insts]
+    finals = [(0, 0), (1, 0), (2, 0)]
+    prec = vdc.FP64 if precision == "fp64" else vdc.FP32_INNER
+    opts = vdc.Opts(restart=20, precision=prec, inner_restart=20, inner_tol=1e-5, outer_restart=8)
+    T, sigma, psi, infos = vdc.solve(models, jobs, finals, opts, want_psi=True)
+    T, sigma, psi = T.cpu().numpy(), sigma.cpu().numpy(), psi.cpu().numpy()
+    for k, (eps_i, vi, mu, mi) in enumerate(jobs):
+        ins = insts[mi]
+        N = 2 * ins["Ng"] * ins["Nu"]
+        _check_solve(ins["params"], ins["Ng"], ins["Nu"], [(eps_i, vi, mu)], finals,
+                     T[k:k + 1], sigma[k:k + 1], psi[k:k + 1, :N], infos[k:k + 1])
+        if precision == "fp32":
+            assert infos[k]["outer_iters"] >= 1
+
+
+def test_mixed_precision_full_size_sample(vdc):
+    """FP32-inner / FP64-outer on the 120 x 120 batched model: the FP64 true
+    residual reaches 1e-10 and the amplitudes match the FP64 oracle."""
+    cfg = inputs.batched_jobs(n_energies=512)
+    p = cfg["params"]
+    sample = [cfg["jobs"][k] for k in (5, 1500, 3070)]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    opts = vdc.Opts(precision=vdc.FP32_INNER, inner_restart=30, inner_tol=1e-5, outer_restart=8)
+    T, sigma, psi, infos = vdc.solve(model, sample, cfg["finals"], opts, want_psi=True)
+    _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
+                 sigma.cpu().numpy(), psi.cpu().numpy(), infos)
