@@ -34,32 +34,6 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def fp64_solver_bytes(infos, nc, m, n_final):
-    """Algorithmic HBM bytes of the FP64 persistent solver for the given job
-    results, counted in passes over one block vector of nc complex FP64
-    (16 B) values:
-      setup per job: 3 table planes read, dinv/x/b/v_0 written        -> 7
-      Arnoldi step j (j+1 basis vectors): matvec reads v_j, dinv and 3
-        table planes, writes w (6); CGS2 reads the basis 4 times
-        (two projections, two updates: 4 (j+1)); v_{j+1} written (1)
-      cycle end with k steps: x += M^-1 V y reads k vectors, dinv, x and
-        writes x (k+3); true residual: matvec of x (5), b read (1),
-        v_0 written (1)                                                -> k+10
-    """
-    passes = 0
-    for inf in infos:
-        it = inf["iters"]
-        cyc = max(1, inf["restarts"])
-        passes += 7
-        # distribute the steps over cycles of length m
-        left = it
-        for _ in range(cyc):
-            k = min(m, left)
-            left -= k
-            passes += sum(6 + 4 * (j + 1) + 1 for j in range(k)) + k + 10
-    return passes * 16.0 * nc
-
-
 def load_traffic(kernel, workload):
     """HBM traffic per launch from committed rocprofv3 counter summaries, if
     they were taken on the current kernel sources; else None."""
@@ -107,7 +81,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--energies", type=int, default=512)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32",
+                    help="fp32: FP32 inner / FP64 outer (FP64 true residual); fp64: FP64 GMRES")
+    ap.add_argument("--inner-restart", type=int, default=30)
+    ap.add_argument("--inner-tol", type=float, default=1e-5)
+    ap.add_argument("--outer-restart", type=int, default=8)
+    ap.add_argument("--both", type=int, default=1, help="also time the other precision")
     ap.add_argument("--plain-sample", type=int, default=48,
                     help="right-hand sides timed on the plain single-solve path (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
@@ -137,59 +116,75 @@ def main():
     p, Ng, Nu = cfg["params"], cfg["Ng"], cfg["Nu"]
     nc = Ng * Nu
     model = vdc.Model2D(p, Ng, Nu)
-    prec = vdc.FP64 if args.precision == "fp64" else vdc.FP32_INNER
-    opts = vdc.Opts(restart=args.restart, tol=1e-10, precision=prec)
-    solver = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts)
-    n_jobs = solver.n_jobs
-    for _ in range(args.warmup):
-        solver.run()
-    torch.cuda.synchronize()
-    ms_tables, ms_solver, conv = [], [], 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        solver.run()
-        a, b = vdc.last_kernel_times()
-        ms_tables.append(a)
-        ms_solver.append(b)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    infos = solver.infos()
-    conv = sum(1 for i in infos if i["status"] == vdc.CONVERGED)
-    value = conv * args.steps / dt
-    iters = [i["iters"] for i in infos]
-    solver_ms = sum(ms_solver) / len(ms_solver)
-    if prec == vdc.FP64:
-        alg = fp64_solver_bytes(infos, nc, args.restart, len(cfg["finals"]))
-    else:
-        alg = None
-    kernel = "gmres_fp64_kernel" if prec == vdc.FP64 else "fgmres_mixed_kernel"
-    workload = f"batched_{args.energies}x3x2_{Ng}x{Nu}_m{args.restart}"
-    achieved = alg / (solver_ms * 1e-3) / 1e9 if alg else None
-    roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=(achieved / HBM_PEAK_GBS) if achieved else None,
-                traffic=load_traffic(kernel, workload), kernel=kernel,
-                algorithmic_bytes=alg, kernel_ms=solver_ms)
+
+    def run_mode(precision):
+        prec = vdc.FP64 if precision == "fp64" else vdc.FP32_INNER
+        opts = vdc.Opts(restart=args.restart, tol=1e-10, precision=prec,
+                        inner_restart=args.inner_restart, inner_tol=args.inner_tol,
+                        outer_restart=args.outer_restart)
+        solver = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts)
+        for _ in range(args.warmup):
+            solver.run()
+        torch.cuda.synchronize()
+        ms_tables, ms_solver = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            solver.run()
+            a, b = vdc.last_kernel_times()
+            ms_tables.append(a)
+            ms_solver.append(b)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        infos = solver.infos()
+        conv = sum(1 for i in infos if i["status"] == vdc.CONVERGED)
+        worst = max(i["rel_res"] for i in infos)
+        iters = [i["iters"] for i in infos]
+        solver_ms = sum(ms_solver) / len(ms_solver)
+        alg = sum(i["alg_bytes"] for i in infos)
+        kernel = "gmres_fp64_kernel" if prec == vdc.FP64 else "fgmres_mixed_kernel"
+        workload = f"batched_{args.energies}x3x2_{Ng}x{Nu}_{precision}"
+        achieved = alg / (solver_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(kernel, workload),
+                    kernel=kernel, algorithmic_bytes_per_launch=alg, kernel_ms=solver_ms)
+        return dict(value=conv * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
+                    converged=conv, worst_rel_res=worst, n_jobs=solver.n_jobs,
+                    iters_mean=sum(iters) / len(iters), iters_max=max(iters),
+                    outer_mean=(sum(i["outer_iters"] for i in infos) / len(infos)),
+                    ms_tables=sum(ms_tables) / len(ms_tables), ms_solver=solver_ms,
+                    roofline=roof, opts=opts)
+
+    head = run_mode(args.precision)
+    other = run_mode("fp64" if args.precision == "fp32" else "fp32") if args.both else None
+    opts = head["opts"]
     out = {
-        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "metric": METRIC, "value": head["value"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c128" if prec == vdc.FP64 else "c64-inner/c128-outer",
+        "dtype": "c128" if args.precision == "fp64" else "c64 inner + c128 outer",
         "data": "synthetic (seeded parameter draw, no dataset)",
         "config": {"workload": "2D generalized model, batched energies x v_i x mu",
                    "basis": f"{Ng}x{Nu} per state", "unknowns": 2 * nc,
-                   "right_hand_sides": n_jobs, "energies": args.energies,
-                   "solver": f"GMRES({args.restart}) Jacobi, tol 1e-10",
+                   "right_hand_sides": head["n_jobs"], "energies": args.energies,
+                   "solver": (f"GMRES({args.restart}) Jacobi" if args.precision == "fp64" else
+                              f"FGMRES({args.outer_restart}) FP64 outer, GMRES({args.inner_restart}) "
+                              f"FP32 inner to {args.inner_tol:g}, Jacobi"),
+                   "tol": "1e-10 relative FP64 true residual",
                    "precision": args.precision},
-        "converged": conv,
-        "iters_mean": sum(iters) / len(iters), "iters_max": max(iters),
-        "ms_tables": sum(ms_tables) / len(ms_tables), "ms_solver": solver_ms,
-        "roofline": roof,
+        "converged": head["converged"], "worst_rel_res": head["worst_rel_res"],
+        "iters_mean": head["iters_mean"], "iters_max": head["iters_max"],
+        "outer_mean": head["outer_mean"],
+        "ms_tables": head["ms_tables"], "ms_solver": head["ms_solver"],
+        "roofline": head["roofline"],
     }
-    if args.plain_sample > 0 and prec == vdc.FP64:
+    if other is not None:
+        out["other_precision"] = {k: v for k, v in other.items() if k != "opts"}
+    if args.plain_sample > 0:
         jobs = cfg["jobs"]
         k = args.plain_sample
         sub = [jobs[int(round(i * (len(jobs) - 1) / max(1, k - 1)))] for i in range(k)]
-        sp = vdc.Solver(model, sub, cfg["finals"], opts)
+        popts = vdc.Opts(restart=args.restart, tol=1e-10, precision=vdc.FP64)
+        sp = vdc.Solver(model, sub, cfg["finals"], popts)
         try:
             sp.run(plain=True)
             torch.cuda.synchronize()
@@ -197,15 +192,16 @@ def main():
             sp.run(plain=True)
             torch.cuda.synchronize()
             tp = time.perf_counter() - t1
-            sb = vdc.Solver(model, sub, cfg["finals"], opts)
+            sb = vdc.Solver(model, sub, cfg["finals"], popts)
             sb.run()
             torch.cuda.synchronize()
             t2 = time.perf_counter()
             sb.run()
             torch.cuda.synchronize()
             tb = time.perf_counter() - t2
-            out["plain"] = dict(sample=k, plain_solves_per_s=k / tp, batched_same_jobs_solves_per_s=k / tb,
-                                speedup_full_batch_vs_plain=value / (k / tp))
+            out["plain"] = dict(sample=k, plain_fp64_solves_per_s=k / tp,
+                                batched_fp64_same_jobs_solves_per_s=k / tb,
+                                speedup_batched_vs_plain=head["value"] / (k / tp))
         except vdc.VdcError as e:
             out["plain"] = dict(error=str(e))
     if args.cpu_sample > 0:

@@ -114,6 +114,10 @@ typedef struct {
   int restarts;              /* GMRES cycles (outer steps for FP32)             */
   int outer_iters;           /* FP32_INNER: outer FGMRES steps, else 0          */
   double rel_res;            /* final ||b - A x|| / ||b||, FP64 true residual   */
+  double alg_bytes;          /* HBM bytes the job's solve moves by the solver's
+                                design (vector passes x element size; see the
+                                byte model in the solver sources), excluding
+                                the level-shift tables' construction           */
 } vdc_job_info;
 
 /* Build a model (host call; allocates and fills its small device tables:

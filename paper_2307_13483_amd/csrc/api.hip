@@ -346,6 +346,7 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
       info[j].restarts = hinfo[j].restarts;
       info[j].outer_iters = hinfo[j].outer;
       info[j].rel_res = hinfo[j].rel_res;
+      info[j].alg_bytes = hinfo[j].alg_bytes;
     }
   }
   return VDC_OK;

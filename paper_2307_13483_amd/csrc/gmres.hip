@@ -71,6 +71,10 @@ gmres_fp64_kernel(SolveArgs a) {
     const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
     double beta = bnorm;
     int iters = 0, cycles = 0, status = VDC_NOT_CONVERGED;
+    // byte model (passes over a block vector of Nc complex FP64 values):
+    // setup 7 (3 table planes read; dinv, x, b, v_0 written), each cycle of k
+    // steps cycle_passes(k) + k + 10 (x update k + 3, true residual 7)
+    double passes = 7.0;
     if (!(bnorm > 0.0) || !isfinite(bnorm)) {
       status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
       beta = 0.0;
@@ -83,6 +87,7 @@ gmres_fp64_kernel(SolveArgs a) {
         if (tid == 0) L.K.g[0] = c64{beta, 0.0};
         const CycleResult cr = krylov_cycle<double>(L.K, L.red, V, ld, Nc, m, a.tol * bnorm,
                                                     a.max_iter, iters, Rm, w, apply);
+        passes += cycle_passes(cr.k) + cr.k + 10.0;
         // ---- x += M^{-1} V y
         combine_neg<double>(V, ld, cr.k, L.K.y, w, Nc);
         for (int i = tid; i < Nc; i += kBlock) x[i] = x[i] - dinv[i] * w[i];
@@ -111,7 +116,8 @@ gmres_fp64_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    finish_job(a, md, jb, x, tid, status, iters, cycles, 0, bnorm > 0.0 ? beta / bnorm : 0.0);
+    finish_job(a, md, jb, x, tid, status, iters, cycles, 0, bnorm > 0.0 ? beta / bnorm : 0.0,
+               passes * 16.0 * Nc);
   }
 }
 

@@ -75,6 +75,7 @@ struct DevGroup {
 struct DevInfo {
   int status, iters, restarts, outer;
   double rel_res;
+  double alg_bytes;
 };
 
 struct c64 { double x, y; };

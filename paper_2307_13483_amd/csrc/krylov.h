@@ -78,6 +78,14 @@ __device__ inline void back_substitute(KrylovLds<R>& L, int k, const c64* Rm, in
   }
 }
 
+// Vector passes of one Arnoldi cycle of k steps by design: per step j the
+// operator reads v_j, the Jacobi scaling and three level-shift planes and
+// writes w (6), CGS2 reads the basis four times (4 (j+1)), v_{j+1} is
+// written (1).
+__host__ __device__ inline double cycle_passes(int k) {
+  return 7.0 * k + 2.0 * k * (k + 1.0);
+}
+
 struct CycleResult {
   int k;           // Arnoldi steps taken
   bool breakdown;  // h_{k,k-1} == 0 (Krylov space exhausted)

@@ -83,6 +83,15 @@ fgmres_mixed_kernel(SolveArgs a) {
     const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
     double beta = bnorm;
     int iters = 0, outer = 0, cycles = 0, status = VDC_NOT_CONVERGED;
+    // byte model in passes over a block vector of Nc values, p64 in complex
+    // FP64 (16 B) and p32 in complex FP32 (8 B):
+    //   setup: 3 FP64 table planes read, x, b, v_0 written; dinv32 written
+    //   outer step: cast v_j (p64 + p32), norm and scale (3 p32), inner cycle
+    //     of k steps (cycle_passes(k) p32), z = -dinv V y (k + 3 p32, p64),
+    //     A z in FP64 (5 p64)
+    //   outer cycle of k_o steps: CGS2 on the outer basis and v_{j+1}
+    //     (cycle_passes(k_o) - 6 k_o p64), x += Z y (k_o + 2), residual 7
+    double p64 = 6.0, p32 = 1.0;
     if (!(bnorm > 0.0) || !isfinite(bnorm)) {
       status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
       beta = 0.0;
@@ -105,6 +114,7 @@ fgmres_mixed_kernel(SolveArgs a) {
                                                      a.tol_in * n0, a.max_iter, iters, Ri,
                                                      w32, apply_in);
           combine_neg<float>(Vi, ld, ci.k, L.Ki.y, w32, Nc);
+          p32 += cycle_passes(ci.k) + ci.k + 3.0;
         } else {
           for (int i = tid; i < Nc; i += kBlock) w32[i] = c32{0.f, 0.f};
         }
@@ -115,12 +125,15 @@ fgmres_mixed_kernel(SolveArgs a) {
         }
         matvec_block<double>(op, L.sq, z, nullptr, wA, wB, out);
         ++outer;
+        p64 += 1.0 + 1.0 + 5.0;
+        p32 += 4.0;
       };
       int ocount = 0;
       for (;;) {
         if (tid == 0) L.Ko.g[0] = c64{beta, 0.0};
         const CycleResult cr = krylov_cycle<double>(L.Ko, L.red, Vo, ld, Nc, m, a.tol * bnorm,
                                                     1 << 30, ocount, Ro, w, apply_out);
+        p64 += cycle_passes(cr.k) - 6.0 * cr.k + cr.k + 2.0 + 7.0;
         // x += Z y
         combine_neg<double>(Z, ld, cr.k, L.Ko.y, w, Nc);
         for (int i = tid; i < Nc; i += kBlock) x[i] = x[i] - w[i];
@@ -150,7 +163,7 @@ fgmres_mixed_kernel(SolveArgs a) {
     }
     __syncthreads();
     finish_job(a, md, jb, x, tid, status, iters, cycles, outer,
-               bnorm > 0.0 ? beta / bnorm : 0.0);
+               bnorm > 0.0 ? beta / bnorm : 0.0, (16.0 * p64 + 8.0 * p32) * Nc);
   }
 }
 

@@ -23,7 +23,7 @@ struct PlainState {
   c64 sn[kMaxRestart];
   c64 y[kMaxRestart];
   double cs[kMaxRestart];
-  double hn, resid, beta, bnorm;
+  double hn, resid, beta, bnorm, passes;
   int k, done, status, iters, cycles, breakdown, stop_cycle;
 };
 
@@ -63,6 +63,7 @@ __global__ void p_rhs(PlainArgs a) {
   s.cycles = 0;
   s.breakdown = 0;
   s.stop_cycle = 0;
+  s.passes = 7.0;
 }
 
 // per-block partial sums of |v|^2 (the v is w or b)
@@ -270,6 +271,7 @@ __global__ void p_status(PlainArgs a) {
   PlainState& s = *a.st;
   if (s.done) return;
   s.cycles += 1;
+  s.passes += 7.0 * s.k + 2.0 * s.k * (s.k + 1.0) + s.k + 10.0;
   const double beta = s.beta;
   if (!isfinite(beta)) {
     s.status = VDC_NONFINITE;
@@ -292,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) p_finish(SolveArgs sa, PlainArgs a) {
   __syncthreads();
   const PlainState& s = *a.st;
   finish_job(sa, a.md, a.jb, a.x, threadIdx.x, s.status, s.iters, s.cycles, 0,
-             s.bnorm > 0.0 ? s.beta / s.bnorm : 0.0);
+             s.bnorm > 0.0 ? s.beta / s.bnorm : 0.0, s.passes * 16.0 * a.md.Nc);
 }
 
 size_t plain_extra_elems(size_t ncap, int m) {

@@ -37,7 +37,7 @@ struct SolveArgs {
 // the status.  Called by all threads of the workgroup after a barrier.
 __device__ inline void finish_job(const SolveArgs& a, const DevModel& md, const DevJob& jb,
                                   const c64* x, int tid, int status, int iters, int cycles,
-                                  int outer, double rel_res) {
+                                  int outer, double rel_res, double alg_bytes) {
   const int out = jb.out;
   if (tid < a.n_final) {
     const int g = a.finals[2 * tid], u = a.finals[2 * tid + 1];
@@ -65,7 +65,7 @@ __device__ inline void finish_job(const SolveArgs& a, const DevModel& md, const 
       psi[(size_t)(1 - act) * md.Nc + i] = c64{0.0, 0.0};
     }
   }
-  if (tid == 0) a.info[out] = DevInfo{status, iters, cycles, outer, rel_res};
+  if (tid == 0) a.info[out] = DevInfo{status, iters, cycles, outer, rel_res, alg_bytes};
 }
 
 }  // namespace vdc

@@ -54,7 +54,8 @@ class SolveOpts(ctypes.Structure):
 
 class JobInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
-                ("outer_iters", ctypes.c_int), ("rel_res", ctypes.c_double)]
+                ("outer_iters", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -236,7 +237,8 @@ class Solver:
     def infos(self):
         return [dict(status=self.info[k].status, iters=self.info[k].iters,
                      restarts=self.info[k].restarts, outer_iters=self.info[k].outer_iters,
-                     rel_res=self.info[k].rel_res) for k in range(self.n_jobs)]
+                     rel_res=self.info[k].rel_res, alg_bytes=self.info[k].alg_bytes)
+                for k in range(self.n_jobs)]
 
 
 def solve(models, jobs, finals, opts=None, plain=False, want_psi=False):
