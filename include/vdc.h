@@ -163,6 +163,33 @@ vdc_status vdc_solve_plain(int n_models, const vdc_model_t* models, const vdc_so
                            double* T_out, double* sigma_out, double* psi_out,
                            vdc_job_info* info, void* stream);
 
+/* Gradient of a loss L(sigma) with respect to the 16 model parameters, by
+ * the adjoint method: for each job, with its forward solution Psi and
+ * amplitudes T (from vdc_solve with the same jobs and finals), one solve with
+ * the same operator (A^T = A, Sec. III.A) of A zeta = sum_f W_f Phi^{v_f mu_f},
+ * W_f = 2 (2 pi^3/eps_i) dL/dsigma_f conj(T_f), then
+ *   dL/dp = Re[sum_f W_f (dPhi_f/dp)^T Psi + zeta^T dPhi_i/dp - zeta^T (dA/dp) Psi]
+ * with the derivatives of Eqs. (18), (21)-(23), (25) (level shift
+ * differentiated through the principal-value transform).  Parameter order:
+ * omega_g, omega_u, kappa1, kappa2, lam, lam1, lam2, gap, A[0][0] (1e),
+ * A[1][0] (2e), A[0][1] (1o), A[1][1] (2o), B in the same order.
+ *   psi        device c16 [n_jobs][2*max(Ng*Nu)]: forward solutions (psi_out)
+ *   T          device c16 [n_jobs][n_final][2]: forward amplitudes (T_out)
+ *   dL_dsigma  device double [n_jobs][n_final]: dL/dsigma_{v_f <- v_i} at the
+ *              job's (eps_i, v_i) (the same value for its mu_i = e and o jobs)
+ *   grad_jobs  device double [n_jobs][16]: each job's contribution
+ *   grad       host double[16] or NULL: sum over jobs (in job order)
+ *   info       host vdc_job_info[n_jobs] or NULL: the adjoint solves
+ * FP64 only.  Workspace: vdc_adjoint_workspace_size().  Synchronises. */
+vdc_status vdc_adjoint_workspace_size(int n_models, const vdc_model_t* models,
+                                      const vdc_solve_opts* opts, int n_jobs,
+                                      const vdc_job* jobs, size_t* bytes);
+vdc_status vdc_solve_adjoint(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                             int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                             const double* psi, const double* T, const double* dL_dsigma,
+                             void* workspace, size_t ws_bytes, double* grad_jobs, double* grad,
+                             vdc_job_info* info, void* stream);
+
 /* Level-shift tables (Eq. (19) with the widths of Eq. (22)): for n_eps
  * electron energies eps (device double[n_eps]) write the six complex values
  * F[f_1^e f_1^e], F[f_1^e f_2^e], F[f_2^e f_2^e], F[f_1^o f_1^o],

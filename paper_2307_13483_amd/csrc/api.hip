@@ -17,6 +17,8 @@ int gmres_fp64_occupancy();
 hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, hipStream_t s);
 int fgmres_mixed_occupancy();
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
+hipError_t launch_adjoint(const SolveArgs& a, int n_groups, hipStream_t s);
+int adjoint_occupancy();
 hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
@@ -33,6 +35,7 @@ struct vdc_model {
   DevModel dev;
   double* d_nodes = nullptr;
   double* d_coef = nullptr;
+  double* d_coefx = nullptr;
 };
 
 namespace {
@@ -92,6 +95,7 @@ struct Plan {
   int max_nc = 0;
   int max_group_pts = 0;
   size_t shift_elems = 0;
+  bool deriv = false;
   size_t table_elems = 0;
   int n_groups = 0;
   size_t ncap = 0, slot_elems = 0;
@@ -108,7 +112,8 @@ int cu_count() {
 }
 
 vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_opts* o,
-                     int n_jobs, const vdc_job* jobs, int n_final, bool plain, Plan& P) {
+                     int n_jobs, const vdc_job* jobs, int n_final, bool plain, Plan& P,
+                     bool adjoint = false) {
   if (n_models <= 0 || !models) return fail(VDC_ERR_INVALID_ARG, "no models");
   if (!o) return fail(VDC_ERR_INVALID_ARG, "opts is NULL");
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(VDC_ERR_INVALID_ARG, "bad job list");
@@ -121,6 +126,10 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (o->precision != VDC_FP64 && o->precision != VDC_FP32_INNER)
     return fail(VDC_ERR_INVALID_ARG, "unknown precision");
   const bool mixed = o->precision == VDC_FP32_INNER;
+  if (mixed && adjoint) return fail(VDC_ERR_UNSUPPORTED, "the adjoint solve is FP64 only");
+  P.deriv = adjoint;
+  const int planes = adjoint ? kPlanesDeriv : kPlanesSolve;
+  const int shift_per_point = adjoint ? 3 * kNumF : kNumF;
   if (mixed) {
     if (plain) return fail(VDC_ERR_UNSUPPORTED, "the plain path is FP64 only");
     if (o->inner_restart < 1 || o->inner_restart > kMaxRestart)
@@ -171,7 +180,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     G.b_min = gvmin_u[g] - (md.Nu - 1);
     G.nb = gvmax_u[g] - G.b_min + 1;
     G.offset = P.shift_elems;
-    P.shift_elems += (size_t)G.na * G.nb * kNumF;
+    P.shift_elems += (size_t)G.na * G.nb * shift_per_point;
     P.max_group_pts = std::max(P.max_group_pts, G.na * G.nb);
   }
   if (P.groups.size() > 65535) return fail(VDC_ERR_INVALID_ARG, "more than 65535 distinct incident energies");
@@ -205,7 +214,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
       t.vg = jb.vi_g;
       t.vu = jb.vi_u;
       t.offset = P.table_elems;
-      P.table_elems += 6 * (size_t)P.models[jb.model].Nc;
+      P.table_elems += 2 * planes * (size_t)P.models[jb.model].Nc;
       it = tab_index.emplace(key, (int)P.tabs.size()).first;
       P.tabs.push_back(t);
     }
@@ -227,13 +236,15 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     P.slot_elems = (size_t)(2 * m + 6) * P.ncap + (size_t)(m + 1) * m + (size_t)(mi + 1) * mi +
                    ((size_t)(mi + 5) * P.ncap + 1) / 2;
   } else {
-    // V (m+1), x, b, dinv, w, wA, wB, R
+    // V (m+1), x, b, dinv, w, wA, wB, R (+ the forward solution for the adjoint)
     P.slot_elems = (size_t)(m + 1 + 6) * P.ncap + (size_t)(m + 1) * m;
     if (plain) P.slot_elems += plain_extra_elems(P.ncap, m);
+    if (adjoint) P.slot_elems += P.ncap;
   }
   P.slot_elems = (P.slot_elems + 31) / 32 * 32;
   int occ = 1;
-  if (!plain) occ = mixed ? fgmres_mixed_occupancy() : gmres_fp64_occupancy();
+  if (!plain)
+    occ = adjoint ? adjoint_occupancy() : (mixed ? fgmres_mixed_occupancy() : gmres_fp64_occupancy());
   P.n_groups = plain ? 1 : std::max(1, std::min(n_jobs, cu_count() * occ));
   size_t off = 0;
   P.off_counter = off; off += 256;
@@ -251,12 +262,21 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   return VDC_OK;
 }
 
+struct AdjointIO {
+  const double* psi;
+  const double* T;
+  const double* dsig;
+  double* grad_jobs;
+  double* grad;
+};
+
 vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
                      int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
                      void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
-                     double* psi_out, vdc_job_info* info, void* stream, bool plain) {
+                     double* psi_out, vdc_job_info* info, void* stream, bool plain,
+                     const AdjointIO* adj = nullptr) {
   Plan P;
-  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, plain, P);
+  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, plain, P, adj != nullptr);
   if (st != VDC_OK) return st;
   if (n_jobs == 0) return VDC_OK;
   if (!workspace) return fail(VDC_ERR_INVALID_ARG, "workspace is NULL");
@@ -265,8 +285,10 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (ws_bytes < P.total)
     return fail(VDC_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) +
                                        " bytes, got " + std::to_string(ws_bytes));
-  if (n_final > 0 && (!finals || !T_out || !sigma_out))
+  if (!adj && n_final > 0 && (!finals || !T_out || !sigma_out))
     return fail(VDC_ERR_INVALID_ARG, "finals/T_out/sigma_out must be non-NULL when n_final > 0");
+  if (adj && (!adj->psi || !adj->grad_jobs || (n_final > 0 && (!finals || !adj->T || !adj->dsig))))
+    return fail(VDC_ERR_INVALID_ARG, "psi, T, dL_dsigma, finals and grad_jobs must be non-NULL");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
   const bool mixed = opts->precision == VDC_FP32_INNER;
@@ -308,6 +330,13 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   a.psi_out = reinterpret_cast<c64*>(psi_out);
   a.psi_ld = 2 * (size_t)P.max_nc;
   a.info = reinterpret_cast<DevInfo*>(ws + P.off_info);
+  a.planes = adj ? kPlanesDeriv : kPlanesSolve;
+  if (adj) {
+    a.psi_in = reinterpret_cast<const c64*>(adj->psi);
+    a.T_in = reinterpret_cast<const c64*>(adj->T);
+    a.dsig = adj->dsig;
+    a.grad = adj->grad_jobs;
+  }
 
   EventSet ev;
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
@@ -316,9 +345,12 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                                    (int)P.tabs.size(), P.max_nc,
                                    reinterpret_cast<c64*>(ws + P.off_shift),
                                    reinterpret_cast<c64*>(ws + P.off_tables),
-                                   mixed ? reinterpret_cast<c32*>(ws + P.off_tables32) : nullptr, s));
+                                   mixed ? reinterpret_cast<c32*>(ws + P.off_tables32) : nullptr, s,
+                                   P.deriv));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
-  if (plain) {
+  if (adj) {
+    HIPCHK(launch_adjoint(a, P.n_groups, s));
+  } else if (plain) {
     std::string err;
     st = solve_plain_impl(a, P.jobs, P.models, s, err);
     if (st != VDC_OK) return fail(st, err);
@@ -338,6 +370,16 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
     HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
     g_ms_tables = t1;
     g_ms_solver = t2;
+  }
+  if (adj && adj->grad) {
+    // per-job contributions summed in job order on the host (fixed order)
+    std::vector<double> g((size_t)n_jobs * 16);
+    HIPCHK(hipMemcpy(g.data(), adj->grad_jobs, sizeof(double) * g.size(), hipMemcpyDeviceToHost));
+    for (int p = 0; p < 16; ++p) {
+      double t = 0.0;
+      for (int j = 0; j < n_jobs; ++j) t += g[(size_t)j * 16 + p];
+      adj->grad[p] = t;
+    }
   }
   if (info) {
     for (int j = 0; j < n_jobs; ++j) {
@@ -417,7 +459,7 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
   dm.l[1] = d->l[1];
   // transform data: nodes, slope jumps c_k of the interpolated width products
   const int K = dm.K;
-  std::vector<double> x(K), coef((size_t)K * kNumF, 0.0);
+  std::vector<double> x(K), coef((size_t)K * kNumF, 0.0), coefx((size_t)K * kNumF, 0.0);
   for (int k = 0; k < K; ++k) {
     const double t = k * std::sqrt(d->hilbert_xmax) / (K - 1);
     x[k] = t * t;
@@ -428,28 +470,38 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
       const int f = fidx(mu, pq);
       std::vector<double> g(K);
       for (int k = 0; k < K; ++k) g[k] = width_pair_host(*d, mu, pairs[pq][0], pairs[pq][1], x[k]);
-      double sprev = 0.0;
+      double sprev = 0.0, sxprev = 0.0;
       for (int k = 0; k < K; ++k) {
         const double s = (k + 1 < K) ? (g[k + 1] - g[k]) / (x[k + 1] - x[k]) : 0.0;
+        const double sx =
+            (k + 1 < K) ? (x[k + 1] * g[k + 1] - x[k] * g[k]) / (x[k + 1] - x[k]) : 0.0;
         coef[(size_t)k * kNumF + f] = s - sprev;
+        coefx[(size_t)k * kNumF + f] = sx - sxprev;
         sprev = s;
+        sxprev = sx;
       }
       dm.glast[f] = g[K - 1];
+      dm.glastx[f] = x[K - 1] * g[K - 1];
     }
   }
   hipError_t e = hipMalloc(&m->d_nodes, sizeof(double) * K);
   if (e == hipSuccess) e = hipMalloc(&m->d_coef, sizeof(double) * K * kNumF);
+  if (e == hipSuccess) e = hipMalloc(&m->d_coefx, sizeof(double) * K * kNumF);
   if (e == hipSuccess) e = hipMemcpy(m->d_nodes, x.data(), sizeof(double) * K, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(m->d_coef, coef.data(), sizeof(double) * K * kNumF, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->d_coefx, coefx.data(), sizeof(double) * K * kNumF, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (m->d_nodes) (void)hipFree(m->d_nodes);
     if (m->d_coef) (void)hipFree(m->d_coef);
+    if (m->d_coefx) (void)hipFree(m->d_coefx);
     delete m;
     return hip_fail(e, "model upload");
   }
   dm.nodes = m->d_nodes;
   dm.coef = m->d_coef;
+  dm.coefx = m->d_coefx;
   *out = m;
   return VDC_OK;
 }
@@ -458,6 +510,7 @@ vdc_status vdc_model_destroy(vdc_model_t m) {
   if (!m) return VDC_OK;
   if (m->d_nodes) (void)hipFree(m->d_nodes);
   if (m->d_coef) (void)hipFree(m->d_coef);
+  if (m->d_coefx) (void)hipFree(m->d_coefx);
   delete m;
   return VDC_OK;
 }
@@ -494,6 +547,27 @@ vdc_status vdc_solve_plain(int n_models, const vdc_model_t* models, const vdc_so
                            double* psi_out, vdc_job_info* info, void* stream) {
   return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
                    T_out, sigma_out, psi_out, info, stream, true);
+}
+
+vdc_status vdc_adjoint_workspace_size(int n_models, const vdc_model_t* models,
+                                      const vdc_solve_opts* opts, int n_jobs,
+                                      const vdc_job* jobs, size_t* bytes) {
+  if (!bytes) return fail(VDC_ERR_INVALID_ARG, "bytes is NULL");
+  Plan P;
+  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, kMaxFinal, false, P, true);
+  if (st != VDC_OK) return st;
+  *bytes = P.total;
+  return VDC_OK;
+}
+
+vdc_status vdc_solve_adjoint(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                             int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                             const double* psi, const double* T, const double* dL_dsigma,
+                             void* workspace, size_t ws_bytes, double* grad_jobs, double* grad,
+                             vdc_job_info* info, void* stream) {
+  AdjointIO io{psi, T, dL_dsigma, grad_jobs, grad};
+  return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
+                   nullptr, nullptr, nullptr, info, stream, false, &io);
 }
 
 vdc_status vdc_level_shift(vdc_model_t m, int n_eps, const double* eps, double* out, void* stream) {

@@ -1,0 +1,103 @@
+// Restarted GMRES(m) in complex FP64 on one symmetry block, run by a whole
+// workgroup (Sec. III.A, right diagonal preconditioning of Sec. III.B):
+// cycles of krylov_cycle, x += M^{-1} V y, and the FP64 true residual b - A x
+// deciding convergence (the stopping rule of Sec. III).  Shared by the
+// forward solver and the adjoint (transposed) solve: A^T = A.
+#pragma once
+#include "krylov.h"
+
+namespace vdc {
+
+struct Fp64Lds {
+  KrylovLds<double> K;
+  double red[kRedSize];
+  double sq[kSqMax + 1];
+  int job;
+};
+
+// Per-workgroup vectors of the FP64 solver (leading dimension ld).
+struct Fp64Slot {
+  c64 *V, *x, *b, *dinv, *w, *wA, *wB, *Rm, *extra;
+};
+
+__device__ inline Fp64Slot fp64_slot(c64* slot, size_t ld, int m) {
+  Fp64Slot s;
+  s.V = slot;
+  s.x = slot + (size_t)(m + 1) * ld;
+  s.b = s.x + ld;
+  s.dinv = s.b + ld;
+  s.w = s.dinv + ld;
+  s.wA = s.w + ld;
+  s.wB = s.wA + ld;
+  s.Rm = s.wB + ld;
+  s.extra = s.Rm + (size_t)(m + 1) * m;
+  return s;
+}
+
+struct BlockSolve {
+  int status, iters, cycles;
+  double bnorm, beta, passes;
+};
+
+// dinv = 1/diag(A) (or 1), x = 0, b = 0 over the block (own elements).
+__device__ inline void fp64_prepare(const OpJob<double>& op, const Fp64Slot& s, int precond) {
+  for (int i = threadIdx.x; i < op.Nc; i += kBlock) {
+    s.dinv[i] = precond ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
+    s.x[i] = c64{0.0, 0.0};
+    s.b[i] = c64{0.0, 0.0};
+  }
+}
+
+// Solves A x = b with b in s.b (complete and visible: call after a barrier).
+// Byte model (passes over a block vector of Nc complex FP64 values): setup 7
+// (3 table planes read; dinv, x, b, v_0 written), each cycle of k steps
+// cycle_passes(k) + k + 10 (x update k + 3, true residual 7).
+__device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& op,
+                                              const Fp64Slot& s, size_t ld, int m, double tol,
+                                              int max_iter) {
+  const int Nc = op.Nc;
+  BlockSolve r{VDC_NOT_CONVERGED, 0, 0, 0.0, 0.0, 7.0};
+  r.bnorm = sqrt(norm_sq<double>(s.b, Nc, L.red));
+  r.beta = r.bnorm;
+  if (!(r.bnorm > 0.0) || !isfinite(r.bnorm)) {
+    r.status = isfinite(r.bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
+    r.beta = 0.0;
+    return r;
+  }
+  for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = (1.0 / r.beta) * s.b[i];
+  auto apply = [&](int j, c64* out) {
+    matvec_block<double>(op, L.sq, s.V + (size_t)j * ld, s.dinv, s.wA, s.wB, out);
+  };
+  for (;;) {
+    if (threadIdx.x == 0) L.K.g[0] = c64{r.beta, 0.0};
+    const CycleResult cr = krylov_cycle<double>(L.K, L.red, s.V, ld, Nc, m, tol * r.bnorm,
+                                                max_iter, r.iters, s.Rm, s.w, apply);
+    r.passes += cycle_passes(cr.k) + cr.k + 10.0;
+    combine_neg<double>(s.V, ld, cr.k, L.K.y, s.w, Nc);
+    for (int i = threadIdx.x; i < Nc; i += kBlock) s.x[i] = s.x[i] - s.dinv[i] * s.w[i];
+    matvec_block<double>(op, L.sq, s.x, nullptr, s.wA, s.wB, s.w);
+    for (int i = threadIdx.x; i < Nc; i += kBlock) s.w[i] = s.b[i] - s.w[i];
+    r.beta = sqrt(norm_sq<double>(s.w, Nc, L.red));
+    ++r.cycles;
+    if (!isfinite(r.beta) || cr.nonfinite) {
+      r.status = VDC_NONFINITE;
+      break;
+    }
+    if (r.beta <= tol * r.bnorm) {
+      r.status = VDC_CONVERGED;
+      break;
+    }
+    if (cr.breakdown) {
+      r.status = VDC_BREAKDOWN;
+      break;
+    }
+    if (r.iters >= max_iter) {
+      r.status = VDC_NOT_CONVERGED;
+      break;
+    }
+    for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = (1.0 / r.beta) * s.w[i];
+  }
+  return r;
+}
+
+}  // namespace vdc

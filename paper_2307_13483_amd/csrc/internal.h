@@ -35,8 +35,10 @@ struct DevModel {
   double A[2][2], B[2][2];
   int l[2];
   double glast[kNumF];   // interpolated width product at the last node
+  double glastx[kNumF];  // the same for x g(x)
   const double* nodes;   // [K]            device
-  const double* coef;    // [K][kNumF]     device: second differences c_k
+  const double* coef;    // [K][kNumF]     device: slope jumps c_k of g
+  const double* coefx;   // [K][kNumF]     device: slope jumps of x g(x)
 };
 
 // One job as the kernels see it (host-filled, device-resident array).
@@ -70,6 +72,11 @@ struct DevGroup {
   int pad;
   size_t offset;
 };
+
+// Planes per parity of a table set: 3 (level shift AA, AB, BB) or, for the
+// adjoint, 9 (level shift, its eps derivative, and the transform of x g).
+constexpr int kPlanesSolve = 3;
+constexpr int kPlanesDeriv = 9;
 
 // Per-job results written by the kernels, copied to vdc_job_info on the host.
 struct DevInfo {
@@ -108,7 +115,7 @@ __host__ __device__ inline float norm2(c32 a) { return a.x * a.x + a.y * a.y; }
 hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,
                                      int n_groups, int max_group_pts, const DevTable* tables_dev,
                                      int n_tables, int max_nc, c64* shift, c64* table_base,
-                                     c32* table32_base, hipStream_t s);
+                                     c32* table32_base, hipStream_t s, bool deriv = false);
 hipError_t launch_level_shift_points(const DevModel& m, int n_eps, const double* eps,
                                      c64* out, hipStream_t s);
 

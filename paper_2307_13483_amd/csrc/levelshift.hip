@@ -175,6 +175,128 @@ gather_tables_kernel(const DevModel* __restrict__ models, const DevGroup* __rest
   }
 }
 
+// Level shift, its eps derivative and the transform of x g(x) (for the
+// derivatives in the width scales B), sharing one logarithm per node:
+//   2 pi dDelta/deps = sum_k c_k ln|eps - x_k| - g_{K-1}/(eps - x_{K-1})
+// (the "+1" of d psi/dt drops out because the slope jumps sum to zero), and
+// the x g transform is the level shift with the slope jumps of x g.
+// Imaginary parts: -g'(eps)/2 and -eps g(eps)/2 (analytic).
+constexpr int kLsStride18 = 16;    // x, c[6], cx[6], pad
+
+__device__ inline void level_shift18_block(const DevModel& m, double eps, bool active,
+                                           double* lds, c64 F[kNumF], c64 D[kNumF],
+                                           c64 X[kNumF]) {
+  double aF[kNumF], aD[kNumF], aX[kNumF];
+#pragma unroll
+  for (int f = 0; f < kNumF; ++f) aF[f] = aD[f] = aX[f] = 0.0;
+  for (int k0 = 0; k0 < m.K; k0 += kLsChunk) {
+    const int nk = min(kLsChunk, m.K - k0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < nk; q += blockDim.x) {
+      double* d = lds + q * kLsStride18;
+      d[0] = m.nodes[k0 + q];
+#pragma unroll
+      for (int f = 0; f < kNumF; ++f) {
+        d[1 + f] = m.coef[(size_t)(k0 + q) * kNumF + f];
+        d[7 + f] = m.coefx[(size_t)(k0 + q) * kNumF + f];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int q = 0; q < nk; ++q) {
+        const double* d = lds + q * kLsStride18;
+        const double t = eps - d[0];
+        const double ln = (t == 0.0) ? 0.0 : ln_abs(t);
+        const double psi = t * ln;
+#pragma unroll
+        for (int f = 0; f < kNumF; ++f) {
+          aF[f] = fma(d[1 + f], psi, aF[f]);
+          aD[f] = fma(d[1 + f], ln, aD[f]);
+          aX[f] = fma(d[7 + f], psi, aX[f]);
+        }
+      }
+    }
+  }
+  const double tl = eps - m.nodes[m.K - 1];
+  const double lnl = (tl == 0.0) ? 0.0 : ln_abs(tl);
+  const double itl = (tl == 0.0) ? 0.0 : 1.0 / tl;
+  const double inv2pi = 1.0 / (2.0 * kPi);
+#pragma unroll
+  for (int f = 0; f < kNumF; ++f) {
+    F[f].x = (aF[f] - m.glast[f] * (lnl + 1.0)) * inv2pi;
+    D[f].x = (aD[f] - m.glast[f] * itl) * inv2pi;
+    X[f].x = (aX[f] - m.glastx[f] * (lnl + 1.0)) * inv2pi;
+  }
+  const int pairs[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+#pragma unroll
+  for (int mu = 0; mu < 2; ++mu) {
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int d1 = pairs[pq][0], d2 = pairs[pq][1];
+      const double g = width_pair(m, mu, d1, d2, eps);
+      const double rate = (eps > 0.0) ? (m.l[mu] + 0.5) / eps - (0.5 / m.B[d1][mu] + 0.5 / m.B[d2][mu])
+                                      : 0.0;
+      F[fidx(mu, pq)].y = -0.5 * g;
+      D[fidx(mu, pq)].y = -0.5 * g * rate;
+      X[fidx(mu, pq)].y = -0.5 * eps * g;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kLsThreads)
+shift_table_deriv_kernel(const DevModel* __restrict__ models, const DevGroup* __restrict__ groups,
+                         c64* __restrict__ shift) {
+  __shared__ double lds[kLsChunk * kLsStride18];
+  const DevGroup gr = groups[blockIdx.y];
+  const DevModel& m = models[gr.model];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int npts = gr.na * gr.nb;
+  const bool active = i < npts;
+  double eps = 0.0;
+  if (active) {
+    const int ia = i / gr.nb, ib = i - ia * gr.nb;
+    eps = gr.eps_i + m.omega_g * (gr.a_min + ia) + m.omega_u * (gr.b_min + ib);
+  }
+  if (blockIdx.x * blockDim.x >= npts) return;
+  c64 F[kNumF], D[kNumF], X[kNumF];
+  level_shift18_block(m, eps, active, lds, F, D, X);
+  if (active) {
+    c64* o = shift + gr.offset + (size_t)i * 3 * kNumF;
+#pragma unroll
+    for (int f = 0; f < kNumF; ++f) {
+      o[f] = F[f];
+      o[kNumF + f] = D[f];
+      o[2 * kNumF + f] = X[f];
+    }
+  }
+}
+
+// Adjoint table sets: per parity 9 planes (F, dF/deps, X) x (AA, AB, BB).
+__global__ void __launch_bounds__(kLsThreads)
+gather_tables_deriv_kernel(const DevModel* __restrict__ models,
+                           const DevGroup* __restrict__ groups,
+                           const DevTable* __restrict__ tabs, const c64* __restrict__ shift,
+                           c64* __restrict__ base) {
+  const DevTable tb = tabs[blockIdx.y];
+  const DevModel& m = models[tb.model];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m.Nc) return;
+  const DevGroup gr = groups[tb.group];
+  const int ng = i / m.Nu, nu = i - ng * m.Nu;
+  const int ia = tb.vg - ng - gr.a_min, ib = tb.vu - nu - gr.b_min;
+  const c64* S = shift + gr.offset + (size_t)(ia * gr.nb + ib) * 3 * kNumF;
+  for (int p = 0; p < 2; ++p) {
+    const bool s1 = ((nu + p) & 1) == 0;
+    c64* dst = base + tb.offset + (size_t)(p * kPlanesDeriv) * m.Nc;
+    for (int kind = 0; kind < 3; ++kind) {
+      const c64* F = S + kind * kNumF;
+      dst[(size_t)(3 * kind) * m.Nc + i] = s1 ? F[0] : F[5];
+      dst[(size_t)(3 * kind + 1) * m.Nc + i] = s1 ? F[1] : F[4];
+      dst[(size_t)(3 * kind + 2) * m.Nc + i] = s1 ? F[2] : F[3];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kLsThreads)
 level_shift_points_kernel(DevModel m, int n, const double* __restrict__ eps, c64* __restrict__ out) {
   __shared__ double lds[kLsChunk * kLsStride];
@@ -191,9 +313,17 @@ level_shift_points_kernel(DevModel m, int n, const double* __restrict__ eps, c64
 hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,
                                      int n_groups, int max_group_pts, const DevTable* tables_dev,
                                      int n_tables, int max_nc, c64* shift, c64* table_base,
-                                     c32* table32_base, hipStream_t s) {
+                                     c32* table32_base, hipStream_t s, bool deriv) {
   if (n_tables <= 0) return hipSuccess;
   dim3 g1((max_group_pts + kLsThreads - 1) / kLsThreads, n_groups);
+  if (deriv) {
+    hipLaunchKernelGGL(shift_table_deriv_kernel, g1, dim3(kLsThreads), 0, s, models_dev,
+                       groups_dev, shift);
+    dim3 g2((max_nc + kLsThreads - 1) / kLsThreads, n_tables);
+    hipLaunchKernelGGL(gather_tables_deriv_kernel, g2, dim3(kLsThreads), 0, s, models_dev,
+                       groups_dev, tables_dev, shift, table_base);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(shift_table_kernel, g1, dim3(kLsThreads), 0, s, models_dev, groups_dev, shift);
   dim3 g2((max_nc + kLsThreads - 1) / kLsThreads, n_tables);
   hipLaunchKernelGGL(gather_tables_kernel, g2, dim3(kLsThreads), 0, s, models_dev, groups_dev,

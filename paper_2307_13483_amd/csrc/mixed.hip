@@ -62,7 +62,7 @@ fgmres_mixed_kernel(SolveArgs a) {
     const DevJob jb = a.jobs[js];
     const DevModel& md = a.models[jb.model];
     const DevTable tb = a.tabs[jb.table];
-    const size_t toff = tb.offset + (size_t)(jb.parity * 3) * md.Nc;
+    const size_t toff = tb.offset + (size_t)(jb.parity * a.planes) * md.Nc;
     const OpJob<double> op = make_op<double>(md, jb, a.tables + toff);
     const OpJob<float> op32 = make_op<float>(md, jb, a.tables32 + toff);
     const int Nc = md.Nc;

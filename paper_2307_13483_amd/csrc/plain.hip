@@ -345,7 +345,7 @@ vdc_status solve_plain_impl(const SolveArgs& sa, const std::vector<DevJob>& jobs
     const DevJob& jb = jobs[q];
     a.md = models[jb.model];
     a.jb = jb;
-    a.tab = sa.tables + htabs[jb.table].offset + (size_t)(jb.parity * 3) * a.md.Nc;
+    a.tab = sa.tables + htabs[jb.table].offset + (size_t)(jb.parity * sa.planes) * a.md.Nc;
     a.nblk = (a.md.Nc + kPT - 1) / kPT;
     const dim3 g1(a.nblk), b1(kPT);
     hipLaunchKernelGGL(p_init, g1, b1, 0, st, a);

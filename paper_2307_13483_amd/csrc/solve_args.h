@@ -29,6 +29,12 @@ struct SolveArgs {
   c64* psi_out;             // [n_jobs][2 Nc] or null (row length of the job's model)
   size_t psi_ld;            // row length of psi_out (2 * max Nc)
   DevInfo* info;            // [n_jobs], indexed by the caller's job order
+  int planes;               // table planes per parity (3, or 9 for the adjoint)
+  // adjoint inputs/outputs
+  const c64* psi_in;        // forward solutions, full layout, row length psi_ld
+  const c64* T_in;          // forward amplitudes [n_jobs][n_final][2]
+  const double* dsig;       // dL/dsigma [n_jobs][n_final]
+  double* grad;             // [n_jobs][16] per-job gradient contributions
 };
 
 // Amplitudes T_{mu_f v_f <- mu_i v_i} = Phi^{v_f mu_f T} Psi (Eq. (24)) for the

@@ -81,6 +81,11 @@ def lib():
         "vdc_solve_plain": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
                                 ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, S, P, P,
                                 P, ctypes.POINTER(JobInfo), P]),
+        "vdc_adjoint_workspace_size": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                           ctypes.POINTER(Job), ctypes.POINTER(S)]),
+        "vdc_solve_adjoint": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                  ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, P, P,
+                                  P, S, P, ctypes.POINTER(D), ctypes.POINTER(JobInfo), P]),
         "vdc_level_shift": (I, [P, I, P, P, P]),
         "vdc_matvec_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
         "vdc_matvec": (I, [P, D, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
@@ -197,6 +202,10 @@ def matvec(model, E, x, parity):
     return y
 
 
+PARAM_NAMES = ("omega_g", "omega_u", "kappa1", "kappa2", "lam", "lam1", "lam2", "gap",
+               "A1e", "A2e", "A1o", "A2o", "B1e", "B2e", "B1o", "B2o")
+
+
 class Solver:
     """Holds a job list and a workspace; ``run`` calls vdc_solve (batched
     persistent launch) or vdc_solve_plain.  ``jobs`` are tuples
@@ -226,6 +235,30 @@ class Solver:
         self.psi = (torch.zeros((self.n_jobs, nmax), dtype=torch.complex128, device="cuda")
                     if want_psi else None)
         self.info = (JobInfo * max(1, self.n_jobs))()
+        self.adj_ws = None
+
+    def adjoint(self, dL_dsigma, stream=None):
+        """vdc_solve_adjoint after run() with want_psi: dL_dsigma [n_jobs, n_final]
+        (device) -> (grad over jobs as a numpy array [16], per-job [n_jobs, 16])."""
+        if self.psi is None:
+            raise ValueError("the adjoint needs the forward solutions: build with want_psi=True")
+        if self.adj_ws is None:
+            nb = ctypes.c_size_t()
+            _check(lib().vdc_adjoint_workspace_size(len(self.models), self.handles,
+                                                    ctypes.byref(self.copts), self.n_jobs,
+                                                    self.jobs, ctypes.byref(nb)))
+            self.adj_bytes = nb.value
+            self._adj_raw, self.adj_ws = _aligned_workspace(nb.value, "cuda")
+            self.grad_jobs = torch.zeros((self.n_jobs, 16), dtype=torch.float64, device="cuda")
+            self.adj_info = (JobInfo * max(1, self.n_jobs))()
+        dsig = torch.as_tensor(dL_dsigma, dtype=torch.float64, device="cuda").contiguous()
+        g = (ctypes.c_double * 16)()
+        _check(lib().vdc_solve_adjoint(len(self.models), self.handles, ctypes.byref(self.copts),
+                                       self.n_jobs, self.jobs, self.n_final, self.finals,
+                                       _ptr(self.psi), _ptr(self.T), _ptr(dsig), _ptr(self.adj_ws),
+                                       self.adj_bytes, _ptr(self.grad_jobs), g, self.adj_info,
+                                       _stream_ptr(stream)))
+        return np.array(list(g)), self.grad_jobs
 
     def run(self, plain=False, stream=None):
         f = lib().vdc_solve_plain if plain else lib().vdc_solve
@@ -252,6 +285,34 @@ def last_kernel_times():
     a, b = ctypes.c_double(), ctypes.c_double()
     _check(lib().vdc_last_kernel_times(ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
+
+
+class CrossSections(torch.autograd.Function):
+    """sigma_{v_f <- v_i}(eps_i) (Eq. (16), summed over mu_i and mu_f) as a
+    differentiable function of the 16 model parameters (PARAM_NAMES order).
+
+    forward(params [16] float64, spec) -> sigma [n_energies, n_final] on the GPU,
+    where spec = dict(base=params dict, Ng, Nu, eps (list), v_i, finals, opts).
+    backward: one adjoint solve per right-hand side (vdc_solve_adjoint).
+    """
+
+    @staticmethod
+    def forward(ctx, params, spec):
+        p = dict(spec["base"])
+        for name, v in zip(PARAM_NAMES, params.detach().cpu().tolist()):
+            p[name] = float(v)
+        model = Model2D(p, spec["Ng"], spec["Nu"])
+        jobs = [(e, spec["v_i"], mu) for e in spec["eps"] for mu in (0, 1)]
+        s = Solver(model, jobs, spec["finals"], spec.get("opts"), want_psi=True).run()
+        ctx.solver, ctx.model = s, model
+        ctx.n_e, ctx.n_f = len(spec["eps"]), len(spec["finals"])
+        return s.sigma.view(ctx.n_e, 2, ctx.n_f).sum(dim=1)
+
+    @staticmethod
+    def backward(ctx, grad_sigma):
+        dsig = grad_sigma.to(torch.float64).contiguous()[:, None, :].expand(ctx.n_e, 2, ctx.n_f)
+        g, _ = ctx.solver.adjoint(dsig.reshape(ctx.n_e * 2, ctx.n_f).contiguous())
+        return torch.tensor(g, dtype=torch.float64), None
 
 
 def version():

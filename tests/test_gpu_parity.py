@@ -299,3 +299,55 @@ def test_mixed_precision_full_size_sample(vdc):
     T, sigma, psi, infos = vdc.solve(model, sample, cfg["finals"], opts, want_psi=True)
     _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
                  sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+
+
+# ------------------------------------------------------------ adjoint
+
+def _grad_case(Ng, Nu, eps, n_final=4):
+    from oracle import adjoint as adj
+    p = inputs.base_params()
+    target = inputs.draw_params(inputs.SEED + 1)
+    finals = [(k, 0) for k in range(n_final)]
+    sig_t, _ = adj.forward(target, Ng, Nu, eps, (0, 0), finals)
+    return p, finals, sig_t
+
+
+@pytest.mark.parametrize("Ng,Nu,eps", [(9, 7, [0.57, 1.73, 2.61]), (20, 16, [0.83, 2.28])])
+def test_adjoint_gradient_matches_oracle(vdc, Ng, Nu, eps):
+    """GPU adjoint (one transposed solve per right-hand side + parameter
+    sweep) against the oracle's explicit-derivative gradient."""
+    import torch
+    from oracle import adjoint as adj
+    p, finals, sig_t = _grad_case(Ng, Nu, eps)
+    L, g_ref, sig_ref = adj.loss_and_grad(p, Ng, Nu, eps, (0, 0), finals, sig_t)
+    model = vdc.Model2D(p, Ng, Nu)
+    jobs = [(e, (0, 0), mu) for e in eps for mu in (0, 1)]
+    s = vdc.Solver(model, jobs, finals, vdc.Opts(restart=20, tol=1e-12), want_psi=True).run()
+    sig = s.sigma.cpu().numpy().reshape(len(eps), 2, len(finals)).sum(axis=1)
+    assert np.allclose(sig, sig_ref, rtol=1e-9, atol=0)
+    dsig = 2.0 * (sig - sig_t)
+    dsig_jobs = torch.tensor(np.repeat(dsig, 2, axis=0))
+    g, gj = s.adjoint(dsig_jobs)
+    assert all(i.status == 0 for i in s.adj_info[:s.n_jobs])
+    scale = np.max(np.abs(g_ref))
+    for k, name in enumerate(vdc.PARAM_NAMES):
+        assert abs(g[k] - g_ref[k]) <= 1e-8 * scale, (name, g[k], g_ref[k])
+
+
+def test_autograd_function_dense_lu_reference(vdc):
+    """The torch.autograd.Function on a 30 x 30 basis against the oracle's
+    dense-LU gradient of the same loss."""
+    import torch
+    from oracle import adjoint as adj
+    Ng = Nu = 30
+    eps = [0.61, 1.37, 2.43]
+    p, finals, sig_t = _grad_case(Ng, Nu, eps, n_final=6)
+    _, g_ref, _ = adj.loss_and_grad(p, Ng, Nu, eps, (0, 0), finals, sig_t, dense=True)
+    params = torch.tensor([p[n] for n in vdc.PARAM_NAMES], dtype=torch.float64, requires_grad=True)
+    spec = dict(base=p, Ng=Ng, Nu=Nu, eps=eps, v_i=(0, 0), finals=finals,
+                opts=vdc.Opts(restart=30, tol=1e-12))
+    sig = vdc.CrossSections.apply(params, spec)
+    loss = ((sig - torch.tensor(sig_t, device=sig.device)) ** 2).sum()
+    loss.backward()
+    g = params.grad.numpy()
+    assert np.max(np.abs(g - g_ref)) <= 1e-8 * np.max(np.abs(g_ref))
