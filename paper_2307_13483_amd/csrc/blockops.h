@@ -37,19 +37,24 @@ __device__ inline void block_sum(R (&v)[NV], R* red, R* out) {
   __syncthreads();
 }
 
-// LDS scratch needed by block_sum/project: kWaves*2*kChunk + 2*kChunk values.
-constexpr int kRedSize = kWaves * 2 * kChunk + 2 * kChunk;
+// Values reduced per projection chunk: kChunk complex dot products plus ||w||^2.
+constexpr int kRedNV = 2 * kChunk + 1;
+// LDS scratch needed by block_sum/project.
+constexpr int kRedSize = kWaves * kRedNV + kRedNV;
 
-// h[l] = sum_i conj(V_l[i]) w[i] for l = 0..nv-1 (interleaved re/im in LDS).
+// h[l] = sum_i conj(V_l[i]) w[i] for l = 0..nv-1 (interleaved re/im in LDS);
+// with wnorm2 given, ||w||^2 is accumulated in the same pass (first chunk).
 template <typename R>
 __device__ inline void project(const typename CT<R>::C* __restrict__ V, size_t ld, int nv,
-                               const typename CT<R>::C* __restrict__ w, int Nc, R* red, R* hout) {
+                               const typename CT<R>::C* __restrict__ w, int Nc, R* red, R* hout,
+                               R* wnorm2 = nullptr) {
   using C = typename CT<R>::C;
   for (int l0 = 0; l0 < nv; l0 += kChunk) {
     const int nl = min(kChunk, nv - l0);
-    R acc[2 * kChunk];
+    R acc[kRedNV];
 #pragma unroll
-    for (int q = 0; q < 2 * kChunk; ++q) acc[q] = R(0);
+    for (int q = 0; q < kRedNV; ++q) acc[q] = R(0);
+    const bool want_norm = wnorm2 != nullptr && l0 == 0;
     for (int i = threadIdx.x; i < Nc; i += kBlock) {
       const C wi = w[i];
       C vv[kChunk];
@@ -61,18 +66,24 @@ __device__ inline void project(const typename CT<R>::C* __restrict__ V, size_t l
         acc[2 * q] += t.x;
         acc[2 * q + 1] += t.y;
       }
+      if (want_norm) acc[2 * kChunk] += norm2(wi);
     }
-    block_sum<2 * kChunk, R>(acc, red, red + kWaves * 2 * kChunk);
-    if (threadIdx.x < 2 * nl) hout[2 * l0 + threadIdx.x] = red[kWaves * 2 * kChunk + threadIdx.x];
+    block_sum<kRedNV, R>(acc, red, red + kWaves * kRedNV);
+    if (threadIdx.x < 2 * nl) hout[2 * l0 + threadIdx.x] = red[kWaves * kRedNV + threadIdx.x];
+    if (want_norm && threadIdx.x == 2 * kChunk) *wnorm2 = red[kWaves * kRedNV + 2 * kChunk];
     __syncthreads();
   }
 }
 
-// w[i] -= sum_l V_l[i] h[l], l = 0..nv-1 (h interleaved in LDS), own elements.
+// w[i] -= sum_l V_l[i] h[l], l = 0..nv-1 (h interleaved in LDS), own elements;
+// with red given, returns ||w||^2 of the result (reduced in the same pass,
+// returned to every thread), else 0.
 template <typename R>
-__device__ inline void subtract(const typename CT<R>::C* __restrict__ V, size_t ld, int nv,
-                                typename CT<R>::C* __restrict__ w, int Nc, const R* h) {
+__device__ inline R subtract(const typename CT<R>::C* __restrict__ V, size_t ld, int nv,
+                             typename CT<R>::C* __restrict__ w, int Nc, const R* h,
+                             R* red = nullptr) {
   using C = typename CT<R>::C;
+  R acc[1] = {R(0)};
   for (int i = threadIdx.x; i < Nc; i += kBlock) {
     C s = w[i];
     int l = 0;
@@ -85,7 +96,13 @@ __device__ inline void subtract(const typename CT<R>::C* __restrict__ V, size_t 
     }
     for (; l < nv; ++l) s = s - V[(size_t)l * ld + i] * C{h[2 * l], h[2 * l + 1]};
     w[i] = s;
+    acc[0] += norm2(s);
   }
+  if (!red) return R(0);
+  block_sum<1, R>(acc, red, red + kWaves);
+  const R v = red[kWaves];
+  __syncthreads();   // every thread has read v before red is reused
+  return v;
 }
 
 // ||w||^2 over the workgroup (own elements), returned to every thread.
@@ -94,7 +111,9 @@ __device__ inline R norm_sq(const typename CT<R>::C* __restrict__ w, int Nc, R* 
   R acc[1] = {R(0)};
   for (int i = threadIdx.x; i < Nc; i += kBlock) acc[0] += norm2(w[i]);
   block_sum<1, R>(acc, red, red + kWaves);
-  return red[kWaves];
+  const R v = red[kWaves];
+  __syncthreads();   // every thread has read v before red is reused
+  return v;
 }
 
 // y = A (dinv * v) (dinv may be null); y, wA, wB are vectors of Nc elements.

@@ -72,7 +72,7 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
     if (threadIdx.x == 0) L.K.g[0] = c64{r.beta, 0.0};
     const CycleResult cr = krylov_cycle<double>(L.K, L.red, s.V, ld, Nc, m, tol * r.bnorm,
                                                 max_iter, r.iters, s.Rm, s.w, apply);
-    r.passes += cycle_passes(cr.k) + cr.k + 10.0;
+    r.passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 10.0;
     combine_neg<double>(s.V, ld, cr.k, L.K.y, s.w, Nc);
     for (int i = threadIdx.x; i < Nc; i += kBlock) s.x[i] = s.x[i] - s.dinv[i] * s.w[i];
     matvec_block<double>(op, L.sq, s.x, nullptr, s.wA, s.wB, s.w);

@@ -114,7 +114,7 @@ fgmres_mixed_kernel(SolveArgs a) {
                                                      a.tol_in * n0, a.max_iter, iters, Ri,
                                                      w32, apply_in);
           combine_neg<float>(Vi, ld, ci.k, L.Ki.y, w32, Nc);
-          p32 += cycle_passes(ci.k) + ci.k + 3.0;
+          p32 += cycle_passes(ci.k, ci.reorth_passes) + ci.k + 3.0;
         } else {
           for (int i = tid; i < Nc; i += kBlock) w32[i] = c32{0.f, 0.f};
         }
@@ -133,7 +133,7 @@ fgmres_mixed_kernel(SolveArgs a) {
         if (tid == 0) L.Ko.g[0] = c64{beta, 0.0};
         const CycleResult cr = krylov_cycle<double>(L.Ko, L.red, Vo, ld, Nc, m, a.tol * bnorm,
                                                     1 << 30, ocount, Ro, w, apply_out);
-        p64 += cycle_passes(cr.k) - 6.0 * cr.k + cr.k + 2.0 + 7.0;
+        p64 += cycle_passes(cr.k, cr.reorth_passes) - 6.0 * cr.k + cr.k + 2.0 + 7.0;
         // x += Z y
         combine_neg<double>(Z, ld, cr.k, L.Ko.y, w, Nc);
         for (int i = tid; i < Nc; i += kBlock) x[i] = x[i] - w[i];
