@@ -244,7 +244,7 @@ adjoint_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    const BlockSolve r = gmres_fp64_block(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter);
+    const BlockSolve r = gmres_fp64_block(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT);
     __syncthreads();
     // -zeta^T (dA/dp) psi
     sweep_dA(op, jb, md, L.S.sq, z, s.x, tab, L.redA, G);
@@ -270,14 +270,14 @@ adjoint_kernel(SolveArgs a) {
   }
 }
 
-hipError_t launch_adjoint(const SolveArgs& a, int n_groups, hipStream_t s) {
-  hipLaunchKernelGGL(adjoint_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
+hipError_t launch_adjoint(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
+  hipLaunchKernelGGL(adjoint_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
-int adjoint_occupancy() {
+int adjoint_occupancy(size_t dyn_lds) {
   int n = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_kernel, kBlock, 0);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_kernel, kBlock, dyn_lds);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

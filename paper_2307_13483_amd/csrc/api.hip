@@ -9,16 +9,17 @@
 #include <vector>
 
 #include "internal.h"
+#include "blockops.h"
 #include "solve_args.h"
 
 namespace vdc {
-hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, hipStream_t s);
-int gmres_fp64_occupancy();
-hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, hipStream_t s);
-int fgmres_mixed_occupancy();
+hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
+int gmres_fp64_occupancy(size_t dyn_lds);
+hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
+int fgmres_mixed_occupancy(size_t dyn_lds);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
-hipError_t launch_adjoint(const SolveArgs& a, int n_groups, hipStream_t s);
-int adjoint_occupancy();
+hipError_t launch_adjoint(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
+int adjoint_occupancy(size_t dyn_lds);
 hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
@@ -93,6 +94,9 @@ struct Plan {
   std::vector<DevTable> tabs;
   std::vector<DevGroup> groups;
   int max_nc = 0;
+  int max_nu = 0;
+  int tileT = 0, tileT32 = 0;
+  size_t dyn_lds = 0;
   int max_group_pts = 0;
   size_t shift_elems = 0;
   bool deriv = false;
@@ -144,7 +148,14 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     if (!models[k]) return fail(VDC_ERR_INVALID_ARG, "NULL model");
     P.models[k] = models[k]->dev;
     P.max_nc = std::max(P.max_nc, models[k]->dev.Nc);
+    P.max_nu = std::max(P.max_nu, models[k]->dev.Nu);
   }
+  // LDS tiles of the fused operator pass (96 KB budget next to the static LDS)
+  const size_t kTileBudget = 96 * 1024;
+  P.tileT = tile_rows(P.max_nu, sizeof(c64), kTileBudget);
+  P.tileT32 = mixed ? tile_rows(P.max_nu, sizeof(c32), kTileBudget) : 0;
+  P.dyn_lds = std::max((size_t)(3 * P.tileT + 8) * P.max_nu * sizeof(c64) * (P.tileT > 0),
+                       (size_t)(3 * P.tileT32 + 8) * P.max_nu * sizeof(c32) * (P.tileT32 > 0));
   std::map<std::pair<int, double>, int> tab_index;
   // jobs sharing (model, eps_i) share one shift table over the offsets they need
   std::map<std::pair<int, double>, int> grp_index;
@@ -244,7 +255,8 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   P.slot_elems = (P.slot_elems + 31) / 32 * 32;
   int occ = 1;
   if (!plain)
-    occ = adjoint ? adjoint_occupancy() : (mixed ? fgmres_mixed_occupancy() : gmres_fp64_occupancy());
+    occ = adjoint ? adjoint_occupancy(P.dyn_lds)
+                  : (mixed ? fgmres_mixed_occupancy(P.dyn_lds) : gmres_fp64_occupancy(P.dyn_lds));
   P.n_groups = plain ? 1 : std::max(1, std::min(n_jobs, cu_count() * occ));
   size_t off = 0;
   P.off_counter = off; off += 256;
@@ -331,6 +343,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   a.psi_ld = 2 * (size_t)P.max_nc;
   a.info = reinterpret_cast<DevInfo*>(ws + P.off_info);
   a.planes = adj ? kPlanesDeriv : kPlanesSolve;
+  a.tileT = P.tileT;
+  a.tileT32 = P.tileT32;
   if (adj) {
     a.psi_in = reinterpret_cast<const c64*>(adj->psi);
     a.T_in = reinterpret_cast<const c64*>(adj->T);
@@ -349,15 +363,15 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                                    P.deriv));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
   if (adj) {
-    HIPCHK(launch_adjoint(a, P.n_groups, s));
+    HIPCHK(launch_adjoint(a, P.n_groups, P.dyn_lds, s));
   } else if (plain) {
     std::string err;
     st = solve_plain_impl(a, P.jobs, P.models, s, err);
     if (st != VDC_OK) return fail(st, err);
   } else if (mixed) {
-    HIPCHK(launch_fgmres_mixed(a, P.n_groups, s));
+    HIPCHK(launch_fgmres_mixed(a, P.n_groups, P.dyn_lds, s));
   } else {
-    HIPCHK(launch_gmres_fp64(a, P.n_groups, s));
+    HIPCHK(launch_gmres_fp64(a, P.n_groups, P.dyn_lds, s));
   }
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
   std::vector<DevInfo> hinfo(n_jobs);

@@ -116,6 +116,102 @@ __device__ inline R norm_sq(const typename CT<R>::C* __restrict__ w, int Nc, R* 
   return v;
 }
 
+// y = A (vscale * dinv * v) (dinv may be null), one fused pass through LDS.
+// The block is walked in tiles of T rows of n_g: the tile's rows of
+// z = vscale dinv v plus two halo rows on each side are staged in LDS (the
+// halo rows were just read by the previous tile, so they come from cache),
+// the pointwise level-shift products (w_A, w_B) of the rows the tile needs
+// are formed in LDS, and y is written once.  lds must hold
+// (3 T + 8) * Nu complex values of precision R.  With bsub given the pass
+// writes y = bsub - A(...) instead (a residual), and with red given it also
+// returns ||y||^2.  Ends with a barrier (y is written by threads other than
+// the element owners).
+template <typename R>
+__device__ inline R matvec_tiled(const OpJob<R>& op, const R* sq,
+                                 const typename CT<R>::C* __restrict__ v, R vscale,
+                                 const typename CT<R>::C* __restrict__ dinv,
+                                 typename CT<R>::C* __restrict__ y,
+                                 typename CT<R>::C* lds, int T,
+                                 const typename CT<R>::C* __restrict__ bsub = nullptr,
+                                 R* red = nullptr) {
+  using C = typename CT<R>::C;
+  R acc[1] = {R(0)};
+  const int Ng = op.Ng, Nu = op.Nu;
+  C* zt = lds;                          // rows g0-2 .. g0+T+1
+  C* wa = lds + (size_t)(T + 4) * Nu;   // rows g0-1 .. g0+T
+  C* wb = wa + (size_t)(T + 2) * Nu;
+  __syncthreads();
+  for (int g0 = 0; g0 < Ng; g0 += T) {
+    const int t = min(T, Ng - g0);
+    const int zr0 = max(0, g0 - 2), zr1 = min(Ng, g0 + t + 2);
+    for (int q = threadIdx.x; q < (zr1 - zr0) * Nu; q += kBlock) {
+      const int i = zr0 * Nu + q;
+      zt[(zr0 - g0 + 2) * Nu + q] = vscale * load_z<R>(v, dinv, i);
+    }
+    __syncthreads();
+    const int wr0 = max(0, g0 - 1), wr1 = min(Ng, g0 + t + 1);
+    for (int q = threadIdx.x; q < (wr1 - wr0) * Nu; q += kBlock) {
+      const int row = wr0 + q / Nu, nu = q - (q / Nu) * Nu;
+      const int a = (nu + op.p) & 1;
+      const C* zr = zt + (row - g0 + 2) * Nu;
+      C zg = cz<R>(), zu = cz<R>();
+      if (row > 0) zg = sq[row] * zr[nu - Nu];
+      if (row + 1 < Ng) zg = zg + sq[row + 1] * zr[nu + Nu];
+      if (nu > 0) zu = sq[nu] * zr[nu - 1];
+      if (nu + 1 < Nu) zu = zu + sq[nu + 1] * zr[nu + 1];
+      const C uA = zr[nu] + op.lamd[a] * zg;
+      const int i = row * Nu + nu;
+      const C fab = op.AB[i];
+      wa[(row - g0 + 1) * Nu + nu] = op.AA[i] * uA + fab * zu;
+      wb[(row - g0 + 1) * Nu + nu] = fab * uA + op.BB[i] * zu;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < t * Nu; q += kBlock) {
+      const int row = g0 + q / Nu, nu = q - (q / Nu) * Nu;
+      const int a = (nu + op.p) & 1;
+      const C* zr = zt + (row - g0 + 2) * Nu;
+      const C* ar = wa + (row - g0 + 1) * Nu;
+      const C* br = wb + (row - g0 + 1) * Nu;
+      C zg = cz<R>(), zu = cz<R>(), ag = cz<R>(), bu = cz<R>();
+      if (row > 0) {
+        zg = sq[row] * zr[nu - Nu];
+        ag = sq[row] * ar[nu - Nu];
+      }
+      if (row + 1 < Ng) {
+        zg = zg + sq[row + 1] * zr[nu + Nu];
+        ag = ag + sq[row + 1] * ar[nu + Nu];
+      }
+      if (nu > 0) {
+        zu = sq[nu] * zr[nu - 1];
+        bu = sq[nu] * br[nu - 1];
+      }
+      if (nu + 1 < Nu) {
+        zu = zu + sq[nu + 1] * zr[nu + 1];
+        bu = bu + sq[nu + 1] * br[nu + 1];
+      }
+      const R d = R(op.dbase[a] - op.omega_g * row - op.omega_u * nu);
+      C out = d * zr[nu] - op.kappa[a] * zg - op.lam * zu - ar[nu] - op.lamd[a] * ag - bu;
+      if (bsub) out = bsub[row * Nu + nu] - out;
+      y[row * Nu + nu] = out;
+      acc[0] += norm2(out);
+    }
+    __syncthreads();
+  }
+  if (!red) return R(0);
+  block_sum<1, R>(acc, red, red + kWaves);
+  const R s = red[kWaves];
+  __syncthreads();
+  return s;
+}
+
+// Rows per tile of matvec_tiled for a block of width Nu and lds_bytes of LDS
+// (0 when even one row does not fit: use matvec_block instead).
+__host__ __device__ inline int tile_rows(int Nu, size_t elem_bytes, size_t lds_bytes) {
+  const long per_row = (long)Nu * (long)elem_bytes;
+  const long t = ((long)(lds_bytes / per_row) - 8) / 3;
+  return t < 1 ? 0 : (t > 32 ? 32 : (int)t);
+}
+
 // y = A (dinv * v) (dinv may be null); y, wA, wB are vectors of Nc elements.
 // Begins with a barrier so v may have just been written by other threads;
 // on return y holds the result at the calling thread's own elements (no
@@ -125,17 +221,52 @@ __device__ inline void matvec_block(const OpJob<R>& op, const R* sq,
                                     const typename CT<R>::C* v,
                                     const typename CT<R>::C* dinv,
                                     typename CT<R>::C* wA, typename CT<R>::C* wB,
-                                    typename CT<R>::C* y) {
+                                    typename CT<R>::C* y, R vscale = R(1)) {
   __syncthreads();
   for (int i = threadIdx.x; i < op.Nc; i += kBlock) {
     typename CT<R>::C yl, a, b;
     op_phase1<R>(op, sq, v, dinv, i, yl, a, b);
-    y[i] = yl;
-    wA[i] = a;
-    wB[i] = b;
+    y[i] = vscale * yl;
+    wA[i] = vscale * a;
+    wB[i] = vscale * b;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < op.Nc; i += kBlock) y[i] = op_phase2<R>(op, sq, wA, wB, i, y[i]);
+}
+
+// y = A (vscale dinv v): the LDS-tiled pass when tile rows T > 0, else the two
+// global phases; ends with a barrier either way.
+template <typename R>
+__device__ inline void apply_A(const OpJob<R>& op, const R* sq, const typename CT<R>::C* v,
+                               R vscale, const typename CT<R>::C* dinv, typename CT<R>::C* y,
+                               typename CT<R>::C* lds, int T, typename CT<R>::C* wA,
+                               typename CT<R>::C* wB) {
+  if (T > 0) {
+    matvec_tiled<R>(op, sq, v, vscale, dinv, y, lds, T);
+  } else {
+    matvec_block<R>(op, sq, v, dinv, wA, wB, y, vscale);
+    __syncthreads();
+  }
+}
+
+// y = b - A x and ||y||^2 (returned to every thread); ends with a barrier.
+template <typename R>
+__device__ inline R residual_A(const OpJob<R>& op, const R* sq, const typename CT<R>::C* x,
+                               const typename CT<R>::C* b, typename CT<R>::C* y,
+                               typename CT<R>::C* lds, int T, typename CT<R>::C* wA,
+                               typename CT<R>::C* wB, R* red) {
+  if (T > 0) return matvec_tiled<R>(op, sq, x, R(1), nullptr, y, lds, T, b, red);
+  matvec_block<R>(op, sq, x, nullptr, wA, wB, y);
+  R acc[1] = {R(0)};
+  for (int i = threadIdx.x; i < op.Nc; i += kBlock) {
+    const typename CT<R>::C r = b[i] - y[i];
+    y[i] = r;
+    acc[0] += norm2(r);
+  }
+  block_sum<1, R>(acc, red, red + kWaves);
+  const R s = red[kWaves];
+  __syncthreads();
+  return s;
 }
 
 }  // namespace vdc

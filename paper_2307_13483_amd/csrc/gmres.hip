@@ -43,21 +43,22 @@ gmres_fp64_kernel(SolveArgs a) {
       for (int q = 0; q < n; ++q) s.b[e[q].g * md.Nu + e[q].u] = c64{e[q].val, 0.0};
     }
     __syncthreads();
-    const BlockSolve r = gmres_fp64_block(L, op, s, a.ncap, a.m, a.tol, a.max_iter);
+    const BlockSolve r = gmres_fp64_block(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT);
     __syncthreads();
     finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);
   }
 }
 
-hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, hipStream_t s) {
-  hipLaunchKernelGGL(gmres_fp64_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
+hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
+  hipLaunchKernelGGL(gmres_fp64_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
-int gmres_fp64_occupancy() {
+int gmres_fp64_occupancy(size_t dyn_lds) {
   int n = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gmres_fp64_kernel, kBlock, 0);
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gmres_fp64_kernel, kBlock, dyn_lds);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

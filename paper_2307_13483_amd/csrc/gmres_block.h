@@ -48,15 +48,21 @@ __device__ inline void fp64_prepare(const OpJob<double>& op, const Fp64Slot& s, 
   }
 }
 
+// Dynamic LDS of the solver kernels: the tiles of matvec_tiled.
+extern __shared__ __align__(16) char vdc_tile_lds[];
+
 // Solves A x = b with b in s.b (complete and visible: call after a barrier).
-// Byte model (passes over a block vector of Nc complex FP64 values): setup 7
-// (3 table planes read; dinv, x, b, v_0 written), each cycle of k steps
-// cycle_passes(k) + k + 10 (x update k + 3, true residual 7).
+// Byte model (passes over a block vector of Nc complex FP64 values): setup 8
+// (two table planes read for the diagonal; dinv, x, b written; b read for its
+// norm and copied to V_0), each cycle of k steps cycle_passes(k) + k + 9:
+// x update k + 3 (basis, dinv, x in; x out) and the true residual b - A x
+// written into V_0 in the operator's pass (x, 3 table planes, b in; V_0 out).
 __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& op,
                                               const Fp64Slot& s, size_t ld, int m, double tol,
-                                              int max_iter) {
+                                              int max_iter, int T) {
   const int Nc = op.Nc;
-  BlockSolve r{VDC_NOT_CONVERGED, 0, 0, 0.0, 0.0, 7.0};
+  c64* lds = reinterpret_cast<c64*>(vdc_tile_lds);
+  BlockSolve r{VDC_NOT_CONVERGED, 0, 0, 0.0, 0.0, 8.0};
   r.bnorm = sqrt(norm_sq<double>(s.b, Nc, L.red));
   r.beta = r.bnorm;
   if (!(r.bnorm > 0.0) || !isfinite(r.bnorm)) {
@@ -64,20 +70,22 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
     r.beta = 0.0;
     return r;
   }
-  for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = (1.0 / r.beta) * s.b[i];
-  auto apply = [&](int j, c64* out) {
-    matvec_block<double>(op, L.sq, s.V + (size_t)j * ld, s.dinv, s.wA, s.wB, out);
+  for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = s.b[i];
+  auto apply = [&](int j, double sc, c64* out) {
+    apply_A<double>(op, L.sq, s.V + (size_t)j * ld, sc, s.dinv, out, lds, T, s.wA, s.wB);
   };
   for (;;) {
-    if (threadIdx.x == 0) L.K.g[0] = c64{r.beta, 0.0};
+    if (threadIdx.x == 0) {
+      L.K.g[0] = c64{r.beta, 0.0};
+      L.K.vs[0] = 1.0 / r.beta;
+    }
+    __syncthreads();
     const CycleResult cr = krylov_cycle<double>(L.K, L.red, s.V, ld, Nc, m, tol * r.bnorm,
-                                                max_iter, r.iters, s.Rm, s.w, apply);
-    r.passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 10.0;
-    combine_neg<double>(s.V, ld, cr.k, L.K.y, s.w, Nc);
-    for (int i = threadIdx.x; i < Nc; i += kBlock) s.x[i] = s.x[i] - s.dinv[i] * s.w[i];
-    matvec_block<double>(op, L.sq, s.x, nullptr, s.wA, s.wB, s.w);
-    for (int i = threadIdx.x; i < Nc; i += kBlock) s.w[i] = s.b[i] - s.w[i];
-    r.beta = sqrt(norm_sq<double>(s.w, Nc, L.red));
+                                                max_iter, r.iters, s.Rm, apply);
+    r.passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 9.0;
+    update_x<double>(s.V, ld, cr.k, L.K.y, L.K.vs, s.dinv, s.x, Nc);
+    // true residual b - A x, written into V_0 (the next cycle's start)
+    r.beta = sqrt(residual_A<double>(op, L.sq, s.x, s.b, s.V, lds, T, s.wA, s.wB, L.red));
     ++r.cycles;
     if (!isfinite(r.beta) || cr.nonfinite) {
       r.status = VDC_NONFINITE;
@@ -95,7 +103,6 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
       r.status = VDC_NOT_CONVERGED;
       break;
     }
-    for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = (1.0 / r.beta) * s.w[i];
   }
   return r;
 }

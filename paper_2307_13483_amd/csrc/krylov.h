@@ -14,12 +14,13 @@ struct KrylovLds {
   c64 sn[kMaxRestart];
   c64 g[kMaxRestart + 1];
   c64 y[kMaxRestart];
-  R h1[2 * (kMaxRestart + 1)];
+  R h1[2 * (kMaxRestart + 1)];   // projection coefficients onto the unit basis
   R h2[2 * (kMaxRestart + 1)];
+  R hs[2 * (kMaxRestart + 1)];   // the same times the stored vectors' scales
+  R vs[kMaxRestart + 1];         // basis vector l is vs[l] * V_l (lazy normalisation)
   c64 hc[kMaxRestart + 1];
   double resid;
   R wnorm2;
-  int reorth;   // steps of the current job that needed the second pass
 };
 
 __device__ inline c64 cdiv(c64 a, c64 b) {
@@ -80,14 +81,14 @@ __device__ inline void back_substitute(KrylovLds<R>& L, int k, const c64* Rm, in
   }
 }
 
-// Vector passes of one Arnoldi cycle of k steps, n2 of which needed the
-// second Gram-Schmidt pass, by design: per step j the operator reads v_j, the
-// Jacobi scaling and three level-shift planes and writes w (6); classical
-// Gram-Schmidt reads the basis twice (2 (j+1)), twice more when repeated;
-// v_{j+1} is written (1).  reorth_passes is the sum of 2 (j+1) over the
-// repeated steps.
+// Vector passes of one Arnoldi cycle of k steps by design: per step j the
+// operator reads v_j, the Jacobi scaling and three level-shift planes and
+// writes w into the basis slot j+1 (5 + 1 = 6, orthogonalised in place, so
+// no separate normalisation pass); classical Gram-Schmidt reads the basis
+// twice (2 (j+1)), twice more when repeated (reorth_passes, the sum of
+// 2 (j+1) over the repeated steps).
 __host__ __device__ inline double cycle_passes(int k, double reorth_passes) {
-  return 7.0 * k + 1.0 * k * (k + 1.0) + reorth_passes;
+  return 6.0 * k + 1.0 * k * (k + 1.0) + reorth_passes;
 }
 
 struct CycleResult {
@@ -108,22 +109,38 @@ struct CycleResult {
 // ||w||^2 - sum |h|^2 makes the GMRES residual estimate stall near 1e-8.
 constexpr double kReorthEta2 = 0.01;
 
-// Runs up to m Arnoldi steps from V_0 (normalised, L.g[0] = beta already set
-// by thread 0), stopping when the least-squares residual drops to tol_abs or
-// iters reaches max_iter.  apply(j, w) must write the preconditioned operator
-// applied to basis vector j into w (own elements).  On return L.y holds the
-// least-squares coefficients (after a barrier).
+// h (coefficients on the unit basis) = raw projections on the stored
+// vectors times their scales; hs = h times the scales again (the
+// coefficients of the stored vectors in the update).  Threads < 2 nv.
+template <typename R>
+__device__ inline void scale_coeffs(R* h, R* hs, const R* vs, int nv) {
+  if (threadIdx.x < 2 * nv) {
+    const R s = vs[threadIdx.x >> 1];
+    h[threadIdx.x] *= s;
+    hs[threadIdx.x] = h[threadIdx.x] * s;
+  }
+  __syncthreads();
+}
+
+// Runs up to m Arnoldi steps.  On entry the stored vector V_0 and its scale
+// L.vs[0] (V_0 * vs[0] has unit norm) and L.g[0] = beta are set (by thread 0
+// for the LDS values, followed by a barrier).  apply(j, s, out) must write
+// the preconditioned operator applied to s * V_j into out = V_{j+1} and end
+// with a barrier.  Stops when the least-squares residual drops to tol_abs or
+// iters reaches max_iter.  On return L.y holds the least-squares
+// coefficients on the unit basis (after a barrier).
 template <typename R, typename Apply>
 __device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<R>::C* V,
                                            size_t ld, int Nc, int m, double tol_abs,
-                                           int max_iter, int& iters, c64* Rm,
-                                           typename CT<R>::C* w, Apply apply) {
+                                           int max_iter, int& iters, c64* Rm, Apply apply) {
   using C = typename CT<R>::C;
   CycleResult res{0, false, false, 0.0, 0};
   for (int j = 0; j < m; ++j) {
-    apply(j, w);
+    C* w = V + (size_t)(j + 1) * ld;
+    apply(j, L.vs[j], w);
     project<R>(V, ld, j + 1, w, Nc, red, L.h1, &L.wnorm2);
-    const double rest = (double)subtract<R>(V, ld, j + 1, w, Nc, L.h1, red);
+    scale_coeffs<R>(L.h1, L.hs, L.vs, j + 1);
+    const double rest = (double)subtract<R>(V, ld, j + 1, w, Nc, L.hs, red);
     // every thread takes the same decision from the same reduced values
     const double wn2 = (double)L.wnorm2;
     double hn;
@@ -133,11 +150,15 @@ __device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<
       __syncthreads();
     } else {
       project<R>(V, ld, j + 1, w, Nc, red, L.h2);
-      hn = sqrt((double)subtract<R>(V, ld, j + 1, w, Nc, L.h2, red));
+      scale_coeffs<R>(L.h2, L.hs, L.vs, j + 1);
+      hn = sqrt((double)subtract<R>(V, ld, j + 1, w, Nc, L.hs, red));
       res.reorth_passes += 2.0 * (j + 1);
       res.reorth += 1;
     }
-    if (threadIdx.x == 0) L.resid = givens_step<R>(L, j, hn, Rm + (size_t)j * (m + 1));
+    if (threadIdx.x == 0) {
+      L.resid = givens_step<R>(L, j, hn, Rm + (size_t)j * (m + 1));
+      L.vs[j + 1] = R(hn > 0.0 ? 1.0 / hn : 0.0);
+    }
     __syncthreads();
     const double r = L.resid;
     ++iters;
@@ -151,20 +172,18 @@ __device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<
       break;
     }
     if (r <= tol_abs || iters >= max_iter) break;
-    if (j + 1 < m) {
-      const R sc = R(1.0 / hn);
-      for (int i = threadIdx.x; i < Nc; i += kBlock) V[(size_t)(j + 1) * ld + i] = sc * w[i];
-    }
   }
   if (threadIdx.x == 0) back_substitute<R>(L, res.k, Rm, m + 1);
   __syncthreads();
   return res;
 }
 
-// w = -sum_l V_l y_l (own elements), y from L.y (FP64), in precision R.
+// x += dinv * sum_l (vs[l] V_l) y_l (own elements; dinv, vs may be null), y from
+// L.y (FP64), in precision R: reads the k basis vectors, dinv and x once.
 template <typename R>
-__device__ inline void combine_neg(const typename CT<R>::C* V, size_t ld, int k, const c64* y,
-                                   typename CT<R>::C* w, int Nc) {
+__device__ inline void update_x(const typename CT<R>::C* V, size_t ld, int k, const c64* y,
+                                const R* vs, const typename CT<R>::C* dinv,
+                                typename CT<R>::C* x, int Nc) {
   using C = typename CT<R>::C;
   for (int i = threadIdx.x; i < Nc; i += kBlock) {
     C s = cz<R>();
@@ -174,10 +193,14 @@ __device__ inline void combine_neg(const typename CT<R>::C* V, size_t ld, int k,
 #pragma unroll
       for (int q = 0; q < kChunk; ++q) vv[q] = V[(size_t)(l + q) * ld + i];
 #pragma unroll
-      for (int q = 0; q < kChunk; ++q) s = s - vv[q] * C{R(y[l + q].x), R(y[l + q].y)};
+      for (int q = 0; q < kChunk; ++q)
+        s = s + vv[q] * C{R(y[l + q].x) * (vs ? vs[l + q] : R(1)),
+                          R(y[l + q].y) * (vs ? vs[l + q] : R(1))};
     }
-    for (; l < k; ++l) s = s - V[(size_t)l * ld + i] * C{R(y[l].x), R(y[l].y)};
-    w[i] = s;
+    for (; l < k; ++l)
+      s = s + V[(size_t)l * ld + i] * C{R(y[l].x) * (vs ? vs[l] : R(1)),
+                                        R(y[l].y) * (vs ? vs[l] : R(1))};
+    x[i] = x[i] + (dinv ? dinv[i] * s : s);
   }
 }
 

@@ -12,7 +12,7 @@
 // One job per workgroup, jobs popped from a device queue as in the FP64
 // solver; "iters" counts inner FP32 Arnoldi steps (the bulk of the bytes),
 // "outer" the FP64 outer steps.
-#include "krylov.h"
+#include "gmres_block.h"
 #include "solve_args.h"
 
 namespace vdc {
@@ -35,13 +35,15 @@ fgmres_mixed_kernel(SolveArgs a) {
   const int tid = threadIdx.x;
   const int m = a.m, mi = a.m_in;
   const size_t ld = a.ncap;
+  c64* lds64 = reinterpret_cast<c64*>(vdc_tile_lds);
+  c32* lds32 = reinterpret_cast<c32*>(vdc_tile_lds);
   c64* slot = a.scratch + (size_t)blockIdx.x * a.slot_elems;
   // FP64 part
   c64* Vo = slot;                                 // (m+1) x ld
   c64* Z = Vo + (size_t)(m + 1) * ld;             // m x ld
   c64* x = Z + (size_t)m * ld;
   c64* b = x + ld;
-  c64* w = b + ld;
+  c64* w = b + ld;                                // unused by the tiled operator
   c64* wA = w + ld;
   c64* wB = wA + ld;
   c64* Ro = wB + ld;                              // (m+1) x m
@@ -52,6 +54,8 @@ fgmres_mixed_kernel(SolveArgs a) {
   c32* w32 = dinv + ld;
   c32* wA32 = w32 + ld;
   c32* wB32 = wA32 + ld;
+  (void)w;
+  (void)w32;
 
   for (;;) {
     __syncthreads();
@@ -85,62 +89,90 @@ fgmres_mixed_kernel(SolveArgs a) {
     int iters = 0, outer = 0, cycles = 0, status = VDC_NOT_CONVERGED;
     // byte model in passes over a block vector of Nc values, p64 in complex
     // FP64 (16 B) and p32 in complex FP32 (8 B):
-    //   setup: 3 FP64 table planes read, x, b, v_0 written; dinv32 written
-    //   outer step: cast v_j (p64 + p32), norm and scale (3 p32), inner cycle
-    //     of k steps (cycle_passes(k) p32), z = -dinv V y (k + 3 p32, p64),
-    //     A z in FP64 (5 p64)
-    //   outer cycle of k_o steps: CGS2 on the outer basis and v_{j+1}
-    //     (cycle_passes(k_o) - 6 k_o p64), x += Z y (k_o + 2), residual 7
-    double p64 = 6.0, p32 = 1.0;
+    //   setup: two FP64 table planes (diagonal), x, b written, b read, V_0
+    //     copied (p64 7); FP32 dinv written (p32 1)
+    //   outer step (cycle_passes counts 6 p64 for its operator: v_j read in
+    //     the cast and the FP64 operator on z_j): v_j cast (1 p32), inner
+    //     cycle of k steps (cycle_passes(k) p32), z_j = dinv V y (k + 1 p32,
+    //     1 p64)
+    //   outer cycle of k_o steps: x += Z y (k_o + 2 p64), residual (6 p64)
+    double p64 = 7.0, p32 = 1.0;
     if (!(bnorm > 0.0) || !isfinite(bnorm)) {
       status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
       beta = 0.0;
     } else {
-      for (int i = tid; i < Nc; i += kBlock) Vo[i] = (1.0 / beta) * b[i];
-      // inner FP32 operator: A (dinv * v)
-      auto apply_in = [&](int j, c32* out) {
-        matvec_block<float>(op32, L.sqf, Vi + (size_t)j * ld, dinv, wA32, wB32, out);
+      for (int i = tid; i < Nc; i += kBlock) Vo[i] = b[i];
+      // inner FP32 operator: A (s dinv v)
+      auto apply_in = [&](int j, float sc, c32* out) {
+        apply_A<float>(op32, L.sqf, Vi + (size_t)j * ld, sc, dinv, out, lds32, a.tileT32, wA32,
+                       wB32);
       };
-      // outer step j: Z_j = inner(V_j), out = A Z_j in FP64
-      auto apply_out = [&](int j, c64* out) {
+      // outer step j: Z_j = inner(s V_j), out = A Z_j in FP64
+      auto apply_out = [&](int j, double sc, c64* out) {
         const c64* v = Vo + (size_t)j * ld;
-        for (int i = tid; i < Nc; i += kBlock) Vi[i] = c32{(float)v[i].x, (float)v[i].y};
-        const double n0 = sqrt((double)norm_sq<float>(Vi, Nc, L.redf));
+        float acc[1] = {0.f};
+        for (int i = tid; i < Nc; i += kBlock) {
+          const c32 t = c32{(float)(sc * v[i].x), (float)(sc * v[i].y)};
+          Vi[i] = t;
+          acc[0] += norm2(t);
+        }
+        block_sum<1, float>(acc, L.redf, L.redf + kWaves);
+        const double n0 = sqrt((double)L.redf[kWaves]);
+        __syncthreads();
+        c64* z = Z + (size_t)j * ld;
+        p32 += 1.0;
         if (n0 > 0.0) {
-          const float sc = (float)(1.0 / n0);
-          for (int i = tid; i < Nc; i += kBlock) Vi[i] = sc * Vi[i];
-          if (tid == 0) L.Ki.g[0] = c64{n0, 0.0};
+          if (tid == 0) {
+            L.Ki.g[0] = c64{n0, 0.0};
+            L.Ki.vs[0] = (float)(1.0 / n0);
+          }
+          __syncthreads();
           const CycleResult ci = krylov_cycle<float>(L.Ki, L.redf, Vi, ld, Nc, mi,
                                                      a.tol_in * n0, a.max_iter, iters, Ri,
-                                                     w32, apply_in);
-          combine_neg<float>(Vi, ld, ci.k, L.Ki.y, w32, Nc);
-          p32 += cycle_passes(ci.k, ci.reorth_passes) + ci.k + 3.0;
+                                                     apply_in);
+          // z = dinv * sum_l (vs_l Vi_l) y_l, widened to FP64
+          for (int i = tid; i < Nc; i += kBlock) {
+            c32 s = c32{0.f, 0.f};
+            int l = 0;
+            for (; l + kChunk <= ci.k; l += kChunk) {
+              c32 vv[kChunk];
+#pragma unroll
+              for (int q = 0; q < kChunk; ++q) vv[q] = Vi[(size_t)(l + q) * ld + i];
+#pragma unroll
+              for (int q = 0; q < kChunk; ++q) {
+                const float f = L.Ki.vs[l + q];
+                s = s + vv[q] * c32{(float)L.Ki.y[l + q].x * f, (float)L.Ki.y[l + q].y * f};
+              }
+            }
+            for (; l < ci.k; ++l) {
+              const float f = L.Ki.vs[l];
+              s = s + Vi[(size_t)l * ld + i] * c32{(float)L.Ki.y[l].x * f, (float)L.Ki.y[l].y * f};
+            }
+            const c32 t = dinv[i] * s;
+            z[i] = c64{(double)t.x, (double)t.y};
+          }
+          p32 += cycle_passes(ci.k, ci.reorth_passes) + ci.k + 1.0;
         } else {
-          for (int i = tid; i < Nc; i += kBlock) w32[i] = c32{0.f, 0.f};
+          for (int i = tid; i < Nc; i += kBlock) z[i] = c64{0.0, 0.0};
         }
-        c64* z = Z + (size_t)j * ld;
-        for (int i = tid; i < Nc; i += kBlock) {
-          const c32 t = dinv[i] * w32[i];
-          z[i] = c64{-(double)t.x, -(double)t.y};
-        }
-        matvec_block<double>(op, L.sq, z, nullptr, wA, wB, out);
+        p64 += 1.0;
+        apply_A<double>(op, L.sq, z, 1.0, nullptr, out, lds64, a.tileT, wA, wB);
         ++outer;
-        p64 += 1.0 + 1.0 + 5.0;
-        p32 += 4.0;
       };
       int ocount = 0;
       for (;;) {
-        if (tid == 0) L.Ko.g[0] = c64{beta, 0.0};
+        if (tid == 0) {
+          L.Ko.g[0] = c64{beta, 0.0};
+          L.Ko.vs[0] = 1.0 / beta;
+        }
+        __syncthreads();
         const CycleResult cr = krylov_cycle<double>(L.Ko, L.red, Vo, ld, Nc, m, a.tol * bnorm,
-                                                    1 << 30, ocount, Ro, w, apply_out);
-        p64 += cycle_passes(cr.k, cr.reorth_passes) - 6.0 * cr.k + cr.k + 2.0 + 7.0;
-        // x += Z y
-        combine_neg<double>(Z, ld, cr.k, L.Ko.y, w, Nc);
-        for (int i = tid; i < Nc; i += kBlock) x[i] = x[i] - w[i];
-        // FP64 true residual
-        matvec_block<double>(op, L.sq, x, nullptr, wA, wB, w);
-        for (int i = tid; i < Nc; i += kBlock) w[i] = b[i] - w[i];
-        beta = sqrt(norm_sq<double>(w, Nc, L.red));
+                                                    1 << 30, ocount, Ro, apply_out);
+        p64 += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 2.0 + 6.0;
+        // x += Z y (Z_l is the preconditioned unit basis vector l)
+        update_x<double>(Z, ld, cr.k, L.Ko.y, nullptr, nullptr, x, Nc);
+        // FP64 true residual into V_0
+        beta = sqrt(residual_A<double>(op, L.sq, x, b, Vo, lds64, a.tileT, wA, wB, L.red));
         ++cycles;
         if (!isfinite(beta) || cr.nonfinite) {
           status = VDC_NONFINITE;
@@ -158,7 +190,6 @@ fgmres_mixed_kernel(SolveArgs a) {
           status = VDC_NOT_CONVERGED;
           break;
         }
-        for (int i = tid; i < Nc; i += kBlock) Vo[i] = (1.0 / beta) * w[i];
       }
     }
     __syncthreads();
@@ -167,14 +198,15 @@ fgmres_mixed_kernel(SolveArgs a) {
   }
 }
 
-hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, hipStream_t s) {
-  hipLaunchKernelGGL(fgmres_mixed_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
+hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
+  hipLaunchKernelGGL(fgmres_mixed_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
-int fgmres_mixed_occupancy() {
+int fgmres_mixed_occupancy(size_t dyn_lds) {
   int n = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fgmres_mixed_kernel, kBlock, 0);
+  hipError_t e =
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fgmres_mixed_kernel, kBlock, dyn_lds);
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 

@@ -30,6 +30,8 @@ struct SolveArgs {
   size_t psi_ld;            // row length of psi_out (2 * max Nc)
   DevInfo* info;            // [n_jobs], indexed by the caller's job order
   int planes;               // table planes per parity (3, or 9 for the adjoint)
+  int tileT;                // rows per LDS tile of the FP64 matvec (0: two-phase)
+  int tileT32;              // the same for the FP32 inner matvec
   // adjoint inputs/outputs
   const c64* psi_in;        // forward solutions, full layout, row length psi_ld
   const c64* T_in;          // forward amplitudes [n_jobs][n_final][2]
