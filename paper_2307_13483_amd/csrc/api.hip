@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <utility>
 #include <vector>
@@ -37,6 +38,7 @@ struct vdc_model {
   double* d_nodes = nullptr;
   double* d_coef = nullptr;
   double* d_coefx = nullptr;
+  double* d_clus = nullptr;
 };
 
 namespace {
@@ -99,12 +101,13 @@ struct Plan {
   size_t dyn_lds = 0;
   int max_group_pts = 0;
   size_t shift_elems = 0;
+  std::vector<int> perm;          // per rectangle shape: points in order of eps
   bool deriv = false;
   size_t table_elems = 0;
   int n_groups = 0;
   size_t ncap = 0, slot_elems = 0;
   // byte offsets
-  size_t off_counter, off_models, off_jobs, off_tabs, off_groups, off_finals, off_info,
+  size_t off_counter, off_models, off_jobs, off_tabs, off_groups, off_perm, off_finals, off_info,
       off_shift, off_tables, off_tables32, off_scratch, total;
 };
 
@@ -183,6 +186,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
       gvmax_u[g] = std::max(gvmax_u[g], jb.vi_u);
     }
   }
+  std::map<std::tuple<int, int, int>, int> perm_index;   // (model, na, nb) -> offset
   for (size_t g = 0; g < P.groups.size(); ++g) {
     DevGroup& G = P.groups[g];
     const DevModel& md = P.models[G.model];
@@ -190,6 +194,21 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     G.na = gvmax_g[g] - G.a_min + 1;
     G.b_min = gvmin_u[g] - (md.Nu - 1);
     G.nb = gvmax_u[g] - G.b_min + 1;
+    const auto pk = std::make_tuple(G.model, G.na, G.nb);
+    auto pit = perm_index.find(pk);
+    if (pit == perm_index.end()) {
+      // eps = eps_i + w_g a + w_u b: order the rectangle's points by w_g ia + w_u ib
+      const int off = (int)P.perm.size();
+      const int npts = G.na * G.nb;
+      std::vector<std::pair<double, int>> key(npts);
+      for (int ia = 0; ia < G.na; ++ia)
+        for (int ib = 0; ib < G.nb; ++ib)
+          key[ia * G.nb + ib] = std::make_pair(md.omega_g * ia + md.omega_u * ib, ia * G.nb + ib);
+      std::sort(key.begin(), key.end());
+      for (int q = 0; q < npts; ++q) P.perm.push_back(key[q].second);
+      pit = perm_index.emplace(pk, off).first;
+    }
+    G.perm_off = pit->second;
     G.offset = P.shift_elems;
     P.shift_elems += (size_t)G.na * G.nb * shift_per_point;
     P.max_group_pts = std::max(P.max_group_pts, G.na * G.nb);
@@ -264,6 +283,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   P.off_jobs = off; off = align256(off + sizeof(DevJob) * std::max(1, n_jobs));
   P.off_tabs = off; off = align256(off + sizeof(DevTable) * std::max<size_t>(1, P.tabs.size()));
   P.off_groups = off; off = align256(off + sizeof(DevGroup) * std::max<size_t>(1, P.groups.size()));
+  P.off_perm = off; off = align256(off + sizeof(int) * std::max<size_t>(1, P.perm.size()));
   P.off_finals = off; off = align256(off + sizeof(int) * 2 * std::max(1, n_final));
   P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
   P.off_shift = off; off = align256(off + sizeof(c64) * P.shift_elems);
@@ -313,6 +333,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + P.off_groups, P.groups.data(), sizeof(DevGroup) * P.groups.size(),
                         hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_perm, P.perm.data(), sizeof(int) * P.perm.size(),
+                        hipMemcpyHostToDevice, s));
   if (n_final > 0)
     HIPCHK(hipMemcpyAsync(ws + P.off_finals, finals, sizeof(int) * 2 * n_final,
                           hipMemcpyHostToDevice, s));
@@ -355,7 +377,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   EventSet ev;
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
   HIPCHK(launch_level_shift_tables(a.models, reinterpret_cast<const DevGroup*>(ws + P.off_groups),
-                                   (int)P.groups.size(), P.max_group_pts, a.tabs,
+                                   (int)P.groups.size(), P.max_group_pts,
+                                   reinterpret_cast<const int*>(ws + P.off_perm), a.tabs,
                                    (int)P.tabs.size(), P.max_nc,
                                    reinterpret_cast<c64*>(ws + P.off_shift),
                                    reinterpret_cast<c64*>(ws + P.off_tables),
@@ -498,24 +521,55 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
       dm.glastx[f] = x[K - 1] * g[K - 1];
     }
   }
+  // far-field moments per cluster of nodes (see levelshift.hip)
+  const int nclust = (K + kClus - 1) / kClus;
+  std::vector<double> clus((size_t)nclust * kClusStride, 0.0);
+  for (int c = 0; c < nclust; ++c) {
+    const int k0 = c * kClus, k1 = std::min(K, k0 + kClus);
+    double* C = clus.data() + (size_t)c * kClusStride;
+    const double xc = 0.5 * (x[k0] + x[k1 - 1]);
+    C[0] = xc;
+    C[1] = 0.5 * (x[k1 - 1] - x[k0]);
+    for (int kind = 0; kind < 2; ++kind) {
+      const std::vector<double>& cf = kind == 0 ? coef : coefx;
+      for (int f = 0; f < kNumF; ++f) {
+        double* M = C + 2 + (kind * kNumF + f) * (kClusP + 1);
+        for (int k = k0; k < k1; ++k) {
+          const double ck = cf[(size_t)k * kNumF + f], d = x[k] - xc;
+          double dn = 1.0;
+          for (int n = 0; n <= kClusP; ++n) {
+            M[n] += ck * dn;
+            dn *= d;
+          }
+        }
+        for (int n = 2; n <= kClusP; ++n) M[n] /= (double)n * (n - 1);
+      }
+    }
+  }
   hipError_t e = hipMalloc(&m->d_nodes, sizeof(double) * K);
   if (e == hipSuccess) e = hipMalloc(&m->d_coef, sizeof(double) * K * kNumF);
   if (e == hipSuccess) e = hipMalloc(&m->d_coefx, sizeof(double) * K * kNumF);
+  if (e == hipSuccess) e = hipMalloc(&m->d_clus, sizeof(double) * clus.size());
   if (e == hipSuccess) e = hipMemcpy(m->d_nodes, x.data(), sizeof(double) * K, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(m->d_coef, coef.data(), sizeof(double) * K * kNumF, hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(m->d_coefx, coefx.data(), sizeof(double) * K * kNumF, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(m->d_clus, clus.data(), sizeof(double) * clus.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     if (m->d_nodes) (void)hipFree(m->d_nodes);
     if (m->d_coef) (void)hipFree(m->d_coef);
     if (m->d_coefx) (void)hipFree(m->d_coefx);
+    if (m->d_clus) (void)hipFree(m->d_clus);
     delete m;
     return hip_fail(e, "model upload");
   }
   dm.nodes = m->d_nodes;
   dm.coef = m->d_coef;
   dm.coefx = m->d_coefx;
+  dm.nclust = nclust;
+  dm.clus = m->d_clus;
   *out = m;
   return VDC_OK;
 }
@@ -525,6 +579,7 @@ vdc_status vdc_model_destroy(vdc_model_t m) {
   if (m->d_nodes) (void)hipFree(m->d_nodes);
   if (m->d_coef) (void)hipFree(m->d_coef);
   if (m->d_coefx) (void)hipFree(m->d_coefx);
+  if (m->d_clus) (void)hipFree(m->d_clus);
   delete m;
   return VDC_OK;
 }
@@ -600,6 +655,7 @@ static size_t matvec_ws(const vdc_model* m, int n_vec) {
   off = align256(off + sizeof(DevModel));
   off = align256(off + sizeof(DevTable));
   off = align256(off + sizeof(DevGroup));
+  off = align256(off + sizeof(int) * Nc);
   off = align256(off + sizeof(c64) * kNumF * Nc);
   off = align256(off + sizeof(int) * std::max(1, n_vec));
   off = align256(off + sizeof(c64) * 6 * Nc);
@@ -631,6 +687,7 @@ vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, con
   DevModel* dmod = reinterpret_cast<DevModel*>(ws + off); off = align256(off + sizeof(DevModel));
   DevTable* dtab = reinterpret_cast<DevTable*>(ws + off); off = align256(off + sizeof(DevTable));
   DevGroup* dgrp = reinterpret_cast<DevGroup*>(ws + off); off = align256(off + sizeof(DevGroup));
+  int* dperm = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * Nc);
   c64* shift = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * Nc);
   int* dpar = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * n_vec);
   c64* tables = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * 6 * Nc);
@@ -647,7 +704,15 @@ vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, con
   g.na = m->dev.Ng;
   g.b_min = -(m->dev.Nu - 1);
   g.nb = m->dev.Nu;
+  g.perm_off = 0;
   g.offset = 0;
+  std::vector<std::pair<double, int>> key(Nc);
+  for (int ia = 0; ia < g.na; ++ia)
+    for (int ib = 0; ib < g.nb; ++ib)
+      key[ia * g.nb + ib] = std::make_pair(m->dev.omega_g * ia + m->dev.omega_u * ib, ia * g.nb + ib);
+  std::sort(key.begin(), key.end());
+  std::vector<int> hperm(Nc);
+  for (size_t q = 0; q < Nc; ++q) hperm[q] = key[q].second;
   DevTable t{};
   t.E = E;
   t.model = 0;
@@ -658,9 +723,10 @@ vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, con
   HIPCHK(hipMemcpyAsync(dmod, &m->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dtab, &t, sizeof(DevTable), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dgrp, &g, sizeof(DevGroup), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dperm, hperm.data(), sizeof(int) * Nc, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(dpar, parity, sizeof(int) * n_vec, hipMemcpyHostToDevice, s));
-  HIPCHK(launch_level_shift_tables(dmod, dgrp, 1, m->dev.Nc, dtab, 1, m->dev.Nc, shift, tables,
-                                   nullptr, s));
+  HIPCHK(launch_level_shift_tables(dmod, dgrp, 1, m->dev.Nc, dperm, dtab, 1, m->dev.Nc, shift,
+                                   tables, nullptr, s));
   HIPCHK(launch_matvec_full(dmod, dtab, tables, n_vec, dpar, reinterpret_cast<const c64*>(x),
                             reinterpret_cast<c64*>(y), z, yc, wA, wB, m->dev.Nc, s));
   // the host-side staging buffers above are read by the copies before return

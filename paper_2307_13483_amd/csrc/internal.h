@@ -16,6 +16,13 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kMaxRestart = 128;
 constexpr int kMaxFinal = 64;
 constexpr int kNumF = 6;          // level-shift functions per energy
+// Far-field expansion of the transform's node sum: clusters of kClus
+// consecutive nodes, moments up to kClusP; per cluster: centre, half-width,
+// then for the 6 functions g and the 6 functions x g: M_0, M_1 and
+// mu_n = M_n / (n (n-1)), n = 2..kClusP.
+constexpr int kClus = 64;
+constexpr int kClusP = 30;
+constexpr int kClusStride = 2 + 2 * kNumF * (kClusP + 1);
 
 // Level-shift function index: mu-major, pairs (11, 12, 22).
 //   0: F[f1e f1e]  1: F[f1e f2e]  2: F[f2e f2e]
@@ -39,6 +46,8 @@ struct DevModel {
   const double* nodes;   // [K]            device
   const double* coef;    // [K][kNumF]     device: slope jumps c_k of g
   const double* coefx;   // [K][kNumF]     device: slope jumps of x g(x)
+  int nclust;            // ceil(K / kClus)
+  const double* clus;    // [nclust][kClusStride] device: far-field moments
 };
 
 // One job as the kernels see it (host-filled, device-resident array).
@@ -69,7 +78,7 @@ struct DevGroup {
   double eps_i;
   int model;
   int a_min, na, b_min, nb;
-  int pad;
+  int perm_off;          // start of its point order (sorted by eps) in the perm array
   size_t offset;
 };
 
@@ -113,9 +122,10 @@ __host__ __device__ inline float norm2(c32 a) { return a.x * a.x + a.y * a.y; }
 
 // Launchers (defined in the .hip files).
 hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,
-                                     int n_groups, int max_group_pts, const DevTable* tables_dev,
-                                     int n_tables, int max_nc, c64* shift, c64* table_base,
-                                     c32* table32_base, hipStream_t s, bool deriv = false);
+                                     int n_groups, int max_group_pts, const int* perm,
+                                     const DevTable* tables_dev, int n_tables, int max_nc,
+                                     c64* shift, c64* table_base, c32* table32_base,
+                                     hipStream_t s, bool deriv = false);
 hipError_t launch_level_shift_points(const DevModel& m, int n_eps, const double* eps,
                                      c64* out, hipStream_t s);
 

@@ -9,9 +9,20 @@
 // (s_{-1} = s_{K-1} = 0; g_0 = 0 because Gamma(0) = 0).  This follows from
 // integrating L(x)/(eps - x) segment by segment and summing by parts.
 // All six functions share the same psi(eps - x_k), so each node costs one
-// logarithm and six fused multiply-adds; nodes and slope jumps are staged
-// through LDS in chunks shared by the workgroup.
+// logarithm and six fused multiply-adds.
 // Imaginary part: -g(eps)/2 = -pi f_d f_d' for eps > 0, else 0 (analytic).
+//
+// Far field: for a cluster of kClus consecutive nodes with centre x_c and
+// half-width r, and t = eps - x_c with |t| >= 3 r, the cluster's part of the
+// sum is the convergent series (psi^(n)(t) = (-1)^n (n-2)! / t^(n-1), n >= 2)
+//     sum_k c_k psi(t - d_k) = t ln|t| M_0 - (ln|t| + 1) M_1
+//                              + sum_{n>=2} M_n / (n (n-1)) t^-(n-1),
+// M_n = sum_k c_k d_k^n, d_k = x_k - x_c, truncated at n = 30 (remainder
+// below 3^-31 / 900 of the cluster's magnitude); its eps derivative follows
+// term by term.  Near clusters are summed node by node.  Points are processed
+// in order of eps (a permutation per offset rectangle), so the lanes of a wave
+// agree on which clusters are far; a cluster is expanded only if it is far
+// for every lane of the wave.
 //
 // Sharing across initial states: eps_nu = eps_i + w_g (v_g - n_g) + w_u (v_u - n_u)
 // depends on (n_g, n_u) only through the offsets (v_g - n_g, v_u - n_u), so
@@ -23,8 +34,6 @@
 namespace vdc {
 
 constexpr int kLsThreads = 256;
-constexpr int kLsChunk = 256;      // nodes staged per LDS chunk
-constexpr int kLsStride = 8;       // doubles per staged node: x, c[6], pad
 
 // ln|t| for t != 0, finite: t = m 2^e with m in [1/sqrt2, sqrt2),
 // ln m = 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.1716, by its odd power series
@@ -70,42 +79,89 @@ __device__ inline double width_pair(const DevModel& m, int mu, int d1, int d2, d
   return A * pow(eps, m.l[mu] + 0.5) * exp(-eps * rB);
 }
 
-// The six complex values at electron energy eps, for a workgroup of
-// kLsThreads threads that all call it (with `active` false for idle threads)
-// so the LDS staging barriers are uniform.
-__device__ inline void level_shift6_block(const DevModel& m, double eps, bool active,
-                                          double* lds, c64 out[kNumF]) {
-  double acc[kNumF];
+// A pointer that is the same for every lane, moved to scalar registers and
+// to the constant address space so that reads through it with lane-uniform
+// offsets become scalar loads (the data is read-only during the kernel).
+typedef const __attribute__((address_space(4))) double* uniform_dptr;
+__device__ inline uniform_dptr uniform_ptr(const double* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (uniform_dptr)(((uint64_t)hi << 32) | lo);
+}
+
+// Sums over the nodes of the transform for one electron energy: aF[f] =
+// sum_k c_k psi(eps - x_k) (g's slope jumps), with DERIV also
+// aD[f] = sum_k c_k ln|eps - x_k| and aX[f] = sum_k cx_k psi(eps - x_k)
+// (x g's slope jumps).  Called by every lane of a wave (inactive lanes pass
+// active = false and vote "far").
+template <bool DERIV>
+__device__ inline void node_sums(const DevModel& m, double eps, bool active, double* aF,
+                                 double* aD, double* aX) {
 #pragma unroll
-  for (int f = 0; f < kNumF; ++f) acc[f] = 0.0;
-  const double* __restrict__ xk = m.nodes;
-  const double* __restrict__ ck = m.coef;
-  for (int k0 = 0; k0 < m.K; k0 += kLsChunk) {
-    const int nk = min(kLsChunk, m.K - k0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < nk; q += blockDim.x) {
-      double* d = lds + q * kLsStride;
-      d[0] = xk[k0 + q];
+  for (int f = 0; f < kNumF; ++f) aF[f] = aD[f] = aX[f] = 0.0;
+  const uniform_dptr clus = uniform_ptr(m.clus);
+  const uniform_dptr nodes = uniform_ptr(m.nodes);
+  const uniform_dptr coef = uniform_ptr(m.coef);
+  const uniform_dptr coefx = uniform_ptr(m.coefx);
+  const int nclust = __builtin_amdgcn_readfirstlane(m.nclust);
+  const int K = __builtin_amdgcn_readfirstlane(m.K);
+  for (int c = 0; c < nclust; ++c) {
+    const uniform_dptr C = clus + (size_t)c * kClusStride;
+    const double xc = C[0], r = C[1];
+    const double t = eps - xc;
+    const bool far = !active || (fabs(t) >= 3.0 * r && t != 0.0);
+    if (__all(far)) {
+      const double L = ln_abs(t);
+      double u = __builtin_amdgcn_rcp(t);
+      u = fma(u, fma(-t, u, 1.0), u);
+      u = fma(u, fma(-t, u, 1.0), u);
+      const double tl = t * L, l1 = L + 1.0;
 #pragma unroll
-      for (int f = 0; f < kNumF; ++f) d[1 + f] = ck[(size_t)(k0 + q) * kNumF + f];
-      d[7] = 0.0;
-    }
-    __syncthreads();
-    if (active) {
-      for (int q = 0; q < nk; ++q) {
-        const double* d = lds + q * kLsStride;
-        const double t = eps - d[0];
-        const double psi = (t == 0.0) ? 0.0 : t * ln_abs(t);
+      for (int f = 0; f < kNumF; ++f) {
+        const uniform_dptr M = C + 2 + f * (kClusP + 1);
+        double ser = M[kClusP];
+        for (int n = kClusP - 1; n >= 2; --n) ser = fma(ser, u, M[n]);
+        aF[f] += fma(tl, M[0], fma(-l1, M[1], u * ser));
+        if (DERIV) {
+          double sd = (kClusP - 1) * M[kClusP];
+          for (int n = kClusP - 1; n >= 2; --n) sd = fma(sd, u, (n - 1) * M[n]);
+          aD[f] += fma(L, M[0], -u * fma(u, sd, M[1]));
+          const uniform_dptr MX = C + 2 + (kNumF + f) * (kClusP + 1);
+          double sx = MX[kClusP];
+          for (int n = kClusP - 1; n >= 2; --n) sx = fma(sx, u, MX[n]);
+          aX[f] += fma(tl, MX[0], fma(-l1, MX[1], u * sx));
+        }
+      }
+    } else if (active) {
+      const int k1 = min(K, (c + 1) * kClus);
+      for (int k = c * kClus; k < k1; ++k) {
+        const double tk = eps - nodes[k];
+        const double ln = (tk == 0.0) ? 0.0 : ln_abs(tk);
+        const double psi = tk * ln;
 #pragma unroll
-        for (int f = 0; f < kNumF; ++f) acc[f] = fma(d[1 + f], psi, acc[f]);
+        for (int f = 0; f < kNumF; ++f) {
+          const double ck = coef[(size_t)k * kNumF + f];
+          aF[f] = fma(ck, psi, aF[f]);
+          if (DERIV) {
+            aD[f] = fma(ck, ln, aD[f]);
+            aX[f] = fma(coefx[(size_t)k * kNumF + f], psi, aX[f]);
+          }
+        }
       }
     }
   }
-  const double tl = eps - xk[m.K - 1];
+}
+
+// The six complex level shifts at eps (Re from the node sums, Im analytic).
+__device__ inline void level_shift6(const DevModel& m, double eps, bool active, c64 out[kNumF]) {
+  double aF[kNumF], aD[kNumF], aX[kNumF];
+  node_sums<false>(m, eps, active, aF, aD, aX);
+  const double tl = eps - m.nodes[m.K - 1];
   const double lnl = (tl == 0.0) ? 0.0 : ln_abs(tl);
   const double inv2pi = 1.0 / (2.0 * kPi);
 #pragma unroll
-  for (int f = 0; f < kNumF; ++f) out[f].x = (acc[f] - m.glast[f] * (lnl + 1.0)) * inv2pi;
+  for (int f = 0; f < kNumF; ++f) out[f].x = (aF[f] - m.glast[f] * (lnl + 1.0)) * inv2pi;
 #pragma unroll
   for (int mu = 0; mu < 2; ++mu) {
     out[fidx(mu, 0)].y = -0.5 * width_pair(m, mu, 0, 0, eps);
@@ -119,22 +175,22 @@ __device__ inline void level_shift6_block(const DevModel& m, double eps, bool ac
 // stored [point][6] from the group's offset.
 __global__ void __launch_bounds__(kLsThreads)
 shift_table_kernel(const DevModel* __restrict__ models, const DevGroup* __restrict__ groups,
-                   c64* __restrict__ shift) {
-  __shared__ double lds[kLsChunk * kLsStride];
+                   const int* __restrict__ perm, c64* __restrict__ shift) {
   const DevGroup gr = groups[blockIdx.y];
   const DevModel& m = models[gr.model];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int npts = gr.na * gr.nb;
-  const bool active = i < npts;
+  if (blockIdx.x * blockDim.x >= npts) return;   // whole workgroup beyond the rectangle
+  const bool active = s < npts;
+  int i = 0;
   double eps = 0.0;
   if (active) {
+    i = perm[gr.perm_off + s];
     const int ia = i / gr.nb, ib = i - ia * gr.nb;
     eps = gr.eps_i + m.omega_g * (gr.a_min + ia) + m.omega_u * (gr.b_min + ib);
   }
-  // a whole workgroup beyond this group's points has nothing to do
-  if (blockIdx.x * blockDim.x >= npts) return;
   c64 F[kNumF];
-  level_shift6_block(m, eps, active, lds, F);
+  level_shift6(m, eps, active, F);
   if (active) {
 #pragma unroll
     for (int f = 0; f < kNumF; ++f) shift[gr.offset + (size_t)i * kNumF + f] = F[f];
@@ -176,47 +232,15 @@ gather_tables_kernel(const DevModel* __restrict__ models, const DevGroup* __rest
 }
 
 // Level shift, its eps derivative and the transform of x g(x) (for the
-// derivatives in the width scales B), sharing one logarithm per node:
+// derivatives in the width scales B), from the same node sums:
 //   2 pi dDelta/deps = sum_k c_k ln|eps - x_k| - g_{K-1}/(eps - x_{K-1})
 // (the "+1" of d psi/dt drops out because the slope jumps sum to zero), and
 // the x g transform is the level shift with the slope jumps of x g.
 // Imaginary parts: -g'(eps)/2 and -eps g(eps)/2 (analytic).
-constexpr int kLsStride18 = 16;    // x, c[6], cx[6], pad
-
-__device__ inline void level_shift18_block(const DevModel& m, double eps, bool active,
-                                           double* lds, c64 F[kNumF], c64 D[kNumF],
-                                           c64 X[kNumF]) {
+__device__ inline void level_shift18(const DevModel& m, double eps, bool active, c64 F[kNumF],
+                                     c64 D[kNumF], c64 X[kNumF]) {
   double aF[kNumF], aD[kNumF], aX[kNumF];
-#pragma unroll
-  for (int f = 0; f < kNumF; ++f) aF[f] = aD[f] = aX[f] = 0.0;
-  for (int k0 = 0; k0 < m.K; k0 += kLsChunk) {
-    const int nk = min(kLsChunk, m.K - k0);
-    __syncthreads();
-    for (int q = threadIdx.x; q < nk; q += blockDim.x) {
-      double* d = lds + q * kLsStride18;
-      d[0] = m.nodes[k0 + q];
-#pragma unroll
-      for (int f = 0; f < kNumF; ++f) {
-        d[1 + f] = m.coef[(size_t)(k0 + q) * kNumF + f];
-        d[7 + f] = m.coefx[(size_t)(k0 + q) * kNumF + f];
-      }
-    }
-    __syncthreads();
-    if (active) {
-      for (int q = 0; q < nk; ++q) {
-        const double* d = lds + q * kLsStride18;
-        const double t = eps - d[0];
-        const double ln = (t == 0.0) ? 0.0 : ln_abs(t);
-        const double psi = t * ln;
-#pragma unroll
-        for (int f = 0; f < kNumF; ++f) {
-          aF[f] = fma(d[1 + f], psi, aF[f]);
-          aD[f] = fma(d[1 + f], ln, aD[f]);
-          aX[f] = fma(d[7 + f], psi, aX[f]);
-        }
-      }
-    }
-  }
+  node_sums<true>(m, eps, active, aF, aD, aX);
   const double tl = eps - m.nodes[m.K - 1];
   const double lnl = (tl == 0.0) ? 0.0 : ln_abs(tl);
   const double itl = (tl == 0.0) ? 0.0 : 1.0 / tl;
@@ -245,21 +269,22 @@ __device__ inline void level_shift18_block(const DevModel& m, double eps, bool a
 
 __global__ void __launch_bounds__(kLsThreads)
 shift_table_deriv_kernel(const DevModel* __restrict__ models, const DevGroup* __restrict__ groups,
-                         c64* __restrict__ shift) {
-  __shared__ double lds[kLsChunk * kLsStride18];
+                         const int* __restrict__ perm, c64* __restrict__ shift) {
   const DevGroup gr = groups[blockIdx.y];
   const DevModel& m = models[gr.model];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int npts = gr.na * gr.nb;
-  const bool active = i < npts;
+  if (blockIdx.x * blockDim.x >= npts) return;
+  const bool active = s < npts;
+  int i = 0;
   double eps = 0.0;
   if (active) {
+    i = perm[gr.perm_off + s];
     const int ia = i / gr.nb, ib = i - ia * gr.nb;
     eps = gr.eps_i + m.omega_g * (gr.a_min + ia) + m.omega_u * (gr.b_min + ib);
   }
-  if (blockIdx.x * blockDim.x >= npts) return;
   c64 F[kNumF], D[kNumF], X[kNumF];
-  level_shift18_block(m, eps, active, lds, F, D, X);
+  level_shift18(m, eps, active, F, D, X);
   if (active) {
     c64* o = shift + gr.offset + (size_t)i * 3 * kNumF;
 #pragma unroll
@@ -299,11 +324,10 @@ gather_tables_deriv_kernel(const DevModel* __restrict__ models,
 
 __global__ void __launch_bounds__(kLsThreads)
 level_shift_points_kernel(DevModel m, int n, const double* __restrict__ eps, c64* __restrict__ out) {
-  __shared__ double lds[kLsChunk * kLsStride];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = i < n;
   c64 F[kNumF];
-  level_shift6_block(m, active ? eps[i] : 0.0, active, lds, F);
+  level_shift6(m, active ? eps[i] : 0.0, active, F);
   if (active) {
 #pragma unroll
     for (int f = 0; f < kNumF; ++f) out[(size_t)i * kNumF + f] = F[f];
@@ -311,20 +335,22 @@ level_shift_points_kernel(DevModel m, int n, const double* __restrict__ eps, c64
 }
 
 hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,
-                                     int n_groups, int max_group_pts, const DevTable* tables_dev,
-                                     int n_tables, int max_nc, c64* shift, c64* table_base,
-                                     c32* table32_base, hipStream_t s, bool deriv) {
+                                     int n_groups, int max_group_pts, const int* perm,
+                                     const DevTable* tables_dev, int n_tables, int max_nc,
+                                     c64* shift, c64* table_base, c32* table32_base,
+                                     hipStream_t s, bool deriv) {
   if (n_tables <= 0) return hipSuccess;
   dim3 g1((max_group_pts + kLsThreads - 1) / kLsThreads, n_groups);
   if (deriv) {
     hipLaunchKernelGGL(shift_table_deriv_kernel, g1, dim3(kLsThreads), 0, s, models_dev,
-                       groups_dev, shift);
+                       groups_dev, perm, shift);
     dim3 g2((max_nc + kLsThreads - 1) / kLsThreads, n_tables);
     hipLaunchKernelGGL(gather_tables_deriv_kernel, g2, dim3(kLsThreads), 0, s, models_dev,
                        groups_dev, tables_dev, shift, table_base);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(shift_table_kernel, g1, dim3(kLsThreads), 0, s, models_dev, groups_dev, shift);
+  hipLaunchKernelGGL(shift_table_kernel, g1, dim3(kLsThreads), 0, s, models_dev, groups_dev, perm,
+                     shift);
   dim3 g2((max_nc + kLsThreads - 1) / kLsThreads, n_tables);
   hipLaunchKernelGGL(gather_tables_kernel, g2, dim3(kLsThreads), 0, s, models_dev, groups_dev,
                      tables_dev, shift, table_base, table32_base);
