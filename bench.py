@@ -79,13 +79,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--restart", type=int, default=20)
+    ap.add_argument("--restart", type=int, default=6)
     ap.add_argument("--energies", type=int, default=512)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp32",
                     help="fp32: FP32 inner / FP64 outer (FP64 true residual); fp64: FP64 GMRES")
-    ap.add_argument("--inner-restart", type=int, default=30)
-    ap.add_argument("--inner-tol", type=float, default=1e-5)
-    ap.add_argument("--outer-restart", type=int, default=8)
+    ap.add_argument("--inner-restart", type=int, default=8)
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--outer-restart", type=int, default=16)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick restart lengths, inner tolerance and tile rows on a job sample "
+                         "before timing (untimed)")
     ap.add_argument("--both", type=int, default=1, help="also time the other precision")
     ap.add_argument("--plain-sample", type=int, default=48,
                     help="right-hand sides timed on the plain single-solve path (0: skip)")
@@ -117,11 +121,19 @@ def main():
     nc = Ng * Nu
     model = vdc.Model2D(p, Ng, Nu)
 
-    def run_mode(precision):
+    def choose(precision):
         prec = vdc.FP64 if precision == "fp64" else vdc.FP32_INNER
         opts = vdc.Opts(restart=args.restart, tol=1e-10, precision=prec,
                         inner_restart=args.inner_restart, inner_tol=args.inner_tol,
-                        outer_restart=args.outer_restart)
+                        outer_restart=args.outer_restart, tile_rows=args.tile_rows)
+        if args.autotune:
+            from paper_2307_13483_amd.autotune import autotune
+            opts, _ = autotune([model], cfg["jobs"], cfg["finals"], base=opts)
+        return opts
+
+    def run_mode(precision):
+        opts = choose(precision)
+        prec = opts.precision
         solver = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts)
         for _ in range(args.warmup):
             solver.run()
@@ -148,6 +160,9 @@ def main():
                     frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(kernel, workload),
                     kernel=kernel, algorithmic_bytes_per_launch=alg, kernel_ms=solver_ms)
         return dict(value=conv * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
+                    chosen=dict(restart=opts.restart, inner_restart=opts.inner_restart,
+                                inner_tol=opts.inner_tol, outer_restart=opts.outer_restart,
+                                tile_rows=opts.tile_rows),
                     converged=conv, worst_rel_res=worst, n_jobs=solver.n_jobs,
                     iters_mean=sum(iters) / len(iters), iters_max=max(iters),
                     outer_mean=(sum(i["outer_iters"] for i in infos) / len(infos)),
@@ -166,9 +181,10 @@ def main():
         "config": {"workload": "2D generalized model, batched energies x v_i x mu",
                    "basis": f"{Ng}x{Nu} per state", "unknowns": 2 * nc,
                    "right_hand_sides": head["n_jobs"], "energies": args.energies,
-                   "solver": (f"GMRES({args.restart}) Jacobi" if args.precision == "fp64" else
-                              f"FGMRES({args.outer_restart}) FP64 outer, GMRES({args.inner_restart}) "
-                              f"FP32 inner to {args.inner_tol:g}, Jacobi"),
+                   "solver": (f"GMRES({opts.restart}) Jacobi" if args.precision == "fp64" else
+                              f"FGMRES({opts.outer_restart}) FP64 outer, GMRES({opts.inner_restart}) "
+                              f"FP32 inner to {opts.inner_tol:g}, Jacobi"),
+                   "tuned": head["chosen"],
                    "tol": "1e-10 relative FP64 true residual",
                    "precision": args.precision},
         "converged": head["converged"], "worst_rel_res": head["worst_rel_res"],
@@ -180,28 +196,26 @@ def main():
     if other is not None:
         out["other_precision"] = {k: v for k, v in other.items() if k != "opts"}
     if args.plain_sample > 0:
+        # the plain single-solve path at its own best restart length (its
+        # per-step cost is launch latency, so it prefers long cycles)
         jobs = cfg["jobs"]
         k = args.plain_sample
         sub = [jobs[int(round(i * (len(jobs) - 1) / max(1, k - 1)))] for i in range(k)]
-        popts = vdc.Opts(restart=args.restart, tol=1e-10, precision=vdc.FP64)
-        sp = vdc.Solver(model, sub, cfg["finals"], popts)
+        rates = {}
         try:
-            sp.run(plain=True)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sp.run(plain=True)
-            torch.cuda.synchronize()
-            tp = time.perf_counter() - t1
-            sb = vdc.Solver(model, sub, cfg["finals"], popts)
-            sb.run()
-            torch.cuda.synchronize()
-            t2 = time.perf_counter()
-            sb.run()
-            torch.cuda.synchronize()
-            tb = time.perf_counter() - t2
-            out["plain"] = dict(sample=k, plain_fp64_solves_per_s=k / tp,
-                                batched_fp64_same_jobs_solves_per_s=k / tb,
-                                speedup_batched_vs_plain=head["value"] / (k / tp))
+            for m in (6, 20, 40):
+                popts = vdc.Opts(restart=m, tol=1e-10, precision=vdc.FP64)
+                sp = vdc.Solver(model, sub, cfg["finals"], popts)
+                sp.run(plain=True)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sp.run(plain=True)
+                torch.cuda.synchronize()
+                rates[m] = k / (time.perf_counter() - t1)
+            best_m = max(rates, key=rates.get)
+            out["plain"] = dict(sample=k, plain_fp64_solves_per_s=rates[best_m], plain_restart=best_m,
+                                plain_by_restart={str(m): r for m, r in rates.items()},
+                                speedup_batched_vs_plain=head["value"] / rates[best_m])
         except vdc.VdcError as e:
             out["plain"] = dict(error=str(e))
     if args.cpu_sample > 0:

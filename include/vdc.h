@@ -105,6 +105,8 @@ typedef struct {
   int inner_restart;         /* FP32_INNER: inner GMRES length (1..128)         */
   double inner_tol;          /* FP32_INNER: inner relative tolerance            */
   int outer_restart;         /* FP32_INNER: outer FGMRES length (1..32)         */
+  int tile_rows;             /* rows of n_g per LDS tile of the fused operator
+                                pass; 0 = the largest that fits               */
 } vdc_solve_opts;
 
 /* Per-job results written to host memory by the solve calls. */

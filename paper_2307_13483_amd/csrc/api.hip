@@ -155,8 +155,13 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   }
   // LDS tiles of the fused operator pass (96 KB budget next to the static LDS)
   const size_t kTileBudget = 96 * 1024;
+  if (o->tile_rows < 0) return fail(VDC_ERR_INVALID_ARG, "tile_rows must be >= 0");
   P.tileT = tile_rows(P.max_nu, sizeof(c64), kTileBudget);
   P.tileT32 = mixed ? tile_rows(P.max_nu, sizeof(c32), kTileBudget) : 0;
+  if (o->tile_rows > 0) {
+    P.tileT = std::min(P.tileT, o->tile_rows);
+    P.tileT32 = std::min(P.tileT32, o->tile_rows);
+  }
   P.dyn_lds = std::max((size_t)(3 * P.tileT + 8) * P.max_nu * sizeof(c64) * (P.tileT > 0),
                        (size_t)(3 * P.tileT32 + 8) * P.max_nu * sizeof(c32) * (P.tileT32 > 0));
   std::map<std::pair<int, double>, int> tab_index;

@@ -49,7 +49,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("outer_restart", ctypes.c_int)]
+                ("outer_restart", ctypes.c_int), ("tile_rows", ctypes.c_int)]
 
 
 class JobInfo(ctypes.Structure):
@@ -169,13 +169,14 @@ class Opts:
     tol: float = 1e-10
     precond: int = PREC_JACOBI
     precision: int = FP64
-    inner_restart: int = 30
-    inner_tol: float = 1e-5
-    outer_restart: int = 8
+    inner_restart: int = 8
+    inner_tol: float = 1e-3
+    outer_restart: int = 16
+    tile_rows: int = 0
 
     def c(self):
         return SolveOpts(self.restart, self.max_iter, self.tol, self.precond, self.precision,
-                         self.inner_restart, self.inner_tol, self.outer_restart)
+                         self.inner_restart, self.inner_tol, self.outer_restart, self.tile_rows)
 
 
 def level_shift(model, eps):
