@@ -74,6 +74,93 @@ def cpu_baseline(cfg, n_sample):
                        f"sparse LU of the assembled {2 * Ng * Nu}-unknown matrix, {dt:.1f} s")
 
 
+def extras(args, model, cfg):
+    """Secondary measurements (not the headline value)."""
+    import numpy as np
+    import torch
+    from paper_2307_13483_amd import inputs, vdc
+    ex = {}
+    # batched operator on 1024 block vectors at one energy: algorithmic bytes
+    # = 32 B per unknown per vector (x in, y out) + 48 B per unknown once
+    # (three level-shift planes, shared by the vectors)
+    nc = cfg["Ng"] * cfg["Nu"]
+    nv = 1024
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn((nv, nc), dtype=torch.complex128, device="cuda", generator=g)
+    par = [k % 2 for k in range(nv)]
+    cache = {}
+    vdc.matvec_block(model, 2.0, x, par, cache)
+    ms = []
+    for _ in range(3):
+        vdc.matvec_block(model, 2.0, x, par, cache)
+        ms.append(vdc.last_kernel_times()[1])
+    t = min(ms) * 1e-3
+    alg = nv * 32.0 * nc + 48.0 * nc
+    ex["matvec"] = dict(vectors=nv, unknowns_per_vector=nc, kernel_ms=t * 1e3,
+                        achieved_GBs=alg / t / 1e9, frac=alg / t / 1e9 / HBM_PEAK_GBS,
+                        algorithmic_bytes=alg)
+    # single energy, 40 x 40 basis, 2 right-hand sides: latency of one call
+    sc = inputs.single_jobs()
+    m0 = vdc.Model2D(sc["params"], sc["Ng"], sc["Nu"])
+    for plain in (False, True):
+        s = vdc.Solver(m0, sc["jobs"], sc["finals"], vdc.Opts(restart=50, tol=1e-10))
+        s.run(plain=plain)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            s.run(plain=plain)
+        torch.cuda.synchronize()
+        ex["single_energy_plain_ms" if plain else "single_energy_batched_ms"] = \
+            (time.perf_counter() - t0) / 5 * 1e3
+    # uneven batch: 64 instances (own draws, n x n, n in 40..160), both mu,
+    # FP32 inner / FP64 outer vs FP64 on the same jobs
+    insts = inputs.uneven_instances()
+    models = [vdc.Model2D(i["params"], i["Ng"], i["Nu"]) for i in insts]
+    jobs = [(i["eps"], (0, 0), mu, k) for k, i in enumerate(insts) for mu in (0, 1)]
+    res = {}
+    for name, o in (("fp32", vdc.Opts(precision=vdc.FP32_INNER)), ("fp64", vdc.Opts(restart=6))):
+        s = vdc.Solver(models, jobs, cfg["finals"], o)
+        s.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        infos = s.infos()
+        res[name] = (s.T.cpu().numpy().copy(), infos, len(jobs) / dt)
+    T32, i32, r32 = res["fp32"]
+    T64, i64, r64 = res["fp64"]
+    err = [float(np.max(np.abs(T32[k] - T64[k])) / max(1e-300, np.max(np.abs(T64[k]))))
+           for k in range(len(jobs))]
+    ex["uneven_mixed"] = dict(instances=len(insts), solves=len(jobs), fp32_inner_solves_per_s=r32,
+                              fp64_solves_per_s=r64,
+                              converged=sum(i["status"] == 0 for i in i32),
+                              worst_rel_res_fp64_true=max(i["rel_res"] for i in i32),
+                              max_rel_amplitude_diff_vs_fp64=max(err),
+                              median_rel_amplitude_diff_vs_fp64=float(np.median(err)))
+    # adjoint: 120 x 120 base model, 256 energies, v_i = 0, finals 0..5
+    aw = inputs.adjoint_workload()
+    ma = vdc.Model2D(aw["params"], aw["Ng"], aw["Nu"])
+    ajobs = [(float(e), (0, 0), mu) for e in aw["eps"] for mu in (0, 1)]
+    s = vdc.Solver(ma, ajobs, aw["finals"], vdc.Opts(restart=6), want_psi=True)
+    dsig = torch.ones((len(ajobs), len(aw["finals"])), dtype=torch.float64, device="cuda")
+    s.run()
+    s.adjoint(dsig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.adjoint(dsig)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ex["adjoint"] = dict(energies=len(aw["eps"]), right_hand_sides=len(ajobs),
+                         forward_ms=(t1 - t0) * 1e3, adjoint_ms=(t2 - t1) * 1e3,
+                         gradient_evals_per_s=1.0 / (t2 - t0),
+                         adjoint_converged=sum(s.adj_info[k].status == 0 for k in range(len(ajobs))))
+    return ex
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +174,9 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--outer-restart", type=int, default=16)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also time the batched matvec, the single-energy, uneven mixed-precision "
+                         "and adjoint workloads (extra fields)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick restart lengths, inner tolerance and tile rows on a job sample "
                          "before timing (untimed)")
@@ -218,6 +308,8 @@ def main():
                                 speedup_batched_vs_plain=head["value"] / rates[best_m])
         except vdc.VdcError as e:
             out["plain"] = dict(error=str(e))
+    if args.extras:
+        out["extras"] = extras(args, model, cfg)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
     print(json.dumps(out), flush=True)

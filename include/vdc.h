@@ -218,6 +218,19 @@ vdc_status vdc_matvec(vdc_model_t model, double E, int n_vec, const int* parity,
  * pointers, either may be NULL. */
 vdc_status vdc_last_kernel_times(double* ms_tables, double* ms_solver);
 
+/* y = A x on vectors in the solvers' symmetry-block layout: n_vec vectors of
+ * Ng*Nu complex values (device c16 [n_vec][Ng*Nu], n_g-major, n_u fastest),
+ * vector v in block parity[v] (host int[n_vec]): at (n_g, n_u) the value is
+ * the component of state 1 if n_u + parity is even, of state 2 otherwise.
+ * One total energy E for all vectors; its level-shift tables are built first.
+ * Uses the solvers' fused LDS-tiled operator pass, one workgroup per vector.
+ * Kernel times are reported by vdc_last_kernel_times (tables, operator).
+ * Workspace: vdc_matvec_block_workspace_size().  Synchronises the stream. */
+vdc_status vdc_matvec_block_workspace_size(vdc_model_t model, int n_vec, size_t* bytes);
+vdc_status vdc_matvec_block(vdc_model_t model, double E, int n_vec, const int* parity,
+                            const double* x, double* y, void* workspace, size_t ws_bytes,
+                            void* stream);
+
 /* Thread-local text of the last error (never NULL). */
 const char* vdc_last_error(void);
 

@@ -21,6 +21,10 @@ int fgmres_mixed_occupancy(size_t dyn_lds);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t launch_adjoint(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
 int adjoint_occupancy(size_t dyn_lds);
+hipError_t launch_matvec_block_batched(const DevModel* md, const DevTable* tab, const c64* tables,
+                                       const int* par, int n_vec, const c64* x, c64* y, int T,
+                                       size_t dyn_lds, int n_groups, c64* wA, c64* wB,
+                                       hipStream_t s);
 hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
@@ -671,6 +675,100 @@ static size_t matvec_ws(const vdc_model* m, int n_vec) {
 vdc_status vdc_matvec_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
   if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
   *bytes = matvec_ws(m, n_vec);
+  return VDC_OK;
+}
+
+// Batched operator on block vectors (the solvers' layout); tables for E are
+// built into the workspace first, then one fused pass per vector.
+static size_t matvec_block_ws(const vdc_model* m, int n_groups) {
+  const size_t Nc = (size_t)m->dev.Nc;
+  size_t off = 0;
+  off = align256(off + sizeof(DevModel));
+  off = align256(off + sizeof(DevTable));
+  off = align256(off + sizeof(DevGroup));
+  off = align256(off + sizeof(int) * Nc);
+  off = align256(off + sizeof(c64) * kNumF * Nc);   // shift table
+  off = align256(off + sizeof(c64) * 6 * Nc);       // block tables
+  off = align256(off + sizeof(c64) * 2 * Nc * n_groups);
+  return off;
+}
+
+static int matvec_groups(int n_vec) { return std::max(1, std::min(n_vec, cu_count() * 2)); }
+
+vdc_status vdc_matvec_block_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
+  if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  *bytes = matvec_block_ws(m, matvec_groups(n_vec)) + align256(sizeof(int) * std::max(1, n_vec));
+  return VDC_OK;
+}
+
+vdc_status vdc_matvec_block(vdc_model_t m, double E, int n_vec, const int* parity,
+                            const double* x, double* y, void* workspace, size_t ws_bytes,
+                            void* stream) {
+  if (!m) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+  if (n_vec < 0 || !std::isfinite(E)) return fail(VDC_ERR_INVALID_ARG, "bad n_vec or E");
+  if (n_vec == 0) return VDC_OK;
+  if (!parity || !x || !y || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  for (int v = 0; v < n_vec; ++v)
+    if (parity[v] != 0 && parity[v] != 1) return fail(VDC_ERR_INVALID_ARG, "parity must be 0 or 1");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  const int ng = matvec_groups(n_vec);
+  const size_t need = matvec_block_ws(m, ng) + align256(sizeof(int) * n_vec);
+  if (ws_bytes < need) return fail(VDC_ERR_WORKSPACE, "workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const size_t Nc = (size_t)m->dev.Nc;
+  char* ws = static_cast<char*>(workspace);
+  size_t off = 0;
+  DevModel* dmod = reinterpret_cast<DevModel*>(ws + off); off = align256(off + sizeof(DevModel));
+  DevTable* dtab = reinterpret_cast<DevTable*>(ws + off); off = align256(off + sizeof(DevTable));
+  DevGroup* dgrp = reinterpret_cast<DevGroup*>(ws + off); off = align256(off + sizeof(DevGroup));
+  int* dperm = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * Nc);
+  c64* shift = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * Nc);
+  c64* tables = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * 6 * Nc);
+  c64* wA = reinterpret_cast<c64*>(ws + off);
+  c64* wB = wA + Nc * ng;
+  off = align256(off + sizeof(c64) * 2 * Nc * ng);
+  int* dpar = reinterpret_cast<int*>(ws + off);
+  DevGroup g{};
+  g.eps_i = E - 0.5 * (m->dev.omega_g + m->dev.omega_u);
+  g.a_min = -(m->dev.Ng - 1);
+  g.na = m->dev.Ng;
+  g.b_min = -(m->dev.Nu - 1);
+  g.nb = m->dev.Nu;
+  DevTable t{};
+  t.E = E;
+  std::vector<std::pair<double, int>> key(Nc);
+  for (int ia = 0; ia < g.na; ++ia)
+    for (int ib = 0; ib < g.nb; ++ib)
+      key[ia * g.nb + ib] = std::make_pair(m->dev.omega_g * ia + m->dev.omega_u * ib, ia * g.nb + ib);
+  std::sort(key.begin(), key.end());
+  std::vector<int> hperm(Nc);
+  for (size_t q = 0; q < Nc; ++q) hperm[q] = key[q].second;
+  HIPCHK(hipMemcpyAsync(dmod, &m->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dtab, &t, sizeof(DevTable), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dgrp, &g, sizeof(DevGroup), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dperm, hperm.data(), sizeof(int) * Nc, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dpar, parity, sizeof(int) * n_vec, hipMemcpyHostToDevice, s));
+  EventSet ev;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  HIPCHK(launch_level_shift_tables(dmod, dgrp, 1, m->dev.Nc, dperm, dtab, 1, m->dev.Nc, shift,
+                                   tables, nullptr, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  const size_t budget = 96 * 1024;
+  const int T = tile_rows(m->dev.Nu, sizeof(c64), budget);
+  const size_t dyn = T > 0 ? (size_t)(3 * T + 8) * m->dev.Nu * sizeof(c64) : 0;
+  HIPCHK(launch_matvec_block_batched(dmod, dtab, tables, dpar, n_vec,
+                                     reinterpret_cast<const c64*>(x), reinterpret_cast<c64*>(y), T,
+                                     dyn, ng, wA, wB, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t1 = 0.f, t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = t1;
+    g_ms_solver = t2;
+  }
   return VDC_OK;
 }
 

@@ -1,7 +1,7 @@
 // Grid-wide application of A = E - H_ef(E) (Eq. (28)) to a batch of
 // full-layout vectors, one symmetry block each: gather the block, the two
 // stencil phases of op2d.h as separate grid-wide passes, scatter back.
-#include "op2d.h"
+#include "blockops.h"
 
 namespace vdc {
 
@@ -82,6 +82,40 @@ matvec_phase2_kernel(const DevModel* __restrict__ md, const DevTable* __restrict
       make_op<double>(m, jb, tables + tab->offset + (size_t)(jb.parity * 3) * m.Nc);
   const size_t o = (size_t)v * m.Nc;
   yc[o + i] = op_phase2<double>(op, sq, wA + o, wB + o, i, yc[o + i]);
+}
+
+// Batched operator on block vectors: one workgroup per vector, the fused
+// LDS-tiled pass of the solvers (x and y in the block layout, n_g-major,
+// n_u contiguous).  All vectors share one total energy and its tables.
+extern __shared__ __align__(16) char vdc_mv_lds[];
+
+__global__ void __launch_bounds__(kBlock)
+matvec_block_batched_kernel(const DevModel* __restrict__ md, const DevTable* __restrict__ tab,
+                            const c64* __restrict__ tables, const int* __restrict__ par,
+                            int n_vec, const c64* __restrict__ x, c64* __restrict__ y, int T,
+                            c64* wA, c64* wB) {
+  __shared__ double sq[kSqMax + 1];
+  fill_sq<double>(sq);
+  const DevModel& m = *md;
+  DevJob jb{};
+  jb.E = tab->E;
+  for (int v = blockIdx.x; v < n_vec; v += gridDim.x) {
+    jb.parity = par[v];
+    const OpJob<double> op =
+        make_op<double>(m, jb, tables + tab->offset + (size_t)(jb.parity * 3) * m.Nc);
+    const size_t o = (size_t)v * m.Nc;
+    apply_A<double>(op, sq, x + o, 1.0, nullptr, y + o, reinterpret_cast<c64*>(vdc_mv_lds), T,
+                    wA + (size_t)blockIdx.x * m.Nc, wB + (size_t)blockIdx.x * m.Nc);
+  }
+}
+
+hipError_t launch_matvec_block_batched(const DevModel* md, const DevTable* tab, const c64* tables,
+                                       const int* par, int n_vec, const c64* x, c64* y, int T,
+                                       size_t dyn_lds, int n_groups, c64* wA, c64* wB,
+                                       hipStream_t s) {
+  hipLaunchKernelGGL(matvec_block_batched_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, md,
+                     tab, tables, par, n_vec, x, y, T, wA, wB);
+  return hipGetLastError();
 }
 
 hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,

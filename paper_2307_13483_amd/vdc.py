@@ -89,6 +89,8 @@ def lib():
         "vdc_level_shift": (I, [P, I, P, P, P]),
         "vdc_matvec_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
         "vdc_matvec": (I, [P, D, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
+        "vdc_matvec_block_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
+        "vdc_matvec_block": (I, [P, D, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
         "vdc_last_kernel_times": (I, [ctypes.POINTER(D), ctypes.POINTER(D)]),
         "vdc_last_error": (ctypes.c_char_p, []),
         "vdc_version": (ctypes.c_char_p, []),
@@ -205,6 +207,27 @@ def matvec(model, E, x, parity):
 
 PARAM_NAMES = ("omega_g", "omega_u", "kappa1", "kappa2", "lam", "lam1", "lam2", "gap",
                "A1e", "A2e", "A1o", "A2o", "B1e", "B2e", "B1o", "B2o")
+
+
+def matvec_block(model, E, x, parity, ws_cache=None):
+    """vdc_matvec_block: y = A(E) x for block vectors x [n_vec, Ng*Nu] (complex128)."""
+    x = torch.as_tensor(x, dtype=torch.complex128, device="cuda").contiguous()
+    if x.dim() == 1:
+        x = x[None]
+    n_vec = x.shape[0]
+    par = (ctypes.c_int * n_vec)(*[int(p) for p in parity])
+    nb = ctypes.c_size_t()
+    _check(lib().vdc_matvec_block_workspace_size(model.handle, n_vec, ctypes.byref(nb)))
+    if ws_cache is not None and ws_cache.get("bytes", 0) >= nb.value:
+        ws = ws_cache["ws"]
+    else:
+        raw, ws = _aligned_workspace(nb.value, x.device)
+        if ws_cache is not None:
+            ws_cache.update(bytes=nb.value, ws=ws, raw=raw)
+    y = torch.empty_like(x)
+    _check(lib().vdc_matvec_block(model.handle, float(E), n_vec, par, _ptr(x), _ptr(y), _ptr(ws),
+                                  nb.value, _stream_ptr()))
+    return y
 
 
 class Solver:
