@@ -134,7 +134,7 @@ __device__ void sweep_dA(const OpJob<double>& op, const DevJob& jb, const DevMod
         yu = yu + sq[nu + 1] * y[i + 1];
       }
       const c64 zi = z[i], yi = y[i];
-      const double ld = op.lamd[a];
+      const double ld = by_state(op.lamd0, op.lamd1, a);
       const c64 uAz = zi + ld * zg, uBz = zu, uAy = yi + ld * yg, uBy = yu;
       if (pass == 0) {
         const c64 FAA = op.AA[i], FAB = op.AB[i];

@@ -12,6 +12,7 @@
 #include "internal.h"
 #include "blockops.h"
 #include "solve_args.h"
+#include "strip.h"
 
 namespace vdc {
 hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
@@ -21,10 +22,9 @@ int fgmres_mixed_occupancy(size_t dyn_lds);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
 hipError_t launch_adjoint(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
 int adjoint_occupancy(size_t dyn_lds);
-hipError_t launch_matvec_block_batched(const DevModel* md, const DevTable* tab, const c64* tables,
-                                       const int* par, int n_vec, const c64* x, c64* y, int T,
-                                       size_t dyn_lds, int n_groups, c64* wA, c64* wB,
-                                       hipStream_t s);
+hipError_t launch_matvec_strip(const DevModel* md, const DevTable* tab, const c64* tables,
+                               const int* par, int n_vec, const c64* x, c64* y, int Ng, int Nu,
+                               int S, hipStream_t s);
 hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64* tables,
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
@@ -679,8 +679,9 @@ vdc_status vdc_matvec_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
 }
 
 // Batched operator on block vectors (the solvers' layout); tables for E are
-// built into the workspace first, then one fused pass per vector.
-static size_t matvec_block_ws(const vdc_model* m, int n_groups) {
+// built into the workspace first, then one strip sweep per (vector, slab,
+// strip).
+static size_t matvec_block_ws(const vdc_model* m) {
   const size_t Nc = (size_t)m->dev.Nc;
   size_t off = 0;
   off = align256(off + sizeof(DevModel));
@@ -689,15 +690,23 @@ static size_t matvec_block_ws(const vdc_model* m, int n_groups) {
   off = align256(off + sizeof(int) * Nc);
   off = align256(off + sizeof(c64) * kNumF * Nc);   // shift table
   off = align256(off + sizeof(c64) * 6 * Nc);       // block tables
-  off = align256(off + sizeof(c64) * 2 * Nc * n_groups);
   return off;
 }
 
-static int matvec_groups(int n_vec) { return std::max(1, std::min(n_vec, cu_count() * 2)); }
+// Rows per slab: enough wavefronts to fill the chip several times over
+// (about 16 per CU), but slabs of at least 8 rows so that the two halo rows
+// re-read at each slab edge stay a small overhead.
+static int strip_slab_rows(int Ng, int Nu, int n_vec) {
+  const long columns = (long)n_vec * strip_count(Nu);
+  const long want = 16L * cu_count();
+  long slabs = (want + columns - 1) / columns;
+  slabs = std::max(1L, std::min<long>(slabs, Ng / 8 > 0 ? Ng / 8 : 1));
+  return (int)((Ng + slabs - 1) / slabs);
+}
 
 vdc_status vdc_matvec_block_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
   if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
-  *bytes = matvec_block_ws(m, matvec_groups(n_vec)) + align256(sizeof(int) * std::max(1, n_vec));
+  *bytes = matvec_block_ws(m) + align256(sizeof(int) * std::max(1, n_vec));
   return VDC_OK;
 }
 
@@ -712,8 +721,7 @@ vdc_status vdc_matvec_block(vdc_model_t m, double E, int n_vec, const int* parit
     if (parity[v] != 0 && parity[v] != 1) return fail(VDC_ERR_INVALID_ARG, "parity must be 0 or 1");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  const int ng = matvec_groups(n_vec);
-  const size_t need = matvec_block_ws(m, ng) + align256(sizeof(int) * n_vec);
+  const size_t need = matvec_block_ws(m) + align256(sizeof(int) * n_vec);
   if (ws_bytes < need) return fail(VDC_ERR_WORKSPACE, "workspace too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const size_t Nc = (size_t)m->dev.Nc;
@@ -725,9 +733,6 @@ vdc_status vdc_matvec_block(vdc_model_t m, double E, int n_vec, const int* parit
   int* dperm = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * Nc);
   c64* shift = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * Nc);
   c64* tables = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * 6 * Nc);
-  c64* wA = reinterpret_cast<c64*>(ws + off);
-  c64* wB = wA + Nc * ng;
-  off = align256(off + sizeof(c64) * 2 * Nc * ng);
   int* dpar = reinterpret_cast<int*>(ws + off);
   DevGroup g{};
   g.eps_i = E - 0.5 * (m->dev.omega_g + m->dev.omega_u);
@@ -754,12 +759,9 @@ vdc_status vdc_matvec_block(vdc_model_t m, double E, int n_vec, const int* parit
   HIPCHK(launch_level_shift_tables(dmod, dgrp, 1, m->dev.Nc, dperm, dtab, 1, m->dev.Nc, shift,
                                    tables, nullptr, s));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
-  const size_t budget = 96 * 1024;
-  const int T = tile_rows(m->dev.Nu, sizeof(c64), budget);
-  const size_t dyn = T > 0 ? (size_t)(3 * T + 8) * m->dev.Nu * sizeof(c64) : 0;
-  HIPCHK(launch_matvec_block_batched(dmod, dtab, tables, dpar, n_vec,
-                                     reinterpret_cast<const c64*>(x), reinterpret_cast<c64*>(y), T,
-                                     dyn, ng, wA, wB, s));
+  const int S = strip_slab_rows(m->dev.Ng, m->dev.Nu, n_vec);
+  HIPCHK(launch_matvec_strip(dmod, dtab, tables, dpar, n_vec, reinterpret_cast<const c64*>(x),
+                             reinterpret_cast<c64*>(y), m->dev.Ng, m->dev.Nu, S, s));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
   HIPCHK(hipStreamSynchronize(s));
   if (ev.ok) {

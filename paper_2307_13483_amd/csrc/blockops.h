@@ -159,7 +159,7 @@ __device__ inline R matvec_tiled(const OpJob<R>& op, const R* sq,
       if (row + 1 < Ng) zg = zg + sq[row + 1] * zr[nu + Nu];
       if (nu > 0) zu = sq[nu] * zr[nu - 1];
       if (nu + 1 < Nu) zu = zu + sq[nu + 1] * zr[nu + 1];
-      const C uA = zr[nu] + op.lamd[a] * zg;
+      const C uA = zr[nu] + by_state(op.lamd0, op.lamd1, a) * zg;
       const int i = row * Nu + nu;
       const C fab = op.AB[i];
       wa[(row - g0 + 1) * Nu + nu] = op.AA[i] * uA + fab * zu;
@@ -189,8 +189,8 @@ __device__ inline R matvec_tiled(const OpJob<R>& op, const R* sq,
         zu = zu + sq[nu + 1] * zr[nu + 1];
         bu = bu + sq[nu + 1] * br[nu + 1];
       }
-      const R d = R(op.dbase[a] - op.omega_g * row - op.omega_u * nu);
-      C out = d * zr[nu] - op.kappa[a] * zg - op.lam * zu - ar[nu] - op.lamd[a] * ag - bu;
+      const R d = R(by_state(op.dbase0, op.dbase1, a) - op.omega_g * row - op.omega_u * nu);
+      C out = d * zr[nu] - by_state(op.kappa0, op.kappa1, a) * zg - op.lam * zu - ar[nu] - by_state(op.lamd0, op.lamd1, a) * ag - bu;
       if (bsub) out = bsub[row * Nu + nu] - out;
       y[row * Nu + nu] = out;
       acc[0] += norm2(out);

@@ -1,7 +1,8 @@
 // Grid-wide application of A = E - H_ef(E) (Eq. (28)) to a batch of
 // full-layout vectors, one symmetry block each: gather the block, the two
 // stencil phases of op2d.h as separate grid-wide passes, scatter back.
-#include "blockops.h"
+#include "op2d.h"
+#include "strip.h"
 
 namespace vdc {
 
@@ -84,37 +85,45 @@ matvec_phase2_kernel(const DevModel* __restrict__ md, const DevTable* __restrict
   yc[o + i] = op_phase2<double>(op, sq, wA + o, wB + o, i, yc[o + i]);
 }
 
-// Batched operator on block vectors: one workgroup per vector, the fused
-// LDS-tiled pass of the solvers (x and y in the block layout, n_g-major,
-// n_u contiguous).  All vectors share one total energy and its tables.
-extern __shared__ __align__(16) char vdc_mv_lds[];
-
-__global__ void __launch_bounds__(kBlock)
-matvec_block_batched_kernel(const DevModel* __restrict__ md, const DevTable* __restrict__ tab,
-                            const c64* __restrict__ tables, const int* __restrict__ par,
-                            int n_vec, const c64* __restrict__ x, c64* __restrict__ y, int T,
-                            c64* wA, c64* wB) {
+// Batched operator on block vectors (n_g-major, n_u contiguous), all at one
+// total energy.  One wavefront per (vector, row slab, column strip), four
+// wavefronts per workgroup; after the sqrt table is in LDS the sweep of
+// strip.h needs no barrier, so a wavefront past the end simply returns.
+__global__ void __launch_bounds__(256, 4)
+matvec_strip_kernel(const DevModel* __restrict__ md, const DevTable* __restrict__ tab,
+                    const c64* __restrict__ tables, const int* __restrict__ par, int n_vec,
+                    const c64* __restrict__ x, c64* __restrict__ y, int S, int n_slabs,
+                    int n_strips) {
   __shared__ double sq[kSqMax + 1];
   fill_sq<double>(sq);
+  __syncthreads();
+  const long task = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const long per_vec = (long)n_slabs * n_strips;
+  if (task >= (long)n_vec * per_vec) return;
+  const int v = (int)(task / per_vec);
+  const int rem = (int)(task - (long)v * per_vec);
+  const int slab = rem / n_strips, strip = rem - slab * n_strips;
   const DevModel& m = *md;
   DevJob jb{};
   jb.E = tab->E;
-  for (int v = blockIdx.x; v < n_vec; v += gridDim.x) {
-    jb.parity = par[v];
-    const OpJob<double> op =
-        make_op<double>(m, jb, tables + tab->offset + (size_t)(jb.parity * 3) * m.Nc);
-    const size_t o = (size_t)v * m.Nc;
-    apply_A<double>(op, sq, x + o, 1.0, nullptr, y + o, reinterpret_cast<c64*>(vdc_mv_lds), T,
-                    wA + (size_t)blockIdx.x * m.Nc, wB + (size_t)blockIdx.x * m.Nc);
-  }
+  jb.parity = par[v];
+  const OpJob<double> op =
+      make_op<double>(m, jb, tables + tab->offset + (size_t)(jb.parity * 3) * m.Nc);
+  const size_t o = (size_t)v * m.Nc;
+  const int g0 = slab * S, g1 = min(m.Ng, g0 + S);
+  strip_sweep<double>(op, sq, x + o, 1.0, nullptr, y + o, nullptr, strip, g0, g1);
 }
 
-hipError_t launch_matvec_block_batched(const DevModel* md, const DevTable* tab, const c64* tables,
-                                       const int* par, int n_vec, const c64* x, c64* y, int T,
-                                       size_t dyn_lds, int n_groups, c64* wA, c64* wB,
-                                       hipStream_t s) {
-  hipLaunchKernelGGL(matvec_block_batched_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, md,
-                     tab, tables, par, n_vec, x, y, T, wA, wB);
+hipError_t launch_matvec_strip(const DevModel* md, const DevTable* tab, const c64* tables,
+                               const int* par, int n_vec, const c64* x, c64* y, int Ng, int Nu,
+                               int S, hipStream_t s) {
+  if (S < 1) return hipErrorInvalidValue;
+  const int n_slabs = (Ng + S - 1) / S, n_strips = strip_count(Nu);
+  const long tasks = (long)n_vec * n_slabs * n_strips;
+  const long blocks = (tasks + 3) / 4;
+  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(matvec_strip_kernel, dim3((unsigned)blocks), dim3(256), 0, s, md, tab, tables,
+                     par, n_vec, x, y, S, n_slabs, n_strips);
   return hipGetLastError();
 }
 

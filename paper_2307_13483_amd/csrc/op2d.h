@@ -43,13 +43,19 @@ template <typename R>
 struct OpJob {
   using C = typename CT<R>::C;
   int Ng, Nu, Nc, p;
-  double dbase[2];         // E - E_d - (w_g + w_u)/2, by active state (FP64)
+  double dbase0, dbase1;   // E - E_d - (w_g + w_u)/2, by active state (FP64)
   double omega_g, omega_u;
-  R kappa[2], lamd[2], lam;
+  R kappa0, kappa1, lamd0, lamd1, lam;
   const C* AA;             // level-shift planes of this job's block
   const C* AB;
   const C* BB;
 };
+
+// Per-state coefficient by active state a in {0, 1}.  The pairs are kept as
+// separate scalars and chosen by a select: a runtime index into an array
+// member would keep the whole struct in private (scratch) memory.
+template <typename T>
+__device__ inline T by_state(T v0, T v1, int a) { return a ? v1 : v0; }
 
 template <typename R>
 __device__ inline OpJob<R> make_op(const DevModel& m, const DevJob& jb,
@@ -60,14 +66,14 @@ __device__ inline OpJob<R> make_op(const DevModel& m, const DevJob& jb,
   op.Nc = m.Nc;
   op.p = jb.parity;
   const double half = 0.5 * (m.omega_g + m.omega_u);
-  op.dbase[0] = jb.E - m.E1 - half;
-  op.dbase[1] = jb.E - m.E2 - half;
+  op.dbase0 = jb.E - m.E1 - half;
+  op.dbase1 = jb.E - m.E2 - half;
   op.omega_g = m.omega_g;
   op.omega_u = m.omega_u;
-  op.kappa[0] = R(m.kappa[0]);
-  op.kappa[1] = R(m.kappa[1]);
-  op.lamd[0] = R(m.lamd[0]);
-  op.lamd[1] = R(m.lamd[1]);
+  op.kappa0 = R(m.kappa[0]);
+  op.kappa1 = R(m.kappa[1]);
+  op.lamd0 = R(m.lamd[0]);
+  op.lamd1 = R(m.lamd[1]);
   op.lam = R(m.lam);
   op.AA = table_block;
   op.AB = table_block + m.Nc;
@@ -105,9 +111,9 @@ __device__ inline void op_phase1(const OpJob<R>& op, const R* sq, const typename
   if (ng + 1 < op.Ng) zg = zg + sq[ng + 1] * load_z<R>(v, dinv, i + op.Nu);
   if (nu > 0) zu = sq[nu] * load_z<R>(v, dinv, i - 1);
   if (nu + 1 < op.Nu) zu = zu + sq[nu + 1] * load_z<R>(v, dinv, i + 1);
-  const R d = R(op.dbase[a] - op.omega_g * ng - op.omega_u * nu);
-  yloc = d * z - op.kappa[a] * zg - op.lam * zu;
-  const C uA = z + op.lamd[a] * zg;
+  const R d = R(by_state(op.dbase0, op.dbase1, a) - op.omega_g * ng - op.omega_u * nu);
+  yloc = d * z - by_state(op.kappa0, op.kappa1, a) * zg - op.lam * zu;
+  const C uA = z + by_state(op.lamd0, op.lamd1, a) * zg;
   const C uB = zu;
   const C fab = op.AB[i];
   wA = op.AA[i] * uA + fab * uB;
@@ -128,7 +134,7 @@ __device__ inline typename CT<R>::C op_phase2(const OpJob<R>& op, const R* sq,
   if (ng + 1 < op.Ng) g = g + sq[ng + 1] * wA[i + op.Nu];
   if (nu > 0) u = sq[nu] * wB[i - 1];
   if (nu + 1 < op.Nu) u = u + sq[nu + 1] * wB[i + 1];
-  return yloc - wA[i] - op.lamd[a] * g - u;
+  return yloc - wA[i] - by_state(op.lamd0, op.lamd1, a) * g - u;
 }
 
 // Diagonal of A at point i (the M^{dg} preconditioner of Sec. III.B):
@@ -140,12 +146,12 @@ __device__ inline typename CT<R>::C op_diag(const OpJob<R>& op, int i) {
   using C = typename CT<R>::C;
   const int ng = i / op.Nu, nu = i - ng * op.Nu;
   const int a = (nu + op.p) & 1;
-  const R d = R(op.dbase[a] - op.omega_g * ng - op.omega_u * nu);
+  const R d = R(by_state(op.dbase0, op.dbase1, a) - op.omega_g * ng - op.omega_u * nu);
   C s = op.AA[i];
   C sg = cz<R>();
   if (ng > 0) sg = R(0.5 * ng) * op.AA[i - op.Nu];
   if (ng + 1 < op.Ng) sg = sg + R(0.5 * (ng + 1)) * op.AA[i + op.Nu];
-  s = s + (op.lamd[a] * op.lamd[a]) * sg;
+  s = s + (by_state(op.lamd0, op.lamd1, a) * by_state(op.lamd0, op.lamd1, a)) * sg;
   if (nu > 0) s = s + R(0.5 * nu) * op.BB[i - 1];
   if (nu + 1 < op.Nu) s = s + R(0.5 * (nu + 1)) * op.BB[i + 1];
   return C{d - s.x, -s.y};
