@@ -63,11 +63,13 @@ struct StripState {
 
 // y[i] = A (vscale dinv v) [i] for rows g0 .. g1-1 of the wavefront's strip
 // (bsub given: y = bsub - A(...)); returns the lane's sum of |y|^2 over the
-// elements it wrote.  sq holds sqrt(n/2) for n = 0..kSqMax (LDS).  Control flow is uniform across the wavefront except
+// elements it wrote.  sq holds sqrt(n/2) for n = 0..kSqMax (LDS).  z is
+// requested ZA rows ahead, the level-shift tables TA rows ahead (more rows
+// in flight against more registers).  Control flow is uniform across the wavefront except
 // for the masked store.  Every load is issued unconditionally from a clamped
 // address and masked afterwards, so the loop body is straight-line code and
 // the loads for the rows ahead stay in flight across steps.
-template <typename R>
+template <typename R, int ZA = 2, int TA = 1>
 __device__ inline R strip_sweep(const OpJob<R>& op, const R* sq,
                                 const typename CT<R>::C* __restrict__ v,
                                 R vscale, const typename CT<R>::C* __restrict__ dinv,
@@ -109,11 +111,10 @@ __device__ inline R strip_sweep(const OpJob<R>& op, const R* sq,
   s.wam = s.wac = s.wbc = s.ylc = cz<R>();
   s.sqm = sqg(g0 - 2);
   s.sqc = sqg(g0 - 1);
-  // Prefetch slots.  z comes from HBM and is requested kZAhead rows ahead
-  // (slot k of pz serves the steps j = r - g0 + 1 with j % kZAhead == k);
-  // the tables are shared by many vectors, mostly hit in L2 and are
-  // requested kTAhead rows ahead.
-  constexpr int kZAhead = 2, kTAhead = 1;
+  // Prefetch slots: slot k of pz serves the steps j = r - g0 + 1 with
+  // j % ZA == k, likewise pt.  The loop below is unrolled by 4.
+  static_assert(4 % ZA == 0 && 4 % TA == 0, "prefetch distances must divide the unroll");
+  constexpr int kZAhead = ZA, kTAhead = TA;
   C pz[kZAhead];
   for (int k = 0; k < kZAhead; ++k) pz[k] = load_row(g0 + k);
   StripTab<R> pt[kTAhead];
