@@ -18,10 +18,9 @@ levelshift   widths, the level-shift integral transform, Eqs. (19), (20), (22)
 model2d      the generalized two-state, two-mode model of Sec. II.C assembled
              as an explicit sparse matrix, Eqs. (18), (23), (25), (28)
 solvers      sparse/dense LU and a textbook GMRES(m) of Sec. III.A
+precond      block-diagonal sections of A as preconditioners, Sec. III.B
 observables  T-matrix and cross sections, Eqs. (15), (16), (24)
 adjoint      d(loss)/d(parameters) by explicit derivative matrices and LU
-poly         the many-state, many-mode polynomial model (Sec. III.C, CO2
-             paragraph) assembled the same way
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py``; none is "parity unpinned".

@@ -5,8 +5,8 @@
 * gmres: textbook restarted GMRES(m) of Saad and Schultz as described in
   Sec. III.A: Arnoldi with modified Gram-Schmidt builds A V_n = V_{n+1} H_n,
   the (n+1) x n least-squares problem for y_n is solved by Givens rotations,
-  x_n = x_0 + M^{-1} V_n y_n (right preconditioning by M, Sec. III.B with the
-  diagonal blocks of A).  Stopping rule of Sec. III: ||b - A x|| < tol ||b||,
+  x_n = x_0 + M^{-1} V_n y_n (right preconditioning by M, Sec. III.B: the
+  diagonal of A, or any block-diagonal section of it given as a solve).  Stopping rule of Sec. III: ||b - A x|| < tol ||b||,
   checked on the true residual at the end of each cycle.
 """
 import numpy as np
@@ -22,8 +22,9 @@ def lu_solve(A, b):
     return sla.lu_solve((lu, piv), np.asarray(b, dtype=np.complex128))
 
 
-def gmres(A, b, m=50, tol=1e-10, max_iter=20000, dinv=None, history=False):
-    """Restarted GMRES(m), x0 = 0, right preconditioner z = dinv * v.
+def gmres(A, b, m=50, tol=1e-10, max_iter=20000, dinv=None, history=False, psolve=None):
+    """Restarted GMRES(m), x0 = 0, right preconditioner z = M^{-1} v: psolve(v)
+    when given, else dinv * v (dinv = 1 without either).
 
     Returns (x, info) with info = dict(iters, restarts, rel_res, converged[, hist]).
     """
@@ -31,6 +32,8 @@ def gmres(A, b, m=50, tol=1e-10, max_iter=20000, dinv=None, history=False):
     n = b.size
     if dinv is None:
         dinv = np.ones(n, dtype=np.complex128)
+    if psolve is None:
+        psolve = (lambda v: dinv * v)
     bnorm = np.linalg.norm(b)
     x = np.zeros(n, dtype=np.complex128)
     if bnorm == 0.0:
@@ -49,7 +52,7 @@ def gmres(A, b, m=50, tol=1e-10, max_iter=20000, dinv=None, history=False):
         V[0] = r / beta
         k = 0
         for j in range(m):
-            w = matvec(dinv * V[j])
+            w = matvec(psolve(V[j]))
             for i in range(j + 1):                       # modified Gram-Schmidt
                 H[i, j] = np.vdot(V[i], w)
                 w = w - H[i, j] * V[i]
@@ -81,7 +84,7 @@ def gmres(A, b, m=50, tol=1e-10, max_iter=20000, dinv=None, history=False):
                 break
             V[j + 1] = w / hnext
         y = sla.solve_triangular(H[:k, :k], g[:k], lower=False)
-        x = x + dinv * (V[:k].T @ y)
+        x = x + psolve(V[:k].T @ y)
         r = b - matvec(x)
         beta = np.linalg.norm(r)
         restarts += 1
