@@ -74,6 +74,11 @@ def cpu_baseline(cfg, n_sample):
                        f"sparse LU of the assembled {2 * Ng * Nu}-unknown matrix, {dt:.1f} s")
 
 
+PRECONDS = {"jacobi": 1, "block": 2}
+PREC_NAMES = {"jacobi": "diagonal preconditioner",
+              "block": "column-block preconditioner (n_u columns, 8 rows of n_g, LDL^T)"}
+
+
 def extras(args, model, cfg):
     """Secondary measurements (not the headline value)."""
     import numpy as np
@@ -174,6 +179,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--outer-restart", type=int, default=16)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--precond", choices=sorted(PRECONDS), default="block",
+                    help="right preconditioner: the diagonal of A or its column blocks")
     ap.add_argument("--extras", type=int, default=1,
                     help="also time the batched matvec, the single-energy, uneven mixed-precision "
                          "and adjoint workloads (extra fields)")
@@ -215,7 +222,8 @@ def main():
         prec = vdc.FP64 if precision == "fp64" else vdc.FP32_INNER
         opts = vdc.Opts(restart=args.restart, tol=1e-10, precision=prec,
                         inner_restart=args.inner_restart, inner_tol=args.inner_tol,
-                        outer_restart=args.outer_restart, tile_rows=args.tile_rows)
+                        outer_restart=args.outer_restart, tile_rows=args.tile_rows,
+                        precond=PRECONDS[args.precond])
         if args.autotune:
             from paper_2307_13483_amd.autotune import autotune
             opts, _ = autotune([model], cfg["jobs"], cfg["finals"], base=opts)
@@ -271,9 +279,10 @@ def main():
         "config": {"workload": "2D generalized model, batched energies x v_i x mu",
                    "basis": f"{Ng}x{Nu} per state", "unknowns": 2 * nc,
                    "right_hand_sides": head["n_jobs"], "energies": args.energies,
-                   "solver": (f"GMRES({opts.restart}) Jacobi" if args.precision == "fp64" else
+                   "solver": (f"GMRES({opts.restart}), {PREC_NAMES[args.precond]}"
+                              if args.precision == "fp64" else
                               f"FGMRES({opts.outer_restart}) FP64 outer, GMRES({opts.inner_restart}) "
-                              f"FP32 inner to {opts.inner_tol:g}, Jacobi"),
+                              f"FP32 inner to {opts.inner_tol:g}, {PREC_NAMES[args.precond]}"),
                    "tuned": head["chosen"],
                    "tol": "1e-10 relative FP64 true residual",
                    "precision": args.precision},

@@ -88,7 +88,11 @@ typedef struct {
   int model;
 } vdc_job;
 
-typedef enum { VDC_PREC_NONE = 0, VDC_PREC_JACOBI = 1 } vdc_precond;
+/* Right preconditioners (Sec. III.B), each a block-diagonal section of A:
+ * JACOBI its diagonal; BLOCK the blocks of one n_u column and 8 consecutive
+ * n_g (the paper's M^u cut into segments), factored once per job by complex
+ * symmetric LDL^T; a block with a vanishing pivot falls back to its diagonal. */
+typedef enum { VDC_PREC_NONE = 0, VDC_PREC_JACOBI = 1, VDC_PREC_BLOCK = 2 } vdc_precond;
 typedef enum {
   VDC_FP64 = 0,              /* restarted GMRES in complex FP64                  */
   VDC_FP32_INNER = 1         /* FGMRES: FP64 outer (true residual, Givens,

@@ -215,7 +215,7 @@ adjoint_kernel(SolveArgs a) {
     const c64* tab = a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc;
     const OpJob<double> op = make_op<double>(md, jb, tab);
     const int Nc = md.Nc, out = jb.out;
-    fp64_prepare(op, s, a.precond);
+    fp64_prepare(op, L.S.sq, s, a.precond);
     const c64* psi = a.psi_in + (size_t)out * a.psi_ld;
     for (int i = tid; i < Nc; i += kBlock) {
       const int act = ((i % md.Nu) + jb.parity) & 1;
@@ -244,7 +244,8 @@ adjoint_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    const BlockSolve r = gmres_fp64_block(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT);
+    const BlockSolve r = gmres_fp64_block(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT,
+                                          a.precond);
     __syncthreads();
     // -zeta^T (dA/dp) psi
     sweep_dA(op, jb, md, L.S.sq, z, s.x, tab, L.redA, G);

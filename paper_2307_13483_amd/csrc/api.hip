@@ -132,7 +132,8 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (o->restart < 1 || o->restart > kMaxRestart) return fail(VDC_ERR_INVALID_ARG, "restart must be 1..128");
   if (o->max_iter < 1) return fail(VDC_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (!(o->tol > 0.0)) return fail(VDC_ERR_INVALID_ARG, "tol must be > 0");
-  if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI)
+  if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI &&
+      o->precond != VDC_PREC_BLOCK)
     return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
   if (o->precision != VDC_FP64 && o->precision != VDC_FP32_INNER)
     return fail(VDC_ERR_INVALID_ARG, "unknown precision");
@@ -270,13 +271,13 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   P.ncap = (size_t)((P.max_nc + 63) / 64) * 64;
   if (mixed) {
     // FP64: Vout (m+1), Z (m), x, b, w, wA, wB, R_out, R_in;
-    // FP32 (in c64 units): Vin (m_in+1), dinv, w, wA, wB
+    // FP32 (in c64 units): Vin (m_in+1) and the inner solver's vectors
     const int mi = o->inner_restart;
     P.slot_elems = (size_t)(2 * m + 6) * P.ncap + (size_t)(m + 1) * m + (size_t)(mi + 1) * mi +
-                   ((size_t)(mi + 5) * P.ncap + 1) / 2;
+                   ((size_t)(mi + 1 + kFp32SlotVectors) * P.ncap + 1) / 2;
   } else {
-    // V (m+1), x, b, dinv, w, wA, wB, R (+ the forward solution for the adjoint)
-    P.slot_elems = (size_t)(m + 1 + 6) * P.ncap + (size_t)(m + 1) * m;
+    // V (m+1), the solver's vectors, R (+ the forward solution for the adjoint)
+    P.slot_elems = (size_t)(m + 1 + kFp64SlotVectors) * P.ncap + (size_t)(m + 1) * m;
     if (plain) P.slot_elems += plain_extra_elems(P.ncap, m);
     if (adjoint) P.slot_elems += P.ncap;
   }

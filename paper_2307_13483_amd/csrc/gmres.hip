@@ -3,8 +3,9 @@
 //
 // Each workgroup pops jobs from a device counter (the host orders the job
 // array longest-first), then for its job:
-//   1. the diagonal preconditioner 1/diag(A) (Sec. III.B) and the right-hand
-//      side Phi^{v_i mu_i} (Eq. (25)) in the job's symmetry block;
+//   1. the preconditioner (Sec. III.B: 1/diag(A), or the LDL^T factors of the
+//      column blocks of segprec.h) and the right-hand side Phi^{v_i mu_i}
+//      (Eq. (25)) in the job's symmetry block;
 //   2. restarted GMRES(m) with right preconditioning (krylov.h), then
 //      x += M^{-1} V y and the FP64 true residual b - A x, which decides
 //      convergence (stopping rule of Sec. III);
@@ -34,7 +35,7 @@ gmres_fp64_kernel(SolveArgs a) {
     const DevTable tb = a.tabs[jb.table];
     const OpJob<double> op = make_op<double>(
         md, jb, a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc);
-    fp64_prepare(op, s, a.precond);
+    fp64_prepare(op, L.sq, s, a.precond);
     __syncthreads();
     // right-hand side Phi^{v_i mu_i} in the block (<= 5 nonzeros)
     if (tid == 0) {
@@ -43,7 +44,8 @@ gmres_fp64_kernel(SolveArgs a) {
       for (int q = 0; q < n; ++q) s.b[e[q].g * md.Nu + e[q].u] = c64{e[q].val, 0.0};
     }
     __syncthreads();
-    const BlockSolve r = gmres_fp64_block(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT);
+    const BlockSolve r =
+        gmres_fp64_block(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT, a.precond);
     __syncthreads();
     finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);

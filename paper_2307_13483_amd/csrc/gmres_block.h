@@ -1,10 +1,12 @@
 // Restarted GMRES(m) in complex FP64 on one symmetry block, run by a whole
-// workgroup (Sec. III.A, right diagonal preconditioning of Sec. III.B):
-// cycles of krylov_cycle, x += M^{-1} V y, and the FP64 true residual b - A x
-// deciding convergence (the stopping rule of Sec. III).  Shared by the
-// forward solver and the adjoint (transposed) solve: A^T = A.
+// workgroup (Sec. III.A, right preconditioning of Sec. III.B by the diagonal
+// of A or by its column blocks, segprec.h): cycles of krylov_cycle,
+// x += M^{-1} V y, and the FP64 true residual b - A x deciding convergence
+// (the stopping rule of Sec. III).  Shared by the forward solver and the
+// adjoint (transposed) solve: A^T = A, and M^T = M for both preconditioners.
 #pragma once
 #include "krylov.h"
+#include "segprec.h"
 
 namespace vdc {
 
@@ -15,9 +17,11 @@ struct Fp64Lds {
   int job;
 };
 
-// Per-workgroup vectors of the FP64 solver (leading dimension ld).
+// Per-workgroup vectors of the FP64 solver (leading dimension ld): dinv is
+// 1/diag(A) for the diagonal preconditioner and D^{-1} of the block factors
+// (with l1, l2) for the block one; zt holds M^{-1} of the vector in work.
 struct Fp64Slot {
-  c64 *V, *x, *b, *dinv, *w, *wA, *wB, *Rm, *extra;
+  c64 *V, *x, *b, *dinv, *w, *wA, *wB, *l1, *l2, *zt, *Rm, *extra;
 };
 
 __device__ inline Fp64Slot fp64_slot(c64* slot, size_t ld, int m) {
@@ -29,7 +33,10 @@ __device__ inline Fp64Slot fp64_slot(c64* slot, size_t ld, int m) {
   s.w = s.dinv + ld;
   s.wA = s.w + ld;
   s.wB = s.wA + ld;
-  s.Rm = s.wB + ld;
+  s.l1 = s.wB + ld;
+  s.l2 = s.l1 + ld;
+  s.zt = s.l2 + ld;
+  s.Rm = s.zt + ld;
   s.extra = s.Rm + (size_t)(m + 1) * m;
   return s;
 }
@@ -39,10 +46,14 @@ struct BlockSolve {
   double bnorm, beta, passes;
 };
 
-// dinv = 1/diag(A) (or 1), x = 0, b = 0 over the block (own elements).
-__device__ inline void fp64_prepare(const OpJob<double>& op, const Fp64Slot& s, int precond) {
+// The preconditioner (dinv = 1/diag(A) or 1, or the block factors) and
+// x = 0, b = 0 over the block.  No barrier.
+__device__ inline void fp64_prepare(const OpJob<double>& op, const double* sq, const Fp64Slot& s,
+                                    int precond) {
+  if (precond == VDC_PREC_BLOCK) seg_factor<double>(op, sq, SegFactor<double>{s.l1, s.l2, s.dinv});
   for (int i = threadIdx.x; i < op.Nc; i += kBlock) {
-    s.dinv[i] = precond ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
+    if (precond != VDC_PREC_BLOCK)
+      s.dinv[i] = precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
     s.x[i] = c64{0.0, 0.0};
     s.b[i] = c64{0.0, 0.0};
   }
@@ -57,12 +68,19 @@ extern __shared__ __align__(16) char vdc_tile_lds[];
 // norm and copied to V_0), each cycle of k steps cycle_passes(k) + k + 9:
 // x update k + 3 (basis, dinv, x in; x out) and the true residual b - A x
 // written into V_0 in the operator's pass (x, 3 table planes, b in; V_0 out).
+// The block preconditioner adds 4 passes to every step (M^{-1} reads the
+// vector and three factor planes and writes zt, the operator reads zt but no
+// dinv), 4 to the x update (sum written to zt and read back with the factor,
+// x in and out) and 3 to the setup (factor: one more table plane, three
+// planes written instead of one).
 __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& op,
                                               const Fp64Slot& s, size_t ld, int m, double tol,
-                                              int max_iter, int T) {
+                                              int max_iter, int T, int precond) {
   const int Nc = op.Nc;
+  const bool blk = precond == VDC_PREC_BLOCK;
+  const SegFactor<double> fac{s.l1, s.l2, s.dinv};
   c64* lds = reinterpret_cast<c64*>(vdc_tile_lds);
-  BlockSolve r{VDC_NOT_CONVERGED, 0, 0, 0.0, 0.0, 8.0};
+  BlockSolve r{VDC_NOT_CONVERGED, 0, 0, 0.0, 0.0, blk ? 11.0 : 8.0};
   r.bnorm = sqrt(norm_sq<double>(s.b, Nc, L.red));
   r.beta = r.bnorm;
   if (!(r.bnorm > 0.0) || !isfinite(r.bnorm)) {
@@ -72,7 +90,12 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
   }
   for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = s.b[i];
   auto apply = [&](int j, double sc, c64* out) {
-    apply_A<double>(op, L.sq, s.V + (size_t)j * ld, sc, s.dinv, out, lds, T, s.wA, s.wB);
+    if (blk) {
+      seg_apply<double>(fac, op.Ng, op.Nu, s.V + (size_t)j * ld, sc, s.zt, false);
+      apply_A<double>(op, L.sq, s.zt, 1.0, nullptr, out, lds, T, s.wA, s.wB);
+    } else {
+      apply_A<double>(op, L.sq, s.V + (size_t)j * ld, sc, s.dinv, out, lds, T, s.wA, s.wB);
+    }
   };
   for (;;) {
     if (threadIdx.x == 0) {
@@ -82,8 +105,14 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
     __syncthreads();
     const CycleResult cr = krylov_cycle<double>(L.K, L.red, s.V, ld, Nc, m, tol * r.bnorm,
                                                 max_iter, r.iters, s.Rm, apply);
-    r.passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 9.0;
-    update_x<double>(s.V, ld, cr.k, L.K.y, L.K.vs, s.dinv, s.x, Nc);
+    r.passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 9.0 + (blk ? 4.0 * cr.k + 4.0 : 0.0);
+    if (blk) {
+      // zt = V y (own elements), then x += M^{-1} zt (block ownership)
+      update_x<double>(s.V, ld, cr.k, L.K.y, L.K.vs, nullptr, s.zt, Nc, true);
+      seg_apply<double>(fac, op.Ng, op.Nu, s.zt, 1.0, s.x, true);
+    } else {
+      update_x<double>(s.V, ld, cr.k, L.K.y, L.K.vs, s.dinv, s.x, Nc);
+    }
     // true residual b - A x, written into V_0 (the next cycle's start)
     r.beta = sqrt(residual_A<double>(op, L.sq, s.x, s.b, s.V, lds, T, s.wA, s.wB, L.red));
     ++r.cycles;

@@ -14,6 +14,11 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr int kBlock = 1024;      // threads per workgroup of the persistent solver
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxRestart = 128;
+// Slot vectors of length ncap besides the basis: FP64 solver (x, b, dinv, w,
+// wA, wB and the block factors l1, l2 with zt), FP32 inner solver (dinv, w,
+// wA, wB, l1, l2, zt).
+constexpr int kFp64SlotVectors = 9;
+constexpr int kFp32SlotVectors = 7;
 constexpr int kMaxFinal = 64;
 constexpr int kNumF = 6;          // level-shift functions per energy
 // Far-field expansion of the transform's node sum: clusters of kClus

@@ -180,10 +180,11 @@ __device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<
 
 // x += dinv * sum_l (vs[l] V_l) y_l (own elements; dinv, vs may be null), y from
 // L.y (FP64), in precision R: reads the k basis vectors, dinv and x once.
+// With assign, x = dinv * sum ... instead (x not read).
 template <typename R>
 __device__ inline void update_x(const typename CT<R>::C* V, size_t ld, int k, const c64* y,
                                 const R* vs, const typename CT<R>::C* dinv,
-                                typename CT<R>::C* x, int Nc) {
+                                typename CT<R>::C* x, int Nc, bool assign = false) {
   using C = typename CT<R>::C;
   for (int i = threadIdx.x; i < Nc; i += kBlock) {
     C s = cz<R>();
@@ -200,7 +201,8 @@ __device__ inline void update_x(const typename CT<R>::C* V, size_t ld, int k, co
     for (; l < k; ++l)
       s = s + V[(size_t)l * ld + i] * C{R(y[l].x) * (vs ? vs[l] : R(1)),
                                         R(y[l].y) * (vs ? vs[l] : R(1))};
-    x[i] = x[i] + (dinv ? dinv[i] * s : s);
+    const C t = dinv ? dinv[i] * s : s;
+    x[i] = assign ? t : x[i] + t;
   }
 }
 

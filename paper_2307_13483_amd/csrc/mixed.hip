@@ -1,7 +1,8 @@
 // Mixed precision on chip: flexible GMRES in complex FP64 (outer) whose
 // variable right preconditioner is one cycle of GMRES run entirely in complex
 // FP32 (inner: FP32 basis, FP32 level-shift tables, FP32 stencil, FP32 dot
-// products accumulated in FP32, FP32 Jacobi scaling).  The outer level keeps
+// products accumulated in FP32, FP32 preconditioner: the diagonal or the
+// column-block factors of segprec.h).  The outer level keeps
 // everything that decides the answer in FP64: the operator applied to the
 // inner results, its Gram-Schmidt, the Hessenberg least squares by Givens, the
 // solution update, the true residual b - A x and the amplitudes.  Because
@@ -50,12 +51,17 @@ fgmres_mixed_kernel(SolveArgs a) {
   c64* Ri = Ro + (size_t)(m + 1) * m;             // (mi+1) x mi
   // FP32 part
   c32* Vi = reinterpret_cast<c32*>(Ri + (size_t)(mi + 1) * mi);   // (mi+1) x ld
-  c32* dinv = Vi + (size_t)(mi + 1) * ld;
+  c32* dinv = Vi + (size_t)(mi + 1) * ld;        // 1/diag(A), or D^{-1} of the blocks
   c32* w32 = dinv + ld;
   c32* wA32 = w32 + ld;
   c32* wB32 = wA32 + ld;
+  c32* l1 = wB32 + ld;                           // block factors (segprec.h)
+  c32* l2 = l1 + ld;
+  c32* zt = l2 + ld;                             // M^{-1} of the inner vector in work
   (void)w;
   (void)w32;
+  const bool blk = a.precond == VDC_PREC_BLOCK;
+  const SegFactor<float> fac{l1, l2, dinv};
 
   for (;;) {
     __syncthreads();
@@ -71,9 +77,13 @@ fgmres_mixed_kernel(SolveArgs a) {
     const OpJob<float> op32 = make_op<float>(md, jb, a.tables32 + toff);
     const int Nc = md.Nc;
 
+    if (blk) seg_factor<float>(op, L.sq, fac);
     for (int i = tid; i < Nc; i += kBlock) {
-      const c64 d = a.precond ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
-      dinv[i] = c32{(float)d.x, (float)d.y};
+      if (!blk) {
+        const c64 d = a.precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i))
+                                                    : c64{1.0, 0.0};
+        dinv[i] = c32{(float)d.x, (float)d.y};
+      }
       x[i] = c64{0.0, 0.0};
       b[i] = c64{0.0, 0.0};
     }
@@ -96,7 +106,13 @@ fgmres_mixed_kernel(SolveArgs a) {
     //     cycle of k steps (cycle_passes(k) p32), z_j = dinv V y (k + 1 p32,
     //     1 p64)
     //   outer cycle of k_o steps: x += Z y (k_o + 2 p64), residual (6 p64)
-    double p64 = 7.0, p32 = 1.0;
+    // The block preconditioner adds: setup one more FP64 table plane and two
+    // more FP32 planes written (p64 1, p32 2); every inner step M^{-1} (vector
+    // and three factor planes read, zt written) before an operator that reads
+    // zt but no dinv (p32 4); z_j: the sum written to zt, M^{-1} in place
+    // (zt and three factor planes read, zt written), zt read for the
+    // widening (p32 7 instead of 1).
+    double p64 = blk ? 8.0 : 7.0, p32 = blk ? 3.0 : 1.0;
     if (!(bnorm > 0.0) || !isfinite(bnorm)) {
       status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
       beta = 0.0;
@@ -104,8 +120,13 @@ fgmres_mixed_kernel(SolveArgs a) {
       for (int i = tid; i < Nc; i += kBlock) Vo[i] = b[i];
       // inner FP32 operator: A (s dinv v)
       auto apply_in = [&](int j, float sc, c32* out) {
-        apply_A<float>(op32, L.sqf, Vi + (size_t)j * ld, sc, dinv, out, lds32, a.tileT32, wA32,
-                       wB32);
+        if (blk) {
+          seg_apply<float>(fac, md.Ng, md.Nu, Vi + (size_t)j * ld, sc, zt, false);
+          apply_A<float>(op32, L.sqf, zt, 1.0f, nullptr, out, lds32, a.tileT32, wA32, wB32);
+        } else {
+          apply_A<float>(op32, L.sqf, Vi + (size_t)j * ld, sc, dinv, out, lds32, a.tileT32, wA32,
+                         wB32);
+        }
       };
       // outer step j: Z_j = inner(s V_j), out = A Z_j in FP64
       auto apply_out = [&](int j, double sc, c64* out) {
@@ -130,7 +151,7 @@ fgmres_mixed_kernel(SolveArgs a) {
           const CycleResult ci = krylov_cycle<float>(L.Ki, L.redf, Vi, ld, Nc, mi,
                                                      a.tol_in * n0, a.max_iter, iters, Ri,
                                                      apply_in);
-          // z = dinv * sum_l (vs_l Vi_l) y_l, widened to FP64
+          // z = M^{-1} sum_l (vs_l Vi_l) y_l, widened to FP64
           for (int i = tid; i < Nc; i += kBlock) {
             c32 s = c32{0.f, 0.f};
             int l = 0;
@@ -148,10 +169,20 @@ fgmres_mixed_kernel(SolveArgs a) {
               const float f = L.Ki.vs[l];
               s = s + Vi[(size_t)l * ld + i] * c32{(float)L.Ki.y[l].x * f, (float)L.Ki.y[l].y * f};
             }
-            const c32 t = dinv[i] * s;
-            z[i] = c64{(double)t.x, (double)t.y};
+            if (blk) {
+              zt[i] = s;
+            } else {
+              const c32 t = dinv[i] * s;
+              z[i] = c64{(double)t.x, (double)t.y};
+            }
           }
-          p32 += cycle_passes(ci.k, ci.reorth_passes) + ci.k + 1.0;
+          if (blk) {
+            seg_apply<float>(fac, md.Ng, md.Nu, zt, 1.0f, zt, false);
+            __syncthreads();
+            for (int i = tid; i < Nc; i += kBlock) z[i] = c64{(double)zt[i].x, (double)zt[i].y};
+          }
+          p32 += cycle_passes(ci.k, ci.reorth_passes) + ci.k + 1.0 +
+                 (blk ? 4.0 * ci.k + 6.0 : 0.0);
         } else {
           for (int i = tid; i < Nc; i += kBlock) z[i] = c64{0.0, 0.0};
         }

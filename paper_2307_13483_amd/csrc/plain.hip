@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "segprec.h"
 #include "solve_args.h"
 
 namespace vdc {
@@ -31,7 +32,7 @@ struct PlainArgs {
   DevModel md;
   DevJob jb;
   const c64* tab;       // block tables of the job (3 planes)
-  c64 *V, *x, *b, *dinv, *w, *wA, *wB, *Rm;
+  c64 *V, *x, *b, *dinv, *w, *wA, *wB, *l1, *l2, *zt, *Rm;
   c64* part;            // [m+1][nblk] partial dots
   double* partn;        // [nblk] partial norms
   PlainState* st;
@@ -46,9 +47,32 @@ __global__ void __launch_bounds__(kPT) p_init(PlainArgs a) {
   const int i = blockIdx.x * kPT + threadIdx.x;
   if (i >= a.md.Nc) return;
   const OpJob<double> op = plain_op(a);
-  a.dinv[i] = a.precond ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
+  if (a.precond != VDC_PREC_BLOCK)
+    a.dinv[i] = a.precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
   a.x[i] = c64{0.0, 0.0};
   a.b[i] = c64{0.0, 0.0};
+}
+
+// block preconditioner factors (segprec.h), one thread per block
+__global__ void __launch_bounds__(kPT) p_factor(PlainArgs a) {
+  __shared__ double sq[kSqMax + 1];
+  fill_sq<double>(sq);
+  __syncthreads();
+  const int c = blockIdx.x * kPT + threadIdx.x;
+  if (c >= seg_blocks(a.md.Ng, a.md.Nu)) return;
+  seg_factor_block<double>(plain_op(a), sq, SegFactor<double>{a.l1, a.l2, a.dinv}, c);
+}
+
+// z = M^{-1} v, or z += M^{-1} v with accumulate, one thread per block; the
+// end-of-cycle call runs until the job is done, the step call until the
+// cycle stops
+__global__ void __launch_bounds__(kPT) p_papply(PlainArgs a, const c64* v, c64* z, int accumulate,
+                                                int end_of_cycle) {
+  if (end_of_cycle ? a.st->done : a.st->stop_cycle) return;
+  const int c = blockIdx.x * kPT + threadIdx.x;
+  if (c >= seg_blocks(a.md.Ng, a.md.Nu)) return;
+  seg_apply_block<double>(SegFactor<double>{a.l1, a.l2, a.dinv}, a.md.Ng, a.md.Nu, v, 1.0, z,
+                          accumulate != 0, c);
 }
 
 __global__ void p_rhs(PlainArgs a) {
@@ -63,7 +87,7 @@ __global__ void p_rhs(PlainArgs a) {
   s.cycles = 0;
   s.breakdown = 0;
   s.stop_cycle = 0;
-  s.passes = 7.0;
+  s.passes = a.precond == VDC_PREC_BLOCK ? 10.0 : 7.0;
 }
 
 // per-block partial sums of |v|^2 (the v is w or b)
@@ -248,14 +272,17 @@ __global__ void p_backsub(PlainArgs a) {
   s.stop_cycle = 0;   // the end-of-cycle kernels run
 }
 
-// x += dinv * sum_l V_l y_l
+// x += dinv * sum_l V_l y_l (block preconditioner: zt = sum_l V_l y_l)
 __global__ void __launch_bounds__(kPT) p_update(PlainArgs a) {
   if (a.st->done) return;
   const int i = blockIdx.x * kPT + threadIdx.x;
   if (i >= a.md.Nc) return;
   c64 t = c64{0.0, 0.0};
   for (int l = 0; l < a.st->k; ++l) t = t + a.V[(size_t)l * a.ld + i] * a.st->y[l];
-  a.x[i] = a.x[i] + a.dinv[i] * t;
+  if (a.precond == VDC_PREC_BLOCK)
+    a.zt[i] = t;
+  else
+    a.x[i] = a.x[i] + a.dinv[i] * t;
 }
 
 // w = b - w (true residual after the matvec of x)
@@ -271,7 +298,8 @@ __global__ void p_status(PlainArgs a) {
   PlainState& s = *a.st;
   if (s.done) return;
   s.cycles += 1;
-  s.passes += 7.0 * s.k + 2.0 * s.k * (s.k + 1.0) + s.k + 10.0;
+  s.passes += 7.0 * s.k + 2.0 * s.k * (s.k + 1.0) + s.k + 10.0 +
+              (a.precond == VDC_PREC_BLOCK ? 4.0 * s.k + 4.0 : 0.0);
   const double beta = s.beta;
   if (!isfinite(beta)) {
     s.status = VDC_NONFINITE;
@@ -317,7 +345,10 @@ vdc_status solve_plain_impl(const SolveArgs& sa, const std::vector<DevJob>& jobs
   a.w = a.dinv + ld;
   a.wA = a.w + ld;
   a.wB = a.wA + ld;
-  a.Rm = a.wB + ld;
+  a.l1 = a.wB + ld;
+  a.l2 = a.l1 + ld;
+  a.zt = a.l2 + ld;
+  a.Rm = a.zt + ld;
   const int nblk_max = (int)((ld + kPT - 1) / kPT);
   a.part = a.Rm + (size_t)(m + 1) * m;
   a.partn = reinterpret_cast<double*>(a.part + (size_t)(m + 1) * nblk_max);
@@ -348,14 +379,23 @@ vdc_status solve_plain_impl(const SolveArgs& sa, const std::vector<DevJob>& jobs
     a.tab = sa.tables + htabs[jb.table].offset + (size_t)(jb.parity * sa.planes) * a.md.Nc;
     a.nblk = (a.md.Nc + kPT - 1) / kPT;
     const dim3 g1(a.nblk), b1(kPT);
+    const bool blk = a.precond == VDC_PREC_BLOCK;
+    const dim3 gs((seg_blocks(a.md.Ng, a.md.Nu) + kPT - 1) / kPT);
     hipLaunchKernelGGL(p_init, g1, b1, 0, st, a);
+    if (blk) hipLaunchKernelGGL(p_factor, gs, b1, 0, st, a);
     hipLaunchKernelGGL(p_rhs, dim3(1), dim3(1), 0, st, a);
     hipLaunchKernelGGL(p_norm_part, g1, b1, 0, st, a, (const c64*)a.b);
     hipLaunchKernelGGL(p_norm_final, dim3(1), dim3(1), 0, st, a, 0);
     hipLaunchKernelGGL(p_scale, g1, b1, 0, st, a, (const c64*)a.b, a.V, 0);
     for (;;) {
       for (int j = 0; j < m; ++j) {
-        hipLaunchKernelGGL(p_phase1, g1, b1, 0, st, a, (const c64*)(a.V + (size_t)j * ld), 1);
+        if (blk) {
+          hipLaunchKernelGGL(p_papply, gs, b1, 0, st, a, (const c64*)(a.V + (size_t)j * ld), a.zt, 0,
+                             0);
+          hipLaunchKernelGGL(p_phase1, g1, b1, 0, st, a, (const c64*)a.zt, 0);
+        } else {
+          hipLaunchKernelGGL(p_phase1, g1, b1, 0, st, a, (const c64*)(a.V + (size_t)j * ld), 1);
+        }
         hipLaunchKernelGGL(p_phase2, g1, b1, 0, st, a);
         for (int pass = 1; pass <= 2; ++pass) {
           hipLaunchKernelGGL(p_dot_part, dim3(a.nblk, j + 1), b1, 0, st, a, j + 1);
@@ -370,6 +410,7 @@ vdc_status solve_plain_impl(const SolveArgs& sa, const std::vector<DevJob>& jobs
       }
       hipLaunchKernelGGL(p_backsub, dim3(1), dim3(1), 0, st, a);
       hipLaunchKernelGGL(p_update, g1, b1, 0, st, a);
+      if (blk) hipLaunchKernelGGL(p_papply, gs, b1, 0, st, a, (const c64*)a.zt, a.x, 1, 1);
       hipLaunchKernelGGL(p_phase1, g1, b1, 0, st, a, (const c64*)a.x, 0);
       hipLaunchKernelGGL(p_phase2, g1, b1, 0, st, a);
       hipLaunchKernelGGL(p_resid, g1, b1, 0, st, a);

@@ -312,17 +312,22 @@ def _grad_case(Ng, Nu, eps, n_final=4):
     return p, finals, sig_t
 
 
-@pytest.mark.parametrize("Ng,Nu,eps", [(9, 7, [0.57, 1.73, 2.61]), (20, 16, [0.83, 2.28])])
-def test_adjoint_gradient_matches_oracle(vdc, Ng, Nu, eps):
+@pytest.mark.parametrize("Ng,Nu,eps,precond", [(9, 7, [0.57, 1.73, 2.61], 1),
+                                               (20, 16, [0.83, 2.28], 1),
+                                               (20, 16, [0.83, 2.28], 2)])
+def test_adjoint_gradient_matches_oracle(vdc, Ng, Nu, eps, precond):
     """GPU adjoint (one transposed solve per right-hand side + parameter
-    sweep) against the oracle's explicit-derivative gradient."""
+    sweep) against the oracle's explicit-derivative gradient; diagonal and
+    block preconditioners (both symmetric, so the transposed solve may use
+    the same one)."""
     import torch
     from oracle import adjoint as adj
     p, finals, sig_t = _grad_case(Ng, Nu, eps)
     L, g_ref, sig_ref = adj.loss_and_grad(p, Ng, Nu, eps, (0, 0), finals, sig_t)
     model = vdc.Model2D(p, Ng, Nu)
     jobs = [(e, (0, 0), mu) for e in eps for mu in (0, 1)]
-    s = vdc.Solver(model, jobs, finals, vdc.Opts(restart=20, tol=1e-12), want_psi=True).run()
+    s = vdc.Solver(model, jobs, finals, vdc.Opts(restart=20, tol=1e-12, precond=precond),
+                   want_psi=True).run()
     sig = s.sigma.cpu().numpy().reshape(len(eps), 2, len(finals)).sum(axis=1)
     assert np.allclose(sig, sig_ref, rtol=1e-9, atol=0)
     dsig = 2.0 * (sig - sig_t)
@@ -386,3 +391,61 @@ def test_block_matvec_matches_assembled_matrix(vdc, Ng, Nu, seed):
         got[np.arange(nc) + act * nc] = y[k]
         bound = 1e-14 * (abs(A) @ np.abs(fulls[k])) + abs(Fbound) @ np.abs(fulls[k]) + 1e-15
         assert np.all(np.abs(got - ref) <= bound)
+
+
+
+# ------------------------------------------------------------ block preconditioner
+
+def test_block_preconditioner_iterations_track_textbook(vdc):
+    """Restarted GMRES right-preconditioned by the column blocks (8 rows of
+    n_g, the last one ragged) against the oracle's textbook GMRES with the
+    same blocks taken as slices of its assembled A and solved by LU."""
+    from oracle import precond as pc
+    p = inputs.draw_params(8)
+    Ng, Nu = 30, 26
+    jobs = [(0.5, (0, 0), 0), (2.6, (1, 0), 1), (1.9, (0, 1), 0)]
+    model = vdc.Model2D(p, Ng, Nu)
+    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)], vdc.Opts(restart=15, precond=vdc.PREC_BLOCK))
+    for k, (e, vi, mu) in enumerate(jobs):
+        mdl, A, b, _, _ = _oracle_job(p, Ng, Nu, e, vi, mu, [(0, 0)])
+        Minv = pc.BlockInverse(A, pc.segmented_blocks(Ng, Nu, 8))
+        _, info = solvers.gmres(A, b, m=15, tol=1e-10, psolve=Minv)
+        assert abs(infos[k]["iters"] - info["iters"]) <= 2, (infos[k], info)
+        _, infoj = solvers.gmres(A, b, m=15, tol=1e-10, dinv=1.0 / m2.jacobi_diagonal(A))
+        assert infos[k]["iters"] <= infoj["iters"] + 2
+
+
+@pytest.mark.parametrize("Ng,Nu,restart", [(1, 1, 5), (2, 3, 4), (13, 29, 7), (30, 26, 12)])
+@pytest.mark.parametrize("path", ["fp64", "fp32", "plain"])
+def test_block_preconditioner_solves(vdc, Ng, Nu, restart, path):
+    """Tiny, ragged and multi-segment bases through the FP64, mixed and plain
+    paths with the block preconditioner; every solve checked against the
+    oracle."""
+    p = inputs.draw_params(21)
+    jobs = [(0.8, (0, 0), 0), (2.1, (min(1, Ng - 1), 0), 1), (1.4, (0, min(1, Nu - 1)), 0)]
+    finals = [(0, 0), (min(2, Ng - 1), 0), (0, min(1, Nu - 1))]
+    model = vdc.Model2D(p, Ng, Nu)
+    prec = vdc.FP32_INNER if path == "fp32" else vdc.FP64
+    opts = vdc.Opts(restart=restart, precond=vdc.PREC_BLOCK, precision=prec, inner_restart=restart,
+                    inner_tol=1e-4, outer_restart=8)
+    T, sigma, psi, infos = vdc.solve(model, jobs, finals, opts, plain=(path == "plain"),
+                                     want_psi=True)
+    _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
+                 psi.cpu().numpy(), infos)
+
+
+def test_block_preconditioner_full_size_mixed(vdc):
+    """120 x 120 batched model, FP32-inner / FP64-outer with the block
+    preconditioner: the FP64 true residual reaches 1e-10, the amplitudes
+    match the oracle, and the inner steps are fewer than with the diagonal."""
+    cfg = inputs.batched_jobs(n_energies=512)
+    p = cfg["params"]
+    sample = [cfg["jobs"][k] for k in (5, 1500, 2600, 3070)]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    base = dict(precision=vdc.FP32_INNER, inner_restart=8, inner_tol=1e-3, outer_restart=16)
+    T, sigma, psi, infos = vdc.solve(model, sample, cfg["finals"],
+                                     vdc.Opts(precond=vdc.PREC_BLOCK, **base), want_psi=True)
+    _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
+                 sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+    _, _, _, jinfos = vdc.solve(model, sample, cfg["finals"], vdc.Opts(**base))
+    assert sum(i["iters"] for i in infos) < sum(i["iters"] for i in jinfos)
