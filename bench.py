@@ -23,14 +23,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "converged solves/s at 1e-10 rel. residual; matvec HBM GB/s; batched+FP32 vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["op2d.h", "blockops.h", "solve_args.h", "gmres.hip", "mixed.hip"]
+CSRC = os.path.join(ROOT, "paper_2307_13483_amd", "csrc")
 
 
 def kernel_hash():
+    """Hash of every HIP source and header: counters taken on other sources
+    are not used."""
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2307_13483_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -108,7 +110,8 @@ def extras(args, model, cfg):
     sc = inputs.single_jobs()
     m0 = vdc.Model2D(sc["params"], sc["Ng"], sc["Nu"])
     for plain in (False, True):
-        s = vdc.Solver(m0, sc["jobs"], sc["finals"], vdc.Opts(restart=50, tol=1e-10))
+        s = vdc.Solver(m0, sc["jobs"], sc["finals"],
+                       vdc.Opts(restart=50, tol=1e-10, precond=PRECONDS[args.precond]))
         s.run(plain=plain)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -123,7 +126,9 @@ def extras(args, model, cfg):
     models = [vdc.Model2D(i["params"], i["Ng"], i["Nu"]) for i in insts]
     jobs = [(i["eps"], (0, 0), mu, k) for k, i in enumerate(insts) for mu in (0, 1)]
     res = {}
-    for name, o in (("fp32", vdc.Opts(precision=vdc.FP32_INNER)), ("fp64", vdc.Opts(restart=6))):
+    pc = PRECONDS[args.precond]
+    for name, o in (("fp32", vdc.Opts(precision=vdc.FP32_INNER, precond=pc)),
+                    ("fp64", vdc.Opts(restart=6, precond=pc))):
         s = vdc.Solver(models, jobs, cfg["finals"], o)
         s.run()
         torch.cuda.synchronize()
@@ -147,7 +152,7 @@ def extras(args, model, cfg):
     aw = inputs.adjoint_workload()
     ma = vdc.Model2D(aw["params"], aw["Ng"], aw["Nu"])
     ajobs = [(float(e), (0, 0), mu) for e in aw["eps"] for mu in (0, 1)]
-    s = vdc.Solver(ma, ajobs, aw["finals"], vdc.Opts(restart=6), want_psi=True)
+    s = vdc.Solver(ma, ajobs, aw["finals"], vdc.Opts(restart=6, precond=pc), want_psi=True)
     dsig = torch.ones((len(ajobs), len(aw["finals"])), dtype=torch.float64, device="cuda")
     s.run()
     s.adjoint(dsig)
@@ -192,6 +197,9 @@ def main():
                     help="right-hand sides timed on the plain single-solve path (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=4,
                     help="right-hand sides timed on the CPU oracle (0: skip)")
+    ap.add_argument("--matvec-probe", type=int, default=0,
+                    help="only run the batched operator (vdc_matvec_block) three times on this "
+                         "many block vectors of the 120 x 120 model, for profiling")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times "
                          "(calibrates the HBM byte counters of a profiler)")
@@ -209,6 +217,20 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.matvec_probe > 0:
+        import torch
+        from paper_2307_13483_amd import inputs, vdc
+        cfg = inputs.batched_jobs()
+        model = vdc.Model2D(cfg["params"], cfg["Ng"], cfg["Nu"])
+        nv, nc = args.matvec_probe, cfg["Ng"] * cfg["Nu"]
+        g = torch.Generator(device="cuda").manual_seed(1)
+        x = torch.randn((nv, nc), dtype=torch.complex128, device="cuda", generator=g)
+        cache = {}
+        for _ in range(3):
+            vdc.matvec_block(model, 2.0, x, [k % 2 for k in range(nv)], cache)
+        torch.cuda.synchronize()
+        print(json.dumps({"matvec_probe_vectors": nv, "kernel_ms": vdc.last_kernel_times()[1]}))
+        return
 
     import torch
     from paper_2307_13483_amd import inputs, vdc
@@ -252,11 +274,14 @@ def main():
         solver_ms = sum(ms_solver) / len(ms_solver)
         alg = sum(i["alg_bytes"] for i in infos)
         kernel = "gmres_fp64_kernel" if prec == vdc.FP64 else "fgmres_mixed_kernel"
-        workload = f"batched_{args.energies}x3x2_{Ng}x{Nu}_{precision}"
+        workload = (f"batched_{args.energies}x3x2_{Ng}x{Nu}_{precision}_{args.precond}"
+                    f"_m{opts.restart}_mi{opts.inner_restart}_ti{opts.inner_tol:g}"
+                    f"_mo{opts.outer_restart}_t{opts.tile_rows}")
         achieved = alg / (solver_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS, traffic=load_traffic(kernel, workload),
-                    kernel=kernel, algorithmic_bytes_per_launch=alg, kernel_ms=solver_ms)
+                    kernel=kernel, algorithmic_bytes_per_launch=alg, kernel_ms=solver_ms,
+                    traffic_key=workload)
         return dict(value=conv * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
                     chosen=dict(restart=opts.restart, inner_restart=opts.inner_restart,
                                 inner_tol=opts.inner_tol, outer_restart=opts.outer_restart,
@@ -303,7 +328,8 @@ def main():
         rates = {}
         try:
             for m in (6, 20, 40):
-                popts = vdc.Opts(restart=m, tol=1e-10, precision=vdc.FP64)
+                popts = vdc.Opts(restart=m, tol=1e-10, precision=vdc.FP64,
+                                 precond=PRECONDS[args.precond])
                 sp = vdc.Solver(model, sub, cfg["finals"], popts)
                 sp.run(plain=True)
                 torch.cuda.synchronize()

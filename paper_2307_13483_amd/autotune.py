@@ -14,17 +14,18 @@ from dataclasses import asdict, replace
 
 from . import vdc
 
-FP64_CANDIDATES = [dict(restart=m) for m in (5, 6, 8, 10, 15)]
+FP64_CANDIDATES = [dict(restart=m) for m in (4, 5, 6, 8, 10, 15)]
 FP32_CANDIDATES = [dict(inner_restart=mi, inner_tol=ti, outer_restart=mo)
-                   for mi, ti, mo in ((4, 1e-3, 32), (6, 1e-3, 24), (8, 1e-3, 16), (8, 1e-3, 24),
-                                      (10, 1e-3, 16), (12, 1e-4, 12), (15, 1e-4, 8))]
+                   for mi, ti, mo in ((4, 1e-3, 32), (6, 1e-3, 24), (6, 1e-2, 32), (8, 1e-3, 16),
+                                      (8, 1e-2, 24), (8, 1e-3, 24), (10, 1e-3, 16), (12, 1e-4, 12),
+                                      (15, 1e-4, 8))]
 TILE_CANDIDATES = (0, 4, 8)
 
 
-def _key(models, n_jobs, precision):
+def _key(models, n_jobs, precision, precond):
     shapes = sorted({(m.Ng, m.Nu) for m in models})
     bucket = 1 << max(0, (n_jobs - 1).bit_length())
-    return f"{precision}:{shapes}:{bucket}"
+    return f"{precision}:p{precond}:{shapes}:{bucket}"
 
 
 def autotune(models, jobs, finals, base=None, sample=384, cache=None, reps=2):
@@ -32,7 +33,7 @@ def autotune(models, jobs, finals, base=None, sample=384, cache=None, reps=2):
     base = base or vdc.Opts()
     models = list(models) if isinstance(models, (list, tuple)) else [models]
     precision = "fp64" if base.precision == vdc.FP64 else "fp32"
-    key = _key(models, len(jobs), precision)
+    key = _key(models, len(jobs), precision, base.precond)
     if cache and os.path.exists(cache):
         with open(cache) as fh:
             saved = json.load(fh)

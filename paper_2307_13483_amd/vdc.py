@@ -169,7 +169,7 @@ class Opts:
     restart: int = 50
     max_iter: int = 20000
     tol: float = 1e-10
-    precond: int = PREC_JACOBI
+    precond: int = PREC_BLOCK
     precision: int = FP64
     inner_restart: int = 8
     inner_tol: float = 1e-3

@@ -181,7 +181,8 @@ def test_iterations_track_textbook_gmres(vdc):
     Ng = Nu = 24
     jobs = [(0.5, (0, 0), 0), (2.6, (1, 0), 1)]
     model = vdc.Model2D(p, Ng, Nu)
-    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)], vdc.Opts(restart=15))
+    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)],
+                               vdc.Opts(restart=15, precond=vdc.PREC_JACOBI))
     for k, (e, vi, mu) in enumerate(jobs):
         mdl, A, b, _, _ = _oracle_job(p, Ng, Nu, e, vi, mu, [(0, 0)])
         _, info = solvers.gmres(A, b, m=15, tol=1e-10, dinv=1.0 / m2.jacobi_diagonal(A))
@@ -447,5 +448,6 @@ def test_block_preconditioner_full_size_mixed(vdc):
                                      vdc.Opts(precond=vdc.PREC_BLOCK, **base), want_psi=True)
     _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
                  sigma.cpu().numpy(), psi.cpu().numpy(), infos)
-    _, _, _, jinfos = vdc.solve(model, sample, cfg["finals"], vdc.Opts(**base))
+    _, _, _, jinfos = vdc.solve(model, sample, cfg["finals"],
+                                vdc.Opts(precond=vdc.PREC_JACOBI, **base))
     assert sum(i["iters"] for i in infos) < sum(i["iters"] for i in jinfos)
