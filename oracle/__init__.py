@@ -21,6 +21,8 @@ solvers      sparse/dense LU and a textbook GMRES(m) of Sec. III.A
 precond      block-diagonal sections of A as preconditioners, Sec. III.B
 observables  T-matrix and cross sections, Eqs. (15), (16), (24)
 adjoint      d(loss)/d(parameters) by explicit derivative matrices and LU
+poly         the CO2-like three-state, four-mode polynomial model (Sec. III.C)
+             assembled the same way, and its bend-block preconditioner
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py``; none is "parity unpinned".

@@ -88,3 +88,46 @@ def adjoint_workload(n_energies=256, n_basis=120, seed=SEED):
     return dict(params=base_params(), target_params=draw_params(seed + 1),
                 Ng=n_basis, Nu=n_basis, eps=np.linspace(0.1, 3.0, n_energies),
                 v_i=(0, 0), finals=[(k, 0) for k in range(6)])
+
+
+# ---------------------------------------------------------------- CO2-like model
+#
+# Three states (sigma, Pi_x, Pi_y), four modes (symmetric stretch s, bend x and
+# y, asymmetric stretch a), partial waves s, p_x, p_y; CO2-like frequencies and
+# state energies, couplings drawn per seed.
+
+CO2_SIZES = dict(s=24, x=24, y=24, a=8)
+
+
+def co2like_params(seed=SEED + 2):
+    """Frequencies w_s = 0.172, w_b = 0.083, w_a = 0.291 eV, E_sigma = 0.5,
+    E_pi = 3.5 eV; linear couplings k_sigma, k_pi, c_sp with magnitude
+    10^U(-3, -1) eV and a random sign; quadratic ones (g*_*, c_rt) with
+    magnitude 10^U(-3, -2) eV and a random sign; the dimensionless factors
+    c_sp2, l_sigma, l_pi with magnitude 10^U(-2, log10 0.2) and a random sign;
+    h_sigma, h_pi ~ U(0.5, 1.5); widths A = 0.2 U(0.8, 1.2), B = 1.0 U(0.8, 1.2)
+    for each (state class, wave class); numpy default_rng(seed), in that order."""
+    p = dict(omega_s=0.172, omega_b=0.083, omega_a=0.291, E_sigma=0.5, E_pi=3.5, K=4096, X=40.0)
+    rng = np.random.default_rng(seed)
+    for k in ("k_sigma", "k_pi", "c_sp"):
+        p[k] = float(rng.choice((-1.0, 1.0)) * 10.0 ** rng.uniform(-3.0, -1.0))
+    for k in ("gs_sigma", "gb_sigma", "ga_sigma", "gs_pi", "gb_pi", "ga_pi", "c_rt"):
+        p[k] = float(rng.choice((-1.0, 1.0)) * 10.0 ** rng.uniform(-3.0, -2.0))
+    for k in ("c_sp2", "l_sigma", "l_pi"):
+        p[k] = float(rng.choice((-1.0, 1.0)) * 10.0 ** rng.uniform(-2.0, np.log10(0.2)))
+    for k in ("h_sigma", "h_pi"):
+        p[k] = float(rng.uniform(0.5, 1.5))
+    for c in ("sigma", "pi"):
+        for w in ("s", "p"):
+            p["A_%s_%s" % (c, w)] = float(0.2 * rng.uniform(0.8, 1.2))
+            p["B_%s_%s" % (c, w)] = float(1.0 * rng.uniform(0.8, 1.2))
+    return p
+
+
+def co2like_jobs(n_energies=128, sizes=None, seed=SEED + 2):
+    """128 incident energies on [0.05, 4.0] eV, v_i = 0, partial waves s, p_x,
+    p_y: 384 right-hand sides."""
+    eps = np.linspace(0.05, 4.0, n_energies)
+    jobs = [(float(e), (0, 0, 0, 0), mu) for e in eps for mu in (0, 1, 2)]
+    return dict(params=co2like_params(seed), sizes=dict(sizes or CO2_SIZES), jobs=jobs,
+                finals=[(v, 0, 0, 0) for v in range(4)] + [(0, 2, 0, 0), (0, 0, 0, 2)])
