@@ -227,13 +227,99 @@ vdc_status vdc_last_kernel_times(double* ms_tables, double* ms_solver);
  * vector v in block parity[v] (host int[n_vec]): at (n_g, n_u) the value is
  * the component of state 1 if n_u + parity is even, of state 2 otherwise.
  * One total energy E for all vectors; its level-shift tables are built first.
- * Uses the solvers' fused LDS-tiled operator pass, one workgroup per vector.
+ * One wavefront per (vector, slab of n_g rows, strip of 60 n_u columns),
+ * no LDS tiles or barriers.  x and y must not overlap.
  * Kernel times are reported by vdc_last_kernel_times (tables, operator).
  * Workspace: vdc_matvec_block_workspace_size().  Synchronises the stream. */
 vdc_status vdc_matvec_block_workspace_size(vdc_model_t model, int n_vec, size_t* bytes);
 vdc_status vdc_matvec_block(vdc_model_t model, double E, int n_vec, const int* parity,
                             const double* x, double* y, void* workspace, size_t ws_bytes,
                             void* stream);
+
+/* ------------------------------------------------------------------------
+ * The CO2-like three-state, four-mode model (Sec. III.C, the model class of
+ * the e + CO2 paragraph): states sigma, Pi_x, Pi_y; modes s (symmetric
+ * stretch), the bend (x, y) and a (asymmetric stretch); partial waves s,
+ * p_x, p_y; H_0 = w_s (n_s+1/2) + w_b (n_x+n_y+1) + w_a (n_a+1/2) (Eq. (21));
+ * U (Eq. (18) extended to second order):
+ *   U_ss = E_sigma + k_sigma q_s + gs_sigma q_s^2 + gb_sigma (q_x^2+q_y^2) + ga_sigma q_a^2,
+ *   U_xx, U_yy = E_pi + k_pi q_s + gs_pi q_s^2 + gb_pi (q_x^2+q_y^2) + ga_pi q_a^2
+ *                +- c_rt (q_x^2 - q_y^2),   U_xy = 2 c_rt q_x q_y,
+ *   U_sx = c_sp (1 + c_sp2 q_s) q_x,  U_sy = c_sp (1 + c_sp2 q_s) q_y;
+ * discrete-continuum couplings f_d^mu(eps) O_d^mu with O_sigma^s = 1 + l_sigma q_s,
+ * O_pix^s = h_pi q_x, O_piy^s = h_pi q_y, O_sigma^px = h_sigma q_x,
+ * O_pix^px = O_piy^py = 1 + l_pi q_s, O_sigma^py = h_sigma q_y (others 0);
+ * widths Gamma = A eps^(l+1/2) exp(-eps/B), l = 0 for the s wave, 1 for the
+ * p waves, (A, B) per state class (sigma, pi) and wave class (s, p)
+ * (Eq. (22)); level shift of Eq. (19); F as in Eq. (23).  All products of
+ * q are products of truncated matrices.
+ *
+ * Every solve runs in one reflection sector (x -> -x, y -> -y): for the
+ * right-hand side Phi^{v mu} the sector bits are px = (v_x + [mu = p_x]) & 1
+ * and py = (v_y + [mu = p_y]) & 1.  Sector vectors hold one complex value per
+ * grid point [n_s][n_a][n_x][n_y] (n_y fastest): at (n_x, n_y) the value is
+ * the amplitude of sigma if (n_x + px, n_y + py) are both even, of Pi_x if
+ * only n_x + px is odd, of Pi_y if only n_y + py is odd, and 0 if both are
+ * odd. */
+typedef struct {
+  double omega_s, omega_b, omega_a;   /* > 0, eV                              */
+  double E_sigma, E_pi;
+  double k_sigma, k_pi;
+  double gs_sigma, gb_sigma, ga_sigma, gs_pi, gb_pi, ga_pi;
+  double c_rt, c_sp, c_sp2;
+  double l_sigma, l_pi, h_sigma, h_pi;
+  double A[2][2];            /* [state class sigma, pi][wave class s, p], >= 0   */
+  double B[2][2];            /* the same, > 0                                    */
+  int Ns, Nx, Ny, Na;        /* basis sizes: 1..1024, Ny 1..31                    */
+  int hilbert_nodes;         /* 16..65536                                        */
+  double hilbert_xmax;       /* > 0 eV                                            */
+} vdc_co2_desc;
+
+typedef struct vdc_co2* vdc_co2_t;   /* opaque */
+
+/* One right-hand side: incident energy eps_i > 0, initial state v = (n_s,
+ * n_x, n_y, n_a) in the basis, incoming partial wave mu_i (0 s, 1 p_x, 2 p_y). */
+typedef struct {
+  double eps_i;
+  int v[4];
+  int mu_i;
+} vdc_co2_job;
+
+vdc_status vdc_co2_create(const vdc_co2_desc* desc, vdc_co2_t* out);
+vdc_status vdc_co2_destroy(vdc_co2_t model);
+
+/* Workspace (device bytes) for vdc_co2_solve.  Host call, no device work. */
+vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs,
+                                  const vdc_co2_job* jobs, size_t* bytes);
+
+/* Solve (E - H_ef) Psi = Phi^{v mu} (Eqs. (26), (28)) for every job in one
+ * persistent launch (after one launch for the level-shift tables of all
+ * distinct energies): restarted FP64 GMRES(opts->restart) with right
+ * preconditioning by the paper's block choice for this model class
+ * (VDC_PREC_BLOCK: one block per (n_s, n_a) holding the bend plane, factored
+ * once per job by complex-symmetric L D L^T; a block with a vanishing pivot
+ * falls back to its diagonal), by the diagonal (VDC_PREC_JACOBI) or by none,
+ * until the FP64 true residual is <= tol ||Phi||.  opts->precision must be
+ * VDC_FP64.  Then the amplitudes T[job][f][mu_f] = Phi^{v_f mu_f T} Psi
+ * (Eq. (24)) for the finals (host int [n_final][4], states in the basis) and
+ * the job's share of sigma (Eq. (16), summed over mu_f).
+ * Outputs (device): T_out complex [n_jobs][n_final][3], sigma_out double
+ * [n_jobs][n_final], psi_out complex [n_jobs][Ns*Na*Nx*Ny] sector vectors or
+ * NULL; info host [n_jobs].  Synchronises the stream. */
+vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs,
+                         const vdc_co2_job* jobs, int n_final, const int* finals,
+                         double* T_out, double* sigma_out, double* psi_out,
+                         vdc_job_info* info, void* workspace, size_t ws_bytes, void* stream);
+
+/* y = A x (which = 0) or y = M^{-1} x for the block preconditioner (which =
+ * 1) at total energy E, on n_vec sector vectors (device complex
+ * [n_vec][Ns*Na*Nx*Ny]), vector v in sector (sectors[2v], sectors[2v+1])
+ * (host ints, 0/1).  x and y must not overlap.  Workspace:
+ * vdc_co2_ops_workspace_size().  Synchronises the stream. */
+vdc_status vdc_co2_ops_workspace_size(vdc_co2_t model, int n_vec, int which, size_t* bytes);
+vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const int* sectors,
+                         const double* x, double* y, void* workspace, size_t ws_bytes,
+                         void* stream);
 
 /* Thread-local text of the last error (never NULL). */
 const char* vdc_last_error(void);

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvdc.so")
-SOURCES = ["api.hip", "levelshift.hip", "matvec.hip", "gmres.hip", "mixed.hip", "plain.hip",
+SOURCES = ["api.hip", "levelshift.hip", "matvec.hip", "gmres.hip", "mixed.hip", "plain.hip", "co2.hip",
            "adjoint.hip"]
 ARCH = "gfx950"
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "co2.h"
 #include "blockops.h"
 #include "solve_args.h"
 #include "strip.h"
@@ -29,6 +30,9 @@ hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
 size_t plain_extra_elems(size_t ncap, int m);
+hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, size_t dyn, hipStream_t s);
+hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, size_t dyn, hipStream_t s);
+size_t co2_factor_lds(int Ny);
 vdc_status solve_plain_impl(const SolveArgs& a, const std::vector<DevJob>& jobs,
                             const std::vector<DevModel>& models, hipStream_t s,
                             std::string& err);
@@ -841,3 +845,351 @@ vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, con
 }
 
 }  // extern "C"
+
+
+// ------------------------------------------------------------------ CO2-like model
+
+
+struct vdc_co2 {
+  vdc_co2_desc desc;
+  Co2Model dev;
+  vdc_model_t ls = nullptr;   // the six level-shift functions (state classes x wave classes)
+};
+
+namespace {
+
+double co2_vib(const Co2Model& m, int s, int b, int a) {
+  return m.omega_s * (s + 0.5) + m.omega_b * (b + 1.0) + m.omega_a * (a + 0.5);
+}
+
+size_t co2_ld(const Co2Model& m) { return ((size_t)m.npts + 63) / 64 * 64; }
+
+size_t co2_fac_elems(const Co2Model& m) {
+  return (size_t)m.Ns * m.Na * m.Nx * m.Ny * (2 * m.Ny + 1);
+}
+
+struct Co2Plan {
+  std::vector<Co2Job> jobs;
+  std::vector<double> energies;
+  size_t ld = 0, slot_elems = 0, fac_off = 0;
+  int n_groups = 1, m = 0;
+  size_t off_model = 0, off_ls = 0, off_jobs = 0, off_eps = 0, off_tab = 0, off_counter = 0,
+         off_finals = 0, off_info = 0, off_scratch = 0, total = 0;
+};
+
+vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const vdc_co2_job* jobs,
+                    int n_final, Co2Plan& P) {
+  if (!model || !o) return fail(VDC_ERR_INVALID_ARG, "NULL model or opts");
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(VDC_ERR_INVALID_ARG, "bad job list");
+  if (n_final < 0 || n_final > kMaxFinal) return fail(VDC_ERR_INVALID_ARG, "n_final must be 0..64");
+  if (o->restart < 1 || o->restart > kMaxRestart) return fail(VDC_ERR_INVALID_ARG, "restart must be 1..128");
+  if (o->max_iter < 1) return fail(VDC_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (!(o->tol > 0.0)) return fail(VDC_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->precision != VDC_FP64) return fail(VDC_ERR_INVALID_ARG, "this model solves in FP64 only");
+  if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI && o->precond != VDC_PREC_BLOCK)
+    return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
+  const Co2Model& md = model->dev;
+  std::map<double, int> eidx;
+  for (int k = 0; k < n_jobs; ++k) {
+    const vdc_co2_job& j = jobs[k];
+    if (!(j.eps_i > 0.0) || !std::isfinite(j.eps_i)) return fail(VDC_ERR_INVALID_ARG, "eps_i must be > 0");
+    const int lim[4] = {md.Ns, md.Nx, md.Ny, md.Na};
+    for (int q = 0; q < 4; ++q)
+      if (j.v[q] < 0 || j.v[q] >= lim[q]) return fail(VDC_ERR_INVALID_ARG, "initial state outside the basis");
+    if (j.mu_i < 0 || j.mu_i > 2) return fail(VDC_ERR_INVALID_ARG, "mu_i must be 0, 1 or 2");
+    Co2Job c{};
+    c.eps_i = j.eps_i;
+    c.E = j.eps_i + co2_vib(md, j.v[0], j.v[1] + j.v[2], j.v[3]);
+    for (int q = 0; q < 4; ++q) c.v[q] = j.v[q];
+    c.mu = j.mu_i;
+    c.px = co2_sector_x(j.v, j.mu_i);
+    c.py = co2_sector_y(j.v, j.mu_i);
+    auto it = eidx.find(c.E);
+    if (it == eidx.end()) it = eidx.emplace(c.E, (int)eidx.size()).first;
+    c.table = it->second;
+    c.out = k;
+    P.jobs.push_back(c);
+  }
+  P.energies.assign(eidx.size(), 0.0);
+  for (auto& kv : eidx) P.energies[kv.second] = kv.first;
+  // higher energies first (more open channels, longer solves on these models)
+  std::stable_sort(P.jobs.begin(), P.jobs.end(),
+                   [](const Co2Job& a, const Co2Job& b) { return a.E > b.E; });
+  P.m = o->restart;
+  P.ld = co2_ld(md);
+  P.fac_off = ((size_t)(P.m + 1 + 6) * P.ld + (size_t)(P.m + 1) * P.m + 31) / 32 * 32;
+  P.slot_elems = P.fac_off + (o->precond == VDC_PREC_BLOCK ? co2_fac_elems(md) : 0);
+  P.slot_elems = (P.slot_elems + 31) / 32 * 32;
+  P.n_groups = std::max(1, std::min(n_jobs, cu_count()));
+  size_t off = 0;
+  P.off_model = off; off = align256(off + sizeof(Co2Model));
+  P.off_ls = off; off = align256(off + sizeof(DevModel));
+  P.off_jobs = off; off = align256(off + sizeof(Co2Job) * std::max(1, n_jobs));
+  P.off_eps = off; off = align256(off + sizeof(double) * std::max<size_t>(1, P.energies.size()) * md.ntab);
+  P.off_tab = off; off = align256(off + sizeof(c64) * kNumF * std::max<size_t>(1, P.energies.size()) * md.ntab);
+  P.off_counter = off; off = align256(off + sizeof(int));
+  P.off_finals = off; off = align256(off + sizeof(int) * 4 * std::max(1, n_final));
+  P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
+  P.off_scratch = off; off = align256(off + sizeof(c64) * P.slot_elems * P.n_groups);
+  P.total = off;
+  return VDC_OK;
+}
+
+// Level-shift rows of every distinct energy: eps = E - E_nu for each
+// (n_s, n_x + n_y, n_a), the six functions at each.
+vdc_status co2_tables(vdc_co2_t model, const std::vector<double>& energies, double* d_eps, c64* d_tab,
+                      hipStream_t s) {
+  const Co2Model& md = model->dev;
+  std::vector<double> eps(energies.size() * (size_t)md.ntab);
+  for (size_t e = 0; e < energies.size(); ++e)
+    for (int si = 0; si < md.Ns; ++si)
+      for (int b = 0; b < md.nb; ++b)
+        for (int a = 0; a < md.Na; ++a)
+          eps[e * md.ntab + ((size_t)si * md.nb + b) * md.Na + a] = energies[e] - co2_vib(md, si, b, a);
+  if (eps.empty()) return VDC_OK;
+  HIPCHK(hipMemcpyAsync(d_eps, eps.data(), sizeof(double) * eps.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(launch_level_shift_points(model->ls->dev, (int)eps.size(), d_eps, d_tab, s));
+  return VDC_OK;
+}
+
+}  // namespace
+
+vdc_status vdc_co2_create(const vdc_co2_desc* d, vdc_co2_t* out) {
+  if (!d || !out) return fail(VDC_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  const int sz[4] = {d->Ns, d->Nx, d->Ny, d->Na};
+  for (int v : sz)
+    if (v < 1 || v > kSqMax - 2) return fail(VDC_ERR_INVALID_ARG, "basis sizes must be 1..1022");
+  if (d->Ny > 31) return fail(VDC_ERR_INVALID_ARG, "Ny must be <= 31 (band of the bend blocks)");
+  if ((size_t)d->Ns * d->Nx * d->Ny * d->Na > (size_t)1 << 26)
+    return fail(VDC_ERR_INVALID_ARG, "basis too large");
+  const double scal[] = {d->omega_s, d->omega_b, d->omega_a, d->E_sigma, d->E_pi, d->k_sigma,
+                         d->k_pi, d->gs_sigma, d->gb_sigma, d->ga_sigma, d->gs_pi, d->gb_pi,
+                         d->ga_pi, d->c_rt, d->c_sp, d->c_sp2, d->l_sigma, d->l_pi, d->h_sigma,
+                         d->h_pi};
+  for (double v : scal)
+    if (!std::isfinite(v)) return fail(VDC_ERR_INVALID_ARG, "non-finite model parameter");
+  if (!(d->omega_s > 0.0) || !(d->omega_b > 0.0) || !(d->omega_a > 0.0))
+    return fail(VDC_ERR_INVALID_ARG, "vibrational frequencies must be > 0");
+  // the level-shift functions through a two-state descriptor: "state" d =
+  // state class (sigma, pi), "partial wave" mu = wave class (s, p)
+  vdc_model2d_desc ld{};
+  ld.omega_g = d->omega_s;
+  ld.omega_u = d->omega_b;
+  ld.E1 = d->E_sigma;
+  ld.gap = d->E_pi - d->E_sigma;
+  for (int c = 0; c < 2; ++c)
+    for (int w = 0; w < 2; ++w) {
+      ld.A[c][w] = d->A[c][w];
+      ld.B[c][w] = d->B[c][w];
+    }
+  ld.l[0] = 0;
+  ld.l[1] = 1;
+  ld.Ng = ld.Nu = 1;
+  ld.hilbert_nodes = d->hilbert_nodes;
+  ld.hilbert_xmax = d->hilbert_xmax;
+  vdc_model_t lsm = nullptr;
+  const vdc_status st = vdc_model2d_create(&ld, &lsm);
+  if (st != VDC_OK) return st;
+  vdc_co2* m = new vdc_co2();
+  m->desc = *d;
+  m->ls = lsm;
+  Co2Model& c = m->dev;
+  c.Ns = d->Ns;
+  c.Nx = d->Nx;
+  c.Ny = d->Ny;
+  c.Na = d->Na;
+  c.npts = d->Ns * d->Na * d->Nx * d->Ny;
+  c.nb = d->Nx + d->Ny - 1;
+  c.ntab = d->Ns * c.nb * d->Na;
+  c.omega_s = d->omega_s;
+  c.omega_b = d->omega_b;
+  c.omega_a = d->omega_a;
+  c.E_sigma = d->E_sigma;
+  c.E_pi = d->E_pi;
+  c.k_sigma = d->k_sigma;
+  c.k_pi = d->k_pi;
+  c.gs[0] = d->gs_sigma;
+  c.gb[0] = d->gb_sigma;
+  c.ga[0] = d->ga_sigma;
+  c.gs[1] = d->gs_pi;
+  c.gb[1] = d->gb_pi;
+  c.ga[1] = d->ga_pi;
+  c.c_rt = d->c_rt;
+  c.c_sp = d->c_sp;
+  c.c_sp2 = d->c_sp2;
+  c.l_sigma = d->l_sigma;
+  c.l_pi = d->l_pi;
+  c.h_sigma = d->h_sigma;
+  c.h_pi = d->h_pi;
+  *out = m;
+  return VDC_OK;
+}
+
+vdc_status vdc_co2_destroy(vdc_co2_t m) {
+  if (!m) return VDC_OK;
+  vdc_model_destroy(m->ls);
+  delete m;
+  return VDC_OK;
+}
+
+vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs,
+                                  const vdc_co2_job* jobs, size_t* bytes) {
+  if (!bytes) return fail(VDC_ERR_INVALID_ARG, "NULL bytes");
+  Co2Plan P;
+  const vdc_status st = co2_plan(model, opts, n_jobs, jobs, 0, P);
+  if (st != VDC_OK) return st;
+  *bytes = P.total + align256(sizeof(int) * 4 * kMaxFinal);
+  return VDC_OK;
+}
+
+vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs,
+                         const vdc_co2_job* jobs, int n_final, const int* finals, double* T_out,
+                         double* sigma_out, double* psi_out, vdc_job_info* info, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  Co2Plan P;
+  vdc_status st = co2_plan(model, opts, n_jobs, jobs, n_final, P);
+  if (st != VDC_OK) return st;
+  if (n_jobs == 0) return VDC_OK;
+  if (!T_out || !sigma_out || !info || !workspace || (n_final > 0 && !finals))
+    return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total) return fail(VDC_ERR_WORKSPACE, "workspace too small");
+  const Co2Model& md = model->dev;
+  for (int f = 0; f < n_final; ++f) {
+    const int lim[4] = {md.Ns, md.Nx, md.Ny, md.Na};
+    for (int q = 0; q < 4; ++q)
+      if (finals[4 * f + q] < 0 || finals[4 * f + q] >= lim[q])
+        return fail(VDC_ERR_INVALID_ARG, "final state outside the basis");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  Co2Model* d_model = reinterpret_cast<Co2Model*>(ws + P.off_model);
+  DevModel* d_ls = reinterpret_cast<DevModel*>(ws + P.off_ls);
+  Co2Job* d_jobs = reinterpret_cast<Co2Job*>(ws + P.off_jobs);
+  double* d_eps = reinterpret_cast<double*>(ws + P.off_eps);
+  c64* d_tab = reinterpret_cast<c64*>(ws + P.off_tab);
+  int* d_counter = reinterpret_cast<int*>(ws + P.off_counter);
+  int* d_finals = reinterpret_cast<int*>(ws + P.off_finals);
+  DevInfo* d_info = reinterpret_cast<DevInfo*>(ws + P.off_info);
+  c64* d_scratch = reinterpret_cast<c64*>(ws + P.off_scratch);
+  HIPCHK(hipMemcpyAsync(d_model, &md, sizeof(Co2Model), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_ls, &model->ls->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_jobs, P.jobs.data(), sizeof(Co2Job) * n_jobs, hipMemcpyHostToDevice, s));
+  if (n_final > 0)
+    HIPCHK(hipMemcpyAsync(d_finals, finals, sizeof(int) * 4 * n_final, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_zero_int(d_counter, 1, s));
+  EventSet ev;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  st = co2_tables(model, P.energies, d_eps, d_tab, s);
+  if (st != VDC_OK) return st;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  Co2Args a{};
+  a.model = d_model;
+  a.ls = d_ls;
+  a.jobs = d_jobs;
+  a.n_jobs = n_jobs;
+  a.tables = d_tab;
+  a.counter = d_counter;
+  a.scratch = d_scratch;
+  a.slot_elems = P.slot_elems;
+  a.ld = P.ld;
+  a.fac_off = P.fac_off;
+  a.m = P.m;
+  a.max_iter = opts->max_iter;
+  a.precond = opts->precond;
+  a.tol = opts->tol;
+  a.n_final = n_final;
+  a.finals = d_finals;
+  a.T_out = reinterpret_cast<c64*>(T_out);
+  a.sigma_out = sigma_out;
+  a.psi_out = reinterpret_cast<c64*>(psi_out);
+  a.info = d_info;
+  HIPCHK(launch_co2_gmres(a, P.n_groups, opts->precond == VDC_PREC_BLOCK ? co2_factor_lds(md.Ny) : 0, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  std::vector<DevInfo> hinfo(n_jobs);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), d_info, sizeof(DevInfo) * n_jobs, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t1 = 0.f, t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = t1;
+    g_ms_solver = t2;
+  }
+  for (int k = 0; k < n_jobs; ++k)
+    info[k] = vdc_job_info{hinfo[k].status, hinfo[k].iters, hinfo[k].restarts, 0, hinfo[k].rel_res,
+                           hinfo[k].alg_bytes};
+  return VDC_OK;
+}
+
+vdc_status vdc_co2_ops_workspace_size(vdc_co2_t model, int n_vec, int which, size_t* bytes) {
+  if (!model || !bytes || n_vec < 0 || (which != 0 && which != 1))
+    return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  const Co2Model& md = model->dev;
+  const int groups = std::max(1, std::min(n_vec, cu_count()));
+  const size_t slot = which == 0 ? 2 * (size_t)md.npts : co2_fac_elems(md);
+  size_t off = 0;
+  off = align256(off + sizeof(Co2Model));
+  off = align256(off + sizeof(double) * md.ntab);
+  off = align256(off + sizeof(c64) * kNumF * md.ntab);
+  off = align256(off + sizeof(int) * 2 * std::max(1, n_vec));
+  off = align256(off + sizeof(c64) * slot * groups);
+  *bytes = off;
+  return VDC_OK;
+}
+
+vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const int* sectors,
+                         const double* x, double* y, void* workspace, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  vdc_status st = vdc_co2_ops_workspace_size(model, n_vec, which, &need);
+  if (st != VDC_OK) return st;
+  if (!std::isfinite(E)) return fail(VDC_ERR_INVALID_ARG, "non-finite E");
+  if (n_vec == 0) return VDC_OK;
+  if (!sectors || !x || !y || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  for (int v = 0; v < 2 * n_vec; ++v)
+    if (sectors[v] != 0 && sectors[v] != 1) return fail(VDC_ERR_INVALID_ARG, "sector bits must be 0 or 1");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(VDC_ERR_WORKSPACE, "workspace too small");
+  const Co2Model& md = model->dev;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  size_t off = 0;
+  Co2Model* d_model = reinterpret_cast<Co2Model*>(ws + off); off = align256(off + sizeof(Co2Model));
+  double* d_eps = reinterpret_cast<double*>(ws + off); off = align256(off + sizeof(double) * md.ntab);
+  c64* d_tab = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * md.ntab);
+  int* d_sec = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * 2 * n_vec);
+  c64* d_scratch = reinterpret_cast<c64*>(ws + off);
+  const int groups = std::max(1, std::min(n_vec, cu_count()));
+  HIPCHK(hipMemcpyAsync(d_model, &md, sizeof(Co2Model), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_sec, sectors, sizeof(int) * 2 * n_vec, hipMemcpyHostToDevice, s));
+  EventSet ev;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  st = co2_tables(model, std::vector<double>{E}, d_eps, d_tab, s);
+  if (st != VDC_OK) return st;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  Co2OpsArgs a{};
+  a.model = d_model;
+  a.tab = d_tab;
+  a.E = E;
+  a.sectors = d_sec;
+  a.n_vec = n_vec;
+  a.which = which;
+  a.x = reinterpret_cast<const c64*>(x);
+  a.y = reinterpret_cast<c64*>(y);
+  a.scratch = d_scratch;
+  a.slot_elems = which == 0 ? 2 * (size_t)md.npts : co2_fac_elems(md);
+  HIPCHK(launch_co2_ops(a, groups, which == 1 ? co2_factor_lds(md.Ny) : 0, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t1 = 0.f, t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = t1;
+    g_ms_solver = t2;
+  }
+  return VDC_OK;
+}

@@ -1,0 +1,361 @@
+// The CO2-like three-state, four-mode model on the device: the operator
+// A = E - H_0 - U - F of Sec. III.C's model class (three discrete states
+// sigma, Pi_x, Pi_y; modes s, bend x and y, a; partial waves s, p_x, p_y;
+// couplings up to second order), applied in one reflection sector, and the
+// paper's preconditioner for this class: one block per (n_s, n_a) holding the
+// whole bend plane, factored by complex-symmetric L D L^T.
+//
+// Reflection sectors.  A commutes with the reflections x -> -x and y -> -y
+// (q_x, Pi_x and p_x change sign under the first, q_y, Pi_y and p_y under the
+// second), and every right-hand side lies in one sector (px, py): the
+// sector's eigenvalues are (-1)^{v_x + [mu = p_x]} and (-1)^{v_y + [mu = p_y]}.
+// In a sector every bend point (n_x, n_y) carries at most one state, fixed
+// by the parities t_x = (n_x + px) & 1, t_y = (n_y + py) & 1:
+//   (0, 0) sigma, (1, 0) Pi_x, (0, 1) Pi_y, (1, 1) none.
+// A vector is one complex value per point of the grid [n_s][n_a][n_x][n_y]
+// (n_y fastest), zero at the "none" points: three quarters of the grid carry
+// a state, a quarter of the full basis of three states.  The continuum channel that can reach a point is fixed by
+// its type as well: the s wave at sigma points, p_x at Pi_x points, p_y at
+// Pi_y points, so the level-shift sandwich has exactly two pointwise
+// components per point (a sigma part w_A and a Pi part w_B), as in the
+// two-state model:
+//   sigma point:  u_A = (1 + l_s q_s) z,  u_B = h_p (q_x + q_y) z   (F^s)
+//   Pi_x point:   u_A = h_s q_x z,        u_B = (1 + l_p q_s) z      (F^p)
+//   Pi_y point:   u_A = h_s q_y z,        u_B = (1 + l_p q_s) z      (F^p)
+//   (w_A, w_B) = [[F_ss, F_sp], [F_sp, F_pp]] (u_A, u_B),
+// and F z is the transposed sandwich of the neighbours' (w_A, w_B).  q acts
+// as [q w]_n = sqrt(n/2) w_{n-1} + sqrt((n+1)/2) w_{n+1} and q^2 is the
+// product of two truncated q.
+//
+// Level shift.  The six functions F[f_d f_d'] (state classes sigma, Pi; wave
+// classes s, p) depend on a point only through eps_nu = E - E_nu, and E_nu
+// through (n_s, n_x + n_y, n_a): one table row per such triple and energy.
+#pragma once
+#include "internal.h"
+
+namespace vdc {
+
+struct Co2Model {
+  int Ns, Nx, Ny, Na;
+  int npts;              // Ns * Na * Nx * Ny
+  int nb;                // Nx + Ny - 1 values of n_x + n_y
+  int ntab;              // Ns * nb * Na table rows per energy
+  double omega_s, omega_b, omega_a;
+  double E_sigma, E_pi;
+  double k_sigma, k_pi;
+  double gs[2], gb[2], ga[2];   // [0] sigma, [1] Pi
+  double c_rt, c_sp, c_sp2;
+  double l_sigma, l_pi, h_sigma, h_pi;
+};
+
+struct Co2Job {
+  double eps_i, E;
+  int v[4];              // initial state (n_s, n_x, n_y, n_a)
+  int mu;                // 0 s, 1 p_x, 2 p_y
+  int px, py;            // sector bits
+  int table;             // index of the job's energy in the table array
+  int out;               // index in the caller's arrays
+};
+
+__host__ __device__ inline int co2_type(int x, int y, int px, int py) {
+  return ((x + px) & 1) | (((y + py) & 1) << 1);
+}
+
+__host__ __device__ inline int co2_sector_x(const int* v, int mu) { return (v[1] + (mu == 1)) & 1; }
+__host__ __device__ inline int co2_sector_y(const int* v, int mu) { return (v[2] + (mu == 2)) & 1; }
+
+// (q^2)_{n n} and (q^2)_{n, n+2} of the truncated product
+__device__ inline double q2_diag(int n, int N) { return 0.5 * n + (n + 1 < N ? 0.5 * (n + 1) : 0.0); }
+
+struct Co2Point {
+  int s, a, x, y, t;
+};
+
+__device__ inline Co2Point co2_point(const Co2Model& m, int i) {
+  Co2Point p;
+  p.y = i % m.Ny;
+  int r = i / m.Ny;
+  p.x = r % m.Nx;
+  r /= m.Nx;
+  p.a = r % m.Na;
+  p.s = r / m.Na;
+  p.t = 0;
+  return p;
+}
+
+// One job's operator: model, sector, energy, table rows of its energy.
+struct Co2Op {
+  const Co2Model* m;
+  const c64* tab;        // [Ns][nb][Na][6]
+  double E;
+  int px, py;
+};
+
+// Level-shift value at point (s, x, y, a) for the wave class of point type t
+// and pair k (0: sigma sigma, 1: sigma Pi, 2: Pi Pi).
+__device__ inline c64 co2_tab(const Co2Op& o, int s, int x, int y, int a, int t, int k) {
+  const Co2Model& m = *o.m;
+  const int w = t == 0 ? 0 : 1;
+  return o.tab[((size_t)(s * m.nb + x + y) * m.Na + a) * kNumF + 3 * w + k];
+}
+
+// Phase 1 at point i: the pointwise level-shift products (w_A, w_B) of the
+// channel that reaches the point.
+__device__ inline void co2_phase1(const Co2Op& o, const double* sq, const c64* v, double vs,
+                                  int i, c64& wa, c64& wb) {
+  const Co2Model& m = *o.m;
+  const Co2Point p = co2_point(m, i);
+  const int t = co2_type(p.x, p.y, o.px, o.py);
+  wa = wb = c64{0.0, 0.0};
+  if (t == 3) return;
+  const int sy = 1, sx = m.Ny, ss = m.Na * m.Nx * m.Ny;
+  auto Z = [&](int d) { return vs * v[i + d]; };
+  c64 qs = c64{0.0, 0.0};
+  if (p.s > 0) qs = sq[p.s] * Z(-ss);
+  if (p.s + 1 < m.Ns) qs = qs + sq[p.s + 1] * Z(ss);
+  c64 us, up;
+  if (t == 0) {
+    c64 q = c64{0.0, 0.0};
+    if (p.x > 0) q = sq[p.x] * Z(-sx);
+    if (p.x + 1 < m.Nx) q = q + sq[p.x + 1] * Z(sx);
+    if (p.y > 0) q = q + sq[p.y] * Z(-sy);
+    if (p.y + 1 < m.Ny) q = q + sq[p.y + 1] * Z(sy);
+    us = Z(0) + m.l_sigma * qs;
+    up = m.h_pi * q;
+  } else {
+    c64 q = c64{0.0, 0.0};
+    if (t == 1) {
+      if (p.x > 0) q = sq[p.x] * Z(-sx);
+      if (p.x + 1 < m.Nx) q = q + sq[p.x + 1] * Z(sx);
+    } else {
+      if (p.y > 0) q = sq[p.y] * Z(-sy);
+      if (p.y + 1 < m.Ny) q = q + sq[p.y + 1] * Z(sy);
+    }
+    us = m.h_sigma * q;
+    up = Z(0) + m.l_pi * qs;
+  }
+  const c64 T0 = co2_tab(o, p.s, p.x, p.y, p.a, t, 0);
+  const c64 T1 = co2_tab(o, p.s, p.x, p.y, p.a, t, 1);
+  const c64 T2 = co2_tab(o, p.s, p.x, p.y, p.a, t, 2);
+  wa = T0 * us + T1 * up;
+  wb = T1 * us + T2 * up;
+}
+
+// Phase 2 at point i: y = (E - E_nu) z - U z - F z.
+__device__ inline c64 co2_phase2(const Co2Op& o, const double* sq, const c64* v, double vs,
+                                 const c64* wA, const c64* wB, int i) {
+  const Co2Model& m = *o.m;
+  const Co2Point p = co2_point(m, i);
+  const int t = co2_type(p.x, p.y, o.px, o.py);
+  if (t == 3) return c64{0.0, 0.0};
+  const int sy = 1, sx = m.Ny, sa = m.Nx * m.Ny, ss = m.Na * m.Nx * m.Ny;
+  const int s = p.s, a = p.a, x = p.x, y = p.y;
+  auto Z = [&](int d) { return vs * v[i + d]; };
+  const c64 z0 = Z(0);
+  const int c = t == 0 ? 0 : 1;
+  const double rt = t == 0 ? 0.0 : (t == 1 ? m.c_rt : -m.c_rt);
+  // diagonal-state polynomial: E_d + k q_s + g_s q_s^2 + (g_b + rt) q_x^2 + (g_b - rt) q_y^2 + g_a q_a^2
+  c64 qs1 = c64{0.0, 0.0};
+  if (s > 0) qs1 = sq[s] * Z(-ss);
+  if (s + 1 < m.Ns) qs1 = qs1 + sq[s + 1] * Z(ss);
+  auto q2 = [&](int n, int N, int st) {
+    c64 r = q2_diag(n, N) * z0;
+    if (n >= 2) r = r + (sq[n - 1] * sq[n]) * Z(-2 * st);
+    if (n + 2 < N) r = r + (sq[n + 1] * sq[n + 2]) * Z(2 * st);
+    return r;
+  };
+  c64 U = (c == 0 ? m.E_sigma : m.E_pi) * z0 + (c == 0 ? m.k_sigma : m.k_pi) * qs1 +
+          m.gs[c] * q2(s, m.Ns, ss) + (m.gb[c] + rt) * q2(x, m.Nx, sx) +
+          (m.gb[c] - rt) * q2(y, m.Ny, sy) + m.ga[c] * q2(a, m.Na, sa);
+  // sigma - Pi couplings c (1 + c' q_s) q_x and c (1 + c' q_s) q_y
+  auto qx_at = [&](int ds) {
+    c64 r = c64{0.0, 0.0};
+    if (x > 0) r = sq[x] * Z(ds - sx);
+    if (x + 1 < m.Nx) r = r + sq[x + 1] * Z(ds + sx);
+    return r;
+  };
+  auto qy_at = [&](int ds) {
+    c64 r = c64{0.0, 0.0};
+    if (y > 0) r = sq[y] * Z(ds - sy);
+    if (y + 1 < m.Ny) r = r + sq[y + 1] * Z(ds + sy);
+    return r;
+  };
+  auto couple = [&](auto qq) {
+    c64 r = qq(0);
+    c64 sl = c64{0.0, 0.0};
+    if (s > 0) sl = sq[s] * qq(-ss);
+    if (s + 1 < m.Ns) sl = sl + sq[s + 1] * qq(ss);
+    return m.c_sp * (r + m.c_sp2 * sl);
+  };
+  if (t == 0) {
+    U = U + couple(qx_at) + couple(qy_at);
+  } else {
+    U = U + (t == 1 ? couple(qx_at) : couple(qy_at));
+    // Pi_x - Pi_y: 2 c_rt q_x q_y
+    c64 xy = c64{0.0, 0.0};
+    for (int dx = -1; dx <= 1; dx += 2) {
+      if (x + dx < 0 || x + dx >= m.Nx) continue;
+      const double ex = dx < 0 ? sq[x] : sq[x + 1];
+      for (int dy = -1; dy <= 1; dy += 2) {
+        if (y + dy < 0 || y + dy >= m.Ny) continue;
+        const double ey = dy < 0 ? sq[y] : sq[y + 1];
+        xy = xy + (ex * ey) * Z(dx * sx + dy * sy);
+      }
+    }
+    U = U + (2.0 * m.c_rt) * xy;
+  }
+  // F z: transposed sandwich of the neighbours' (w_A, w_B)
+  const c64* w = t == 0 ? wA : wB;
+  auto W = [&](int d) { return w[i + d]; };
+  c64 Fz = W(0);
+  c64 sl = c64{0.0, 0.0};
+  if (s > 0) sl = sq[s] * W(-ss);
+  if (s + 1 < m.Ns) sl = sl + sq[s + 1] * W(ss);
+  Fz = Fz + (t == 0 ? m.l_sigma : m.l_pi) * sl;
+  if (t == 0 || t == 1) {
+    c64 r = c64{0.0, 0.0};
+    if (x > 0) r = sq[x] * W(-sx);
+    if (x + 1 < m.Nx) r = r + sq[x + 1] * W(sx);
+    Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * r;
+  }
+  if (t == 0 || t == 2) {
+    c64 r = c64{0.0, 0.0};
+    if (y > 0) r = sq[y] * W(-sy);
+    if (y + 1 < m.Ny) r = r + sq[y + 1] * W(sy);
+    Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * r;
+  }
+  const double Ev = m.omega_s * (s + 0.5) + m.omega_b * (x + y + 1.0) + m.omega_a * (a + 0.5);
+  return (o.E - Ev) * z0 - U - Fz;
+}
+
+// y = A (vs v) over the whole vector by one workgroup; wA, wB are scratch
+// vectors.  Begins with a barrier (v may have just been written by other
+// threads) and ends with one.  With red given, also returns ||y||^2 (to every
+// thread) and with bsub, y = bsub - A (vs v).
+__device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* v, double vs,
+                                   c64* y, c64* wA, c64* wB, const c64* bsub = nullptr,
+                                   double* red = nullptr);
+
+// Launch arguments of the solver and of the operator / preconditioner apply.
+struct Co2Args {
+  const Co2Model* model;
+  const DevModel* ls;        // level-shift functions (widths, transform nodes)
+  const Co2Job* jobs;
+  int n_jobs;
+  const c64* tables;         // [n_energies][ntab][6]
+  int* counter;
+  c64* scratch;
+  size_t slot_elems, ld, fac_off;
+  int m, max_iter, precond;
+  double tol;
+  int n_final;
+  const int* finals;         // [n_final][4]
+  c64* T_out;                // [n_jobs][n_final][3]
+  double* sigma_out;         // [n_jobs][n_final]
+  c64* psi_out;              // [n_jobs][npts] or null
+  DevInfo* info;
+};
+
+struct Co2OpsArgs {
+  const Co2Model* model;
+  const c64* tab;            // the energy's table rows
+  double E;
+  const int* sectors;        // [n_vec][2]
+  int n_vec, which;          // 0: operator, 1: block preconditioner
+  const c64* x;
+  c64* y;
+  c64* scratch;              // per workgroup: wA, wB (2 npts) or the factor
+  size_t slot_elems;
+};
+
+// ------------------------------------------------------------------ blocks
+
+// In-plane element A((x, y), (x + dx, y + dy)) of the block (s, a), |dx|, |dy|
+// <= 2; zero where a point carries no state.
+__device__ inline c64 co2_band_entry(const Co2Op& o, const double* sq, int s, int a, int x, int y,
+                                     int dx, int dy) {
+  const Co2Model& m = *o.m;
+  const int t = co2_type(x, y, o.px, o.py);
+  const int x2 = x + dx, y2 = y + dy;
+  if (t == 3 || x2 < 0 || x2 >= m.Nx || y2 < 0 || y2 >= m.Ny) return c64{0.0, 0.0};
+  const int t2 = co2_type(x2, y2, o.px, o.py);
+  if (t2 == 3) return c64{0.0, 0.0};
+  auto Tt = [&](int xx, int yy, int k) { return co2_tab(o, s, xx, yy, a, co2_type(xx, yy, o.px, o.py), k); };
+  const double hs2 = m.h_sigma * m.h_sigma, hp2 = m.h_pi * m.h_pi;
+  if (dx == 0 && dy == 0) {
+    const int c = t == 0 ? 0 : 1;
+    const double rt = t == 0 ? 0.0 : (t == 1 ? m.c_rt : -m.c_rt);
+    const double U = (c == 0 ? m.E_sigma : m.E_pi) + m.gs[c] * q2_diag(s, m.Ns) +
+                     (m.gb[c] + rt) * q2_diag(x, m.Nx) + (m.gb[c] - rt) * q2_diag(y, m.Ny) +
+                     m.ga[c] * q2_diag(a, m.Na);
+    const double Ev = m.omega_s * (s + 0.5) + m.omega_b * (x + y + 1.0) + m.omega_a * (a + 0.5);
+    const int k = t == 0 ? 0 : 2;     // the point's own pair
+    auto along_s = [&]() {
+      c64 r = c64{0.0, 0.0};
+      if (s > 0) r = (0.5 * s) * co2_tab(o, s - 1, x, y, a, t, k);
+      if (s + 1 < m.Ns) r = r + (0.5 * (s + 1)) * co2_tab(o, s + 1, x, y, a, t, k);
+      return r;
+    };
+    auto along_x = [&](int kk) {
+      c64 r = c64{0.0, 0.0};
+      if (x > 0) r = (0.5 * x) * Tt(x - 1, y, kk);
+      if (x + 1 < m.Nx) r = r + (0.5 * (x + 1)) * Tt(x + 1, y, kk);
+      return r;
+    };
+    auto along_y = [&](int kk) {
+      c64 r = c64{0.0, 0.0};
+      if (y > 0) r = (0.5 * y) * Tt(x, y - 1, kk);
+      if (y + 1 < m.Ny) r = r + (0.5 * (y + 1)) * Tt(x, y + 1, kk);
+      return r;
+    };
+    c64 F;
+    if (t == 0)
+      F = Tt(x, y, 0) + (m.l_sigma * m.l_sigma) * along_s() + hs2 * (along_x(0) + along_y(0));
+    else
+      F = Tt(x, y, 2) + (m.l_pi * m.l_pi) * along_s() + hp2 * (t == 1 ? along_x(2) : along_y(2));
+    return c64{(o.E - Ev - U) - F.x, -F.y};
+  }
+  auto q1 = [&](int n1, int n2) { return sq[n1 > n2 ? n1 : n2]; };   // |n1 - n2| = 1
+  if ((dx == 0) != (dy == 0) && (dx == 1 || dx == -1 || dy == 1 || dy == -1)) {
+    if (t != 0 && t2 != 0) return c64{0.0, 0.0};
+    const int xs = t == 0 ? x : x2, ys = t == 0 ? y : y2;    // the sigma point
+    const int xp = t == 0 ? x2 : x, yp = t == 0 ? y2 : y;    // the Pi point
+    const double q = dx ? q1(x, x2) : q1(y, y2);
+    const c64 ch = m.h_pi * Tt(xs, ys, 1) + m.h_sigma * Tt(xp, yp, 1);
+    return c64{-(m.c_sp + ch.x) * q, -ch.y * q};
+  }
+  if (dy == 0 && (dx == 2 || dx == -2)) {
+    if (t != t2) return c64{0.0, 0.0};
+    const int xm = (x + x2) / 2;
+    const double q = q1(x, xm) * q1(xm, x2);
+    const int c = t == 0 ? 0 : 1;
+    const double rt = t == 0 ? 0.0 : (t == 1 ? m.c_rt : -m.c_rt);
+    c64 f = c64{0.0, 0.0};
+    if (t == 0) f = hs2 * Tt(xm, y, 0);
+    if (t == 1) f = hp2 * Tt(xm, y, 2);
+    return c64{-(m.gb[c] + rt + f.x) * q, -f.y * q};
+  }
+  if (dx == 0 && (dy == 2 || dy == -2)) {
+    if (t != t2) return c64{0.0, 0.0};
+    const int ym = (y + y2) / 2;
+    const double q = q1(y, ym) * q1(ym, y2);
+    const int c = t == 0 ? 0 : 1;
+    const double rt = t == 0 ? 0.0 : (t == 1 ? m.c_rt : -m.c_rt);
+    c64 f = c64{0.0, 0.0};
+    if (t == 0) f = hs2 * Tt(x, ym, 0);
+    if (t == 2) f = hp2 * Tt(x, ym, 2);
+    return c64{-(m.gb[c] - rt + f.x) * q, -f.y * q};
+  }
+  if ((dx == 1 || dx == -1) && (dy == 1 || dy == -1)) {
+    if (!((t == 1 && t2 == 2) || (t == 2 && t2 == 1))) return c64{0.0, 0.0};
+    const int xpx = t == 1 ? x : x2, ypx = t == 1 ? y : y2;   // Pi_x point
+    const int xpy = t == 1 ? x2 : x, ypy = t == 1 ? y2 : y;   // Pi_y point
+    const int kx = xpy, ky = ypx;                             // the sigma point between
+    const double q = q1(xpx, kx) * q1(ky, ypy);
+    const c64 f = hp2 * Tt(kx, ky, 2);
+    return c64{-(2.0 * m.c_rt + f.x) * q, -f.y * q};
+  }
+  return c64{0.0, 0.0};
+}
+
+}  // namespace vdc

@@ -58,6 +58,20 @@ class JobInfo(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double)]
 
 
+class Co2Desc(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in (
+        "omega_s", "omega_b", "omega_a", "E_sigma", "E_pi", "k_sigma", "k_pi", "gs_sigma",
+        "gb_sigma", "ga_sigma", "gs_pi", "gb_pi", "ga_pi", "c_rt", "c_sp", "c_sp2", "l_sigma",
+        "l_pi", "h_sigma", "h_pi")] + [
+        ("A", (ctypes.c_double * 2) * 2), ("B", (ctypes.c_double * 2) * 2),
+        ("Ns", ctypes.c_int), ("Nx", ctypes.c_int), ("Ny", ctypes.c_int), ("Na", ctypes.c_int),
+        ("hilbert_nodes", ctypes.c_int), ("hilbert_xmax", ctypes.c_double)]
+
+
+class Co2Job(ctypes.Structure):
+    _fields_ = [("eps_i", ctypes.c_double), ("v", ctypes.c_int * 4), ("mu_i", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -92,6 +106,15 @@ def lib():
         "vdc_matvec_block_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
         "vdc_matvec_block": (I, [P, D, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
         "vdc_last_kernel_times": (I, [ctypes.POINTER(D), ctypes.POINTER(D)]),
+        "vdc_co2_create": (I, [ctypes.POINTER(Co2Desc), ctypes.POINTER(P)]),
+        "vdc_co2_destroy": (I, [P]),
+        "vdc_co2_workspace_size": (I, [P, ctypes.POINTER(SolveOpts), I, ctypes.POINTER(Co2Job),
+                                       ctypes.POINTER(S)]),
+        "vdc_co2_solve": (I, [P, ctypes.POINTER(SolveOpts), I, ctypes.POINTER(Co2Job), I,
+                              ctypes.POINTER(ctypes.c_int), P, P, P, ctypes.POINTER(JobInfo), P, S,
+                              P]),
+        "vdc_co2_ops_workspace_size": (I, [P, I, I, ctypes.POINTER(S)]),
+        "vdc_co2_apply": (I, [P, D, I, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
         "vdc_last_error": (ctypes.c_char_p, []),
         "vdc_version": (ctypes.c_char_p, []),
     }
@@ -341,3 +364,89 @@ class CrossSections(torch.autograd.Function):
 
 def version():
     return lib().vdc_version().decode()
+
+
+
+# ---------------------------------------------------------------- CO2-like model
+
+CO2_PARAMS = ("omega_s", "omega_b", "omega_a", "E_sigma", "E_pi", "k_sigma", "k_pi", "gs_sigma",
+              "gb_sigma", "ga_sigma", "gs_pi", "gb_pi", "ga_pi", "c_rt", "c_sp", "c_sp2",
+              "l_sigma", "l_pi", "h_sigma", "h_pi")
+
+
+class Co2Model:
+    """The CO2-like three-state, four-mode model (vdc_co2_create); ``params``
+    uses the names of inputs.co2like_params, ``sizes`` the keys s, x, y, a."""
+
+    def __init__(self, params, sizes):
+        d = Co2Desc()
+        for k in CO2_PARAMS:
+            setattr(d, k, float(params[k]))
+        for c, cn in enumerate(("sigma", "pi")):
+            for w, wn in enumerate(("s", "p")):
+                d.A[c][w] = float(params["A_%s_%s" % (cn, wn)])
+                d.B[c][w] = float(params["B_%s_%s" % (cn, wn)])
+        d.Ns, d.Nx, d.Ny, d.Na = (int(sizes[k]) for k in ("s", "x", "y", "a"))
+        d.hilbert_nodes = int(params.get("K", 4096))
+        d.hilbert_xmax = float(params.get("X", 40.0))
+        self.sizes = dict(s=d.Ns, x=d.Nx, y=d.Ny, a=d.Na)
+        self.npts = d.Ns * d.Nx * d.Ny * d.Na
+        h = ctypes.c_void_p()
+        _check(lib().vdc_co2_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vdc_co2_destroy(self.handle)
+            self.handle = None
+
+
+def co2_sector(v, mu):
+    """Sector bits (px, py) of the right-hand side Phi^{v mu} (mu 0 s, 1 p_x, 2 p_y)."""
+    return ((v[1] + (mu == 1)) & 1, (v[2] + (mu == 2)) & 1)
+
+
+def co2_solve(model, jobs, finals, opts=None, want_psi=False, stream=None):
+    """vdc_co2_solve.  jobs: (eps_i, (n_s, n_x, n_y, n_a), mu_i); finals: 4-tuples.
+    Returns (T [n_jobs, n_final, 3], sigma [n_jobs, n_final], psi or None, infos)."""
+    opts = opts or Opts(restart=20, precision=FP64)
+    n = len(jobs)
+    cj = (Co2Job * max(1, n))()
+    for k, (e, v, mu) in enumerate(jobs):
+        cj[k].eps_i = float(e)
+        for q in range(4):
+            cj[k].v[q] = int(v[q])
+        cj[k].mu_i = int(mu)
+    so = opts.c()
+    ws = ctypes.c_size_t()
+    _check(lib().vdc_co2_workspace_size(model.handle, ctypes.byref(so), n, cj, ctypes.byref(ws)))
+    nf = len(finals)
+    fin = (ctypes.c_int * max(1, 4 * nf))(*[int(c) for f in finals for c in f])
+    T = torch.zeros((n, nf, 3), dtype=torch.complex128, device="cuda")
+    sigma = torch.zeros((n, nf), dtype=torch.float64, device="cuda")
+    psi = torch.zeros((n, model.npts), dtype=torch.complex128, device="cuda") if want_psi else None
+    info = (JobInfo * max(1, n))()
+    raw, w = _aligned_workspace(ws.value, "cuda")
+    _check(lib().vdc_co2_solve(model.handle, ctypes.byref(so), n, cj, nf, fin, _ptr(T),
+                               _ptr(sigma), _ptr(psi), info, _ptr(w), ws.value,
+                               _stream_ptr(stream)))
+    infos = [dict(status=info[k].status, iters=info[k].iters, restarts=info[k].restarts,
+                  rel_res=info[k].rel_res, alg_bytes=info[k].alg_bytes) for k in range(n)]
+    return T, sigma, psi, infos
+
+
+def co2_apply(model, E, x, sectors, which=0, stream=None):
+    """vdc_co2_apply: y = A(E) x (which 0) or the block preconditioner's
+    M^{-1} x (which 1) for sector vectors x [n_vec, npts]."""
+    x = torch.as_tensor(x, dtype=torch.complex128, device="cuda").contiguous()
+    if x.dim() == 1:
+        x = x[None]
+    n = x.shape[0]
+    sec = (ctypes.c_int * max(1, 2 * n))(*[int(b) for s_ in sectors for b in s_])
+    ws = ctypes.c_size_t()
+    _check(lib().vdc_co2_ops_workspace_size(model.handle, n, int(which), ctypes.byref(ws)))
+    y = torch.empty_like(x)
+    raw, w = _aligned_workspace(ws.value, "cuda")
+    _check(lib().vdc_co2_apply(model.handle, float(E), int(which), n, sec, _ptr(x), _ptr(y),
+                               _ptr(w), ws.value, _stream_ptr(stream)))
+    return y

@@ -51,3 +51,17 @@ def test_null_arguments_rejected():
     assert L.vdc_model2d_create(None, None) == vdc.VDC_ERR_INVALID_ARG
     assert L.vdc_level_shift(None, 1, None, None, None) == vdc.VDC_ERR_INVALID_ARG
     assert L.vdc_model_destroy(None) == vdc.VDC_OK
+
+
+def test_invalid_co2_model_rejected_before_device_work():
+    from paper_2307_13483_amd import vdc
+    p = inputs.co2like_params()
+    for bad in (dict(s=4, x=4, y=32, a=2), dict(s=0, x=4, y=4, a=2)):
+        with pytest.raises(vdc.VdcError) as e:
+            vdc.Co2Model(p, bad)
+        assert e.value.code == vdc.VDC_ERR_INVALID_ARG
+    with pytest.raises(vdc.VdcError) as e:
+        vdc.Co2Model(dict(p, omega_b=0.0), dict(s=4, x=4, y=4, a=2))
+    assert e.value.code == vdc.VDC_ERR_INVALID_ARG
+    assert vdc.lib().vdc_co2_create(None, None) == vdc.VDC_ERR_INVALID_ARG
+    assert vdc.lib().vdc_co2_destroy(None) == vdc.VDC_OK

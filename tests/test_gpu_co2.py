@@ -1,0 +1,183 @@
+"""GPU parity for the CO2-like three-state, four-mode model: the operator
+and the bend-block preconditioner on sector vectors against the oracle's
+assembled matrix and its block slices, and whole solves against LU.
+
+Tolerances: the operator is compared element by element within a bound
+built from the level-shift tables' rounding (64 ulp of the transform's sum
+of magnitudes, as for the two-state model) propagated through the oracle's
+own operator structure, plus 1e-14 |A| |x|; the preconditioner apply within
+1e-10 of the result's scale (LDL^T without pivoting versus LU with
+pivoting on blocks of condition number below 1e4 here); solves as for the
+two-state model (true residual <= 1e-10 + rounding, amplitudes within 1e-8
+relative of the LU solution)."""
+import numpy as np
+import pytest
+
+from oracle import levelshift as ls
+from oracle import poly
+from oracle import precond as pc
+from oracle import solvers
+from paper_2307_13483_amd import inputs
+
+pytestmark = pytest.mark.gpu
+P = inputs.co2like_params()
+
+
+@pytest.fixture(scope="module")
+def vdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_13483_amd import vdc as v
+    v.lib()
+    return v
+
+
+def _sector_index(sizes, px, py):
+    """For every sector-vector point (grid [s][a][x][y]): the index of its
+    state's component in the oracle's full layout, or -1 where no state."""
+    Ns, Nx, Ny, Na = (sizes[k] for k in ("s", "x", "y", "a"))
+    n = Ns * Nx * Ny * Na
+    out = np.full(n, -1, dtype=np.int64)
+    k = 0
+    for s in range(Ns):
+        for a in range(Na):
+            for x in range(Nx):
+                for y in range(Ny):
+                    t = ((x + px) & 1) | (((y + py) & 1) << 1)
+                    if t != 3:
+                        out[k] = t * n + ((s * Nx + x) * Ny + y) * Na + a
+                    k += 1
+    return out
+
+
+def _bound_tables(p, eps):
+    """Rounding bounds of the six level-shift functions (hook of PolyModel)."""
+    x = ls.grid_nodes(p["K"], p["X"])
+    out = {}
+    for w in ("s", "p"):
+        l = 0 if w == "s" else 1
+        pars = {"sigma": (p["A_sigma_" + w], p["B_sigma_" + w]), "pi": (p["A_pi_" + w], p["B_pi_" + w])}
+        for key, (c1, c2) in (("ss", ("sigma", "sigma")), ("sp", ("sigma", "pi")), ("pp", ("pi", "pi"))):
+            A1, B1 = pars[c1]
+            A2, B2 = pars[c2]
+            g = ls.pair_g(x, A1, B1, A2, B2, l)
+            sl = np.diff(g) / np.diff(x)
+            c = np.concatenate([[sl[0]], np.diff(sl), [-sl[-1]]])
+            b = []
+            for e in np.atleast_1d(eps):
+                t = e - x
+                psi = np.abs(t * np.log(np.abs(np.where(t == 0, 1.0, t))))
+                b.append(64 * 2.2e-16 * np.sum(np.abs(c) * psi) / (2 * np.pi) + 1e-15)
+            out[(w, key)] = np.array(b) + 0j
+    return out
+
+
+@pytest.mark.parametrize("sizes,eps", [(dict(s=5, x=6, y=7, a=4), 1.7), (dict(s=3, x=9, y=4, a=3), 3.1),
+                                       (dict(s=1, x=2, y=3, a=1), 0.6)])
+def test_operator_matches_assembled_matrix(vdc, sizes, eps):
+    E = poly.total_energy(P, eps, (0, 0, 0, 0))
+    M = poly.PolyModel(P, sizes, E)
+    A = M.matrix().tocsr()
+    Mb = poly.PolyModel(P, sizes, E, tables=_bound_tables)
+    model = vdc.Co2Model(P, sizes)
+    rng = np.random.default_rng(3)
+    sectors = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    xs, fulls = [], []
+    for (px, py) in sectors:
+        idx = _sector_index(sizes, px, py)
+        z = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+        z[idx < 0] = 0
+        full = np.zeros(3 * M.n, dtype=complex)
+        full[idx[idx >= 0]] = z[idx >= 0]
+        xs.append(z)
+        fulls.append(full)
+    y = vdc.co2_apply(model, E, np.array(xs), sectors, which=0).cpu().numpy()
+    for k, (px, py) in enumerate(sectors):
+        idx = _sector_index(sizes, px, py)
+        ref = A @ fulls[k]
+        got = np.zeros_like(ref)
+        got[idx[idx >= 0]] = y[k][idx >= 0]
+        assert np.all(y[k][idx < 0] == 0)
+        ax = np.abs(fulls[k])
+        # 1e-14 |A| |x| for the arithmetic, plus the table bounds propagated
+        # through the sandwich: |F_bound| |x|, row block by row block
+        Fb_rows = np.concatenate([sum(abs(Mb.F_block(d1, d2)) @ ax[d2 * M.n:(d2 + 1) * M.n]
+                                      for d2 in range(3)) for d1 in range(3)])
+        bound = 1e-14 * (abs(A) @ ax) + np.abs(Fb_rows) + 1e-15
+        assert np.all(np.abs(got - ref) <= bound), (px, py)
+
+
+@pytest.mark.parametrize("sizes,eps", [(dict(s=3, x=6, y=6, a=2), 2.0), (dict(s=2, x=7, y=5, a=3), 0.9)])
+def test_block_preconditioner_matches_block_slices(vdc, sizes, eps):
+    E = poly.total_energy(P, eps, (0, 0, 0, 0))
+    M = poly.PolyModel(P, sizes, E)
+    A = M.matrix().tocsr()
+    Minv = pc.BlockInverse(A, poly.bend_blocks(sizes))
+    model = vdc.Co2Model(P, sizes)
+    rng = np.random.default_rng(4)
+    sectors = [(0, 0), (1, 0), (0, 1)]
+    xs, fulls = [], []
+    for (px, py) in sectors:
+        idx = _sector_index(sizes, px, py)
+        z = rng.standard_normal(idx.size) + 1j * rng.standard_normal(idx.size)
+        z[idx < 0] = 0
+        full = np.zeros(3 * M.n, dtype=complex)
+        full[idx[idx >= 0]] = z[idx >= 0]
+        xs.append(z)
+        fulls.append(full)
+    y = vdc.co2_apply(model, E, np.array(xs), sectors, which=1).cpu().numpy()
+    for k, (px, py) in enumerate(sectors):
+        idx = _sector_index(sizes, px, py)
+        ref = Minv(fulls[k])
+        assert np.max(np.abs(y[k][idx >= 0] - ref[idx[idx >= 0]])) <= 1e-10 * np.max(np.abs(ref))
+        assert np.all(y[k][idx < 0] == 0)
+
+
+def _check(vdc, sizes, jobs, finals, T, sigma, psi, infos, tol=1e-10):
+    for k, (eps, v, mu) in enumerate(jobs):
+        E = poly.total_energy(P, eps, v)
+        M = poly.PolyModel(P, sizes, E)
+        A = M.matrix().tocsr()
+        b = M.phi(v, poly.WAVES[mu])
+        x_lu = solvers.lu_solve(A, b)
+        px, py = vdc.co2_sector(v, mu)
+        idx = _sector_index(sizes, px, py)
+        full = np.zeros(3 * M.n, dtype=complex)
+        full[idx[idx >= 0]] = psi[k][idx >= 0]
+        assert infos[k]["status"] == 0, infos[k]
+        res = np.linalg.norm(b - A @ full) / np.linalg.norm(b)
+        assert res <= tol + 1e-13
+        assert np.linalg.norm(full - x_lu) <= 1e-8 * np.linalg.norm(x_lu)
+        for f, vf in enumerate(finals):
+            for m_, muf in enumerate(poly.WAVES):
+                Tref = M.phi(vf, muf) @ x_lu
+                assert abs(T[k, f, m_] - Tref) <= 1e-8 * max(1e-300, np.max(np.abs(x_lu))) * 10
+        eps_h = eps / ls.HARTREE_EV
+        sig = 2 * np.pi ** 3 / eps_h * np.sum(np.abs(T[k]) ** 2, axis=1)
+        assert np.allclose(sigma[k], sig, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_solves_match_lu(vdc, precond):
+    sizes = dict(s=4, x=6, y=6, a=2)
+    jobs = [(e, (0, 0, 0, 0), mu) for e in (0.6, 2.1) for mu in (0, 1, 2)] + [(1.4, (1, 1, 0, 0), 0)]
+    finals = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 2, 0, 0), (0, 1, 1, 0)]
+    model = vdc.Co2Model(P, sizes)
+    opts = vdc.Opts(restart=20, precision=vdc.FP64, precond=precond)
+    T, sigma, psi, infos = vdc.co2_solve(model, jobs, finals, opts, want_psi=True)
+    _check(vdc, sizes, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+
+
+def test_iterations_track_textbook_gmres(vdc):
+    sizes = dict(s=5, x=8, y=8, a=3)
+    jobs = [(2.0, (0, 0, 0, 0), 0), (2.0, (0, 0, 0, 0), 1), (3.3, (0, 0, 0, 0), 2)]
+    model = vdc.Co2Model(P, sizes)
+    _, _, _, infos = vdc.co2_solve(model, jobs, [(0, 0, 0, 0)],
+                                   vdc.Opts(restart=20, precision=vdc.FP64, precond=vdc.PREC_BLOCK))
+    for k, (eps, v, mu) in enumerate(jobs):
+        M = poly.PolyModel(P, sizes, poly.total_energy(P, eps, v))
+        A = M.matrix().tocsr()
+        b = M.phi(v, poly.WAVES[mu])
+        _, info = solvers.gmres(A, b, m=20, tol=1e-10, psolve=pc.BlockInverse(A, poly.bend_blocks(sizes)))
+        assert abs(infos[k]["iters"] - info["iters"]) <= 2, (infos[k], info)
