@@ -52,64 +52,123 @@ __device__ inline c64 co2_plane_entry(const Co2Op& o, const double* sq, int s, i
 }
 
 // Factor every plane block into fac ([plane][j][w + 1]: 1/D_j, then
-// L(j + k, j) for k = 1..w), w = 2 Ny the half bandwidth.  Right-looking
-// elimination on a ring of w + 1 columns in LDS (column c holds A(c + k, c),
-// k = 0..w, as updated so far).  A plane whose pivot falls below 1e-14 of its
-// diagonal entry is replaced by its diagonal.  Barriers inside.
+// L(j + k, j) for k = 1..w), w = 2 Ny the half bandwidth.
+//   1. The band of every block, A(c + k, c), is written into fac by all
+//      threads at once (only the in-plane neighbour offsets can be nonzero).
+//   2. Each plane is eliminated right-looking on a ring of w + 1 + kCo2Cols
+//      columns in LDS (column c holds A(c + k, c), k = 0..w, as updated so
+//      far); the band columns are fetched kCo2Cols at a time, and the factor
+//      rows are staged in LDS and written back kCo2Cols at a time (over band
+//      columns already in the ring), so memory waits at one barrier in
+//      kCo2Cols rather than at every pivot.
+// A plane whose pivot falls below 1e-14 of its diagonal entry is replaced by
+// its diagonal.  Barriers inside.
+constexpr int kCo2Cols = 16;
+
+size_t co2_factor_lds_bytes(int Ny) {
+  const size_t W1 = 2 * (size_t)Ny + 1, R = W1 + kCo2Cols;
+  return (R * W1 + W1 + R + (size_t)kCo2Cols * W1) * sizeof(c64);
+}
+
 __device__ inline void co2_factor_planes(const Co2Op& o, const double* sq, c64* fac, int* flag) {
   const Co2Model& m = *o.m;
-  const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1;
-  c64* ring = reinterpret_cast<c64*>(vdc_co2_lds);   // [W1][W1]
-  c64* lrow = ring + W1 * W1;                          // [W1]
+  const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1, R = W1 + kCo2Cols;
+  const int planes = m.Ns * m.Na;
+  c64* ring = reinterpret_cast<c64*>(vdc_co2_lds);   // [R][W1]
+  c64* lrow = ring + R * W1;                           // [W1]
+  c64* diag0 = lrow + W1;                              // [R] original diagonal per slot
+  c64* fbuf = diag0 + R;                               // [kCo2Cols][W1] factor rows
   const int tid = threadIdx.x;
-  for (int P = 0; P < m.Ns * m.Na; ++P) {
-    const int s = P / m.Na, a = P - s * m.Na;
+  __syncthreads();
+  for (size_t q = tid; q < (size_t)planes * n * W1; q += kBlock) {
+    const int k = (int)(q % W1);
+    const size_t cq = q / W1;
+    const int c = (int)(cq % n), P = (int)(cq / n);
+    const int r = c + k;
+    c64 v = c64{0.0, 0.0};
+    if (r < n) {
+      const int xr = r / m.Ny, xc = c / m.Ny;
+      const int dx = xc - xr, dy = (c - xc * m.Ny) - (r - xr * m.Ny);
+      if (dx >= -2 && dy >= -2 && dy <= 2) v = co2_plane_entry(o, sq, P / m.Na, P % m.Na, r, c);
+    }
+    fac[q] = v;
+  }
+  __syncthreads();
+  // this thread's share of the rank-one update: the pairs (column offset
+  // co, row offset k), co = 1..w, k = 0..w - co, of q = tid + u kBlock; the
+  // same for every pivot (w W1 <= 62 * 63 < kUpd kBlock for Ny <= 31)
+  constexpr int kUpd = 4;
+  int uco[kUpd], uk[kUpd];
+#pragma unroll
+  for (int u = 0; u < kUpd; ++u) {
+    const int q = tid + u * kBlock;
+    const int co = q / W1 + 1, k = q - (co - 1) * W1;
+    const bool ok = q < w * W1 && k <= w - co;
+    uco[u] = ok ? co : 0;
+    uk[u] = k;
+  }
+  for (int P = 0; P < planes; ++P) {
     c64* F = fac + (size_t)P * n * W1;
-    __syncthreads();
     if (tid == 0) *flag = 1;
-    for (int q = tid; q < W1 * W1; q += kBlock) {
-      const int c = q / W1, k = q - c * W1;
-      ring[q] = (c < n && c + k < n) ? co2_plane_entry(o, sq, s, a, c + k, c) : c64{0.0, 0.0};
+    // columns 0 .. R-1 into the ring
+    for (int q = tid; q < R * W1; q += kBlock) {
+      const int c = q / W1;
+      ring[q] = c < n ? F[q] : c64{0.0, 0.0};
+      if (q % W1 == 0) diag0[c] = ring[q];
     }
     __syncthreads();
+    int sl = 0;                           // ring slot of the pivot column, j % R
     for (int j = 0; j < n; ++j) {
-      const int sl = j % W1;
       const c64 D = ring[sl * W1];
       const c64 Di = cinv<double>(D);
+      const int jb = j % kCo2Cols;
       if (tid <= w) {
         const c64 L = tid == 0 ? Di : ring[sl * W1 + tid] * Di;
         lrow[tid] = L;
-        F[(size_t)j * W1 + tid] = L;
+        fbuf[jb * W1 + tid] = L;
       }
       if (tid == 0) {
-        const c64 a0 = co2_plane_entry(o, sq, s, a, j, j);
         const double nd = sqrt(norm2(D));
-        if (!(isfinite(nd) && nd > 1e-14 * sqrt(norm2(a0)))) *flag = 0;
+        if (!(isfinite(nd) && nd > 1e-14 * sqrt(norm2(diag0[sl])))) *flag = 0;
       }
       __syncthreads();
-      // A(c + k, c) -= L(c, j) D L(c + k, j) for the next w columns; the
-      // freed slot takes column j + w + 1
-      for (int q = tid; q < W1 * W1; q += kBlock) {
-        const int co = q / W1, k = q - co * W1;
-        if (co == 0) {
-          const int cn = j + W1;
-          ring[sl * W1 + k] = (cn < n && cn + k < n) ? co2_plane_entry(o, sq, s, a, cn + k, cn)
-                                                      : c64{0.0, 0.0};
-        } else if (k <= w - co) {
-          const int slot = (j + co) % W1;
-          ring[slot * W1 + k] = ring[slot * W1 + k] - (lrow[co] * D) * lrow[co + k];
+      // A(c + k, c) -= L(c, j) D L(c + k, j) for the next w columns
+#pragma unroll
+      for (int u = 0; u < kUpd; ++u) {
+        if (uco[u] == 0) continue;
+        int slot = sl + uco[u];
+        if (slot >= R) slot -= R;
+        c64* e = ring + slot * W1 + uk[u];
+        *e = *e - (lrow[uco[u]] * D) * lrow[uco[u] + uk[u]];
+      }
+      // every kCo2Cols pivots (and at the end): the staged factor rows out,
+      // and the next kCo2Cols band columns into the slots of the columns just
+      // eliminated
+      if (jb == kCo2Cols - 1 || j + 1 == n) {
+        const int j0 = j - jb;
+        for (int q = tid; q < (j + 1 - j0) * W1; q += kBlock)
+          F[(size_t)j0 * W1 + q] = fbuf[q];
+        if (jb == kCo2Cols - 1) {
+          for (int q = tid; q < kCo2Cols * W1; q += kBlock) {
+            const int c = j + 1 - kCo2Cols + R + q / W1, k = q % W1;
+            const int slot = c % R;
+            const c64 v = c < n ? F[(size_t)c * W1 + k] : c64{0.0, 0.0};
+            ring[slot * W1 + k] = v;
+            if (k == 0) diag0[slot] = v;
+          }
         }
       }
       __syncthreads();
+      if (++sl == R) sl = 0;
     }
     if (!*flag) {
       for (int j = tid; j < n; j += kBlock) {
-        F[(size_t)j * W1] = cinv<double>(co2_plane_entry(o, sq, s, a, j, j));
+        F[(size_t)j * W1] = cinv<double>(co2_plane_entry(o, sq, P / m.Na, P % m.Na, j, j));
         for (int k = 1; k <= w; ++k) F[(size_t)j * W1 + k] = c64{0.0, 0.0};
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 __device__ inline c64 lane0(c64 v) {
@@ -404,10 +463,7 @@ __global__ void __launch_bounds__(kBlock) co2_ops_kernel(Co2OpsArgs a) {
   }
 }
 
-size_t co2_factor_lds(int Ny) {
-  const size_t W1 = 2 * (size_t)Ny + 1;
-  return (W1 * W1 + W1) * sizeof(c64);
-}
+size_t co2_factor_lds(int Ny) { return co2_factor_lds_bytes(Ny); }
 
 hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, size_t dyn, hipStream_t s) {
   hipLaunchKernelGGL(co2_gmres_kernel, dim3(n_groups), dim3(kBlock), dyn, s, a);
