@@ -231,7 +231,12 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times "
                          "(calibrates the HBM byte counters of a profiler)")
+    ap.add_argument("--co2-probe", action="store_true",
+                    help="only run the CO2-like workload (384 solves) and print its figures")
     args = ap.parse_args()
+    if args.co2_probe:
+        print(json.dumps({"co2like": co2like(args)}), flush=True)
+        return
     if args.copy_probe:
         import torch
         n = 1 << 30

@@ -288,7 +288,11 @@ typedef struct {
 vdc_status vdc_co2_create(const vdc_co2_desc* desc, vdc_co2_t* out);
 vdc_status vdc_co2_destroy(vdc_co2_t model);
 
-/* Workspace (device bytes) for vdc_co2_solve.  Host call, no device work. */
+/* Workspace (device bytes) for vdc_co2_solve.  Host call, no device work.
+ * With VDC_PREC_BLOCK it holds every job's block factor (FP32, by columns
+ * and by rows: 16 (2 Ny + 1) bytes per grid point and job, 43 MB per job at
+ * 24 x 24 x 24 x 8), so it grows with n_jobs; callers with less memory pass
+ * fewer jobs per call. */
 vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs,
                                   const vdc_co2_job* jobs, size_t* bytes);
 
@@ -297,8 +301,11 @@ vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, i
  * distinct energies): restarted FP64 GMRES(opts->restart) with right
  * preconditioning by the paper's block choice for this model class
  * (VDC_PREC_BLOCK: one block per (n_s, n_a) holding the bend plane, factored
- * once per job by complex-symmetric L D L^T; a block with a vanishing pivot
- * falls back to its diagonal), by the diagonal (VDC_PREC_JACOBI) or by none,
+ * once per job by complex-symmetric L D L^T without pivoting, formed and
+ * stored in FP32 and applied in FP64 as the exact inverse of the stored
+ * factor; a block with a vanishing pivot falls back to its diagonal; needs
+ * Ny <= 24, else VDC_ERR_UNSUPPORTED), by the diagonal (VDC_PREC_JACOBI) or
+ * by none,
  * until the FP64 true residual is <= tol ||Phi||.  opts->precision must be
  * VDC_FP64.  Then the amplitudes T[job][f][mu_f] = Phi^{v_f mu_f T} Psi
  * (Eq. (24)) for the finals (host int [n_final][4], states in the basis) and
@@ -312,7 +319,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
                          vdc_job_info* info, void* workspace, size_t ws_bytes, void* stream);
 
 /* y = A x (which = 0) or y = M^{-1} x for the block preconditioner (which =
- * 1) at total energy E, on n_vec sector vectors (device complex
+ * 1, the factor of vdc_co2_solve, Ny <= 24) at total energy E, on n_vec sector vectors (device complex
  * [n_vec][Ns*Na*Nx*Ny]), vector v in sector (sectors[2v], sectors[2v+1])
  * (host ints, 0/1).  x and y must not overlap.  Workspace:
  * vdc_co2_ops_workspace_size().  Synchronises the stream. */

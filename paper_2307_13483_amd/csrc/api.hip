@@ -30,9 +30,10 @@ hipError_t launch_matvec_full(const DevModel* md, const DevTable* tab, const c64
                               int n_vec, const int* parity_dev, const c64* x, c64* y, c64* z,
                               c64* yc, c64* wA, c64* wB, int Nc, hipStream_t s);
 size_t plain_extra_elems(size_t ncap, int m);
-hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, size_t dyn, hipStream_t s);
-hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, size_t dyn, hipStream_t s);
-size_t co2_factor_lds(int Ny);
+hipError_t launch_co2_factor(const Co2FactorArgs& a, int Ns, int Na, hipStream_t s);
+hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, hipStream_t s);
+hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, hipStream_t s);
+int co2_factor_max_ny();
 vdc_status solve_plain_impl(const SolveArgs& a, const std::vector<DevJob>& jobs,
                             const std::vector<DevModel>& models, hipStream_t s,
                             std::string& err);
@@ -864,17 +865,20 @@ double co2_vib(const Co2Model& m, int s, int b, int a) {
 
 size_t co2_ld(const Co2Model& m) { return ((size_t)m.npts + 63) / 64 * 64; }
 
+// FP32 complex entries of one job's block factor: every plane's band by
+// columns, then by rows, plus 64 entries of padding (the apply reads whole
+// 64-lane rows)
 size_t co2_fac_elems(const Co2Model& m) {
-  return (size_t)m.Ns * m.Na * m.Nx * m.Ny * (2 * m.Ny + 1);
+  return (2 * (size_t)m.Ns * m.Na * m.Nx * m.Ny * (2 * m.Ny + 1) + 64 + 31) / 32 * 32;
 }
 
 struct Co2Plan {
   std::vector<Co2Job> jobs;
   std::vector<double> energies;
-  size_t ld = 0, slot_elems = 0, fac_off = 0;
+  size_t ld = 0, slot_elems = 0, fac_job_elems = 0;
   int n_groups = 1, m = 0;
   size_t off_model = 0, off_ls = 0, off_jobs = 0, off_eps = 0, off_tab = 0, off_counter = 0,
-         off_finals = 0, off_info = 0, off_scratch = 0, total = 0;
+         off_finals = 0, off_info = 0, off_fac = 0, off_scratch = 0, total = 0;
 };
 
 vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const vdc_co2_job* jobs,
@@ -889,6 +893,8 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI && o->precond != VDC_PREC_BLOCK)
     return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
   const Co2Model& md = model->dev;
+  if (o->precond == VDC_PREC_BLOCK && md.Ny > co2_factor_max_ny())
+    return fail(VDC_ERR_UNSUPPORTED, "the block preconditioner needs Ny <= 24");
   std::map<double, int> eidx;
   for (int k = 0; k < n_jobs; ++k) {
     const vdc_co2_job& j = jobs[k];
@@ -917,9 +923,8 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
                    [](const Co2Job& a, const Co2Job& b) { return a.E > b.E; });
   P.m = o->restart;
   P.ld = co2_ld(md);
-  P.fac_off = ((size_t)(P.m + 1 + 6) * P.ld + (size_t)(P.m + 1) * P.m + 31) / 32 * 32;
-  P.slot_elems = P.fac_off + (o->precond == VDC_PREC_BLOCK ? co2_fac_elems(md) : 0);
-  P.slot_elems = (P.slot_elems + 31) / 32 * 32;
+  P.slot_elems = ((size_t)(P.m + 1 + 6) * P.ld + (size_t)(P.m + 1) * P.m + 31) / 32 * 32;
+  P.fac_job_elems = o->precond == VDC_PREC_BLOCK ? co2_fac_elems(md) : 0;
   P.n_groups = std::max(1, std::min(n_jobs, cu_count()));
   size_t off = 0;
   P.off_model = off; off = align256(off + sizeof(Co2Model));
@@ -930,6 +935,7 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   P.off_counter = off; off = align256(off + sizeof(int));
   P.off_finals = off; off = align256(off + sizeof(int) * 4 * std::max(1, n_final));
   P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
+  P.off_fac = off; off = align256(off + sizeof(c32) * P.fac_job_elems * n_jobs);
   P.off_scratch = off; off = align256(off + sizeof(c64) * P.slot_elems * P.n_groups);
   P.total = off;
   return VDC_OK;
@@ -1073,6 +1079,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   int* d_counter = reinterpret_cast<int*>(ws + P.off_counter);
   int* d_finals = reinterpret_cast<int*>(ws + P.off_finals);
   DevInfo* d_info = reinterpret_cast<DevInfo*>(ws + P.off_info);
+  c32* d_fac = reinterpret_cast<c32*>(ws + P.off_fac);
   c64* d_scratch = reinterpret_cast<c64*>(ws + P.off_scratch);
   HIPCHK(hipMemcpyAsync(d_model, &md, sizeof(Co2Model), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d_ls, &model->ls->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
@@ -1085,6 +1092,16 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   st = co2_tables(model, P.energies, d_eps, d_tab, s);
   if (st != VDC_OK) return st;
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  if (opts->precond == VDC_PREC_BLOCK) {
+    Co2FactorArgs f{};
+    f.model = d_model;
+    f.jobs = d_jobs;
+    f.n_jobs = n_jobs;
+    f.tables = d_tab;
+    f.fac = d_fac;
+    f.fac_job_elems = P.fac_job_elems;
+    HIPCHK(launch_co2_factor(f, md.Ns, md.Na, s));
+  }
   Co2Args a{};
   a.model = d_model;
   a.ls = d_ls;
@@ -1095,7 +1112,8 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   a.scratch = d_scratch;
   a.slot_elems = P.slot_elems;
   a.ld = P.ld;
-  a.fac_off = P.fac_off;
+  a.fac = d_fac;
+  a.fac_job_elems = P.fac_job_elems;
   a.m = P.m;
   a.max_iter = opts->max_iter;
   a.precond = opts->precond;
@@ -1106,7 +1124,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   a.sigma_out = sigma_out;
   a.psi_out = reinterpret_cast<c64*>(psi_out);
   a.info = d_info;
-  HIPCHK(launch_co2_gmres(a, P.n_groups, opts->precond == VDC_PREC_BLOCK ? co2_factor_lds(md.Ny) : 0, s));
+  HIPCHK(launch_co2_gmres(a, P.n_groups, s));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
   std::vector<DevInfo> hinfo(n_jobs);
   HIPCHK(hipMemcpyAsync(hinfo.data(), d_info, sizeof(DevInfo) * n_jobs, hipMemcpyDeviceToHost, s));
@@ -1128,14 +1146,18 @@ vdc_status vdc_co2_ops_workspace_size(vdc_co2_t model, int n_vec, int which, siz
   if (!model || !bytes || n_vec < 0 || (which != 0 && which != 1))
     return fail(VDC_ERR_INVALID_ARG, "bad argument");
   const Co2Model& md = model->dev;
+  if (which == 1 && md.Ny > co2_factor_max_ny())
+    return fail(VDC_ERR_UNSUPPORTED, "the block preconditioner needs Ny <= 24");
   const int groups = std::max(1, std::min(n_vec, cu_count()));
-  const size_t slot = which == 0 ? 2 * (size_t)md.npts : co2_fac_elems(md);
+  const size_t fac = which == 1 ? co2_fac_elems(md) : 0;
   size_t off = 0;
   off = align256(off + sizeof(Co2Model));
   off = align256(off + sizeof(double) * md.ntab);
   off = align256(off + sizeof(c64) * kNumF * md.ntab);
   off = align256(off + sizeof(int) * 2 * std::max(1, n_vec));
-  off = align256(off + sizeof(c64) * slot * groups);
+  off = align256(off + sizeof(Co2Job) * std::max(1, n_vec));
+  off = align256(off + sizeof(c32) * fac * std::max(1, n_vec));
+  off = align256(off + sizeof(c64) * 2 * (size_t)md.npts * groups);
   *bytes = off;
   return VDC_OK;
 }
@@ -1161,15 +1183,37 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
   double* d_eps = reinterpret_cast<double*>(ws + off); off = align256(off + sizeof(double) * md.ntab);
   c64* d_tab = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * md.ntab);
   int* d_sec = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * 2 * n_vec);
+  Co2Job* d_jobs = reinterpret_cast<Co2Job*>(ws + off); off = align256(off + sizeof(Co2Job) * n_vec);
+  const size_t fac_job = which == 1 ? co2_fac_elems(md) : 0;
+  c32* d_fac = reinterpret_cast<c32*>(ws + off); off = align256(off + sizeof(c32) * fac_job * n_vec);
   c64* d_scratch = reinterpret_cast<c64*>(ws + off);
   const int groups = std::max(1, std::min(n_vec, cu_count()));
+  std::vector<Co2Job> vj(n_vec);
+  for (int v = 0; v < n_vec; ++v) {
+    vj[v] = Co2Job{};
+    vj[v].E = E;
+    vj[v].px = sectors[2 * v];
+    vj[v].py = sectors[2 * v + 1];
+    vj[v].table = 0;
+  }
   HIPCHK(hipMemcpyAsync(d_model, &md, sizeof(Co2Model), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d_sec, sectors, sizeof(int) * 2 * n_vec, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_jobs, vj.data(), sizeof(Co2Job) * n_vec, hipMemcpyHostToDevice, s));
   EventSet ev;
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
   st = co2_tables(model, std::vector<double>{E}, d_eps, d_tab, s);
   if (st != VDC_OK) return st;
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  if (which == 1) {
+    Co2FactorArgs f{};
+    f.model = d_model;
+    f.jobs = d_jobs;
+    f.n_jobs = n_vec;
+    f.tables = d_tab;
+    f.fac = d_fac;
+    f.fac_job_elems = fac_job;
+    HIPCHK(launch_co2_factor(f, md.Ns, md.Na, s));
+  }
   Co2OpsArgs a{};
   a.model = d_model;
   a.tab = d_tab;
@@ -1180,8 +1224,10 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
   a.x = reinterpret_cast<const c64*>(x);
   a.y = reinterpret_cast<c64*>(y);
   a.scratch = d_scratch;
-  a.slot_elems = which == 0 ? 2 * (size_t)md.npts : co2_fac_elems(md);
-  HIPCHK(launch_co2_ops(a, groups, which == 1 ? co2_factor_lds(md.Ny) : 0, s));
+  a.slot_elems = 2 * (size_t)md.npts;
+  a.fac = d_fac;
+  a.fac_job_elems = fac_job;
+  HIPCHK(launch_co2_ops(a, groups, s));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
   HIPCHK(hipStreamSynchronize(s));
   if (ev.ok) {

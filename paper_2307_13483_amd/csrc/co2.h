@@ -245,7 +245,9 @@ struct Co2Args {
   const c64* tables;         // [n_energies][ntab][6]
   int* counter;
   c64* scratch;
-  size_t slot_elems, ld, fac_off;
+  size_t slot_elems, ld;
+  const c32* fac;            // block factors, [n_jobs][planes][n][2 Ny + 1] (job order of jobs)
+  size_t fac_job_elems;
   int m, max_iter, precond;
   double tol;
   int n_final;
@@ -256,6 +258,17 @@ struct Co2Args {
   DevInfo* info;
 };
 
+// The bend-plane block factorisation of every (job, plane): one wavefront
+// per plane.
+struct Co2FactorArgs {
+  const Co2Model* model;
+  const Co2Job* jobs;        // E, sector and table row of each job
+  int n_jobs;
+  const c64* tables;
+  c32* fac;                  // [n_jobs][planes][n][2 Ny + 1]
+  size_t fac_job_elems;
+};
+
 struct Co2OpsArgs {
   const Co2Model* model;
   const c64* tab;            // the energy's table rows
@@ -264,8 +277,10 @@ struct Co2OpsArgs {
   int n_vec, which;          // 0: operator, 1: block preconditioner
   const c64* x;
   c64* y;
-  c64* scratch;              // per workgroup: wA, wB (2 npts) or the factor
+  c64* scratch;              // per workgroup: wA, wB (2 npts)
   size_t slot_elems;
+  const c32* fac;            // which == 1: the factor of every vector
+  size_t fac_job_elems;
 };
 
 // ------------------------------------------------------------------ blocks

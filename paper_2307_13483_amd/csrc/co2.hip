@@ -8,9 +8,6 @@
 
 namespace vdc {
 
-// LDS of the block factorisation: a ring of w + 1 band columns.
-extern __shared__ __align__(16) char vdc_co2_lds[];
-
 __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* v, double vs,
                                    c64* y, c64* wA, c64* wB, const c64* bsub, double* red) {
   const int n = o.m->npts;
@@ -51,192 +48,279 @@ __device__ inline c64 co2_plane_entry(const Co2Op& o, const double* sq, int s, i
   return co2_band_entry(o, sq, s, a, xr, yr, dx, dy);
 }
 
-// Factor every plane block into fac ([plane][j][w + 1]: 1/D_j, then
-// L(j + k, j) for k = 1..w), w = 2 Ny the half bandwidth.
-//   1. The band of every block, A(c + k, c), is written into fac by all
-//      threads at once (only the in-plane neighbour offsets can be nonzero).
-//   2. Each plane is eliminated right-looking on a ring of w + 1 + kCo2Cols
-//      columns in LDS (column c holds A(c + k, c), k = 0..w, as updated so
-//      far); the band columns are fetched kCo2Cols at a time, and the factor
-//      rows are staged in LDS and written back kCo2Cols at a time (over band
-//      columns already in the ring), so memory waits at one barrier in
-//      kCo2Cols rather than at every pivot.
-// A plane whose pivot falls below 1e-14 of its diagonal entry is replaced by
-// its diagonal.  Barriers inside.
-constexpr int kCo2Cols = 16;
+// ------------------------------------------------------------------ block factorisation
+//
+// Each plane block (fixed n_s, n_a; points j = x Ny + y, y fastest) is
+// banded with half bandwidth w = 2 Ny and complex symmetric; it is factored
+// A = L D L^T without pivoting (Sec. III.B), the band and its updates in
+// FP32 (pivots and multipliers formed in FP64), and stored in FP32 twice:
+// by columns, F[j][0] = 1/D_j, F[j][k] = L(j + k, j), and by rows,
+// G[i][0] = 1/D_i, G[i][k] = L(i, i - k), k = 1..w (zero before column 0),
+// so that both triangular sweeps of the apply read contiguous rows.  The
+// job's planes hold F, then G, then 64 entries of padding.  The applied
+// preconditioner is the exact inverse of that stored L D L^T, applied in
+// FP64: a fixed linear operator (its distance from the block's inverse only
+// changes the iteration count), so GMRES sees no rounding-dependent
+// preconditioner.
+//
+// One wavefront per plane.  First the wavefront writes the plane's band,
+// A(c + k, c), into the plane's own factor storage (FP32, the layout of the
+// factor).  Then the elimination runs with the active part of the band in
+// registers: lane (R mod 64) holds row R, register c the column j0 + c (j0
+// the first pivot of the current group of kFacU pivots), so a pivot needs
+// no LDS and no barrier: the pivot column reaches every lane by readlane and
+// each lane updates its own row.  After kFacU pivots the registers move down
+// by kFacU (the columns just eliminated leave) and the kFacU rows that become
+// active enter through LDS; their band entries were fetched one group
+// earlier.  Column j of the factor is written at pivot j, over band entries
+// every row has already read.
 
-size_t co2_factor_lds_bytes(int Ny) {
-  const size_t W1 = 2 * (size_t)Ny + 1, R = W1 + kCo2Cols;
-  return (R * W1 + W1 + R + (size_t)kCo2Cols * W1) * sizeof(c64);
+constexpr int kFacU = 4;                          // pivots per register shift
+constexpr int kFacMaxW = 48;                      // largest half bandwidth: Ny <= 24
+constexpr int kFacSlots = kFacMaxW + kFacU;       // register columns per row
+constexpr int kFacWaves = 4;                      // planes per workgroup
+constexpr int kFacRowW = kFacMaxW + 1;
+constexpr int kFacPre = (kFacU * kFacRowW + 63) / 64;   // band entries per lane per group
+// a pivot below this fraction of its original diagonal entry (squared
+// magnitudes) sends the plane to its diagonal
+constexpr double kFacPivotTol = 1e-10;
+
+__device__ inline double rlane(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline c64 rlane(c64 v, int l) { return c64{rlane(v.x, l), rlane(v.y, l)}; }
+__device__ inline float rlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline c32 rlane(c32 v, int l) { return c32{rlane(v.x, l), rlane(v.y, l)}; }
+__device__ inline c32 to32(c64 v) { return c32{(float)v.x, (float)v.y}; }
+__device__ inline c64 to64(c32 v) { return c64{(double)v.x, (double)v.y}; }
+
+// Orders this wavefront's LDS writes before its later LDS reads.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline void co2_factor_planes(const Co2Op& o, const double* sq, c64* fac, int* flag) {
-  const Co2Model& m = *o.m;
-  const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1, R = W1 + kCo2Cols;
-  const int planes = m.Ns * m.Na;
-  c64* ring = reinterpret_cast<c64*>(vdc_co2_lds);   // [R][W1]
-  c64* lrow = ring + R * W1;                           // [W1]
-  c64* diag0 = lrow + W1;                              // [R] original diagonal per slot
-  c64* fbuf = diag0 + R;                               // [kCo2Cols][W1] factor rows
-  const int tid = threadIdx.x;
+__global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArgs a) {
+  __shared__ double sq[kSqMax + 1];
+  __shared__ c32 stage[kFacWaves][kFacU * kFacSlots];
+  fill_sq<double>(sq);
   __syncthreads();
-  for (size_t q = tid; q < (size_t)planes * n * W1; q += kBlock) {
-    const int k = (int)(q % W1);
-    const size_t cq = q / W1;
-    const int c = (int)(cq % n), P = (int)(cq / n);
-    const int r = c + k;
-    c64 v = c64{0.0, 0.0};
-    if (r < n) {
-      const int xr = r / m.Ny, xc = c / m.Ny;
-      const int dx = xc - xr, dy = (c - xc * m.Ny) - (r - xr * m.Ny);
-      if (dx >= -2 && dy >= -2 && dy <= 2) v = co2_plane_entry(o, sq, P / m.Na, P % m.Na, r, c);
-    }
-    fac[q] = v;
-  }
-  __syncthreads();
-  // this thread's share of the rank-one update: the pairs (column offset
-  // co, row offset k), co = 1..w, k = 0..w - co, of q = tid + u kBlock; the
-  // same for every pivot (w W1 <= 62 * 63 < kUpd kBlock for Ny <= 31)
-  constexpr int kUpd = 4;
-  int uco[kUpd], uk[kUpd];
-#pragma unroll
-  for (int u = 0; u < kUpd; ++u) {
-    const int q = tid + u * kBlock;
-    const int co = q / W1 + 1, k = q - (co - 1) * W1;
-    const bool ok = q < w * W1 && k <= w - co;
-    uco[u] = ok ? co : 0;
-    uk[u] = k;
-  }
-  for (int P = 0; P < planes; ++P) {
-    c64* F = fac + (size_t)P * n * W1;
-    if (tid == 0) *flag = 1;
-    // columns 0 .. R-1 into the ring
-    for (int q = tid; q < R * W1; q += kBlock) {
-      const int c = q / W1;
-      ring[q] = c < n ? F[q] : c64{0.0, 0.0};
-      if (q % W1 == 0) diag0[c] = ring[q];
-    }
-    __syncthreads();
-    int sl = 0;                           // ring slot of the pivot column, j % R
-    for (int j = 0; j < n; ++j) {
-      const c64 D = ring[sl * W1];
-      const c64 Di = cinv<double>(D);
-      const int jb = j % kCo2Cols;
-      if (tid <= w) {
-        const c64 L = tid == 0 ? Di : ring[sl * W1 + tid] * Di;
-        lrow[tid] = L;
-        fbuf[jb * W1 + tid] = L;
-      }
-      if (tid == 0) {
-        const double nd = sqrt(norm2(D));
-        if (!(isfinite(nd) && nd > 1e-14 * sqrt(norm2(diag0[sl])))) *flag = 0;
-      }
-      __syncthreads();
-      // A(c + k, c) -= L(c, j) D L(c + k, j) for the next w columns
-#pragma unroll
-      for (int u = 0; u < kUpd; ++u) {
-        if (uco[u] == 0) continue;
-        int slot = sl + uco[u];
-        if (slot >= R) slot -= R;
-        c64* e = ring + slot * W1 + uk[u];
-        *e = *e - (lrow[uco[u]] * D) * lrow[uco[u] + uk[u]];
-      }
-      // every kCo2Cols pivots (and at the end): the staged factor rows out,
-      // and the next kCo2Cols band columns into the slots of the columns just
-      // eliminated
-      if (jb == kCo2Cols - 1 || j + 1 == n) {
-        const int j0 = j - jb;
-        for (int q = tid; q < (j + 1 - j0) * W1; q += kBlock)
-          F[(size_t)j0 * W1 + q] = fbuf[q];
-        if (jb == kCo2Cols - 1) {
-          for (int q = tid; q < kCo2Cols * W1; q += kBlock) {
-            const int c = j + 1 - kCo2Cols + R + q / W1, k = q % W1;
-            const int slot = c % R;
-            const c64 v = c < n ? F[(size_t)c * W1 + k] : c64{0.0, 0.0};
-            ring[slot * W1 + k] = v;
-            if (k == 0) diag0[slot] = v;
-          }
-        }
-      }
-      __syncthreads();
-      if (++sl == R) sl = 0;
-    }
-    if (!*flag) {
-      for (int j = tid; j < n; j += kBlock) {
-        F[(size_t)j * W1] = cinv<double>(co2_plane_entry(o, sq, P / m.Na, P % m.Na, j, j));
-        for (int k = 1; k <= w; ++k) F[(size_t)j * W1 + k] = c64{0.0, 0.0};
-      }
-    }
-    __syncthreads();
-  }
-}
-
-__device__ inline c64 lane0(c64 v) {
-  return c64{__shfl(v.x, 0), __shfl(v.y, 0)};
-}
-
-__device__ inline c64 wave_sum(c64 v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o);
-    v.y += __shfl_xor(v.y, o);
-  }
-  return v;
-}
-
-constexpr int kCo2Chunk = 4;   // factor rows loaded ahead per wavefront
-
-// z = M^{-1} (vs v) (z may be v): one wavefront per plane, forward L, D^{-1},
-// backward L^T; lane k holds the running value of row j + k.  Begins and ends
-// with a barrier.
-__device__ inline void co2_block_apply(const Co2Model& m, const c64* fac, const c64* v, double vs,
-                                       c64* z) {
-  __syncthreads();
+  const Co2Model& m = *a.model;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int planes = m.Ns * m.Na, per_job = (planes + kFacWaves - 1) / kFacWaves;
+  const int job = blockIdx.x / per_job, P = (blockIdx.x - job * per_job) * kFacWaves + wv;
+  if (job >= a.n_jobs || P >= planes) return;
+  const Co2Job& jb = a.jobs[job];
+  const Co2Op op{a.model, a.tables + (size_t)jb.table * m.ntab * kNumF, jb.E, jb.px, jb.py};
   const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1;
+  const int ps = P / m.Na, pa = P - ps * m.Na;
+  c32* F = a.fac + (size_t)job * a.fac_job_elems + (size_t)P * n * W1;
+  c32* G = F + (size_t)planes * n * W1;
+  // the entries of G before column 0; the band, A(c + k, c) at F[c W1 + k]:
+  // zeros, then the in-plane stencil entries, k = dx' Ny + dy' for the seven
+  // offsets (dx', dy'), dx' >= 0, of |dx'| + |dy'| <= 2 (points without a
+  // state carry the identity)
+  for (int q = lane; q < min(w, n) * W1; q += 64) {
+    const int i = q / W1, k = q - i * W1;
+    if (k > i) G[q] = c32{0.f, 0.f};
+  }
+  for (int q = lane; q < n * W1; q += 64) F[q] = c32{0.f, 0.f};
+  __threadfence_block();   // the zeros land before the entries below
+  for (int e = lane; e < n * 7; e += 64) {
+    const int c = e / 7, o = e - 7 * c;
+    const int xc = c / m.Ny, yc = c - xc * m.Ny;
+    const int xr = xc + (o >= 3) + (o >= 6), yr = yc + (o < 3 ? o : (o < 6 ? o - 4 : 0));
+    if (xr < m.Nx && yr >= 0 && yr < m.Ny) {
+      const int r = xr * m.Ny + yr;
+      F[(size_t)c * W1 + (r - c)] = to32(co2_plane_entry(op, sq, ps, pa, r, c));
+    }
+  }
+  __threadfence_block();   // written by every lane, read back by other lanes below
+  c32* st = stage[wv];
+  // this lane's share of a group's band entries: entry e = lane + 64 i is
+  // (row b, offset d) = A(r0 + b, r0 + b - d), e = b W1 + d (b >= kFacU: none)
+  auto row_of = [&](int i) {
+    const int e = lane + 64 * i;
+    int b = 0;
+#pragma unroll
+    for (int u = 1; u <= kFacU; ++u) b += e >= u * W1;
+    return b;
+  };
+  c32 T[kFacPre];
+  auto fetch = [&](int r0, int cnt) {
+#pragma unroll
+    for (int i = 0; i < kFacPre; ++i) {
+      const int b = row_of(i), d = lane + 64 * i - b * W1, R = r0 + b;
+      T[i] = (b < cnt && R < n && R - d >= 0) ? F[(size_t)(R - d) * W1 + d] : c32{0.f, 0.f};
+    }
+  };
+  c32 A[kFacSlots];
+#pragma unroll
+  for (int c = 0; c < kFacSlots; ++c) A[c] = c32{0.f, 0.f};
+  float d0 = 0.f;   // |original diagonal entry|^2 of this lane's row
+  // the fetched rows r0 .. r0 + cnt - 1 into their lanes, register c =
+  // column j0 + c, through LDS laid out by register
+  auto enter = [&](int r0, int cnt, int j0) {
+    for (int q = lane; q < kFacU * kFacSlots; q += 64) st[q] = c32{0.f, 0.f};
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < kFacPre; ++i) {
+      const int b = row_of(i), d = lane + 64 * i - b * W1, c = r0 - j0 + b - d;
+      if (b < cnt && c >= 0 && c < kFacSlots) st[b * kFacSlots + c] = T[i];
+    }
+    wave_lds_sync();
+    const int b = (lane - r0) & 63;
+    if (b < cnt) {
+#pragma unroll
+      for (int c = 0; c < kFacSlots; ++c) A[c] = st[b * kFacSlots + c];
+      d0 = norm2(st[b * kFacSlots + (r0 + b - j0)]);
+    }
+    wave_lds_sync();
+  };
+  for (int r0 = 0; r0 < w + kFacU && r0 < n; r0 += kFacU) {
+    const int cnt = min(kFacU, min(w + kFacU, n) - r0);
+    fetch(r0, cnt);
+    enter(r0, cnt, 0);
+  }
+  if (kFacU < n - w) fetch(kFacU + w, min(kFacU, n - kFacU - w));
+  bool ok = true;
+#pragma unroll 1
+  for (int j0 = 0; j0 < n; j0 += kFacU) {
+    // the last group may run past n: such pivots store nothing and update
+    // no row
+#pragma unroll
+    for (int t = 0; t < kFacU; ++t) {
+      const int j = j0 + t;
+      const c64 D = to64(rlane(A[t], j & 63));
+      const double nd = norm2(D);
+      if (j < n) ok = ok && isfinite(nd) && nd > kFacPivotTol * (double)rlane(d0, j & 63);
+      const c64 Di = cinv<double>(D);
+      const int r = (lane - j) & 63;            // this lane's row is j + r
+      const bool act = r >= 1 && r <= w && j + r < n;
+      const c64 L = act ? to64(A[t]) * Di : c64{0.0, 0.0};
+      if (r <= w && j < n) {
+        const c32 o = to32(r == 0 ? Di : L);
+        F[(size_t)j * W1 + r] = o;
+        if (j + r < n) G[(size_t)(j + r) * W1 + r] = o;
+      }
+      // A(j + r, j + c') -= L(j + r, j) A(j + c', j), c' = 1..48, in every
+      // lane (L = 0 in rows outside the pivot's band; offsets past w and
+      // entries right of a row's diagonal land in registers no live row
+      // uses)
+      const c32 Lf = to32(L);
+#pragma unroll
+      for (int cp = 1; cp <= kFacMaxW; ++cp) {
+        const c32 sc = rlane(A[t], (j + cp) & 63);
+        c32& e = A[t + cp];
+        e.x = fmaf(-Lf.x, sc.x, e.x);
+        e.x = fmaf(Lf.y, sc.y, e.x);
+        e.y = fmaf(-Lf.x, sc.y, e.y);
+        e.y = fmaf(-Lf.y, sc.x, e.y);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c + kFacU < kFacSlots; ++c) A[c] = A[c + kFacU];
+    // rows j0 + U + w .. enter now (their first pivot is in the next
+    // group); the group after that is fetched for the next round
+    const int nj0 = j0 + kFacU, r0 = nj0 + w;
+    if (r0 < n) {
+      enter(r0, min(kFacU, n - r0), nj0);
+      if (r0 + kFacU < n) fetch(r0 + kFacU, min(kFacU, n - r0 - kFacU));
+    }
+  }
+  if (!ok) {
+    // a vanishing pivot: the plane falls back to its diagonal
+    for (int q = lane; q < n * W1; q += 64) {
+      const int j = q / W1, k = q - j * W1;
+      const c32 o = k == 0 ? to32(cinv<double>(co2_plane_entry(op, sq, ps, pa, j, j))) : c32{0.f, 0.f};
+      F[q] = o;
+      G[q] = o;
+    }
+  }
+}
+
+// Lane i takes the value of lane i + 1, lane 63 that of lane 0 (DPP
+// wave_rol:1).
+__device__ inline int dpp_rot(int v) { return __builtin_amdgcn_mov_dpp(v, 0x134, 0xf, 0xf, false); }
+__device__ inline double lane_rot(double v) {
+  return __hiloint2double(dpp_rot(__double2hiint(v)), dpp_rot(__double2loint(v)));
+}
+__device__ inline c64 lane_rot(c64 a) { return c64{lane_rot(a.x), lane_rot(a.y)}; }
+
+// Vector values enter the sweeps through the lanes past the band: w + Q <= 63.
+constexpr int kApplyQ = 15;
+
+// z = M^{-1} (vs v) (z may be v): one wavefront per plane, two sweeps of the
+// same form.  Forward L y = vs v over the columns of L (F): lane k carries
+// the running value of row j + k; at step j lane 0 holds y_j, every other
+// lane subtracts L(j + k, j) y_j, and the lanes rotate down by one, so y_j
+// goes to lane 63.  Backward L^T z = D^{-1} y over the rows of L (G): lane k
+// carries row j - k; lane 0 holds z_j, every other lane subtracts
+// L(j, j - k) z_j, the lanes rotate.  The lanes past the band (k > w) carry
+// the next kApplyQ starting values, which enter at lane w without a
+// per-step select; after kApplyQ steps the results of the chunk sit in
+// lanes 64 - kApplyQ .. 63 and are stored, and the starting lanes are
+// refilled (a value above them needs more than kApplyQ steps to reach the
+// band).  Factor rows are loaded kApplyQ steps ahead by all 64 lanes (the
+// lanes past the band read the next row and are masked; the job's storage
+// is padded for the last row).  Steps past the plane's end only touch
+// values that are never stored.  Begins and ends with a barrier.
+__device__ __attribute__((always_inline)) inline void co2_block_apply(
+    const Co2Model& m, const c32* fac, const c64* v, double vs, c64* z) {
+  __syncthreads();
+  constexpr int Q = kApplyQ;
+  const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1, planes = m.Ns * m.Na;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool band = lane >= 1 && lane <= w;
-  for (int P = wave; P < m.Ns * m.Na; P += kWaves) {
-    const c64* F = fac + (size_t)P * n * W1;
+  const bool feed = lane > w && lane <= w + Q;   // refilled per chunk
+  const int outq = lane - (64 - Q);              // the chunk step this lane holds at its end
+  auto step = [&](c64& acc, c32& Lq, const c32* next_row) {
+    const c64 x = rlane(acc, 0);
+    const c32 Lm = band ? Lq : c32{0.f, 0.f};
+    Lq = next_row[lane];
+    const double lx = Lm.x, ly = Lm.y;
+    acc.x = fma(-lx, x.x, acc.x);
+    acc.x = fma(ly, x.y, acc.x);
+    acc.y = fma(-lx, x.y, acc.y);
+    acc.y = fma(-ly, x.x, acc.y);
+    acc = lane_rot(acc);
+  };
+  for (int P = wave; P < planes; P += kWaves) {
+    const c32* F = fac + (size_t)P * n * W1;
+    const c32* G = fac + (size_t)(planes + P) * n * W1;
     const c64* vp = v + (size_t)P * n;
     c64* zp = z + (size_t)P * n;
-    c64 acc = (lane <= w && lane < n) ? vs * vp[lane] : c64{0.0, 0.0};
-    for (int j0 = 0; j0 < n; j0 += kCo2Chunk) {
-      c64 Lr[kCo2Chunk];
+    // forward: lane k starts with row k
+    c32 Lr[Q];
 #pragma unroll
-      for (int q = 0; q < kCo2Chunk; ++q)
-        Lr[q] = (band && j0 + q < n) ? F[(size_t)(j0 + q) * W1 + lane] : c64{0.0, 0.0};
+    for (int q = 0; q < Q; ++q) Lr[q] = F[(size_t)min(q, n - 1) * W1 + lane];
+    c64 acc = lane < n && lane <= w + Q ? vs * vp[lane] : c64{0.0, 0.0};
+    for (int j0 = 0; j0 < n; j0 += Q) {
+      const int e = j0 + Q + lane;   // starting values of the next chunk
+      const c64 vnext = feed && e < n ? vs * vp[e] : c64{0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < kCo2Chunk; ++q) {
-        const int j = j0 + q;
-        if (j >= n) break;
-        const c64 yj = lane0(acc);
-        if (lane == 0) zp[j] = yj;
-        acc = acc - Lr[q] * yj;
-        acc = lane_next(acc);
-        if (lane == w) acc = (j + 1 + w < n) ? vs * vp[j + 1 + w] : c64{0.0, 0.0};
-      }
+      for (int q = 0; q < Q; ++q) step(acc, Lr[q], F + (size_t)min(j0 + q + Q, n - 1) * W1);
+      if (outq >= 0 && j0 + outq < n) zp[j0 + outq] = acc;
+      if (feed) acc = vnext;
     }
-    c64 zw = c64{0.0, 0.0};
-    for (int j1 = n - 1; j1 >= 0; j1 -= kCo2Chunk) {
-      // lane 0 holds D^{-1}_j y_j, lanes 1..w the row of L^T
-      c64 Lr[kCo2Chunk];
+    __threadfence_block();   // y, written above by several lanes, is read back below
+    // backward: lane k starts with row n - 1 - k, D^{-1} y
 #pragma unroll
-      for (int q = 0; q < kCo2Chunk; ++q) {
-        const int j = j1 - q;
-        Lr[q] = c64{0.0, 0.0};
-        if (j >= 0 && lane <= w) Lr[q] = F[(size_t)j * W1 + lane];
-        if (j >= 0 && lane == 0) Lr[q] = Lr[q] * zp[j];
-      }
+    for (int q = 0; q < Q; ++q) Lr[q] = G[(size_t)max(n - 1 - q, 0) * W1 + lane];
+    auto start = [&](int i) {
+      return i >= 0 ? to64(G[(size_t)i * W1]) * zp[i] : c64{0.0, 0.0};
+    };
+    acc = lane <= w + Q ? start(n - 1 - lane) : c64{0.0, 0.0};
+    for (int j1 = n - 1; j1 >= 0; j1 -= Q) {
+      const c64 snext = feed ? start(j1 - Q - lane) : c64{0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < kCo2Chunk; ++q) {
-        const int j = j1 - q;
-        if (j < 0) break;
-        const c64 dot = wave_sum(band ? Lr[q] * zw : c64{0.0, 0.0});
-        const c64 zj = lane0(Lr[q]) - dot;
-        if (lane == 0) zp[j] = zj;
-        zw = lane_prev(zw);
-        if (lane == 1) zw = zj;
-      }
+      for (int q = 0; q < Q; ++q) step(acc, Lr[q], G + (size_t)max(j1 - q - Q, 0) * W1);
+      if (outq >= 0 && j1 - outq >= 0) zp[j1 - outq] = acc;
+      if (feed) acc = snext;
     }
   }
   __syncthreads();
@@ -290,25 +374,24 @@ __device__ inline int co2_phi_entries(const Co2Model& m, const DevModel& ls, con
   return n;
 }
 
-
-
 struct Co2Lds {
   KrylovLds<double> K;
   double red[kRedSize];
   double sq[kSqMax + 1];
-  int job, flag;
+  int job;
 };
 
-// Byte model (passes over a sector vector of npts complex FP64 values, W1 =
-// 2 Ny + 1 factor entries per point): setup: x, b written, b read, V_0
-// copied (5), plus the factor written (W1) or dinv written (1); Arnoldi step:
-// M^{-1} (vector and factor read, zt written: W1 + 2) or the diagonal (v,
-// dinv read, zt written: 3), then the operator (zt read twice, w_A, w_B
-// written and read, y written: 7), and the projection passes of
-// cycle_passes (which counts 6 for an operator of its own); cycle end with k
-// steps: the update (basis k and x in/out, with M^{-1}: zt written and read
-// back, W1 + 2 for M^{-1}: k + W1 + 6; with the diagonal: k + 3) and the true
-// residual (x twice, w_A, w_B twice, b, residual out: 8).
+// Byte model (passes over a sector vector of npts complex FP64 values; the
+// FP32 factor of W1 = 2 Ny + 1 entries per point, stored by columns and by
+// rows, is W1 passes): setup: x, b written, b read, V_0 copied (5), plus the
+// factor written by the factor kernel (W1) or dinv written (1); Arnoldi
+// step: M^{-1} (the columns read forward, the rows backward, and the vector
+// in, y out, y in, zt out: W1 + 4) or the diagonal (v, dinv read, zt written: 3), then the
+// operator (zt read twice, w_A, w_B written and read, y written: 7), and the
+// projection passes of cycle_passes (which counts 6 for an operator of its
+// own); cycle end with k steps: the update (basis k and zt out, M^{-1} in
+// place, x in/out and zt in: k + W1 + 8; with the diagonal: k + 3) and the
+// true residual (x twice, w_A, w_B twice, b, residual out: 8).
 __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
   __shared__ Co2Lds L;
   fill_sq<double>(L.sq);
@@ -326,7 +409,6 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
   c64* wB = wA + ld;
   c64* dinv = wB + ld;
   c64* Rm = dinv + ld;
-  c64* fac = slot + a.fac_off;
   const bool blk = a.precond == VDC_PREC_BLOCK;
   const double W1 = 2.0 * md.Ny + 1.0;
   for (;;) {
@@ -337,9 +419,9 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
     if (js >= a.n_jobs) break;
     const Co2Job jb = a.jobs[js];
     const Co2Op op{a.model, a.tables + (size_t)jb.table * md.ntab * kNumF, jb.E, jb.px, jb.py};
+    const c32* fac = blk ? a.fac + (size_t)js * a.fac_job_elems : nullptr;
     double passes = 5.0;
     if (blk) {
-      co2_factor_planes(op, L.sq, fac, &L.flag);
       passes += W1;
     } else if (a.precond == VDC_PREC_JACOBI) {
       co2_jacobi(op, L.sq, dinv);
@@ -382,8 +464,8 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
         __syncthreads();
         const CycleResult cr = krylov_cycle<double>(L.K, L.red, V, ld, npts, m, a.tol * bnorm,
                                                     a.max_iter, iters, Rm, apply);
-        passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k * ((blk ? W1 + 2.0 : 3.0) + 1.0) +
-                  (blk ? cr.k + W1 + 6.0 : cr.k + 3.0) + 8.0;
+        passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k * ((blk ? W1 + 4.0 : 3.0) + 1.0) +
+                  (blk ? cr.k + W1 + 8.0 : cr.k + 3.0) + 8.0;
         if (blk) {
           update_x<double>(V, ld, cr.k, L.K.y, L.K.vs, nullptr, zt, npts, true);
           co2_block_apply(md, fac, zt, 1.0, zt);
@@ -446,7 +528,6 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
 
 __global__ void __launch_bounds__(kBlock) co2_ops_kernel(Co2OpsArgs a) {
   __shared__ double sq[kSqMax + 1];
-  __shared__ int flag;
   fill_sq<double>(sq);
   const Co2Model& md = *a.model;
   c64* slot = a.scratch + (size_t)blockIdx.x * a.slot_elems;
@@ -457,21 +538,29 @@ __global__ void __launch_bounds__(kBlock) co2_ops_kernel(Co2OpsArgs a) {
     if (a.which == 0) {
       co2_apply(op, sq, xv, 1.0, yv, slot, slot + md.npts);
     } else {
-      co2_factor_planes(op, sq, slot, &flag);
-      co2_block_apply(md, slot, xv, 1.0, yv);
+      co2_block_apply(md, a.fac + (size_t)v * a.fac_job_elems, xv, 1.0, yv);
     }
   }
 }
 
-size_t co2_factor_lds(int Ny) { return co2_factor_lds_bytes(Ny); }
+int co2_factor_max_ny() { return kFacMaxW / 2; }
 
-hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, size_t dyn, hipStream_t s) {
-  hipLaunchKernelGGL(co2_gmres_kernel, dim3(n_groups), dim3(kBlock), dyn, s, a);
+hipError_t launch_co2_factor(const Co2FactorArgs& a, int Ns, int Na, hipStream_t s) {
+  const int per_job = (Ns * Na + kFacWaves - 1) / kFacWaves;
+  const size_t groups = (size_t)per_job * a.n_jobs;
+  if (groups == 0) return hipSuccess;
+  if (groups > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(co2_factor_kernel, dim3((unsigned)groups), dim3(64 * kFacWaves), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, size_t dyn, hipStream_t s) {
-  hipLaunchKernelGGL(co2_ops_kernel, dim3(n_groups), dim3(kBlock), dyn, s, a);
+hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, hipStream_t s) {
+  hipLaunchKernelGGL(co2_gmres_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, hipStream_t s) {
+  hipLaunchKernelGGL(co2_ops_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
