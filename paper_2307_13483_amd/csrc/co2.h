@@ -99,6 +99,13 @@ __device__ inline c64 co2_tab(const Co2Op& o, int s, int x, int y, int a, int t,
   return o.tab[((size_t)(s * m.nb + x + y) * m.Na + a) * kNumF + 3 * w + k];
 }
 
+// The operator at one point is branch-free in its memory accesses: every
+// neighbour is loaded unconditionally, from the point itself where the
+// neighbour lies past the basis edge, and weighted by zero there (the
+// weights are sqrt(n/2) read at index 0 = 0), so that all loads of a point
+// can be in flight together.  Terms are added in the same order as a
+// branchy evaluation would add them (a skipped term adds zero).
+
 // Phase 1 at point i: the pointwise level-shift products (w_A, w_B) of the
 // channel that reaches the point.
 __device__ inline void co2_phase1(const Co2Op& o, const double* sq, const c64* v, double vs,
@@ -106,39 +113,24 @@ __device__ inline void co2_phase1(const Co2Op& o, const double* sq, const c64* v
   const Co2Model& m = *o.m;
   const Co2Point p = co2_point(m, i);
   const int t = co2_type(p.x, p.y, o.px, o.py);
-  wa = wb = c64{0.0, 0.0};
-  if (t == 3) return;
   const int sy = 1, sx = m.Ny, ss = m.Na * m.Nx * m.Ny;
-  auto Z = [&](int d) { return vs * v[i + d]; };
-  c64 qs = c64{0.0, 0.0};
-  if (p.s > 0) qs = sq[p.s] * Z(-ss);
-  if (p.s + 1 < m.Ns) qs = qs + sq[p.s + 1] * Z(ss);
-  c64 us, up;
-  if (t == 0) {
-    c64 q = c64{0.0, 0.0};
-    if (p.x > 0) q = sq[p.x] * Z(-sx);
-    if (p.x + 1 < m.Nx) q = q + sq[p.x + 1] * Z(sx);
-    if (p.y > 0) q = q + sq[p.y] * Z(-sy);
-    if (p.y + 1 < m.Ny) q = q + sq[p.y + 1] * Z(sy);
-    us = Z(0) + m.l_sigma * qs;
-    up = m.h_pi * q;
-  } else {
-    c64 q = c64{0.0, 0.0};
-    if (t == 1) {
-      if (p.x > 0) q = sq[p.x] * Z(-sx);
-      if (p.x + 1 < m.Nx) q = q + sq[p.x + 1] * Z(sx);
-    } else {
-      if (p.y > 0) q = sq[p.y] * Z(-sy);
-      if (p.y + 1 < m.Ny) q = q + sq[p.y + 1] * Z(sy);
-    }
-    us = m.h_sigma * q;
-    up = Z(0) + m.l_pi * qs;
-  }
-  const c64 T0 = co2_tab(o, p.s, p.x, p.y, p.a, t, 0);
-  const c64 T1 = co2_tab(o, p.s, p.x, p.y, p.a, t, 1);
-  const c64 T2 = co2_tab(o, p.s, p.x, p.y, p.a, t, 2);
+  auto Z = [&](bool ok, int d) { return vs * v[ok ? i + d : i]; };
+  // sqrt(n/2) z(n - 1) + sqrt((n + 1)/2) z(n + 1) along one mode
+  auto pair = [&](int n, int N, int st) {
+    const bool lo = n > 0, hi = n + 1 < N;
+    return sq[lo ? n : 0] * Z(lo, -st) + sq[hi ? n + 1 : 0] * Z(hi, st);
+  };
+  const c64 z0 = vs * v[i];
+  const c64 qs = pair(p.s, m.Ns, ss), qx = pair(p.x, m.Nx, sx), qy = pair(p.y, m.Ny, sy);
+  const int tt = t == 3 ? 0 : t;
+  const c64 T0 = co2_tab(o, p.s, p.x, p.y, p.a, tt, 0);
+  const c64 T1 = co2_tab(o, p.s, p.x, p.y, p.a, tt, 1);
+  const c64 T2 = co2_tab(o, p.s, p.x, p.y, p.a, tt, 2);
+  const c64 us = t == 0 ? z0 + m.l_sigma * qs : m.h_sigma * (t == 1 ? qx : qy);
+  const c64 up = t == 0 ? m.h_pi * (qx + qy) : z0 + m.l_pi * qs;
   wa = T0 * us + T1 * up;
   wb = T1 * us + T2 * up;
+  if (t == 3) wa = wb = c64{0.0, 0.0};
 }
 
 // Phase 2 at point i: y = (E - E_nu) z - U z - F z.
@@ -147,85 +139,53 @@ __device__ inline c64 co2_phase2(const Co2Op& o, const double* sq, const c64* v,
   const Co2Model& m = *o.m;
   const Co2Point p = co2_point(m, i);
   const int t = co2_type(p.x, p.y, o.px, o.py);
-  if (t == 3) return c64{0.0, 0.0};
   const int sy = 1, sx = m.Ny, sa = m.Nx * m.Ny, ss = m.Na * m.Nx * m.Ny;
   const int s = p.s, a = p.a, x = p.x, y = p.y;
-  auto Z = [&](int d) { return vs * v[i + d]; };
-  const c64 z0 = Z(0);
+  auto Z = [&](bool ok, int d) { return vs * v[ok ? i + d : i]; };
+  const c64 z0 = vs * v[i];
   const int c = t == 0 ? 0 : 1;
   const double rt = t == 0 ? 0.0 : (t == 1 ? m.c_rt : -m.c_rt);
   // diagonal-state polynomial: E_d + k q_s + g_s q_s^2 + (g_b + rt) q_x^2 + (g_b - rt) q_y^2 + g_a q_a^2
-  c64 qs1 = c64{0.0, 0.0};
-  if (s > 0) qs1 = sq[s] * Z(-ss);
-  if (s + 1 < m.Ns) qs1 = qs1 + sq[s + 1] * Z(ss);
+  const bool s_lo = s > 0, s_hi = s + 1 < m.Ns;
+  const double ws_lo = sq[s_lo ? s : 0], ws_hi = sq[s_hi ? s + 1 : 0];
+  const c64 qs1 = ws_lo * Z(s_lo, -ss) + ws_hi * Z(s_hi, ss);
   auto q2 = [&](int n, int N, int st) {
-    c64 r = q2_diag(n, N) * z0;
-    if (n >= 2) r = r + (sq[n - 1] * sq[n]) * Z(-2 * st);
-    if (n + 2 < N) r = r + (sq[n + 1] * sq[n + 2]) * Z(2 * st);
-    return r;
+    const bool lo = n >= 2, hi = n + 2 < N;
+    return q2_diag(n, N) * z0 + (sq[lo ? n - 1 : 0] * sq[lo ? n : 0]) * Z(lo, -2 * st) +
+           (sq[hi ? n + 1 : 0] * sq[hi ? n + 2 : 0]) * Z(hi, 2 * st);
   };
   c64 U = (c == 0 ? m.E_sigma : m.E_pi) * z0 + (c == 0 ? m.k_sigma : m.k_pi) * qs1 +
           m.gs[c] * q2(s, m.Ns, ss) + (m.gb[c] + rt) * q2(x, m.Nx, sx) +
           (m.gb[c] - rt) * q2(y, m.Ny, sy) + m.ga[c] * q2(a, m.Na, sa);
-  // sigma - Pi couplings c (1 + c' q_s) q_x and c (1 + c' q_s) q_y
-  auto qx_at = [&](int ds) {
-    c64 r = c64{0.0, 0.0};
-    if (x > 0) r = sq[x] * Z(ds - sx);
-    if (x + 1 < m.Nx) r = r + sq[x + 1] * Z(ds + sx);
-    return r;
+  // sigma - Pi couplings c (1 + c' q_s) q_x and c (1 + c' q_s) q_y, at the
+  // point's s - 1, s, s + 1
+  const bool x_lo = x > 0, x_hi = x + 1 < m.Nx, y_lo = y > 0, y_hi = y + 1 < m.Ny;
+  const double wx_lo = sq[x_lo ? x : 0], wx_hi = sq[x_hi ? x + 1 : 0];
+  const double wy_lo = sq[y_lo ? y : 0], wy_hi = sq[y_hi ? y + 1 : 0];
+  auto qx_at = [&](bool ok, int ds) {
+    return wx_lo * Z(ok && x_lo, ds - sx) + wx_hi * Z(ok && x_hi, ds + sx);
   };
-  auto qy_at = [&](int ds) {
-    c64 r = c64{0.0, 0.0};
-    if (y > 0) r = sq[y] * Z(ds - sy);
-    if (y + 1 < m.Ny) r = r + sq[y + 1] * Z(ds + sy);
-    return r;
+  auto qy_at = [&](bool ok, int ds) {
+    return wy_lo * Z(ok && y_lo, ds - sy) + wy_hi * Z(ok && y_hi, ds + sy);
   };
-  auto couple = [&](auto qq) {
-    c64 r = qq(0);
-    c64 sl = c64{0.0, 0.0};
-    if (s > 0) sl = sq[s] * qq(-ss);
-    if (s + 1 < m.Ns) sl = sl + sq[s + 1] * qq(ss);
-    return m.c_sp * (r + m.c_sp2 * sl);
-  };
-  if (t == 0) {
-    U = U + couple(qx_at) + couple(qy_at);
-  } else {
-    U = U + (t == 1 ? couple(qx_at) : couple(qy_at));
-    // Pi_x - Pi_y: 2 c_rt q_x q_y
-    c64 xy = c64{0.0, 0.0};
-    for (int dx = -1; dx <= 1; dx += 2) {
-      if (x + dx < 0 || x + dx >= m.Nx) continue;
-      const double ex = dx < 0 ? sq[x] : sq[x + 1];
-      for (int dy = -1; dy <= 1; dy += 2) {
-        if (y + dy < 0 || y + dy >= m.Ny) continue;
-        const double ey = dy < 0 ? sq[y] : sq[y + 1];
-        xy = xy + (ex * ey) * Z(dx * sx + dy * sy);
-      }
-    }
-    U = U + (2.0 * m.c_rt) * xy;
-  }
+  const c64 cx = m.c_sp * (qx_at(true, 0) + m.c_sp2 * (ws_lo * qx_at(s_lo, -ss) + ws_hi * qx_at(s_hi, ss)));
+  const c64 cy = m.c_sp * (qy_at(true, 0) + m.c_sp2 * (ws_lo * qy_at(s_lo, -ss) + ws_hi * qy_at(s_hi, ss)));
+  // Pi_x - Pi_y: 2 c_rt q_x q_y
+  const c64 xy = (wx_lo * wy_lo) * Z(x_lo && y_lo, -sx - sy) + (wx_lo * wy_hi) * Z(x_lo && y_hi, -sx + sy) +
+                 (wx_hi * wy_lo) * Z(x_hi && y_lo, sx - sy) + (wx_hi * wy_hi) * Z(x_hi && y_hi, sx + sy);
+  U = t == 0 ? (U + cx) + cy : (U + (t == 1 ? cx : cy)) + (2.0 * m.c_rt) * xy;
   // F z: transposed sandwich of the neighbours' (w_A, w_B)
   const c64* w = t == 0 ? wA : wB;
-  auto W = [&](int d) { return w[i + d]; };
-  c64 Fz = W(0);
-  c64 sl = c64{0.0, 0.0};
-  if (s > 0) sl = sq[s] * W(-ss);
-  if (s + 1 < m.Ns) sl = sl + sq[s + 1] * W(ss);
-  Fz = Fz + (t == 0 ? m.l_sigma : m.l_pi) * sl;
-  if (t == 0 || t == 1) {
-    c64 r = c64{0.0, 0.0};
-    if (x > 0) r = sq[x] * W(-sx);
-    if (x + 1 < m.Nx) r = r + sq[x + 1] * W(sx);
-    Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * r;
-  }
-  if (t == 0 || t == 2) {
-    c64 r = c64{0.0, 0.0};
-    if (y > 0) r = sq[y] * W(-sy);
-    if (y + 1 < m.Ny) r = r + sq[y + 1] * W(sy);
-    Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * r;
-  }
+  auto W = [&](bool ok, int d) { return w[ok ? i + d : i]; };
+  const c64 sl = ws_lo * W(s_lo, -ss) + ws_hi * W(s_hi, ss);
+  const c64 rx = wx_lo * W(x_lo, -sx) + wx_hi * W(x_hi, sx);
+  const c64 ry = wy_lo * W(y_lo, -sy) + wy_hi * W(y_hi, sy);
+  c64 Fz = w[i] + (t == 0 ? m.l_sigma : m.l_pi) * sl;
+  if (t == 0 || t == 1) Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * rx;
+  if (t == 0 || t == 2) Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * ry;
   const double Ev = m.omega_s * (s + 0.5) + m.omega_b * (x + y + 1.0) + m.omega_a * (a + 0.5);
-  return (o.E - Ev) * z0 - U - Fz;
+  const c64 out = (o.E - Ev) * z0 - U - Fz;
+  return t == 3 ? c64{0.0, 0.0} : out;
 }
 
 // y = A (vs v) over the whole vector by one workgroup; wA, wB are scratch

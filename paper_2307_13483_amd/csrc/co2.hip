@@ -12,6 +12,7 @@ __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* 
                                    c64* y, c64* wA, c64* wB, const c64* bsub, double* red) {
   const int n = o.m->npts;
   __syncthreads();
+#pragma unroll 1
   for (int i = threadIdx.x; i < n; i += kBlock) {
     c64 a, b;
     co2_phase1(o, sq, v, vs, i, a, b);
@@ -20,6 +21,7 @@ __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* 
   }
   __syncthreads();
   double acc[1] = {0.0};
+#pragma unroll 1
   for (int i = threadIdx.x; i < n; i += kBlock) {
     c64 r = co2_phase2(o, sq, v, vs, wA, wB, i);
     if (bsub) r = bsub[i] - r;
