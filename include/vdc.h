@@ -289,8 +289,9 @@ vdc_status vdc_co2_create(const vdc_co2_desc* desc, vdc_co2_t* out);
 vdc_status vdc_co2_destroy(vdc_co2_t model);
 
 /* Workspace (device bytes) for vdc_co2_solve.  Host call, no device work.
- * With VDC_PREC_BLOCK it holds every job's block factor (FP32, by columns
- * and by rows: 16 (2 Ny + 1) bytes per grid point and job, 43 MB per job at
+ * With VDC_PREC_BLOCK it holds every job's block factor (the multipliers in
+ * FP16 by columns and by rows, 1/D in FP32, and the factor kernel's band
+ * staging: 8 (2 Ny + 1) + 64 bytes per grid point and job, 50 MB per job at
  * 24 x 24 x 24 x 8), so it grows with n_jobs; callers with less memory pass
  * fewer jobs per call. */
 vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs,
@@ -301,9 +302,9 @@ vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, i
  * distinct energies): restarted FP64 GMRES(opts->restart) with right
  * preconditioning by the paper's block choice for this model class
  * (VDC_PREC_BLOCK: one block per (n_s, n_a) holding the bend plane, factored
- * once per job by complex-symmetric L D L^T without pivoting, formed and
- * stored in FP32 and applied in FP64 as the exact inverse of the stored
- * factor; a block with a vanishing pivot falls back to its diagonal; needs
+ * once per job by complex-symmetric L D L^T without pivoting, formed in
+ * FP32, stored with L in FP16 and 1/D in FP32, and applied in FP64 as the
+ * exact inverse of the stored factor; a block with a vanishing pivot falls back to its diagonal; needs
  * Ny <= 24, else VDC_ERR_UNSUPPORTED), by the diagonal (VDC_PREC_JACOBI) or
  * by none,
  * until the FP64 true residual is <= tol ||Phi||.  opts->precision must be

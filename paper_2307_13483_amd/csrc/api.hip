@@ -865,17 +865,15 @@ double co2_vib(const Co2Model& m, int s, int b, int a) {
 
 size_t co2_ld(const Co2Model& m) { return ((size_t)m.npts + 63) / 64 * 64; }
 
-// FP32 complex entries of one job's block factor: every plane's band by
-// columns, then by rows, plus 64 entries of padding (the apply reads whole
-// 64-lane rows)
-size_t co2_fac_elems(const Co2Model& m) {
-  return (2 * (size_t)m.Ns * m.Na * m.Nx * m.Ny * (2 * m.Ny + 1) + 64 + 31) / 32 * 32;
+// Bytes of one job's block factor (Co2FacLayout)
+size_t co2_fac_bytes(const Co2Model& m) {
+  return co2_fac_layout(m.Ns * m.Na, m.Nx * m.Ny, 2 * m.Ny + 1).total;
 }
 
 struct Co2Plan {
   std::vector<Co2Job> jobs;
   std::vector<double> energies;
-  size_t ld = 0, slot_elems = 0, fac_job_elems = 0;
+  size_t ld = 0, slot_elems = 0, fac_job_bytes = 0;
   int n_groups = 1, m = 0;
   size_t off_model = 0, off_ls = 0, off_jobs = 0, off_eps = 0, off_tab = 0, off_counter = 0,
          off_finals = 0, off_info = 0, off_fac = 0, off_scratch = 0, total = 0;
@@ -924,7 +922,7 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   P.m = o->restart;
   P.ld = co2_ld(md);
   P.slot_elems = ((size_t)(P.m + 1 + 6) * P.ld + (size_t)(P.m + 1) * P.m + 31) / 32 * 32;
-  P.fac_job_elems = o->precond == VDC_PREC_BLOCK ? co2_fac_elems(md) : 0;
+  P.fac_job_bytes = o->precond == VDC_PREC_BLOCK ? co2_fac_bytes(md) : 0;
   P.n_groups = std::max(1, std::min(n_jobs, cu_count()));
   size_t off = 0;
   P.off_model = off; off = align256(off + sizeof(Co2Model));
@@ -935,7 +933,7 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   P.off_counter = off; off = align256(off + sizeof(int));
   P.off_finals = off; off = align256(off + sizeof(int) * 4 * std::max(1, n_final));
   P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
-  P.off_fac = off; off = align256(off + sizeof(c32) * P.fac_job_elems * n_jobs);
+  P.off_fac = off; off = align256(off + P.fac_job_bytes * n_jobs);
   P.off_scratch = off; off = align256(off + sizeof(c64) * P.slot_elems * P.n_groups);
   P.total = off;
   return VDC_OK;
@@ -1079,7 +1077,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   int* d_counter = reinterpret_cast<int*>(ws + P.off_counter);
   int* d_finals = reinterpret_cast<int*>(ws + P.off_finals);
   DevInfo* d_info = reinterpret_cast<DevInfo*>(ws + P.off_info);
-  c32* d_fac = reinterpret_cast<c32*>(ws + P.off_fac);
+  unsigned char* d_fac = reinterpret_cast<unsigned char*>(ws + P.off_fac);
   c64* d_scratch = reinterpret_cast<c64*>(ws + P.off_scratch);
   HIPCHK(hipMemcpyAsync(d_model, &md, sizeof(Co2Model), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(d_ls, &model->ls->dev, sizeof(DevModel), hipMemcpyHostToDevice, s));
@@ -1099,7 +1097,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
     f.n_jobs = n_jobs;
     f.tables = d_tab;
     f.fac = d_fac;
-    f.fac_job_elems = P.fac_job_elems;
+    f.fac_job_bytes = P.fac_job_bytes;
     HIPCHK(launch_co2_factor(f, md.Ns, md.Na, s));
   }
   Co2Args a{};
@@ -1113,7 +1111,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   a.slot_elems = P.slot_elems;
   a.ld = P.ld;
   a.fac = d_fac;
-  a.fac_job_elems = P.fac_job_elems;
+  a.fac_job_bytes = P.fac_job_bytes;
   a.m = P.m;
   a.max_iter = opts->max_iter;
   a.precond = opts->precond;
@@ -1149,14 +1147,14 @@ vdc_status vdc_co2_ops_workspace_size(vdc_co2_t model, int n_vec, int which, siz
   if (which == 1 && md.Ny > co2_factor_max_ny())
     return fail(VDC_ERR_UNSUPPORTED, "the block preconditioner needs Ny <= 24");
   const int groups = std::max(1, std::min(n_vec, cu_count()));
-  const size_t fac = which == 1 ? co2_fac_elems(md) : 0;
+  const size_t fac = which == 1 ? co2_fac_bytes(md) : 0;
   size_t off = 0;
   off = align256(off + sizeof(Co2Model));
   off = align256(off + sizeof(double) * md.ntab);
   off = align256(off + sizeof(c64) * kNumF * md.ntab);
   off = align256(off + sizeof(int) * 2 * std::max(1, n_vec));
   off = align256(off + sizeof(Co2Job) * std::max(1, n_vec));
-  off = align256(off + sizeof(c32) * fac * std::max(1, n_vec));
+  off = align256(off + fac * std::max(1, n_vec));
   off = align256(off + sizeof(c64) * 2 * (size_t)md.npts * groups);
   *bytes = off;
   return VDC_OK;
@@ -1184,8 +1182,8 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
   c64* d_tab = reinterpret_cast<c64*>(ws + off); off = align256(off + sizeof(c64) * kNumF * md.ntab);
   int* d_sec = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * 2 * n_vec);
   Co2Job* d_jobs = reinterpret_cast<Co2Job*>(ws + off); off = align256(off + sizeof(Co2Job) * n_vec);
-  const size_t fac_job = which == 1 ? co2_fac_elems(md) : 0;
-  c32* d_fac = reinterpret_cast<c32*>(ws + off); off = align256(off + sizeof(c32) * fac_job * n_vec);
+  const size_t fac_job = which == 1 ? co2_fac_bytes(md) : 0;
+  unsigned char* d_fac = reinterpret_cast<unsigned char*>(ws + off); off = align256(off + fac_job * n_vec);
   c64* d_scratch = reinterpret_cast<c64*>(ws + off);
   const int groups = std::max(1, std::min(n_vec, cu_count()));
   std::vector<Co2Job> vj(n_vec);
@@ -1211,7 +1209,7 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
     f.n_jobs = n_vec;
     f.tables = d_tab;
     f.fac = d_fac;
-    f.fac_job_elems = fac_job;
+    f.fac_job_bytes = fac_job;
     HIPCHK(launch_co2_factor(f, md.Ns, md.Na, s));
   }
   Co2OpsArgs a{};
@@ -1226,7 +1224,7 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
   a.scratch = d_scratch;
   a.slot_elems = 2 * (size_t)md.npts;
   a.fac = d_fac;
-  a.fac_job_elems = fac_job;
+  a.fac_job_bytes = fac_job;
   HIPCHK(launch_co2_ops(a, groups, s));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
   HIPCHK(hipStreamSynchronize(s));

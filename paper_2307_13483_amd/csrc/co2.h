@@ -196,6 +196,29 @@ __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* 
                                    c64* y, c64* wA, c64* wB, const c64* bsub = nullptr,
                                    double* red = nullptr);
 
+// Complex FP16 (the stored multipliers of the block factor).
+struct c16 { _Float16 x, y; };
+
+// One job's block factor storage in bytes, for planes of n points and W1 =
+// 2 Ny + 1: L by columns (F) and by rows (G), complex FP16 [planes][n][W1];
+// 1/D, complex FP32 [planes][n]; the band staging of the factor kernel,
+// complex FP32 [planes][n][7]; 256 bytes of padding (the apply reads whole
+// 64-lane rows).
+struct Co2FacLayout {
+  size_t F, G, Dinv, S, total;
+};
+
+__host__ __device__ inline Co2FacLayout co2_fac_layout(int planes, int n, int W1) {
+  Co2FacLayout l;
+  const size_t pn = (size_t)planes * n;
+  l.F = 0;
+  l.G = l.F + pn * W1 * sizeof(c16);
+  l.Dinv = l.G + pn * W1 * sizeof(c16);
+  l.S = (l.Dinv + pn * sizeof(c32) + 255) / 256 * 256;
+  l.total = (l.S + pn * 7 * sizeof(c32) + 256 + 255) / 256 * 256;
+  return l;
+}
+
 // Launch arguments of the solver and of the operator / preconditioner apply.
 struct Co2Args {
   const Co2Model* model;
@@ -206,8 +229,8 @@ struct Co2Args {
   int* counter;
   c64* scratch;
   size_t slot_elems, ld;
-  const c32* fac;            // block factors, [n_jobs][planes][n][2 Ny + 1] (job order of jobs)
-  size_t fac_job_elems;
+  const unsigned char* fac;  // block factors, one Co2FacLayout per job (job order of jobs)
+  size_t fac_job_bytes;
   int m, max_iter, precond;
   double tol;
   int n_final;
@@ -225,8 +248,8 @@ struct Co2FactorArgs {
   const Co2Job* jobs;        // E, sector and table row of each job
   int n_jobs;
   const c64* tables;
-  c32* fac;                  // [n_jobs][planes][n][2 Ny + 1]
-  size_t fac_job_elems;
+  unsigned char* fac;        // one Co2FacLayout per job
+  size_t fac_job_bytes;
 };
 
 struct Co2OpsArgs {
@@ -239,8 +262,8 @@ struct Co2OpsArgs {
   c64* y;
   c64* scratch;              // per workgroup: wA, wB (2 npts)
   size_t slot_elems;
-  const c32* fac;            // which == 1: the factor of every vector
-  size_t fac_job_elems;
+  const unsigned char* fac;  // which == 1: the factor of every vector
+  size_t fac_job_bytes;
 };
 
 // ------------------------------------------------------------------ blocks

@@ -55,37 +55,40 @@ __device__ inline c64 co2_plane_entry(const Co2Op& o, const double* sq, int s, i
 // Each plane block (fixed n_s, n_a; points j = x Ny + y, y fastest) is
 // banded with half bandwidth w = 2 Ny and complex symmetric; it is factored
 // A = L D L^T without pivoting (Sec. III.B), the band and its updates in
-// FP32 (pivots and multipliers formed in FP64), and stored in FP32 twice:
-// by columns, F[j][0] = 1/D_j, F[j][k] = L(j + k, j), and by rows,
-// G[i][0] = 1/D_i, G[i][k] = L(i, i - k), k = 1..w (zero before column 0),
-// so that both triangular sweeps of the apply read contiguous rows.  The
-// job's planes hold F, then G, then 64 entries of padding.  The applied
-// preconditioner is the exact inverse of that stored L D L^T, applied in
-// FP64: a fixed linear operator (its distance from the block's inverse only
-// changes the iteration count), so GMRES sees no rounding-dependent
-// preconditioner.
+// FP32 (pivots and multipliers formed in FP64).  L is stored in FP16 twice,
+// by columns, F[j][k] = L(j + k, j), and by rows, G[i][k] = L(i, i - k),
+// k = 1..w (entry 0 and entries before column 0 are zero), so that both
+// triangular sweeps of the apply read contiguous rows; 1/D is stored in
+// FP32 (Co2FacLayout).  The applied preconditioner is the exact inverse of
+// the stored L D L^T, applied in FP64: a fixed linear operator (its
+// distance from the block's inverse only changes the iteration count), so
+// GMRES sees no rounding-dependent preconditioner.
 //
-// One wavefront per plane.  First the wavefront writes the plane's band,
-// A(c + k, c), into the plane's own factor storage (FP32, the layout of the
-// factor).  Then the elimination runs with the active part of the band in
-// registers: lane (R mod 64) holds row R, register c the column j0 + c (j0
-// the first pivot of the current group of kFacU pivots), so a pivot needs
-// no LDS and no barrier: the pivot column reaches every lane by readlane and
-// each lane updates its own row.  After kFacU pivots the registers move down
-// by kFacU (the columns just eliminated leave) and the kFacU rows that become
-// active enter through LDS; their band entries were fetched one group
-// earlier.  Column j of the factor is written at pivot j, over band entries
-// every row has already read.
+// One wavefront per plane.  First the wavefront writes the plane's nonzero
+// band entries to the staging area S: for column c and the seven stencil
+// offsets o, (dx', dy') with dx' >= 0 of |dx'| + |dy'| <= 2, the entry
+// A(c + dx' Ny + dy', c) (zero where that point lies outside the plane;
+// points without a state carry the identity).  Then the elimination runs
+// with the active part of the band in registers: lane (R mod 64) holds row
+// R, register c the column j0 + c (j0 the first pivot of the current group
+// of kFacU pivots), so a pivot needs no LDS and no barrier: the pivot column
+// reaches every lane by readlane and each lane updates its own row.  After
+// kFacU pivots the registers move down by kFacU (the columns just eliminated
+// leave) and the kFacU rows that become active enter through LDS; their
+// band entries were fetched one group earlier.
 
 constexpr int kFacU = 4;                          // pivots per register shift
 constexpr int kFacMaxW = 48;                      // largest half bandwidth: Ny <= 24
 constexpr int kFacSlots = kFacMaxW + kFacU;       // register columns per row
 constexpr int kFacWaves = 4;                      // planes per workgroup
-constexpr int kFacRowW = kFacMaxW + 1;
-constexpr int kFacPre = (kFacU * kFacRowW + 63) / 64;   // band entries per lane per group
+constexpr int kFacStencil = 7;                    // stencil offsets per column
 // a pivot below this fraction of its original diagonal entry (squared
 // magnitudes) sends the plane to its diagonal
 constexpr double kFacPivotTol = 1e-10;
+
+// Stencil offset o = 0..6: (dx', dy') = (0,0) (0,1) (0,2) (1,-1) (1,0) (1,1) (2,0).
+__host__ __device__ inline int stencil_dx(int o) { return (o >= 3) + (o >= 6); }
+__host__ __device__ inline int stencil_dy(int o) { return o < 3 ? o : (o < 6 ? o - 4 : 0); }
 
 __device__ inline double rlane(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
@@ -98,6 +101,8 @@ __device__ inline float rlane(float v, int l) {
 __device__ inline c32 rlane(c32 v, int l) { return c32{rlane(v.x, l), rlane(v.y, l)}; }
 __device__ inline c32 to32(c64 v) { return c32{(float)v.x, (float)v.y}; }
 __device__ inline c64 to64(c32 v) { return c64{(double)v.x, (double)v.y}; }
+__device__ inline c16 to16(c64 v) { return c16{(_Float16)(float)v.x, (_Float16)(float)v.y}; }
+__device__ inline c64 to64(c16 v) { return c64{(double)(float)v.x, (double)(float)v.y}; }
 
 // Orders this wavefront's LDS writes before its later LDS reads.
 __device__ inline void wave_lds_sync() {
@@ -120,65 +125,53 @@ __global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArg
   const Co2Op op{a.model, a.tables + (size_t)jb.table * m.ntab * kNumF, jb.E, jb.px, jb.py};
   const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1;
   const int ps = P / m.Na, pa = P - ps * m.Na;
-  c32* F = a.fac + (size_t)job * a.fac_job_elems + (size_t)P * n * W1;
-  c32* G = F + (size_t)planes * n * W1;
-  // the entries of G before column 0; the band, A(c + k, c) at F[c W1 + k]:
-  // zeros, then the in-plane stencil entries, k = dx' Ny + dy' for the seven
-  // offsets (dx', dy'), dx' >= 0, of |dx'| + |dy'| <= 2 (points without a
-  // state carry the identity)
+  const Co2FacLayout lay = co2_fac_layout(planes, n, W1);
+  unsigned char* base = a.fac + (size_t)job * a.fac_job_bytes;
+  c16* F = reinterpret_cast<c16*>(base + lay.F) + (size_t)P * n * W1;
+  c16* G = reinterpret_cast<c16*>(base + lay.G) + (size_t)P * n * W1;
+  c32* Dinv = reinterpret_cast<c32*>(base + lay.Dinv) + (size_t)P * n;
+  c32* S = reinterpret_cast<c32*>(base + lay.S) + (size_t)P * n * kFacStencil;
+  // entries of G before column 0, and the staged band
   for (int q = lane; q < min(w, n) * W1; q += 64) {
     const int i = q / W1, k = q - i * W1;
-    if (k > i) G[q] = c32{0.f, 0.f};
+    if (k > i) G[q] = c16{0, 0};
   }
-  for (int q = lane; q < n * W1; q += 64) F[q] = c32{0.f, 0.f};
-  __threadfence_block();   // the zeros land before the entries below
-  for (int e = lane; e < n * 7; e += 64) {
-    const int c = e / 7, o = e - 7 * c;
+  for (int e = lane; e < n * kFacStencil; e += 64) {
+    const int c = e / kFacStencil, o = e - kFacStencil * c;
     const int xc = c / m.Ny, yc = c - xc * m.Ny;
-    const int xr = xc + (o >= 3) + (o >= 6), yr = yc + (o < 3 ? o : (o < 6 ? o - 4 : 0));
-    if (xr < m.Nx && yr >= 0 && yr < m.Ny) {
-      const int r = xr * m.Ny + yr;
-      F[(size_t)c * W1 + (r - c)] = to32(co2_plane_entry(op, sq, ps, pa, r, c));
-    }
+    const int xr = xc + stencil_dx(o), yr = yc + stencil_dy(o);
+    c64 v = c64{0.0, 0.0};
+    if (xr < m.Nx && yr >= 0 && yr < m.Ny) v = co2_plane_entry(op, sq, ps, pa, xr * m.Ny + yr, c);
+    S[e] = to32(v);
   }
   __threadfence_block();   // written by every lane, read back by other lanes below
   c32* st = stage[wv];
-  // this lane's share of a group's band entries: entry e = lane + 64 i is
-  // (row b, offset d) = A(r0 + b, r0 + b - d), e = b W1 + d (b >= kFacU: none)
-  auto row_of = [&](int i) {
-    const int e = lane + 64 * i;
-    int b = 0;
-#pragma unroll
-    for (int u = 1; u <= kFacU; ++u) b += e >= u * W1;
-    return b;
-  };
-  c32 T[kFacPre];
+  // this lane's entry of a group's band: (row b, offset o), lane = b 7 + o
+  // (lanes from kFacU 7 on hold none)
+  const int fb = lane / kFacStencil, fo = lane - kFacStencil * fb;
+  const int foff = stencil_dx(fo) * m.Ny + stencil_dy(fo);
+  c32 T = c32{0.f, 0.f};
   auto fetch = [&](int r0, int cnt) {
-#pragma unroll
-    for (int i = 0; i < kFacPre; ++i) {
-      const int b = row_of(i), d = lane + 64 * i - b * W1, R = r0 + b;
-      T[i] = (b < cnt && R < n && R - d >= 0) ? F[(size_t)(R - d) * W1 + d] : c32{0.f, 0.f};
-    }
+    const int R = r0 + fb, c = R - foff;
+    T = (fb < cnt && R < n && c >= 0) ? S[(size_t)c * kFacStencil + fo] : c32{0.f, 0.f};
   };
   c32 A[kFacSlots];
 #pragma unroll
   for (int c = 0; c < kFacSlots; ++c) A[c] = c32{0.f, 0.f};
   float d0 = 0.f;   // |original diagonal entry|^2 of this lane's row
   // the fetched rows r0 .. r0 + cnt - 1 into their lanes, register c =
-  // column j0 + c, through LDS laid out by register
+  // column j0 + c, through LDS laid out by register (where two offsets of a
+  // small plane name the same column, at most one of them is nonzero)
   auto enter = [&](int r0, int cnt, int j0) {
     for (int q = lane; q < kFacU * kFacSlots; q += 64) st[q] = c32{0.f, 0.f};
     wave_lds_sync();
-#pragma unroll
-    for (int i = 0; i < kFacPre; ++i) {
-      const int b = row_of(i), d = lane + 64 * i - b * W1, c = r0 - j0 + b - d;
-      if (b < cnt && c >= 0 && c < kFacSlots) st[b * kFacSlots + c] = T[i];
-    }
+    const int c = r0 - j0 + fb - foff;
+    if (fb < cnt && c >= 0 && c < kFacSlots && (T.x != 0.f || T.y != 0.f)) st[fb * kFacSlots + c] = T;
     wave_lds_sync();
     const int b = (lane - r0) & 63;
     if (b < cnt) {
 #pragma unroll
-      for (int c = 0; c < kFacSlots; ++c) A[c] = st[b * kFacSlots + c];
+      for (int cc = 0; cc < kFacSlots; ++cc) A[cc] = st[b * kFacSlots + cc];
       d0 = norm2(st[b * kFacSlots + (r0 + b - j0)]);
     }
     wave_lds_sync();
@@ -205,9 +198,10 @@ __global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArg
       const bool act = r >= 1 && r <= w && j + r < n;
       const c64 L = act ? to64(A[t]) * Di : c64{0.0, 0.0};
       if (r <= w && j < n) {
-        const c32 o = to32(r == 0 ? Di : L);
+        const c16 o = to16(L);
         F[(size_t)j * W1 + r] = o;
         if (j + r < n) G[(size_t)(j + r) * W1 + r] = o;
+        if (r == 0) Dinv[j] = to32(Di);
       }
       // A(j + r, j + c') -= L(j + r, j) A(j + c', j), c' = 1..48, in every
       // lane (L = 0 in rows outside the pivot's band; offsets past w and
@@ -237,11 +231,10 @@ __global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArg
   if (!ok) {
     // a vanishing pivot: the plane falls back to its diagonal
     for (int q = lane; q < n * W1; q += 64) {
-      const int j = q / W1, k = q - j * W1;
-      const c32 o = k == 0 ? to32(cinv<double>(co2_plane_entry(op, sq, ps, pa, j, j))) : c32{0.f, 0.f};
-      F[q] = o;
-      G[q] = o;
+      F[q] = c16{0, 0};
+      G[q] = c16{0, 0};
     }
+    for (int j = lane; j < n; j += 64) Dinv[j] = to32(cinv<double>(co2_plane_entry(op, sq, ps, pa, j, j)));
   }
 }
 
@@ -272,7 +265,7 @@ constexpr int kApplyQ = 15;
 // is padded for the last row).  Steps past the plane's end only touch
 // values that are never stored.  Begins and ends with a barrier.
 __device__ __attribute__((always_inline)) inline void co2_block_apply(
-    const Co2Model& m, const c32* fac, const c64* v, double vs, c64* z) {
+    const Co2Model& m, const unsigned char* fac, const c64* v, double vs, c64* z) {
   __syncthreads();
   constexpr int Q = kApplyQ;
   const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1, planes = m.Ns * m.Na;
@@ -280,11 +273,12 @@ __device__ __attribute__((always_inline)) inline void co2_block_apply(
   const bool band = lane >= 1 && lane <= w;
   const bool feed = lane > w && lane <= w + Q;   // refilled per chunk
   const int outq = lane - (64 - Q);              // the chunk step this lane holds at its end
-  auto step = [&](c64& acc, c32& Lq, const c32* next_row) {
+  const Co2FacLayout lay = co2_fac_layout(planes, n, W1);
+  auto step = [&](c64& acc, c16& Lq, const c16* next_row) {
     const c64 x = rlane(acc, 0);
-    const c32 Lm = band ? Lq : c32{0.f, 0.f};
+    const c16 Lh = Lq;
     Lq = next_row[lane];
-    const double lx = Lm.x, ly = Lm.y;
+    const double lx = band ? (double)(float)Lh.x : 0.0, ly = band ? (double)(float)Lh.y : 0.0;
     acc.x = fma(-lx, x.x, acc.x);
     acc.x = fma(ly, x.y, acc.x);
     acc.y = fma(-lx, x.y, acc.y);
@@ -292,12 +286,13 @@ __device__ __attribute__((always_inline)) inline void co2_block_apply(
     acc = lane_rot(acc);
   };
   for (int P = wave; P < planes; P += kWaves) {
-    const c32* F = fac + (size_t)P * n * W1;
-    const c32* G = fac + (size_t)(planes + P) * n * W1;
+    const c16* F = reinterpret_cast<const c16*>(fac + lay.F) + (size_t)P * n * W1;
+    const c16* G = reinterpret_cast<const c16*>(fac + lay.G) + (size_t)P * n * W1;
+    const c32* Dinv = reinterpret_cast<const c32*>(fac + lay.Dinv) + (size_t)P * n;
     const c64* vp = v + (size_t)P * n;
     c64* zp = z + (size_t)P * n;
     // forward: lane k starts with row k
-    c32 Lr[Q];
+    c16 Lr[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) Lr[q] = F[(size_t)min(q, n - 1) * W1 + lane];
     c64 acc = lane < n && lane <= w + Q ? vs * vp[lane] : c64{0.0, 0.0};
@@ -313,9 +308,7 @@ __device__ __attribute__((always_inline)) inline void co2_block_apply(
     // backward: lane k starts with row n - 1 - k, D^{-1} y
 #pragma unroll
     for (int q = 0; q < Q; ++q) Lr[q] = G[(size_t)max(n - 1 - q, 0) * W1 + lane];
-    auto start = [&](int i) {
-      return i >= 0 ? to64(G[(size_t)i * W1]) * zp[i] : c64{0.0, 0.0};
-    };
+    auto start = [&](int i) { return i >= 0 ? to64(Dinv[i]) * zp[i] : c64{0.0, 0.0}; };
     acc = lane <= w + Q ? start(n - 1 - lane) : c64{0.0, 0.0};
     for (int j1 = n - 1; j1 >= 0; j1 -= Q) {
       const c64 snext = feed ? start(j1 - Q - lane) : c64{0.0, 0.0};
@@ -384,15 +377,16 @@ struct Co2Lds {
 };
 
 // Byte model (passes over a sector vector of npts complex FP64 values; the
-// FP32 factor of W1 = 2 Ny + 1 entries per point, stored by columns and by
-// rows, is W1 passes): setup: x, b written, b read, V_0 copied (5), plus the
-// factor written by the factor kernel (W1) or dinv written (1); Arnoldi
-// step: M^{-1} (the columns read forward, the rows backward, and the vector
-// in, y out, y in, zt out: W1 + 4) or the diagonal (v, dinv read, zt written: 3), then the
+// factor, W1 = 2 Ny + 1 complex FP16 multipliers per point by columns and
+// again by rows plus 1/D in FP32, is M = W1 / 2 + 1 / 2 passes): setup: x, b
+// written, b read, V_0 copied (5), plus the factor written by the factor
+// kernel (M) or dinv written (1); Arnoldi step: M^{-1} (the columns read
+// forward, the rows and 1/D backward, and the vector in, y out, y in, zt
+// out: M + 4) or the diagonal (v, dinv read, zt written: 3), then the
 // operator (zt read twice, w_A, w_B written and read, y written: 7), and the
 // projection passes of cycle_passes (which counts 6 for an operator of its
 // own); cycle end with k steps: the update (basis k and zt out, M^{-1} in
-// place, x in/out and zt in: k + W1 + 8; with the diagonal: k + 3) and the
+// place, x in/out and zt in: k + M + 8; with the diagonal: k + 3) and the
 // true residual (x twice, w_A, w_B twice, b, residual out: 8).
 __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
   __shared__ Co2Lds L;
@@ -421,10 +415,11 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
     if (js >= a.n_jobs) break;
     const Co2Job jb = a.jobs[js];
     const Co2Op op{a.model, a.tables + (size_t)jb.table * md.ntab * kNumF, jb.E, jb.px, jb.py};
-    const c32* fac = blk ? a.fac + (size_t)js * a.fac_job_elems : nullptr;
+    const unsigned char* fac = blk ? a.fac + (size_t)js * a.fac_job_bytes : nullptr;
     double passes = 5.0;
+    const double Mp = 0.5 * W1 + 0.5;   // the factor, in passes
     if (blk) {
-      passes += W1;
+      passes += Mp;
     } else if (a.precond == VDC_PREC_JACOBI) {
       co2_jacobi(op, L.sq, dinv);
       passes += 1.0;
@@ -466,8 +461,8 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
         __syncthreads();
         const CycleResult cr = krylov_cycle<double>(L.K, L.red, V, ld, npts, m, a.tol * bnorm,
                                                     a.max_iter, iters, Rm, apply);
-        passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k * ((blk ? W1 + 4.0 : 3.0) + 1.0) +
-                  (blk ? cr.k + W1 + 8.0 : cr.k + 3.0) + 8.0;
+        passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k * ((blk ? Mp + 4.0 : 3.0) + 1.0) +
+                  (blk ? cr.k + Mp + 8.0 : cr.k + 3.0) + 8.0;
         if (blk) {
           update_x<double>(V, ld, cr.k, L.K.y, L.K.vs, nullptr, zt, npts, true);
           co2_block_apply(md, fac, zt, 1.0, zt);
@@ -540,7 +535,7 @@ __global__ void __launch_bounds__(kBlock) co2_ops_kernel(Co2OpsArgs a) {
     if (a.which == 0) {
       co2_apply(op, sq, xv, 1.0, yv, slot, slot + md.npts);
     } else {
-      co2_block_apply(md, a.fac + (size_t)v * a.fac_job_elems, xv, 1.0, yv);
+      co2_block_apply(md, a.fac + (size_t)v * a.fac_job_bytes, xv, 1.0, yv);
     }
   }
 }
