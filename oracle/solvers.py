@@ -8,6 +8,11 @@
   x_n = x_0 + M^{-1} V_n y_n (right preconditioning by M, Sec. III.B: the
   diagonal of A, or any block-diagonal section of it given as a solve).  Stopping rule of Sec. III: ||b - A x|| < tol ||b||,
   checked on the true residual at the end of each cycle.
+* cocg: the conjugate orthogonal conjugate gradient method of Sec. III.A
+  (conjugate gradients with the symmetrized bilinear form <a|b>_S = sum a_i
+  b_i in place of the scalar product, for complex symmetric A), preconditioned
+  as M^{-1} A M^{-T} y = M^{-1} b, x = M^{-T} y (Sec. III.B), written in the
+  coupled two-term form with K = M M^T applied as a solve.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -94,4 +99,77 @@ def gmres(A, b, m=50, tol=1e-10, max_iter=20000, dinv=None, history=False, psolv
                 converged=bool(beta <= tol * bnorm))
     if history:
         info["hist"] = np.array(hist)
+    return x, info
+
+
+def bilinear(a, b):
+    """<a|b>_S = <a*|b> = sum_i a_i b_i: the symmetrized bilinear form of
+    Sec. III.A (no complex conjugation)."""
+    return np.sum(np.asarray(a) * np.asarray(b))
+
+
+def cocg(A, b, tol=1e-10, max_iter=20000, psolve=None, history=False):
+    """Preconditioned COCG, x0 = 0 (Sec. III.A, III.B).
+
+    The basis vectors of the paper's recurrence are, up to scaling, the
+    residuals r_k, conjugate orthogonal in the preconditioned form:
+    <r_i | K^{-1} r_j>_S = 0 for i != j.  With K = M M^T (psolve = K^{-1},
+    identity when None) the iteration is conjugate gradients on
+    M^{-1} A M^{-T} with <.|.>_S, mapped back to x = M^{-T} y:
+        r = b, z = K^{-1} r, p = z, rho = <r|z>_S
+        repeat: q = A p, alpha = rho / <p|q>_S, x += alpha p, r -= alpha q,
+                z = K^{-1} r, rho' = <r|z>_S, p = z + (rho'/rho) p.
+    Stops when the updated residual satisfies ||r|| <= tol ||b|| and the true
+    residual b - A x does as well; if only the updated one does, the
+    iteration restarts from the true residual.  A vanishing <p|q>_S or
+    <r|z>_S is a breakdown (the bilinear form is not definite).
+
+    Returns (x, info) with info = dict(iters, restarts, rel_res, converged,
+    breakdown[, residuals]) (residuals: the r_k, when history is set).
+    """
+    b = np.asarray(b, dtype=np.complex128)
+    if psolve is None:
+        psolve = (lambda v: v)
+    bnorm = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    if bnorm == 0.0:
+        return x, dict(iters=0, restarts=0, rel_res=0.0, converged=True, breakdown=False)
+    r = b.copy()
+    z = psolve(r)
+    p = z.copy()
+    rho = bilinear(r, z)
+    iters, restarts, breakdown, rs = 0, 0, False, [r.copy()]
+    rel = 1.0
+    while iters < max_iter:
+        q = A @ p
+        mu = bilinear(p, q)
+        if mu == 0.0 or rho == 0.0:
+            breakdown = True
+            break
+        alpha = rho / mu
+        x = x + alpha * p
+        r = r - alpha * q
+        iters += 1
+        if np.linalg.norm(r) <= tol * bnorm:
+            rt = b - A @ x
+            rel = np.linalg.norm(rt) / bnorm
+            if rel <= tol:
+                break
+            r = rt                                   # restart from the true residual
+            z = psolve(r)
+            p = z.copy()
+            rho = bilinear(r, z)
+            restarts += 1
+            continue
+        if history:
+            rs.append(r.copy())
+        z = psolve(r)
+        rho_new = bilinear(r, z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    rel = np.linalg.norm(b - A @ x) / bnorm
+    info = dict(iters=iters, restarts=restarts, rel_res=rel, converged=bool(rel <= tol),
+                breakdown=breakdown)
+    if history:
+        info["residuals"] = rs
     return x, info
