@@ -81,7 +81,7 @@ PREC_NAMES = {"jacobi": "diagonal preconditioner",
               "block": "column-block preconditioner (n_u columns, 8 rows of n_g, LDL^T)"}
 
 
-def co2like(args):
+def co2like(args, method=None):
     """The CO2-like three-state, four-mode model: 24 x 24 x 24 x 8 basis (110 592
     grid points, a quarter of the 331 776 state amplitudes per reflection
     sector), 128 energies on [0.05, 4.0] eV x partial waves s, p_x, p_y, v_i = 0,
@@ -90,7 +90,8 @@ def co2like(args):
     from paper_2307_13483_amd import inputs, vdc
     cfg = inputs.co2like_jobs()
     model = vdc.Co2Model(cfg["params"], cfg["sizes"])
-    opts = vdc.Opts(restart=20, precision=vdc.FP64, precond=vdc.PREC_BLOCK, max_iter=2000)
+    opts = vdc.Opts(restart=20, precision=vdc.FP64, precond=vdc.PREC_BLOCK, max_iter=2000,
+                    method=vdc.GMRES if method is None else method)
     vdc.co2_solve(model, cfg["jobs"][:8], cfg["finals"], opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -106,6 +107,59 @@ def co2like(args):
                 iters_max=max(it), ms_tables=ms_tab, ms_solver=ms_sol,
                 algorithmic_bytes=alg, achieved_GBs=alg / (ms_sol * 1e-3) / 1e9,
                 frac=alg / (ms_sol * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+
+def cocg_batched(model, cfg, precond, mixed=False):
+    """The batched workload (the same 3072 right-hand sides and 120 x 120
+    model as the headline) solved by COCG in FP64 with the given
+    preconditioner: solves/s of the whole call (tables included) and the
+    solver kernel's algorithmic rate."""
+    import torch
+    from paper_2307_13483_amd import vdc
+    opts = vdc.Opts(precond=precond, method=vdc.COCG, max_iter=20000)
+    if mixed:
+        opts = vdc.Opts(precond=precond, method=vdc.COCG, max_iter=20000, precision=vdc.FP32_INNER,
+                        inner_restart=100, inner_tol=1e-4)
+    s = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts)
+    s.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    infos = s.infos()
+    ms_tab, ms_sol = vdc.last_kernel_times()
+    it = [i["iters"] for i in infos]
+    alg = sum(i["alg_bytes"] for i in infos)
+    return dict(solves=len(infos), solves_per_s=len(infos) / dt,
+                converged=sum(i["status"] == vdc.CONVERGED for i in infos),
+                worst_rel_res=max(i["rel_res"] for i in infos), iters_mean=sum(it) / len(it),
+                iters_max=max(it), restarts=sum(i["restarts"] for i in infos),
+                outer_mean=sum(i["outer_iters"] for i in infos) / len(infos), ms_solver=ms_sol,
+                achieved_GBs=alg / (ms_sol * 1e-3) / 1e9,
+                frac=alg / (ms_sol * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+
+def eels_batched(model, cfg):
+    """The 2D energy-loss spectra (Eq. (17)) of the batched workload: its 3072
+    right-hand sides solved (mixed precision, block preconditioner, with the
+    solutions kept), then every final state of the 120 x 120 basis spread
+    on a 1 meV loss grid from -0.05 to 1.2 eV with the 10 meV resolution."""
+    import torch
+    from paper_2307_13483_amd import vdc
+    s = vdc.Solver(model, cfg["jobs"], cfg["finals"],
+                   vdc.Opts(precision=vdc.FP32_INNER, precond=vdc.PREC_BLOCK), want_psi=True).run()
+    n_grid = 1251
+    vdc.eels(model, cfg["jobs"], s.psi, -0.05, 0.001, n_grid)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = vdc.eels(model, cfg["jobs"], s.psi, -0.05, 0.001, n_grid)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nc = cfg["Ng"] * cfg["Nu"]
+    return dict(right_hand_sides=len(cfg["jobs"]), final_states_per_rhs=nc, grid_points=n_grid,
+                call_ms=dt * 1e3, kernel_ms=vdc.last_kernel_times()[1],
+                total=float(S.sum().item()) * 0.001)
 
 
 def extras(args, model, cfg):
@@ -191,7 +245,13 @@ def extras(args, model, cfg):
     s.adjoint(dsig)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    from paper_2307_13483_amd import vdc as _v
     ex["co2like"] = co2like(args)
+    ex["co2like_cocg"] = co2like(args, _v.COCG)
+    ex["eels_batched"] = eels_batched(model, cfg)
+    ex["cocg_batched"] = {name: cocg_batched(model, cfg, pc, mx) for name, pc, mx in
+                          (("block", _v.PREC_BLOCK, False), ("jacobi", _v.PREC_JACOBI, False),
+                           ("block_fp32_inner", _v.PREC_BLOCK, True))}
     ex["adjoint"] = dict(energies=len(aw["eps"]), right_hand_sides=len(ajobs),
                          forward_ms=(t1 - t0) * 1e3, adjoint_ms=(t2 - t1) * 1e3,
                          gradient_evals_per_s=1.0 / (t2 - t0),
@@ -233,9 +293,31 @@ def main():
                          "(calibrates the HBM byte counters of a profiler)")
     ap.add_argument("--co2-probe", action="store_true",
                     help="only run the CO2-like workload (384 solves) and print its figures")
+    ap.add_argument("--eels-probe", action="store_true",
+                    help="only solve the batched workload and form its 2D energy-loss spectra")
+    ap.add_argument("--cocg-probe", action="store_true",
+                    help="only run the batched workload by COCG (block and diagonal preconditioners)")
     args = ap.parse_args()
     if args.co2_probe:
-        print(json.dumps({"co2like": co2like(args)}), flush=True)
+        from paper_2307_13483_amd import vdc
+        print(json.dumps({"co2like": co2like(args), "co2like_cocg": co2like(args, vdc.COCG)}),
+              flush=True)
+        return
+    if args.eels_probe:
+        from paper_2307_13483_amd import inputs, vdc
+        cfg = inputs.batched_jobs(n_energies=args.energies)
+        model = vdc.Model2D(cfg["params"], cfg["Ng"], cfg["Nu"])
+        print(json.dumps({"eels_batched": eels_batched(model, cfg)}), flush=True)
+        return
+    if args.cocg_probe:
+        from paper_2307_13483_amd import inputs, vdc
+        cfg = inputs.batched_jobs(n_energies=args.energies)
+        model = vdc.Model2D(cfg["params"], cfg["Ng"], cfg["Nu"])
+        print(json.dumps({"cocg_batched": {name: cocg_batched(model, cfg, pc, mx) for name, pc, mx in
+                                           (("block", vdc.PREC_BLOCK, False),
+                                            ("jacobi", vdc.PREC_JACOBI, False),
+                                            ("block_fp32_inner", vdc.PREC_BLOCK, True))}}),
+              flush=True)
         return
     if args.copy_probe:
         import torch

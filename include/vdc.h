@@ -100,6 +100,20 @@ typedef enum {
                                 accumulation as the variable preconditioner   */
 } vdc_precision;
 
+/* Krylov method of vdc_solve (Sec. III.A): restarted GMRES (with the
+ * precision above), or COCG, conjugate gradients with the bilinear form
+ * <a|b>_S = sum a_i b_i for the complex symmetric A, preconditioned as
+ * M^{-1} A M^{-T} with M M^T the JACOBI or BLOCK section (both symmetric).
+ * COCG with VDC_FP32_INNER (vdc_solve only) is FP64 iterative refinement
+ * whose correction equations are solved by COCG entirely in FP32 to the
+ * relative residual inner_tol or inner_restart steps; iters then counts the
+ * FP32 steps, outer_iters the refinements.  In FP64 (vdc_solve and
+ * vdc_co2_solve) restart is ignored, max_iter counts COCG steps, and the
+ * true residual decides convergence (the iteration restarts from it when the
+ * updated residual has converged but it has not).  A vanishing bilinear
+ * form at a fresh start is VDC_BREAKDOWN. */
+typedef enum { VDC_GMRES = 0, VDC_COCG = 1 } vdc_method;
+
 typedef struct {
   int restart;               /* GMRES restart length m, 1..128                  */
   int max_iter;              /* total Arnoldi steps (inner steps for FP32)      */
@@ -111,6 +125,7 @@ typedef struct {
   int outer_restart;         /* FP32_INNER: outer FGMRES length (1..32)         */
   int tile_rows;             /* rows of n_g per LDS tile of the fused operator
                                 pass; 0 = the largest that fits               */
+  int method;                /* vdc_method (vdc_solve only; 0 = GMRES)         */
 } vdc_solve_opts;
 
 /* Per-job results written to host memory by the solve calls. */
@@ -132,7 +147,7 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* desc, vdc_model_t* out);
 vdc_status vdc_model_destroy(vdc_model_t model);
 
 /* Bytes of device workspace that vdc_solve / vdc_solve_plain need for this job
- * list.  Host call, no device work. */
+ * list (for VDC_COCG: vdc_solve only).  Host call, no device work. */
 vdc_status vdc_workspace_size(int n_models, const vdc_model_t* models,
                               const vdc_solve_opts* opts, int n_jobs, const vdc_job* jobs,
                               size_t* bytes);
@@ -236,6 +251,23 @@ vdc_status vdc_matvec_block(vdc_model_t model, double E, int n_vec, const int* p
                             const double* x, double* y, void* workspace, size_t ws_bytes,
                             void* stream);
 
+/* Two-dimensional electron energy-loss spectrum (Eq. (17)) of solved
+ * right-hand sides of the two-state model: for job k (eps_i, v_i, mu_i; host
+ * vdc_job, model index 0) and its full-layout solution psi[k] (device complex
+ * [n_jobs][psi_ld], psi_ld >= 2 Ng Nu, e.g. psi_out of vdc_solve), S_out[k][j]
+ * (device double [n_jobs][n_grid]) = sum over every final state v_f of the
+ * basis of this right-hand side's share of sigma_{v_f <- v_i} (Eq. (16) for
+ * its mu_i, summed over mu_f; 0 for closed channels) times rho(loss_j -
+ * (E_{v_f} - E_{v_i})), loss_j = loss0 + j dloss, rho a unit-area Gaussian of
+ * full width at half maximum fwhm (eV; 0.010 in Sec. II.B).  The gerade and
+ * ungerade parts are the jobs with mu_i = e and o; S is their sum.  Final
+ * states farther than 8 standard deviations of rho from loss_j are skipped
+ * (their weight is below 1e-13 of the peak).  Synchronises the stream. */
+vdc_status vdc_eels_workspace_size(vdc_model_t model, int n_jobs, size_t* bytes);
+vdc_status vdc_eels(vdc_model_t model, int n_jobs, const vdc_job* jobs, const double* psi,
+                    size_t psi_ld, int n_grid, double loss0, double dloss, double fwhm,
+                    double* S_out, void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * The CO2-like three-state, four-mode model (Sec. III.C, the model class of
  * the e + CO2 paragraph): states sigma, Pi_x, Pi_y; modes s (symmetric
@@ -299,7 +331,9 @@ vdc_status vdc_co2_workspace_size(vdc_co2_t model, const vdc_solve_opts* opts, i
 
 /* Solve (E - H_ef) Psi = Phi^{v mu} (Eqs. (26), (28)) for every job in one
  * persistent launch (after one launch for the level-shift tables of all
- * distinct energies): restarted FP64 GMRES(opts->restart) with right
+ * distinct energies, and with VDC_PREC_BLOCK one for the block factors):
+ * with opts->method = VDC_COCG, FP64 COCG as described at vdc_method (the
+ * paper's method for its CO2 model), else restarted FP64 GMRES(opts->restart) with right
  * preconditioning by the paper's block choice for this model class
  * (VDC_PREC_BLOCK: one block per (n_s, n_a) holding the bend plane, factored
  * once per job by complex-symmetric L D L^T without pivoting, formed in

@@ -11,6 +11,7 @@
 
 #include "internal.h"
 #include "co2.h"
+#include "eels.h"
 #include "blockops.h"
 #include "solve_args.h"
 #include "strip.h"
@@ -18,6 +19,10 @@
 namespace vdc {
 hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
 int gmres_fp64_occupancy(size_t dyn_lds);
+hipError_t launch_cocg_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
+int cocg_fp64_occupancy(size_t dyn_lds);
+hipError_t launch_cocg_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
+int cocg_mixed_occupancy(size_t dyn_lds);
 hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
 int fgmres_mixed_occupancy(size_t dyn_lds);
 hipError_t launch_zero_int(int* p, int n, hipStream_t s);
@@ -142,7 +147,12 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
   if (o->precision != VDC_FP64 && o->precision != VDC_FP32_INNER)
     return fail(VDC_ERR_INVALID_ARG, "unknown precision");
+  if (o->method != VDC_GMRES && o->method != VDC_COCG)
+    return fail(VDC_ERR_INVALID_ARG, "unknown method");
   const bool mixed = o->precision == VDC_FP32_INNER;
+  const bool cocg = o->method == VDC_COCG;
+  if (cocg && (plain || adjoint))
+    return fail(VDC_ERR_UNSUPPORTED, "COCG runs in the batched solve only");
   if (mixed && adjoint) return fail(VDC_ERR_UNSUPPORTED, "the adjoint solve is FP64 only");
   P.deriv = adjoint;
   const int planes = adjoint ? kPlanesDeriv : kPlanesSolve;
@@ -272,7 +282,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     const double cb = P.models[b.model].Nc * (0.5 + b.E);
     return ca > cb;
   });
-  const int m = mixed ? o->outer_restart : o->restart;
+  const int m = cocg ? 4 : (mixed ? o->outer_restart : o->restart);
   P.ncap = (size_t)((P.max_nc + 63) / 64) * 64;
   if (mixed) {
     // FP64: Vout (m+1), Z (m), x, b, w, wA, wB, R_out, R_in;
@@ -290,7 +300,8 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   int occ = 1;
   if (!plain)
     occ = adjoint ? adjoint_occupancy(P.dyn_lds)
-                  : (mixed ? fgmres_mixed_occupancy(P.dyn_lds) : gmres_fp64_occupancy(P.dyn_lds));
+                  : (mixed ? (cocg ? cocg_mixed_occupancy(P.dyn_lds) : fgmres_mixed_occupancy(P.dyn_lds))
+                           : (cocg ? cocg_fp64_occupancy(P.dyn_lds) : gmres_fp64_occupancy(P.dyn_lds)));
   P.n_groups = plain ? 1 : std::max(1, std::min(n_jobs, cu_count() * occ));
   size_t off = 0;
   P.off_counter = off; off += 256;
@@ -366,7 +377,7 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   a.scratch = reinterpret_cast<c64*>(ws + P.off_scratch);
   a.slot_elems = P.slot_elems;
   a.ncap = P.ncap;
-  a.m = mixed ? opts->outer_restart : opts->restart;
+  a.m = opts->method == VDC_COCG ? 4 : (mixed ? opts->outer_restart : opts->restart);
   a.max_iter = opts->max_iter;
   a.tol = opts->tol;
   a.precond = opts->precond;
@@ -406,8 +417,12 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
     std::string err;
     st = solve_plain_impl(a, P.jobs, P.models, s, err);
     if (st != VDC_OK) return fail(st, err);
+  } else if (mixed && opts->method == VDC_COCG) {
+    HIPCHK(launch_cocg_mixed(a, P.n_groups, P.dyn_lds, s));
   } else if (mixed) {
     HIPCHK(launch_fgmres_mixed(a, P.n_groups, P.dyn_lds, s));
+  } else if (opts->method == VDC_COCG) {
+    HIPCHK(launch_cocg_fp64(a, P.n_groups, P.dyn_lds, s));
   } else {
     HIPCHK(launch_gmres_fp64(a, P.n_groups, P.dyn_lds, s));
   }
@@ -607,7 +622,7 @@ vdc_status vdc_workspace_size(int n_models, const vdc_model_t* models, const vdc
   vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, kMaxFinal, false, P);
   if (st != VDC_OK) return st;
   size_t total = P.total;
-  if (opts->precision == VDC_FP64) {
+  if (opts->precision == VDC_FP64 && opts->method == VDC_GMRES) {
     Plan Q;
     st = make_plan(n_models, models, opts, n_jobs, jobs, kMaxFinal, true, Q);
     if (st != VDC_OK) return st;
@@ -845,6 +860,106 @@ vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, con
   return VDC_OK;
 }
 
+// 2D electron energy-loss spectra (Eq. (17)) from full-layout solutions.
+namespace {
+size_t eels_groups(int n_jobs) { return (size_t)std::max(1, std::min(n_jobs, cu_count())); }
+}  // namespace
+
+vdc_status vdc_eels_workspace_size(vdc_model_t model, int n_jobs, size_t* bytes) {
+  if (!model || !bytes || n_jobs < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  const int Nc = model->dev.Nc;
+  size_t off = 0;
+  off = align256(off + sizeof(DevModel));
+  off = align256(off + sizeof(EelsJob) * std::max(1, n_jobs));
+  off = align256(off + sizeof(int) * Nc);
+  off = align256(off + sizeof(double) * Nc);
+  off = align256(off + sizeof(int));
+  off = align256(off + sizeof(double) * Nc * eels_groups(n_jobs));
+  *bytes = off;
+  return VDC_OK;
+}
+
+vdc_status vdc_eels(vdc_model_t model, int n_jobs, const vdc_job* jobs, const double* psi,
+                    size_t psi_ld, int n_grid, double loss0, double dloss, double fwhm,
+                    double* S_out, void* workspace, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  vdc_status st = vdc_eels_workspace_size(model, n_jobs, &need);
+  if (st != VDC_OK) return st;
+  if (n_jobs == 0) return VDC_OK;
+  const DevModel& md = model->dev;
+  if (!jobs || !psi || !S_out || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  if (n_grid < 1) return fail(VDC_ERR_INVALID_ARG, "n_grid must be >= 1");
+  if (!(fwhm > 0.0) || !(dloss > 0.0) || !std::isfinite(loss0) || !std::isfinite(fwhm) ||
+      !std::isfinite(dloss))
+    return fail(VDC_ERR_INVALID_ARG, "fwhm and dloss must be > 0, loss0 finite");
+  if (psi_ld < 2 * (size_t)md.Nc) return fail(VDC_ERR_INVALID_ARG, "psi_ld must be >= 2 Ng Nu");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(VDC_ERR_WORKSPACE, "workspace too small");
+  std::vector<EelsJob> ej(n_jobs);
+  for (int k = 0; k < n_jobs; ++k) {
+    const vdc_job& j = jobs[k];
+    if (!(j.eps_i > 0.0) || !std::isfinite(j.eps_i)) return fail(VDC_ERR_INVALID_ARG, "eps_i must be > 0");
+    if (j.vi_g < 0 || j.vi_g >= md.Ng || j.vi_u < 0 || j.vi_u >= md.Nu)
+      return fail(VDC_ERR_INVALID_ARG, "initial state outside the basis");
+    if (j.model != 0) return fail(VDC_ERR_INVALID_ARG, "jobs of vdc_eels refer to its one model (0)");
+    const double Evi = md.omega_g * (j.vi_g + 0.5) + md.omega_u * (j.vi_u + 0.5);
+    ej[k] = EelsJob{j.eps_i, j.eps_i + Evi, Evi, k};
+  }
+  // final states by vibrational energy (ties by index)
+  std::vector<int> order(md.Nc);
+  std::vector<double> Evf(md.Nc);
+  for (int q = 0; q < md.Nc; ++q) order[q] = q;
+  auto energy = [&](int q) {
+    const int g = q / md.Nu, u = q - g * md.Nu;
+    return md.omega_g * (g + 0.5) + md.omega_u * (u + 0.5);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return energy(a) < energy(b); });
+  for (int q = 0; q < md.Nc; ++q) Evf[q] = energy(order[q]);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  size_t off = 0;
+  DevModel* d_model = reinterpret_cast<DevModel*>(ws + off); off = align256(off + sizeof(DevModel));
+  EelsJob* d_jobs = reinterpret_cast<EelsJob*>(ws + off); off = align256(off + sizeof(EelsJob) * n_jobs);
+  int* d_order = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int) * md.Nc);
+  double* d_Evf = reinterpret_cast<double*>(ws + off); off = align256(off + sizeof(double) * md.Nc);
+  int* d_counter = reinterpret_cast<int*>(ws + off); off = align256(off + sizeof(int));
+  double* d_share = reinterpret_cast<double*>(ws + off);
+  HIPCHK(hipMemcpyAsync(d_model, &md, sizeof(DevModel), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_jobs, ej.data(), sizeof(EelsJob) * n_jobs, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_order, order.data(), sizeof(int) * md.Nc, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_Evf, Evf.data(), sizeof(double) * md.Nc, hipMemcpyHostToDevice, s));
+  HIPCHK(launch_zero_int(d_counter, 1, s));
+  EelsArgs a{};
+  a.model = d_model;
+  a.jobs = d_jobs;
+  a.n_jobs = n_jobs;
+  a.psi = reinterpret_cast<const c64*>(psi);
+  a.psi_ld = psi_ld;
+  a.order = d_order;
+  a.Evf = d_Evf;
+  a.share = d_share;
+  a.counter = d_counter;
+  a.n_grid = n_grid;
+  a.d0 = loss0;
+  a.dd = dloss;
+  a.fwhm = fwhm;
+  a.S = S_out;
+  EventSet ev;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  HIPCHK(launch_eels(a, (int)eels_groups(n_jobs), s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = 0.f;
+    g_ms_solver = t2;
+  }
+  return VDC_OK;
+}
+
 }  // extern "C"
 
 
@@ -890,6 +1005,8 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   if (o->precision != VDC_FP64) return fail(VDC_ERR_INVALID_ARG, "this model solves in FP64 only");
   if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI && o->precond != VDC_PREC_BLOCK)
     return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
+  if (o->method != VDC_GMRES && o->method != VDC_COCG)
+    return fail(VDC_ERR_INVALID_ARG, "unknown method");
   const Co2Model& md = model->dev;
   if (o->precond == VDC_PREC_BLOCK && md.Ny > co2_factor_max_ny())
     return fail(VDC_ERR_UNSUPPORTED, "the block preconditioner needs Ny <= 24");
@@ -919,7 +1036,7 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   // higher energies first (more open channels, longer solves on these models)
   std::stable_sort(P.jobs.begin(), P.jobs.end(),
                    [](const Co2Job& a, const Co2Job& b) { return a.E > b.E; });
-  P.m = o->restart;
+  P.m = o->method == VDC_COCG ? 4 : o->restart;   // COCG keeps r, p, q, z in V_0..V_3
   P.ld = co2_ld(md);
   P.slot_elems = ((size_t)(P.m + 1 + 6) * P.ld + (size_t)(P.m + 1) * P.m + 31) / 32 * 32;
   P.fac_job_bytes = o->precond == VDC_PREC_BLOCK ? co2_fac_bytes(md) : 0;
@@ -1115,6 +1232,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   a.m = P.m;
   a.max_iter = opts->max_iter;
   a.precond = opts->precond;
+  a.method = opts->method;
   a.tol = opts->tol;
   a.n_final = n_final;
   a.finals = d_finals;

@@ -124,7 +124,9 @@ __device__ inline R norm_sq(const typename CT<R>::C* __restrict__ w, int Nc, R* 
 // are formed in LDS, and y is written once.  lds must hold
 // (3 T + 8) * Nu complex values of precision R.  With bsub given the pass
 // writes y = bsub - A(...) instead (a residual), and with red given it also
-// returns ||y||^2.  Ends with a barrier (y is written by threads other than
+// returns ||y||^2; with bdot given as well, bdot[0..1] receives the bilinear
+// form sum_i z_i y_i (no conjugate) of the staged input z = vscale dinv v
+// and the output.  Ends with a barrier (y is written by threads other than
 // the element owners).
 template <typename R>
 __device__ inline R matvec_tiled(const OpJob<R>& op, const R* sq,
@@ -133,9 +135,9 @@ __device__ inline R matvec_tiled(const OpJob<R>& op, const R* sq,
                                  typename CT<R>::C* __restrict__ y,
                                  typename CT<R>::C* lds, int T,
                                  const typename CT<R>::C* __restrict__ bsub = nullptr,
-                                 R* red = nullptr) {
+                                 R* red = nullptr, R* bdot = nullptr) {
   using C = typename CT<R>::C;
-  R acc[1] = {R(0)};
+  R acc[3] = {R(0), R(0), R(0)};
   const int Ng = op.Ng, Nu = op.Nu;
   C* zt = lds;                          // rows g0-2 .. g0+T+1
   C* wa = lds + (size_t)(T + 4) * Nu;   // rows g0-1 .. g0+T
@@ -194,11 +196,24 @@ __device__ inline R matvec_tiled(const OpJob<R>& op, const R* sq,
       if (bsub) out = bsub[row * Nu + nu] - out;
       y[row * Nu + nu] = out;
       acc[0] += norm2(out);
+      if (bdot) {
+        const C t = zr[nu] * out;
+        acc[1] += t.x;
+        acc[2] += t.y;
+      }
     }
     __syncthreads();
   }
   if (!red) return R(0);
-  block_sum<1, R>(acc, red, red + kWaves);
+  if (bdot) {
+    block_sum<3, R>(acc, red, red + kWaves * 3);
+    const R s = red[kWaves * 3];
+    if (threadIdx.x < 2) bdot[threadIdx.x] = red[kWaves * 3 + 1 + threadIdx.x];
+    __syncthreads();
+    return s;
+  }
+  R a1[1] = {acc[0]};
+  block_sum<1, R>(a1, red, red + kWaves);
   const R s = red[kWaves];
   __syncthreads();
   return s;

@@ -191,10 +191,11 @@ __device__ inline c64 co2_phase2(const Co2Op& o, const double* sq, const c64* v,
 // y = A (vs v) over the whole vector by one workgroup; wA, wB are scratch
 // vectors.  Begins with a barrier (v may have just been written by other
 // threads) and ends with one.  With red given, also returns ||y||^2 (to every
-// thread) and with bsub, y = bsub - A (vs v).
+// thread) and with bsub, y = bsub - A (vs v); with bdot given as well,
+// bdot[0..1] receives sum_i (vs v_i) y_i (the bilinear form, no conjugate).
 __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* v, double vs,
                                    c64* y, c64* wA, c64* wB, const c64* bsub = nullptr,
-                                   double* red = nullptr);
+                                   double* red = nullptr, double* bdot = nullptr);
 
 // Complex FP16 (the stored multipliers of the block factor).
 struct c16 { _Float16 x, y; };
@@ -231,7 +232,7 @@ struct Co2Args {
   size_t slot_elems, ld;
   const unsigned char* fac;  // block factors, one Co2FacLayout per job (job order of jobs)
   size_t fac_job_bytes;
-  int m, max_iter, precond;
+  int m, max_iter, precond, method;   // method: VDC_GMRES or VDC_COCG
   double tol;
   int n_final;
   const int* finals;         // [n_final][4]

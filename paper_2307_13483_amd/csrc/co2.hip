@@ -9,7 +9,8 @@
 namespace vdc {
 
 __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* v, double vs,
-                                   c64* y, c64* wA, c64* wB, const c64* bsub, double* red) {
+                                   c64* y, c64* wA, c64* wB, const c64* bsub, double* red,
+                                   double* bdot) {
   const int n = o.m->npts;
   __syncthreads();
 #pragma unroll 1
@@ -20,20 +21,26 @@ __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* 
     wB[i] = b;
   }
   __syncthreads();
-  double acc[1] = {0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
   for (int i = threadIdx.x; i < n; i += kBlock) {
     c64 r = co2_phase2(o, sq, v, vs, wA, wB, i);
     if (bsub) r = bsub[i] - r;
     y[i] = r;
     acc[0] += norm2(r);
+    if (bdot) {
+      const c64 t = (vs * v[i]) * r;
+      acc[1] += t.x;
+      acc[2] += t.y;
+    }
   }
   if (!red) {
     __syncthreads();
     return 0.0;
   }
-  block_sum<1, double>(acc, red, red + kWaves);
-  const double s = red[kWaves];
+  block_sum<3, double>(acc, red, red + 3 * kWaves);
+  const double s = red[3 * kWaves];
+  if (bdot && threadIdx.x < 2) bdot[threadIdx.x] = red[3 * kWaves + 1 + threadIdx.x];
   __syncthreads();
   return s;
 }
@@ -373,6 +380,7 @@ struct Co2Lds {
   KrylovLds<double> K;
   double red[kRedSize];
   double sq[kSqMax + 1];
+  double dot[2];
   int job;
 };
 
@@ -387,7 +395,10 @@ struct Co2Lds {
 // projection passes of cycle_passes (which counts 6 for an operator of its
 // own); cycle end with k steps: the update (basis k and zt out, M^{-1} in
 // place, x in/out and zt in: k + M + 8; with the diagonal: k + 3) and the
-// true residual (x twice, w_A, w_B twice, b, residual out: 8).
+// true residual (x twice, w_A, w_B twice, b, residual out: 8).  COCG: setup
+// as above plus r = b (2), K^{-1} r (block M + 4, diagonal 3) and <r|z>_S
+// (2); per step the operator with <p|Ap>_S (7), x and r (6), K^{-1} r, its
+// <r|z>_S (2) and p = z + beta p (3); a true-residual check 8.
 __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
   __shared__ Co2Lds L;
   fill_sq<double>(L.sq);
@@ -441,6 +452,110 @@ __global__ void __launch_bounds__(kBlock) co2_gmres_kernel(Co2Args a) {
     if (!(bnorm > 0.0) || !isfinite(bnorm)) {
       status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
       beta = 0.0;
+    } else if (a.method == VDC_COCG) {
+      // COCG (Sec. III.A) preconditioned as M^{-1} A M^{-T} with K = M M^T
+      // the block L D L^T or the diagonal (both symmetric), in the two-term
+      // form; r, p, q, z in V_0..V_3.  The true residual decides; the
+      // iteration restarts from it when only the updated one has converged,
+      // and after one breakdown of the bilinear form.
+      c64* r = V;
+      c64* p = V + ld;
+      c64* q = V + 2 * ld;
+      c64* z = V + 3 * ld;
+      auto kinv = [&](const c64* src, c64* dst) {   // dst = K^{-1} src, then a barrier
+        if (blk) {
+          co2_block_apply(md, fac, src, 1.0, dst);
+          passes += Mp + 4.0;
+        } else {
+          for (int i = tid; i < npts; i += kBlock)
+            dst[i] = a.precond == VDC_PREC_JACOBI ? dinv[i] * src[i] : src[i];
+          __syncthreads();
+          passes += 3.0;
+        }
+      };
+      auto bilin = [&](const c64* u, const c64* w) {   // <u|w>_S over own elements
+        double acc[2] = {0.0, 0.0};
+        for (int i = tid; i < npts; i += kBlock) {
+          const c64 t = u[i] * w[i];
+          acc[0] += t.x;
+          acc[1] += t.y;
+        }
+        block_sum<2, double>(acc, L.red, L.red + 2 * kWaves);
+        const c64 v = c64{L.red[2 * kWaves], L.red[2 * kWaves + 1]};
+        __syncthreads();
+        passes += 2.0;
+        return v;
+      };
+      for (int i = tid; i < npts; i += kBlock) r[i] = b[i];
+      passes += 2.0;
+      kinv(r, p);
+      c64 rho = bilin(r, p);
+      bool fresh = true;
+      for (;;) {
+        co2_apply(op, L.sq, p, 1.0, q, wA, wB, nullptr, L.red, L.dot);
+        passes += 7.0;
+        const c64 mu = c64{L.dot[0], L.dot[1]};
+        const double mn = norm2(mu), rn = norm2(rho);
+        if (!(mn > 0.0) || !(rn > 0.0) || !isfinite(mn) || !isfinite(rn)) {
+          if (fresh) {
+            status = (isfinite(mn) && isfinite(rn)) ? VDC_BREAKDOWN : VDC_NONFINITE;
+            break;
+          }
+          beta = sqrt(co2_apply(op, L.sq, x, 1.0, r, wA, wB, b, L.red));
+          passes += 8.0;
+          ++cycles;
+          if (beta <= a.tol * bnorm) {
+            status = VDC_CONVERGED;
+            break;
+          }
+          kinv(r, p);
+          rho = bilin(r, p);
+          fresh = true;
+          continue;
+        }
+        const c64 alpha = cdiv(rho, mu);
+        double acc[1] = {0.0};
+        for (int i = tid; i < npts; i += kBlock) {
+          x[i] = x[i] + alpha * p[i];
+          const c64 ri = r[i] - alpha * q[i];
+          r[i] = ri;
+          acc[0] += norm2(ri);
+        }
+        block_sum<1, double>(acc, L.red, L.red + kWaves);
+        const double rr = L.red[kWaves];
+        __syncthreads();
+        passes += 6.0;
+        ++iters;
+        fresh = false;
+        if (!isfinite(rr)) {
+          status = VDC_NONFINITE;
+          break;
+        }
+        if (sqrt(rr) <= a.tol * bnorm || iters >= a.max_iter) {
+          beta = sqrt(co2_apply(op, L.sq, x, 1.0, r, wA, wB, b, L.red));
+          passes += 8.0;
+          ++cycles;
+          if (beta <= a.tol * bnorm) {
+            status = VDC_CONVERGED;
+            break;
+          }
+          if (!isfinite(beta)) {
+            status = VDC_NONFINITE;
+            break;
+          }
+          if (iters >= a.max_iter) break;
+          kinv(r, p);
+          rho = bilin(r, p);
+          fresh = true;
+          continue;
+        }
+        kinv(r, z);
+        const c64 rho_new = bilin(r, z);
+        const c64 bt = cdiv(rho_new, rho);
+        rho = rho_new;
+        for (int i = tid; i < npts; i += kBlock) p[i] = z[i] + bt * p[i];
+        passes += 3.0;
+      }
     } else {
       for (int i = tid; i < npts; i += kBlock) V[i] = b[i];
       auto apply = [&](int j, double sc, c64* out) {

@@ -1,0 +1,454 @@
+// Persistent batched COCG in complex FP64 (Sec. III.A), one job per
+// workgroup at a time, the whole solve on chip: conjugate gradients with the
+// symmetrized bilinear form <a|b>_S = sum_i a_i b_i, for the complex
+// symmetric A of the model, preconditioned as M^{-1} A M^{-T} (Sec. III.B)
+// with K = M M^T the diagonal of A or its column blocks (segprec.h; both
+// symmetric), in the coupled two-term form:
+//   r = b, z = K^{-1} r, p = z, rho = <r|z>_S;
+//   repeat: q = A p, mu = <p|q>_S (in the operator's pass), alpha = rho/mu,
+//           x += alpha p, r -= alpha q, z = K^{-1} r, rho' = <r|z>_S,
+//           p = z + (rho'/rho) p.
+// Short recurrences: no basis is stored and no orthogonalisation pass is
+// made.  When ||r|| <= tol ||b|| the FP64 true residual b - A x decides
+// (stopping rule of Sec. III); if it is larger the iteration restarts from
+// it.  A vanishing <p|q>_S or <r|z>_S (the form is not definite) restarts
+// from the true residual once, and is reported as a breakdown if it recurs
+// at once.  Every wave reaches the queue-exhausted exit.
+#include "gmres_block.h"
+#include "solve_args.h"
+
+namespace vdc {
+
+struct CocgLds {
+  double red[kRedSize];
+  double sq[kSqMax + 1];
+  double dot[2];
+  int job;
+};
+
+// Byte model (passes over a block vector of Nc complex FP64 values):
+// setup: the preconditioner and x, b (as the FP64 GMRES: 5, block 8), ||b||
+// (1), r = b (2), z = K^{-1} r into p with rho (diagonal: r, dinv in, p out:
+// 3; block: r and 3 factor planes in, p out, then r, p for rho: 7);
+// iteration: the operator (p and 3 table planes in, q out: 5, <p|q>_S from
+// the staged p), the update (x, p, r, q in, x, r out: 6; diagonal: dinv in
+// for rho': 7), the next direction (diagonal: r, dinv, p in, p out: 4;
+// block: z = K^{-1} r: 5, rho': 2, p = z + beta p: 3); a true-residual check
+// 6 (+ the setup's z, rho and p passes on a restart).
+__global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
+  __shared__ CocgLds L;
+  fill_sq<double>(L.sq);
+  const int tid = threadIdx.x;
+  const Fp64Slot s = fp64_slot(a.scratch + (size_t)blockIdx.x * a.slot_elems, a.ncap, 4);
+  c64* lds = reinterpret_cast<c64*>(vdc_tile_lds);
+  c64* r = s.V;
+  c64* p = s.V + a.ncap;
+  c64* q = s.V + 2 * a.ncap;
+  c64* z = s.V + 3 * a.ncap;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) L.job = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int js = L.job;
+    if (js >= a.n_jobs) break;
+    const DevJob jb = a.jobs[js];
+    const DevModel& md = a.models[jb.model];
+    const DevTable tb = a.tabs[jb.table];
+    const OpJob<double> op = make_op<double>(
+        md, jb, a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc);
+    const int Nc = md.Nc;
+    const bool blk = a.precond == VDC_PREC_BLOCK;
+    const SegFactor<double> fac{s.l1, s.l2, s.dinv};
+    fp64_prepare(op, L.sq, s, a.precond);
+    __syncthreads();
+    if (tid == 0) {
+      PhiEntry e[6];
+      const int n = phi_entries(md, jb.mu, jb.eps_i, jb.vi_g, jb.vi_u, e);
+      for (int k = 0; k < n; ++k) s.b[e[k].g * md.Nu + e[k].u] = c64{e[k].val, 0.0};
+    }
+    __syncthreads();
+    double passes = blk ? 9.0 : 6.0;
+    const double bnorm = sqrt(norm_sq<double>(s.b, Nc, L.red));
+    for (int i = tid; i < Nc; i += kBlock) r[i] = s.b[i];
+    passes += 2.0;
+    // p = z = K^{-1} r and rho = <r|z>_S (own elements; block: after its
+    // own barrier)
+    auto restart_direction = [&]() -> c64 {
+      double acc[2] = {0.0, 0.0};
+      if (blk) {
+        seg_apply<double>(fac, op.Ng, op.Nu, r, 1.0, p, false);
+        __syncthreads();
+        for (int i = tid; i < Nc; i += kBlock) {
+          const c64 t = r[i] * p[i];
+          acc[0] += t.x;
+          acc[1] += t.y;
+        }
+        passes += 7.0;
+      } else {
+        for (int i = tid; i < Nc; i += kBlock) {
+          const c64 zi = s.dinv[i] * r[i];
+          p[i] = zi;
+          const c64 t = r[i] * zi;
+          acc[0] += t.x;
+          acc[1] += t.y;
+        }
+        passes += 3.0;
+      }
+      block_sum<2, double>(acc, L.red, L.red + kWaves * 2);
+      const c64 rho = c64{L.red[kWaves * 2], L.red[kWaves * 2 + 1]};
+      __syncthreads();
+      return rho;
+    };
+    int iters = 0, restarts = 0, status = VDC_NOT_CONVERGED;
+    double beta_true = bnorm;
+    if (!(bnorm > 0.0) || !isfinite(bnorm)) {
+      status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
+      beta_true = 0.0;
+    } else {
+      c64 rho = restart_direction();
+      bool fresh = true;   // p was just reset from the true residual
+      for (;;) {
+        // q = A p and mu = <p|q>_S
+        double mu[2] = {0.0, 0.0};
+        if (a.tileT > 0) {
+          matvec_tiled<double>(op, L.sq, p, 1.0, nullptr, q, lds, a.tileT, nullptr, L.red, L.dot);
+          mu[0] = L.dot[0];
+          mu[1] = L.dot[1];
+        } else {
+          matvec_block<double>(op, L.sq, p, nullptr, s.wA, s.wB, q);
+          double acc[2] = {0.0, 0.0};
+          for (int i = tid; i < Nc; i += kBlock) {
+            const c64 t = p[i] * q[i];
+            acc[0] += t.x;
+            acc[1] += t.y;
+          }
+          block_sum<2, double>(acc, L.red, L.red + kWaves * 2);
+          mu[0] = L.red[kWaves * 2];
+          mu[1] = L.red[kWaves * 2 + 1];
+          __syncthreads();
+          passes += 2.0;
+        }
+        passes += 5.0;
+        const c64 muc = c64{mu[0], mu[1]};
+        const double mn = norm2(muc), rn = norm2(rho);
+        if (!(mn > 0.0) || !(rn > 0.0) || !isfinite(mn) || !isfinite(rn)) {
+          // breakdown of the bilinear form: restart from the true residual
+          // once; at once again, give up
+          if (fresh) {
+            status = (isfinite(mn) && isfinite(rn)) ? VDC_BREAKDOWN : VDC_NONFINITE;
+            break;
+          }
+          beta_true = sqrt(residual_A<double>(op, L.sq, s.x, s.b, r, lds, a.tileT, s.wA, s.wB, L.red));
+          passes += 6.0;
+          if (beta_true <= a.tol * bnorm) {
+            status = VDC_CONVERGED;
+            break;
+          }
+          rho = restart_direction();
+          ++restarts;
+          fresh = true;
+          continue;
+        }
+        const c64 alpha = cdiv(rho, muc);
+        // x += alpha p, r -= alpha q, ||r||^2 (and rho' for the diagonal)
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int i = tid; i < Nc; i += kBlock) {
+          s.x[i] = s.x[i] + alpha * p[i];
+          const c64 ri = r[i] - alpha * q[i];
+          r[i] = ri;
+          acc[0] += norm2(ri);
+          if (!blk) {
+            const c64 t = ri * (s.dinv[i] * ri);
+            acc[1] += t.x;
+            acc[2] += t.y;
+          }
+        }
+        block_sum<3, double>(acc, L.red, L.red + kWaves * 3);
+        const double rr = L.red[kWaves * 3];
+        c64 rho_new = c64{L.red[kWaves * 3 + 1], L.red[kWaves * 3 + 2]};
+        __syncthreads();
+        passes += blk ? 6.0 : 7.0;
+        ++iters;
+        fresh = false;
+        if (!isfinite(rr)) {
+          status = VDC_NONFINITE;
+          break;
+        }
+        if (sqrt(rr) <= a.tol * bnorm || iters >= a.max_iter) {
+          // the true residual decides; restart from it if needed
+          beta_true = sqrt(residual_A<double>(op, L.sq, s.x, s.b, r, lds, a.tileT, s.wA, s.wB, L.red));
+          passes += 6.0;
+          if (beta_true <= a.tol * bnorm) {
+            status = VDC_CONVERGED;
+            break;
+          }
+          if (!isfinite(beta_true)) {
+            status = VDC_NONFINITE;
+            break;
+          }
+          if (iters >= a.max_iter) break;
+          rho = restart_direction();
+          ++restarts;
+          fresh = true;
+          continue;
+        }
+        if (blk) {
+          seg_apply<double>(fac, op.Ng, op.Nu, r, 1.0, z, false);
+          __syncthreads();
+          double ad[2] = {0.0, 0.0};
+          for (int i = tid; i < Nc; i += kBlock) {
+            const c64 t = r[i] * z[i];
+            ad[0] += t.x;
+            ad[1] += t.y;
+          }
+          block_sum<2, double>(ad, L.red, L.red + kWaves * 2);
+          rho_new = c64{L.red[kWaves * 2], L.red[kWaves * 2 + 1]};
+          __syncthreads();
+          passes += 7.0;
+        }
+        const c64 beta = cdiv(rho_new, rho);
+        rho = rho_new;
+        for (int i = tid; i < Nc; i += kBlock) {
+          const c64 zi = blk ? z[i] : s.dinv[i] * r[i];
+          p[i] = zi + beta * p[i];
+        }
+        passes += blk ? 3.0 : 4.0;
+      }
+    }
+    __syncthreads();
+    finish_job(a, md, jb, s.x, tid, status, iters, restarts, 0,
+               bnorm > 0.0 ? beta_true / bnorm : 0.0, passes * 16.0 * md.Nc);
+  }
+}
+
+// Mixed precision (the pattern of the FP32-inner solver): FP64 iterative
+// refinement whose correction equations A d = r / ||r|| are solved by COCG
+// entirely in complex FP32 (FP32 tables, stencil, preconditioner and
+// bilinear forms accumulated in FP32) to the relative residual tol_in, or
+// m_in steps: every outer step forms the FP64 true residual b - A x, which
+// decides convergence, casts it to FP32, runs the inner COCG from d = 0 and
+// adds ||r|| d to x in FP64.  "iters" counts inner FP32 steps, "outer" the
+// refinement steps.
+//
+// Byte model (p64: passes of complex FP64, p32 of complex FP32): setup as the
+// FP64 COCG's preconditioner (p64 5, block: p64 1 and p32 3 for the FP32
+// factors) plus x, b; per outer step the residual (x, 3 table planes, b in,
+// r out: p64 6), its cast (p64 1, p32 1), the inner start (r, dinv in, p
+// out: p32 3; block: p32 7) and x += ||r|| d (p64 2, p32 1); per inner step
+// the operator (p32 5), the update of d, r (p32 6, diagonal 7) and the next
+// direction (diagonal p32 4; block p32 10).
+struct CocgMixedLds {
+  double red[kRedSize];
+  float redf[kRedSize];
+  double sq[kSqMax + 1];
+  float sqf[kSqMax + 1];
+  float dot[2];
+  int job;
+};
+
+__global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
+  __shared__ CocgMixedLds L;
+  fill_sq<double>(L.sq);
+  fill_sq<float>(L.sqf);
+  const int tid = threadIdx.x;
+  const size_t ld = a.ncap;
+  c64* lds64 = reinterpret_cast<c64*>(vdc_tile_lds);
+  c32* lds32 = reinterpret_cast<c32*>(vdc_tile_lds);
+  c64* slot = a.scratch + (size_t)blockIdx.x * a.slot_elems;
+  c64* x = slot;                      // FP64
+  c64* b = x + ld;
+  c64* r64 = b + ld;
+  c64* wA = r64 + ld;
+  c64* wB = wA + ld;
+  c32* r = reinterpret_cast<c32*>(wB + ld);   // FP32
+  c32* p = r + ld;
+  c32* q = p + ld;
+  c32* z = q + ld;
+  c32* d = z + ld;
+  c32* dinv = d + ld;
+  c32* l1 = dinv + ld;
+  c32* l2 = l1 + ld;
+  c32* wA32 = l2 + ld;
+  c32* wB32 = wA32 + ld;
+  const bool blk = a.precond == VDC_PREC_BLOCK;
+  const SegFactor<float> fac{l1, l2, dinv};
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) L.job = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int js = L.job;
+    if (js >= a.n_jobs) break;
+    const DevJob jb = a.jobs[js];
+    const DevModel& md = a.models[jb.model];
+    const DevTable tb = a.tabs[jb.table];
+    const size_t toff = tb.offset + (size_t)(jb.parity * a.planes) * md.Nc;
+    const OpJob<double> op = make_op<double>(md, jb, a.tables + toff);
+    const OpJob<float> op32 = make_op<float>(md, jb, a.tables32 + toff);
+    const int Nc = md.Nc;
+    if (blk) seg_factor<float>(op, L.sq, fac);
+    for (int i = tid; i < Nc; i += kBlock) {
+      if (!blk) {
+        const c64 dd = a.precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i))
+                                                     : c64{1.0, 0.0};
+        dinv[i] = c32{(float)dd.x, (float)dd.y};
+      }
+      x[i] = c64{0.0, 0.0};
+      b[i] = c64{0.0, 0.0};
+    }
+    __syncthreads();
+    if (tid == 0) {
+      PhiEntry e[6];
+      const int n = phi_entries(md, jb.mu, jb.eps_i, jb.vi_g, jb.vi_u, e);
+      for (int k = 0; k < n; ++k) b[e[k].g * md.Nu + e[k].u] = c64{e[k].val, 0.0};
+    }
+    __syncthreads();
+    double p64 = blk ? 6.0 : 7.0, p32 = blk ? 3.0 : 1.0;
+    const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
+    p64 += 1.0;
+    int iters = 0, outer = 0, status = VDC_NOT_CONVERGED;
+    double beta = bnorm;
+    // z = K^{-1} src (FP32), then a barrier
+    auto kinv = [&](const c32* src, c32* dst) {
+      if (blk) {
+        seg_apply<float>(fac, op.Ng, op.Nu, src, 1.0f, dst, false);
+        __syncthreads();
+      } else {
+        for (int i = tid; i < Nc; i += kBlock) dst[i] = dinv[i] * src[i];
+        __syncthreads();
+      }
+    };
+    auto bilin = [&](const c32* u, const c32* w) {
+      float acc[2] = {0.f, 0.f};
+      for (int i = tid; i < Nc; i += kBlock) {
+        const c32 t = u[i] * w[i];
+        acc[0] += t.x;
+        acc[1] += t.y;
+      }
+      block_sum<2, float>(acc, L.redf, L.redf + 2 * kWaves);
+      const c32 v = c32{L.redf[2 * kWaves], L.redf[2 * kWaves + 1]};
+      __syncthreads();
+      return v;
+    };
+    if (!(bnorm > 0.0) || !isfinite(bnorm)) {
+      status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
+      beta = 0.0;
+    } else {
+      for (int i = tid; i < Nc; i += kBlock) r64[i] = b[i];
+      p64 += 2.0;
+      for (;;) {
+        // r64 holds the FP64 true residual, beta its norm
+        if (beta <= a.tol * bnorm) {
+          status = VDC_CONVERGED;
+          break;
+        }
+        if (iters >= a.max_iter) break;
+        const double sc = 1.0 / beta;
+        for (int i = tid; i < Nc; i += kBlock) {
+          const c64 t = sc * r64[i];
+          r[i] = c32{(float)t.x, (float)t.y};
+          d[i] = c32{0.f, 0.f};
+        }
+        p64 += 1.0;
+        p32 += 2.0;
+        __syncthreads();
+        // inner COCG on A d = r (unit norm) in FP32
+        kinv(r, p);
+        c32 rho = bilin(r, p);
+        p32 += blk ? 7.0 : 3.0;
+        int k = 0;
+        bool bad = false;
+        for (;;) {
+          if (a.tileT32 > 0) {
+            matvec_tiled<float>(op32, L.sqf, p, 1.0f, nullptr, q, lds32, a.tileT32, nullptr,
+                                L.redf, L.dot);
+          } else {
+            matvec_block<float>(op32, L.sqf, p, nullptr, wA32, wB32, q);
+            float acc[2] = {0.f, 0.f};
+            for (int i = tid; i < Nc; i += kBlock) {
+              const c32 t = p[i] * q[i];
+              acc[0] += t.x;
+              acc[1] += t.y;
+            }
+            block_sum<2, float>(acc, L.redf, L.redf + 2 * kWaves);
+            if (tid < 2) L.dot[tid] = L.redf[2 * kWaves + tid];
+            __syncthreads();
+            p32 += 2.0;
+          }
+          p32 += 5.0;
+          const c32 mu = c32{L.dot[0], L.dot[1]};
+          const float mn = norm2(mu), rn = norm2(rho);
+          if (!(mn > 0.f) || !(rn > 0.f) || !isfinite(mn) || !isfinite(rn)) {
+            bad = k == 0;
+            break;
+          }
+          const c32 alpha = cinv<float>(mu) * rho;
+          float acc[1] = {0.f};
+          for (int i = tid; i < Nc; i += kBlock) {
+            d[i] = d[i] + alpha * p[i];
+            const c32 ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            acc[0] += norm2(ri);
+          }
+          block_sum<1, float>(acc, L.redf, L.redf + kWaves);
+          const float rr = L.redf[kWaves];
+          __syncthreads();
+          p32 += 6.0;
+          ++k;
+          ++iters;
+          if (rr <= (float)(a.tol_in * a.tol_in) || k >= a.m_in || iters >= a.max_iter ||
+              !isfinite(rr))
+            break;
+          kinv(r, z);
+          const c32 rho_new = bilin(r, z);
+          const c32 bt = cinv<float>(rho) * rho_new;
+          rho = rho_new;
+          for (int i = tid; i < Nc; i += kBlock) p[i] = z[i] + bt * p[i];
+          p32 += blk ? 10.0 : 4.0;
+        }
+        if (bad) {
+          status = VDC_BREAKDOWN;
+          break;
+        }
+        // x += ||r|| d in FP64, then the true residual
+        for (int i = tid; i < Nc; i += kBlock)
+          x[i] = x[i] + beta * c64{(double)d[i].x, (double)d[i].y};
+        p64 += 2.0;
+        p32 += 1.0;
+        ++outer;
+        beta = sqrt(residual_A<double>(op, L.sq, x, b, r64, lds64, a.tileT, wA, wB, L.red));
+        p64 += 6.0;
+        if (!isfinite(beta)) {
+          status = VDC_NONFINITE;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    finish_job(a, md, jb, x, tid, status, iters, outer, outer,
+               bnorm > 0.0 ? beta / bnorm : 0.0, (p64 * 16.0 + p32 * 8.0) * md.Nc);
+  }
+}
+
+hipError_t launch_cocg_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
+  hipLaunchKernelGGL(cocg_mixed_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  return hipGetLastError();
+}
+
+int cocg_mixed_occupancy(size_t dyn_lds) {
+  int n = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cocg_mixed_kernel, kBlock, dyn_lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_cocg_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
+  hipLaunchKernelGGL(cocg_fp64_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  return hipGetLastError();
+}
+
+int cocg_fp64_occupancy(size_t dyn_lds) {
+  int n = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cocg_fp64_kernel, kBlock, dyn_lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+}  // namespace vdc

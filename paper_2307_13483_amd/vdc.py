@@ -20,6 +20,7 @@ VDC_OK, VDC_ERR_INVALID_ARG, VDC_ERR_WORKSPACE, VDC_ERR_HIP, VDC_ERR_UNSUPPORTED
 CONVERGED, NOT_CONVERGED, BREAKDOWN, NONFINITE = range(4)
 PREC_NONE, PREC_JACOBI, PREC_BLOCK = 0, 1, 2
 FP64, FP32_INNER = 0, 1
+GMRES, COCG = 0, 1
 STATUS_NAMES = {CONVERGED: "converged", NOT_CONVERGED: "not_converged",
                 BREAKDOWN: "breakdown", NONFINITE: "nonfinite"}
 
@@ -49,7 +50,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("outer_restart", ctypes.c_int), ("tile_rows", ctypes.c_int)]
+                ("outer_restart", ctypes.c_int), ("tile_rows", ctypes.c_int),
+                ("method", ctypes.c_int)]
 
 
 class JobInfo(ctypes.Structure):
@@ -115,6 +117,8 @@ def lib():
                               P]),
         "vdc_co2_ops_workspace_size": (I, [P, I, I, ctypes.POINTER(S)]),
         "vdc_co2_apply": (I, [P, D, I, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
+        "vdc_eels_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
+        "vdc_eels": (I, [P, I, ctypes.POINTER(Job), P, S, I, D, D, D, P, P, S, P]),
         "vdc_last_error": (ctypes.c_char_p, []),
         "vdc_version": (ctypes.c_char_p, []),
     }
@@ -198,10 +202,12 @@ class Opts:
     inner_tol: float = 1e-3
     outer_restart: int = 16
     tile_rows: int = 0
+    method: int = GMRES
 
     def c(self):
         return SolveOpts(self.restart, self.max_iter, self.tol, self.precond, self.precision,
-                         self.inner_restart, self.inner_tol, self.outer_restart, self.tile_rows)
+                         self.inner_restart, self.inner_tol, self.outer_restart, self.tile_rows,
+                         self.method)
 
 
 def level_shift(model, eps):
@@ -251,6 +257,26 @@ def matvec_block(model, E, x, parity, ws_cache=None):
     _check(lib().vdc_matvec_block(model.handle, float(E), n_vec, par, _ptr(x), _ptr(y), _ptr(ws),
                                   nb.value, _stream_ptr()))
     return y
+
+
+def eels(model, jobs, psi, loss0, dloss, n_grid, fwhm=0.010):
+    """vdc_eels: the 2D energy-loss spectrum (Eq. (17)) of each solved
+    right-hand side.  jobs: tuples (eps_i, (n_g, n_u), mu_i) of one model;
+    psi: device complex [n_jobs, 2 Ng Nu] full-layout solutions (e.g.
+    Solver(..., want_psi=True).psi).  Returns S, device float64 [n_jobs, n_grid]
+    on loss0 + j dloss; sum the rows of mu_i = e and o for the total."""
+    n = len(jobs)
+    arr = (Job * max(1, n))()
+    for k, jb in enumerate(jobs):
+        arr[k] = Job(float(jb[0]), int(jb[1][0]), int(jb[1][1]), int(jb[2]), 0)
+    psi = psi.contiguous()
+    S = torch.zeros((n, n_grid), dtype=torch.float64, device="cuda")
+    nb = ctypes.c_size_t()
+    _check(lib().vdc_eels_workspace_size(model.handle, n, ctypes.byref(nb)))
+    raw, ws = _aligned_workspace(nb.value, "cuda")
+    _check(lib().vdc_eels(model.handle, n, arr, _ptr(psi), psi.shape[1], int(n_grid), float(loss0),
+                          float(dloss), float(fwhm), _ptr(S), _ptr(ws), nb.value, _stream_ptr()))
+    return S
 
 
 class Solver:

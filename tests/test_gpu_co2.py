@@ -200,3 +200,35 @@ def test_iterations_track_textbook_gmres(vdc):
         b = M.phi(v, poly.WAVES[mu])
         _, info = solvers.gmres(A, b, m=20, tol=1e-10, psolve=pc.BlockInverse(A, poly.bend_blocks(sizes)))
         assert abs(infos[k]["iters"] - info["iters"]) <= 2, (infos[k], info)
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_cocg_solves_match_lu(vdc, precond):
+    """COCG (the paper's method for its CO2 model), split-preconditioned by
+    the diagonal or the bend blocks: every solve against LU."""
+    sizes = dict(s=4, x=6, y=6, a=2)
+    jobs = [(e, (0, 0, 0, 0), mu) for e in (0.6, 2.1) for mu in (0, 1, 2)] + [(1.4, (1, 1, 0, 0), 0)]
+    finals = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 2, 0, 0), (0, 1, 1, 0)]
+    model = vdc.Co2Model(P, sizes)
+    opts = vdc.Opts(precision=vdc.FP64, precond=precond, method=vdc.COCG, max_iter=5000)
+    T, sigma, psi, infos = vdc.co2_solve(model, jobs, finals, opts, want_psi=True)
+    _check(vdc, sizes, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+
+
+def test_cocg_iterations_track_oracle(vdc):
+    """Bend-block preconditioned COCG against the oracle's COCG with the
+    exact block inverse: the step counts agree within 3 steps or 5 % (the
+    GPU's factor is stored in FP16)."""
+    sizes = dict(s=5, x=8, y=8, a=3)
+    jobs = [(2.0, (0, 0, 0, 0), 0), (2.0, (0, 0, 0, 0), 1), (3.3, (0, 0, 0, 0), 2)]
+    model = vdc.Co2Model(P, sizes)
+    _, _, _, infos = vdc.co2_solve(model, jobs, [(0, 0, 0, 0)],
+                                   vdc.Opts(precision=vdc.FP64, precond=vdc.PREC_BLOCK,
+                                            method=vdc.COCG, max_iter=5000))
+    for k, (eps, v, mu) in enumerate(jobs):
+        M = poly.PolyModel(P, sizes, poly.total_energy(P, eps, v))
+        A = M.matrix().tocsr()
+        b = M.phi(v, poly.WAVES[mu])
+        _, info = solvers.cocg(A, b, tol=1e-10, psolve=pc.BlockInverse(A, poly.bend_blocks(sizes)))
+        assert info["converged"]
+        assert abs(infos[k]["iters"] - info["iters"]) <= max(3, 0.05 * info["iters"]), (infos[k], info)

@@ -451,3 +451,82 @@ def test_block_preconditioner_full_size_mixed(vdc):
     _, _, _, jinfos = vdc.solve(model, sample, cfg["finals"],
                                 vdc.Opts(precond=vdc.PREC_JACOBI, **base))
     assert sum(i["iters"] for i in infos) < sum(i["iters"] for i in jinfos)
+
+
+# ------------------------------------------------------------ COCG
+
+@pytest.mark.parametrize("Ng,Nu", [(1, 1), (2, 3), (13, 29), (30, 26)])
+@pytest.mark.parametrize("precond", [0, 1, 2])
+def test_cocg_solves(vdc, Ng, Nu, precond):
+    """COCG (bilinear form, split-preconditioned by the diagonal or the
+    column blocks, or none) on tiny, ragged and multi-segment bases: every
+    solve checked against the oracle's LU solution."""
+    p = inputs.draw_params(21)
+    jobs = [(0.8, (0, 0), 0), (2.1, (min(1, Ng - 1), 0), 1), (1.4, (0, min(1, Nu - 1)), 0)]
+    finals = [(0, 0), (min(2, Ng - 1), 0), (0, min(1, Nu - 1))]
+    model = vdc.Model2D(p, Ng, Nu)
+    opts = vdc.Opts(precond=precond, method=vdc.COCG, max_iter=5000)
+    T, sigma, psi, infos = vdc.solve(model, jobs, finals, opts, want_psi=True)
+    _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
+                 psi.cpu().numpy(), infos)
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_cocg_iterations_track_oracle(vdc, precond):
+    """The same preconditioner as the oracle's COCG (the diagonal, or the
+    8-row column blocks as slices of its assembled A solved by LU): the step
+    counts agree to rounding (within 3 % or 3 steps)."""
+    from oracle import precond as pc
+    p = inputs.draw_params(8)
+    Ng, Nu = 30, 26
+    jobs = [(0.5, (0, 0), 0), (2.6, (1, 0), 1), (1.9, (0, 1), 0)]
+    model = vdc.Model2D(p, Ng, Nu)
+    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)],
+                               vdc.Opts(precond=precond, method=vdc.COCG, max_iter=5000))
+    for k, (e, vi, mu) in enumerate(jobs):
+        mdl, A, b, _, _ = _oracle_job(p, Ng, Nu, e, vi, mu, [(0, 0)])
+        if precond == 2:
+            ps = pc.BlockInverse(A, pc.segmented_blocks(Ng, Nu, 8))
+        else:
+            dinv = 1.0 / m2.jacobi_diagonal(A)
+            ps = (lambda v, d=dinv: d * v)
+        _, info = solvers.cocg(A, b, tol=1e-10, psolve=ps)
+        assert info["converged"]
+        assert abs(infos[k]["iters"] - info["iters"]) <= max(3, 0.03 * info["iters"]), (infos[k], info)
+
+
+def test_cocg_batched_full_size_sampled(vdc):
+    """The 120 x 120 batched workload's model on a sample of its jobs by
+    COCG with the block preconditioner, all in one launch; every job checked
+    against the oracle."""
+    cfg = inputs.batched_jobs(n_energies=512)
+    p = cfg["params"]
+    sample = [cfg["jobs"][k] for k in (0, 1, 1001, 2000, 3071, 2502)]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    T, sigma, psi, infos = vdc.solve(model, sample, cfg["finals"],
+                                     vdc.Opts(precond=vdc.PREC_BLOCK, method=vdc.COCG, max_iter=5000),
+                                     want_psi=True)
+    _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
+                 sigma.cpu().numpy(), psi.cpu().numpy(), infos)
+
+
+def test_cocg_rejected_where_unsupported(vdc):
+    model = vdc.Model2D(inputs.draw_params(21), 6, 5)
+    with pytest.raises(vdc.VdcError):
+        vdc.solve(model, [(0.8, (0, 0), 0)], [(0, 0)], vdc.Opts(method=vdc.COCG), plain=True)
+
+
+@pytest.mark.parametrize("Ng,Nu", [(1, 1), (13, 29), (30, 26)])
+@pytest.mark.parametrize("precond", [1, 2])
+def test_cocg_mixed_precision_solves(vdc, Ng, Nu, precond):
+    """FP64 refinement with FP32 COCG correction solves: every solve reaches
+    the FP64 true residual target and the oracle's LU solution."""
+    p = inputs.draw_params(21)
+    jobs = [(0.8, (0, 0), 0), (2.1, (min(1, Ng - 1), 0), 1), (1.4, (0, min(1, Nu - 1)), 0)]
+    finals = [(0, 0), (min(2, Ng - 1), 0), (0, min(1, Nu - 1))]
+    model = vdc.Model2D(p, Ng, Nu)
+    opts = vdc.Opts(precond=precond, method=vdc.COCG, precision=vdc.FP32_INNER, inner_restart=100,
+                    inner_tol=1e-4, max_iter=20000)
+    T, sigma, psi, infos = vdc.solve(model, jobs, finals, opts, want_psi=True)
+    _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
+                 psi.cpu().numpy(), infos)
