@@ -109,6 +109,20 @@ def co2like(args, method=None):
                 frac=alg / (ms_sol * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
 
+def solver_name(opts, precond):
+    from paper_2307_13483_amd import vdc
+    pc = PREC_NAMES[precond]
+    if opts.method == vdc.COCG:
+        if opts.precision == vdc.FP64:
+            return f"COCG FP64, {pc}"
+        return (f"FP64 refinement, COCG FP32 correction solves to {opts.inner_tol:g} "
+                f"(<= {opts.inner_restart} steps), {pc}")
+    if opts.precision == vdc.FP64:
+        return f"GMRES({opts.restart}), {pc}"
+    return (f"FGMRES({opts.outer_restart}) FP64 outer, GMRES({opts.inner_restart}) "
+            f"FP32 inner to {opts.inner_tol:g}, {pc}")
+
+
 def cocg_batched(model, cfg, precond, mixed=False):
     """The batched workload (the same 3072 right-hand sides and 120 x 120
     model as the headline) solved by COCG in FP64 with the given
@@ -388,8 +402,12 @@ def main():
         iters = [i["iters"] for i in infos]
         solver_ms = sum(ms_solver) / len(ms_solver)
         alg = sum(i["alg_bytes"] for i in infos)
-        kernel = "gmres_fp64_kernel" if prec == vdc.FP64 else "fgmres_mixed_kernel"
+        cocg = opts.method == vdc.COCG
+        kernel = {(vdc.FP64, False): "gmres_fp64_kernel", (vdc.FP32_INNER, False): "fgmres_mixed_kernel",
+                  (vdc.FP64, True): "cocg_fp64_kernel", (vdc.FP32_INNER, True): "cocg_mixed_kernel"}[
+                      (prec, cocg)]
         workload = (f"batched_{args.energies}x3x2_{Ng}x{Nu}_{precision}_{args.precond}"
+                    f"_{'cocg' if cocg else 'gmres'}"
                     f"_m{opts.restart}_mi{opts.inner_restart}_ti{opts.inner_tol:g}"
                     f"_mo{opts.outer_restart}_t{opts.tile_rows}")
         achieved = alg / (solver_ms * 1e-3) / 1e9
@@ -398,9 +416,9 @@ def main():
                     kernel=kernel, algorithmic_bytes_per_launch=alg, kernel_ms=solver_ms,
                     traffic_key=workload)
         return dict(value=conv * args.steps / dt, ms_per_step=dt / args.steps * 1e3,
-                    chosen=dict(restart=opts.restart, inner_restart=opts.inner_restart,
-                                inner_tol=opts.inner_tol, outer_restart=opts.outer_restart,
-                                tile_rows=opts.tile_rows),
+                    chosen=dict(method="COCG" if cocg else "GMRES", restart=opts.restart,
+                                inner_restart=opts.inner_restart, inner_tol=opts.inner_tol,
+                                outer_restart=opts.outer_restart, tile_rows=opts.tile_rows),
                     converged=conv, worst_rel_res=worst, n_jobs=solver.n_jobs,
                     iters_mean=sum(iters) / len(iters), iters_max=max(iters),
                     outer_mean=(sum(i["outer_iters"] for i in infos) / len(infos)),
@@ -419,10 +437,7 @@ def main():
         "config": {"workload": "2D generalized model, batched energies x v_i x mu",
                    "basis": f"{Ng}x{Nu} per state", "unknowns": 2 * nc,
                    "right_hand_sides": head["n_jobs"], "energies": args.energies,
-                   "solver": (f"GMRES({opts.restart}), {PREC_NAMES[args.precond]}"
-                              if args.precision == "fp64" else
-                              f"FGMRES({opts.outer_restart}) FP64 outer, GMRES({opts.inner_restart}) "
-                              f"FP32 inner to {opts.inner_tol:g}, {PREC_NAMES[args.precond]}"),
+                   "solver": solver_name(opts, args.precond),
                    "tuned": head["chosen"],
                    "tol": "1e-10 relative FP64 true residual",
                    "precision": args.precision},

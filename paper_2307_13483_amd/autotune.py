@@ -1,5 +1,6 @@
-"""Autotuner for the batched solve: restart lengths, inner tolerance and the
-rows per LDS tile of the fused operator pass.
+"""Autotuner for the batched solve: Krylov method (GMRES or COCG), restart
+lengths, inner step limits and tolerance, and the rows per LDS tile of the
+fused operator pass.
 
 Each candidate runs the batched solve (vdc_solve) on an evenly spaced sample
 of the job list (the list is cost-ordered by energy, so the sample spans the
@@ -14,18 +15,24 @@ from dataclasses import asdict, replace
 
 from . import vdc
 
-FP64_CANDIDATES = [dict(restart=m) for m in (4, 5, 6, 8, 10, 15)]
-FP32_CANDIDATES = [dict(inner_restart=mi, inner_tol=ti, outer_restart=mo)
-                   for mi, ti, mo in ((4, 1e-3, 32), (6, 1e-3, 24), (6, 1e-2, 32), (8, 1e-3, 16),
-                                      (8, 1e-2, 24), (8, 1e-3, 24), (10, 1e-3, 16), (12, 1e-4, 12),
-                                      (15, 1e-4, 8))]
+# GMRES restart lengths and COCG (Sec. III.A) in FP64; FGMRES with FP32 GMRES
+# inner cycles, and FP64 refinement with FP32 COCG correction solves (inner
+# step limit, inner tolerance)
+FP64_CANDIDATES = ([dict(method=vdc.GMRES, restart=m) for m in (4, 5, 6, 8, 10, 15)] +
+                   [dict(method=vdc.COCG)])
+FP32_CANDIDATES = ([dict(method=vdc.GMRES, inner_restart=mi, inner_tol=ti, outer_restart=mo)
+                    for mi, ti, mo in ((4, 1e-3, 32), (6, 1e-3, 24), (6, 1e-2, 32), (8, 1e-3, 16),
+                                       (8, 1e-2, 24), (8, 1e-3, 24), (10, 1e-3, 16), (12, 1e-4, 12),
+                                       (15, 1e-4, 8))] +
+                   [dict(method=vdc.COCG, inner_restart=mi, inner_tol=ti)
+                    for mi, ti in ((60, 1e-3), (100, 1e-3), (100, 1e-4), (200, 1e-5))])
 TILE_CANDIDATES = (0, 4, 8)
 
 
 def _key(models, n_jobs, precision, precond):
     shapes = sorted({(m.Ng, m.Nu) for m in models})
     bucket = 1 << max(0, (n_jobs - 1).bit_length())
-    return f"{precision}:p{precond}:{shapes}:{bucket}"
+    return f"{precision}:p{precond}:{shapes}:{bucket}:methods"
 
 
 def autotune(models, jobs, finals, base=None, sample=384, cache=None, reps=2):
