@@ -120,7 +120,8 @@ typedef struct {
   double tol;                /* relative true-residual target, > 0            */
   int precond;               /* vdc_precond                                     */
   int precision;             /* vdc_precision                                   */
-  int inner_restart;         /* FP32_INNER: inner GMRES length (1..128)         */
+  int inner_restart;         /* FP32_INNER: inner GMRES length (1..128), or
+                                the inner COCG step limit (>= 1)             */
   double inner_tol;          /* FP32_INNER: inner relative tolerance            */
   int outer_restart;         /* FP32_INNER: outer FGMRES length (1..32)         */
   int tile_rows;             /* rows of n_g per LDS tile of the fused operator

@@ -159,8 +159,8 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   const int shift_per_point = adjoint ? 3 * kNumF : kNumF;
   if (mixed) {
     if (plain) return fail(VDC_ERR_UNSUPPORTED, "the plain path is FP64 only");
-    if (o->inner_restart < 1 || o->inner_restart > kMaxRestart)
-      return fail(VDC_ERR_INVALID_ARG, "inner_restart must be 1..128");
+    if (o->inner_restart < 1 || (!cocg && o->inner_restart > kMaxRestart))
+      return fail(VDC_ERR_INVALID_ARG, "inner_restart must be 1..128 (>= 1 for COCG)");
     if (o->outer_restart < 1 || o->outer_restart > 32)
       return fail(VDC_ERR_INVALID_ARG, "outer_restart must be 1..32");
     if (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0))

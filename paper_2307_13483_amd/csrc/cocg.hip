@@ -31,10 +31,11 @@ struct CocgLds {
 // (1), r = b (2), z = K^{-1} r into p with rho (diagonal: r, dinv in, p out:
 // 3; block: r and 3 factor planes in, p out, then r, p for rho: 7);
 // iteration: the operator (p and 3 table planes in, q out: 5, <p|q>_S from
-// the staged p), the update (x, p, r, q in, x, r out: 6; diagonal: dinv in
-// for rho': 7), the next direction (diagonal: r, dinv, p in, p out: 4;
-// block: z = K^{-1} r: 5, rho': 2, p = z + beta p: 3); a true-residual check
-// 6 (+ the setup's z, rho and p passes on a restart).
+// the staged p), the update of x and r with rho' (x, p, r, q in, x, r out,
+// and dinv in: 7; block, by column blocks with z = K^{-1} r: 3 factor planes
+// in and z out as well: 10), the next direction (diagonal: r, dinv, p in, p
+// out: 4; block: z, p in, p out: 3); a true-residual check 6 (+ the setup's
+// z, rho and p passes on a restart).
 __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
   __shared__ CocgLds L;
   fill_sq<double>(L.sq);
@@ -150,14 +151,17 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
           continue;
         }
         const c64 alpha = cdiv(rho, muc);
-        // x += alpha p, r -= alpha q, ||r||^2 (and rho' for the diagonal)
+        // x += alpha p, r -= alpha q, ||r||^2 and rho' = <r|K^{-1} r>_S in one
+        // pass (block: by column blocks, z = K^{-1} r stored)
         double acc[3] = {0.0, 0.0, 0.0};
-        for (int i = tid; i < Nc; i += kBlock) {
-          s.x[i] = s.x[i] + alpha * p[i];
-          const c64 ri = r[i] - alpha * q[i];
-          r[i] = ri;
-          acc[0] += norm2(ri);
-          if (!blk) {
+        if (blk) {
+          seg_cocg_step<double>(fac, op.Ng, op.Nu, alpha, p, q, s.x, r, z, acc);
+        } else {
+          for (int i = tid; i < Nc; i += kBlock) {
+            s.x[i] = s.x[i] + alpha * p[i];
+            const c64 ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            acc[0] += norm2(ri);
             const c64 t = ri * (s.dinv[i] * ri);
             acc[1] += t.x;
             acc[2] += t.y;
@@ -165,9 +169,9 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
         }
         block_sum<3, double>(acc, L.red, L.red + kWaves * 3);
         const double rr = L.red[kWaves * 3];
-        c64 rho_new = c64{L.red[kWaves * 3 + 1], L.red[kWaves * 3 + 2]};
+        const c64 rho_new = c64{L.red[kWaves * 3 + 1], L.red[kWaves * 3 + 2]};
         __syncthreads();
-        passes += blk ? 6.0 : 7.0;
+        passes += blk ? 10.0 : 7.0;
         ++iters;
         fresh = false;
         if (!isfinite(rr)) {
@@ -191,20 +195,6 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
           ++restarts;
           fresh = true;
           continue;
-        }
-        if (blk) {
-          seg_apply<double>(fac, op.Ng, op.Nu, r, 1.0, z, false);
-          __syncthreads();
-          double ad[2] = {0.0, 0.0};
-          for (int i = tid; i < Nc; i += kBlock) {
-            const c64 t = r[i] * z[i];
-            ad[0] += t.x;
-            ad[1] += t.y;
-          }
-          block_sum<2, double>(ad, L.red, L.red + kWaves * 2);
-          rho_new = c64{L.red[kWaves * 2], L.red[kWaves * 2 + 1]};
-          __syncthreads();
-          passes += 7.0;
         }
         const c64 beta = cdiv(rho_new, rho);
         rho = rho_new;
@@ -235,8 +225,10 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
 // factors) plus x, b; per outer step the residual (x, 3 table planes, b in,
 // r out: p64 6), its cast (p64 1, p32 1), the inner start (r, dinv in, p
 // out: p32 3; block: p32 7) and x += ||r|| d (p64 2, p32 1); per inner step
-// the operator (p32 5), the update of d, r (p32 6, diagonal 7) and the next
-// direction (diagonal p32 4; block p32 10).
+// the operator (p32 5), the update of d and r with rho' (diagonal: d, p, r,
+// q, dinv in, d, r out: p32 7; block, by column blocks with z = K^{-1} r:
+// the same and 3 factor planes in, z out: p32 10) and the next direction
+// (diagonal: r, dinv, p in, p out: p32 4; block: z, p in, p out: p32 3).
 struct CocgMixedLds {
   double red[kRedSize];
   float redf[kRedSize];
@@ -382,28 +374,36 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
             break;
           }
           const c32 alpha = cinv<float>(mu) * rho;
-          float acc[1] = {0.f};
-          for (int i = tid; i < Nc; i += kBlock) {
-            d[i] = d[i] + alpha * p[i];
-            const c32 ri = r[i] - alpha * q[i];
-            r[i] = ri;
-            acc[0] += norm2(ri);
+          // d += alpha p, r -= alpha q, ||r||^2 and rho' = <r|K^{-1} r>_S in
+          // one pass (block: by column blocks, z = K^{-1} r stored)
+          float acc[3] = {0.f, 0.f, 0.f};
+          if (blk) {
+            seg_cocg_step<float>(fac, op.Ng, op.Nu, alpha, p, q, d, r, z, acc);
+          } else {
+            for (int i = tid; i < Nc; i += kBlock) {
+              d[i] = d[i] + alpha * p[i];
+              const c32 ri = r[i] - alpha * q[i];
+              r[i] = ri;
+              acc[0] += norm2(ri);
+              const c32 t = ri * (dinv[i] * ri);
+              acc[1] += t.x;
+              acc[2] += t.y;
+            }
           }
-          block_sum<1, float>(acc, L.redf, L.redf + kWaves);
-          const float rr = L.redf[kWaves];
+          block_sum<3, float>(acc, L.redf, L.redf + 3 * kWaves);
+          const float rr = L.redf[3 * kWaves];
+          const c32 rho_new = c32{L.redf[3 * kWaves + 1], L.redf[3 * kWaves + 2]};
           __syncthreads();
-          p32 += 6.0;
+          p32 += blk ? 10.0 : 7.0;
           ++k;
           ++iters;
           if (rr <= (float)(a.tol_in * a.tol_in) || k >= a.m_in || iters >= a.max_iter ||
               !isfinite(rr))
             break;
-          kinv(r, z);
-          const c32 rho_new = bilin(r, z);
           const c32 bt = cinv<float>(rho) * rho_new;
           rho = rho_new;
-          for (int i = tid; i < Nc; i += kBlock) p[i] = z[i] + bt * p[i];
-          p32 += blk ? 10.0 : 4.0;
+          for (int i = tid; i < Nc; i += kBlock) p[i] = (blk ? z[i] : dinv[i] * r[i]) + bt * p[i];
+          p32 += blk ? 3.0 : 4.0;
         }
         if (bad) {
           status = VDC_BREAKDOWN;

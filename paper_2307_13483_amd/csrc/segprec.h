@@ -150,4 +150,58 @@ __device__ inline void seg_apply(const SegFactor<R>& f, int Ng, int Nu,
     seg_apply_block<R>(f, Ng, Nu, v, vscale, z, accumulate, c);
 }
 
+// One COCG step's vector work over the column blocks, each block by one
+// thread: x += alpha p and r -= alpha q on the block's elements, then
+// z = M^{-1} r from the updated r held in registers; acc[0] += ||r||^2 and
+// acc[1] + i acc[2] += <r|z>_S (no conjugate) over the thread's blocks.
+// Begins with a barrier (p, q may have just been written by other threads);
+// x, r and z are then owned by blocks, so a barrier must precede element
+// ownership again.
+template <typename R>
+__device__ inline void seg_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
+                                     typename CT<R>::C alpha,
+                                     const typename CT<R>::C* __restrict__ p,
+                                     const typename CT<R>::C* __restrict__ q,
+                                     typename CT<R>::C* __restrict__ x,
+                                     typename CT<R>::C* __restrict__ r,
+                                     typename CT<R>::C* __restrict__ z, R* acc) {
+  using C = typename CT<R>::C;
+  __syncthreads();
+  const int nb = seg_blocks(Ng, Nu);
+  for (int c = threadIdx.x; c < nb; c += kBlock) {
+    const int u = c % Nu, g0 = (c / Nu) * kSegRows, L = min(kSegRows, Ng - g0);
+    C rv[kSegRows], y[kSegRows];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k) {
+      rv[k] = y[k] = cz<R>();
+      if (k < L) {
+        const int i = (g0 + k) * Nu + u;
+        x[i] = x[i] + alpha * p[i];
+        const C ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rv[k] = ri;
+        acc[0] += norm2(ri);
+        C t = ri;
+        if (k >= 1) t = t - f.l1[i - Nu] * y[k - 1];
+        if (k >= 2) t = t - f.l2[i - 2 * Nu] * y[k - 2];
+        y[k] = t;
+      }
+    }
+#pragma unroll
+    for (int k = kSegRows - 1; k >= 0; --k) {
+      if (k < L) {
+        const int i = (g0 + k) * Nu + u;
+        C t = f.dinv[i] * y[k];
+        if (k + 1 < L) t = t - f.l1[i] * y[k + 1];
+        if (k + 2 < L) t = t - f.l2[i] * y[k + 2];
+        y[k] = t;
+        z[i] = t;
+        const C rz = rv[k] * t;
+        acc[1] += rz.x;
+        acc[2] += rz.y;
+      }
+    }
+  }
+}
+
 }  // namespace vdc
