@@ -14,6 +14,7 @@ Prints one JSON line (see DESIGN.md for the byte model behind "roofline").
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -26,11 +27,26 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2307_13483_amd", "csrc")
 
 
-def kernel_hash():
-    """Hash of every HIP source and header: counters taken on other sources
-    are not used."""
+# the translation unit of each profiled kernel
+KERNEL_SOURCES = {"gmres_fp64_kernel": "gmres.hip", "fgmres_mixed_kernel": "mixed.hip",
+                  "cocg_fp64_kernel": "cocg.hip", "cocg_mixed_kernel": "cocg.hip",
+                  "matvec_strip_kernel": "matvec.hip", "co2_gmres_kernel": "co2.hip",
+                  "co2_factor_kernel": "co2.hip"}
+
+
+def kernel_hash(kernel):
+    """Hash of the kernel's source file and every header it includes
+    (transitively): counters taken on other sources are not used."""
+    seen, todo = [], [KERNEL_SOURCES[kernel]]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(CSRC, f)):
+            continue
+        seen.append(f)
+        with open(os.path.join(CSRC, f)) as fh:
+            todo += re.findall(r'^#include "([^"]+)"', fh.read(), re.M)
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in sorted(seen):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -44,7 +60,7 @@ def load_traffic(kernel, workload):
         with open(path) as fh:
             d = json.load(fh)
         e = d[kernel][workload]
-        if e.get("kernel_hash") != kernel_hash():
+        if e.get("kernel_hash") != kernel_hash(kernel):
             return None
         return e["bytes_per_launch"]
     except Exception:
@@ -286,6 +302,8 @@ def main():
     ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--outer-restart", type=int, default=16)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--method", choices=["gmres", "cocg"], default="gmres",
+                    help="Krylov method when --autotune 0 (the autotuner chooses otherwise)")
     ap.add_argument("--precond", choices=sorted(PRECONDS), default="block",
                     help="right preconditioner: the diagonal of A or its column blocks")
     ap.add_argument("--extras", type=int, default=1,
@@ -374,7 +392,8 @@ def main():
         opts = vdc.Opts(restart=args.restart, tol=1e-10, precision=prec,
                         inner_restart=args.inner_restart, inner_tol=args.inner_tol,
                         outer_restart=args.outer_restart, tile_rows=args.tile_rows,
-                        precond=PRECONDS[args.precond])
+                        precond=PRECONDS[args.precond],
+                        method=vdc.COCG if args.method == "cocg" else vdc.GMRES)
         if args.autotune:
             from paper_2307_13483_amd.autotune import autotune
             opts, _ = autotune([model], cfg["jobs"], cfg["finals"], base=opts)
