@@ -90,6 +90,33 @@ def adjoint_workload(n_energies=256, n_basis=120, seed=SEED):
                 v_i=(0, 0), finals=[(k, 0) for k in range(6)])
 
 
+
+# ---------------------------------------------------------------- ECD86 model
+
+def ecd86_params():
+    """The pseudo Jahn-Teller model of Estrada, Cederbaum and Domcke with the
+    values of Table I, in this descriptor: couplings to the continuum
+    independent of the coordinates (lam1 = lam2 = 0), state 1 coupled only to
+    the even wave and state 2 only to the odd one (no width for (2, e) and
+    (1, o)), l = 2 for the even and l = 1 for the odd wave; the width
+    a eps^(l+1/2) exp(-b eps) is A = a, B = 1/b.  B2e and B1o only stand in
+    for the absent widths."""
+    return dict(omega_g=0.258, omega_u=0.091, kappa1=-0.212, kappa2=0.254, lam=0.318,
+                lam1=0.0, lam2=0.0, gap=2.85 - 2.45,
+                A1e=0.086, A2e=0.0, A1o=0.0, A2o=0.186,
+                B1e=1.0 / 0.833, B2e=1.0, B1o=1.0, B2o=1.0 / 0.375,
+                E1=2.45, l_e=2, l_o=1, K=4096, X=40.0)
+
+
+def ecd86_jobs(n_energies=256, n_basis=60):
+    """256 energies on [0.1, 5.0] eV x mu in {e, o} from v_i = 0, finals
+    v_f = 0..5; 60 x 60 basis per state (the cross sections change by less
+    than 1e-6 relative from 60 to 100 per mode up to 4 eV)."""
+    eps = np.linspace(0.1, 5.0, n_energies)
+    jobs = [(float(e), (0, 0), mu) for e in eps for mu in range(2)]
+    return dict(params=ecd86_params(), Ng=n_basis, Nu=n_basis, jobs=jobs,
+                finals=[(k, 0) for k in range(6)])
+
 # ---------------------------------------------------------------- CO2-like model
 #
 # Three states (sigma, Pi_x, Pi_y), four modes (symmetric stretch s, bend x and

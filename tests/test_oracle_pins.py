@@ -89,8 +89,9 @@ def _closed_form_delta(eps, A1, B1, A2, B2, l):
     return -A * B ** (l + 0.5) / (2 * math.pi) * _closed_form_I(l, eps / B)
 
 
-@pytest.mark.parametrize("l", [0, 1])
-@pytest.mark.parametrize("pair", [(0.2, 1.0, 0.2, 1.0), (0.186, 1 / 0.375, 0.15, 1 / 0.8)])
+@pytest.mark.parametrize("l", [0, 1, 2])
+@pytest.mark.parametrize("pair", [(0.2, 1.0, 0.2, 1.0), (0.186, 1 / 0.375, 0.15, 1 / 0.8),
+                                  (0.086, 1 / 0.833, 0.086, 1 / 0.833)])
 def test_level_shift_vs_dawson_closed_form(l, pair):
     """The 4096-node transform reproduces the analytic level shift of the
     width a eps^(l+1/2) e^(-b eps) (Sec. II.B) to the grid's accuracy, and

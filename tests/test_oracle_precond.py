@@ -82,3 +82,101 @@ def test_block_preconditioned_gmres_reaches_the_lu_solution():
     assert np.linalg.norm(x - x_lu) <= 1e-8 * np.linalg.norm(x_lu)
     xj, infoj = solvers.gmres(A, b, m=6, tol=1e-11, dinv=1.0 / m2.jacobi_diagonal(A))
     assert info["iters"] <= infoj["iters"]
+
+
+# ------------------------------------------------- the paper's six block choices
+
+def test_paper_blocks_partition_and_sizes():
+    Ng, Nu = 5, 4
+    sizes = {"dg": Nu, "gu": 2, "du": Ng, "d": Ng * Nu, "g": 2 * Nu, "u": 2 * Ng}
+    for fixed, size in sizes.items():
+        blocks = pc.paper_blocks(Ng, Nu, fixed)
+        idx = np.concatenate(blocks)
+        assert np.array_equal(np.sort(idx), np.arange(2 * Ng * Nu))
+        assert all(len(b) == size for b in blocks)
+
+
+def _same(A, f1, f2, Ng, Nu):
+    M1 = pc.block_matrix(A, pc.paper_blocks(Ng, Nu, f1))
+    M2 = pc.block_matrix(A, pc.paper_blocks(Ng, Nu, f2))
+    return abs(M1 - M2).max() == 0.0
+
+
+def test_ecd86_block_choices_that_coincide():
+    """Sec. IV on the ECD86 model: M^{dg} and M^{gu} hold only the diagonal
+    of A, and M^{du}, M^d and M^u hold the same elements (A has no term that
+    the larger blocks would add)."""
+    Ng, Nu = 7, 6
+    mdl, A = _model(inputs.ecd86_params(), Ng, Nu, eps=3.1)
+    D = sp.diags(A.diagonal())
+    for f in ("dg", "gu"):
+        assert abs(pc.block_matrix(A, pc.paper_blocks(Ng, Nu, f)) - D).max() == 0.0
+    assert _same(A, "du", "d", Ng, Nu) and _same(A, "du", "u", Ng, Nu)
+    # the large rows M^g do hold more: the lam q_u couplings
+    assert not _same(A, "g", "dg", Ng, Nu)
+
+
+def test_ecd86_rows_hold_exactly_the_lam_coupling():
+    """Within a row (fixed n_g) the ECD86 matrix couples only through
+    -lam q_u between the two states (Eq. (18)); q_u's matrix elements are
+    sqrt(max(n, n')/2) for |n - n'| = 1."""
+    Ng, Nu = 4, 7
+    p = inputs.ecd86_params()
+    mdl, A = _model(p, Ng, Nu, eps=2.2)
+    A = A.toarray()
+    n = Ng * Nu
+    for g in range(Ng):
+        for d in range(2):
+            for u in range(Nu):
+                for d2 in range(2):
+                    for u2 in range(Nu):
+                        if (d, u) == (d2, u2):
+                            continue
+                        a = A[d * n + g * Nu + u, d2 * n + g * Nu + u2]
+                        want = -p["lam"] * np.sqrt(max(u, u2) / 2.0) if (d != d2 and abs(u - u2) == 1) else 0.0
+                        assert a == pytest.approx(want, abs=1e-15)
+
+
+def test_generalized_model_du_equals_u_and_dg_differs_from_gu():
+    """Sec. IV on the generalized model: M^{du} and M^u coincide (at fixed n_u
+    the two states never meet), while the small blocks M^{dg} and M^{gu} are
+    distinct (its q_u sandwiches put elements inside M^{dg})."""
+    Ng, Nu = 6, 5
+    mdl, A = _model(inputs.draw_params(16), Ng, Nu, eps=2.0)
+    assert _same(A, "du", "u", Ng, Nu)
+    assert not _same(A, "dg", "gu", Ng, Nu)
+
+
+def test_rows_are_exact_without_g_couplings():
+    """With kappa_d = lam_d = 0 nothing in A changes n_g, so M^g = A and
+    preconditioned GMRES finishes in one step at the LU solution."""
+    p = inputs.draw_params(17)
+    p.update(kappa1=0.0, kappa2=0.0, lam1=0.0, lam2=0.0)
+    Ng, Nu = 6, 7
+    mdl, A = _model(p, Ng, Nu, eps=2.3)
+    assert abs(pc.block_matrix(A, pc.paper_blocks(Ng, Nu, "g")) - A).max() == 0.0
+    b = mdl.phi((0, 0), "o")
+    x, info = solvers.gmres(A, b, m=4, tol=1e-12, psolve=pc.BlockInverse(A, pc.paper_blocks(Ng, Nu, "g")))
+    assert info["iters"] == 1
+    np.testing.assert_allclose(x, solvers.lu_solve(A, b), rtol=1e-11)
+
+
+def test_ecd86_rows_cut_the_iterations_where_the_paper_finds():
+    """Sec. IV, ECD86: convergence is fast at low energy and slows above
+    2 eV; M^g is the most effective block choice there, far ahead of the
+    diagonal.  Small basis, GMRES(50) and COCG."""
+    Ng = Nu = 30
+    it = {}
+    for eps in (1.0, 3.0):
+        mdl, A = _model(inputs.ecd86_params(), Ng, Nu, eps=eps)
+        b = mdl.phi((0, 0), "e")
+        dinv = 1.0 / np.asarray(A.diagonal()).ravel()
+        rows = pc.BlockInverse(A, pc.paper_blocks(Ng, Nu, "g"))
+        it[eps] = dict(diag=solvers.gmres(A, b, m=50, dinv=dinv)[1]["iters"],
+                       rows=solvers.gmres(A, b, m=50, psolve=rows)[1]["iters"],
+                       cocg_diag=solvers.cocg(A, b, psolve=lambda v: dinv * v)[1]["iters"],
+                       cocg_rows=solvers.cocg(A, b, psolve=rows)[1]["iters"])
+    assert it[1.0]["diag"] <= 30 and it[1.0]["rows"] <= it[1.0]["diag"]
+    assert it[3.0]["diag"] >= 3 * it[1.0]["diag"]
+    assert 3 * it[3.0]["rows"] <= it[3.0]["diag"]
+    assert 3 * it[3.0]["cocg_rows"] <= it[3.0]["cocg_diag"]
