@@ -92,7 +92,7 @@ def cpu_baseline(cfg, n_sample):
                        f"sparse LU of the assembled {2 * Ng * Nu}-unknown matrix, {dt:.1f} s")
 
 
-PRECONDS = {"jacobi": 1, "block": 2}
+PRECONDS = {"jacobi": 1, "block": 2, "rows": 3}
 PREC_NAMES = {"jacobi": "diagonal preconditioner",
               "block": "column-block preconditioner (n_u columns, 8 rows of n_g, LDL^T)"}
 
@@ -144,12 +144,37 @@ def cocg_batched(model, cfg, precond, mixed=False):
     model as the headline) solved by COCG in FP64 with the given
     preconditioner: solves/s of the whole call (tables included) and the
     solver kernel's algorithmic rate."""
-    import torch
     from paper_2307_13483_amd import vdc
     opts = vdc.Opts(precond=precond, method=vdc.COCG, max_iter=20000)
     if mixed:
         opts = vdc.Opts(precond=precond, method=vdc.COCG, max_iter=20000, precision=vdc.FP32_INNER,
                         inner_restart=100, inner_tol=1e-4)
+    return batched_run(model, cfg, opts)
+
+
+def ecd86_batched():
+    """The ECD86 model (Table I) on 256 energies on [0.1, 5.0] eV x both
+    partial waves from v_i = 0, 60 x 60 basis: the paper's best block choice
+    M^g (whole n_g rows) with COCG in FP64, with FP64 refinement over FP32
+    COCG, and with GMRES(50); the diagonal with COCG for the step counts."""
+    from paper_2307_13483_amd import inputs, vdc
+    cfg = inputs.ecd86_jobs()
+    model = vdc.Model2D(cfg["params"], cfg["Ng"], cfg["Nu"])
+    runs = (("rows_cocg", vdc.Opts(precond=vdc.PREC_ROWS, method=vdc.COCG, max_iter=20000)),
+            ("rows_cocg_fp32_inner", vdc.Opts(precond=vdc.PREC_ROWS, method=vdc.COCG, max_iter=20000,
+                                              precision=vdc.FP32_INNER, inner_restart=400,
+                                              inner_tol=1e-5)),
+            ("rows_gmres50", vdc.Opts(precond=vdc.PREC_ROWS, restart=50, max_iter=20000)),
+            ("jacobi_cocg", vdc.Opts(precond=vdc.PREC_JACOBI, method=vdc.COCG, max_iter=20000)))
+    return {name: batched_run(model, cfg, o) for name, o in runs}
+
+
+def batched_run(model, cfg, opts):
+    """One timed vdc_solve call over the configuration's jobs (after one
+    untimed call): solves/s of the whole call (tables included), step
+    counts and the solver kernel's algorithmic rate."""
+    import torch
+    from paper_2307_13483_amd import vdc
     s = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts)
     s.run()
     torch.cuda.synchronize()
@@ -282,6 +307,7 @@ def extras(args, model, cfg):
     ex["cocg_batched"] = {name: cocg_batched(model, cfg, pc, mx) for name, pc, mx in
                           (("block", _v.PREC_BLOCK, False), ("jacobi", _v.PREC_JACOBI, False),
                            ("block_fp32_inner", _v.PREC_BLOCK, True))}
+    ex["ecd86"] = ecd86_batched()
     ex["adjoint"] = dict(energies=len(aw["eps"]), right_hand_sides=len(ajobs),
                          forward_ms=(t1 - t0) * 1e3, adjoint_ms=(t2 - t1) * 1e3,
                          gradient_evals_per_s=1.0 / (t2 - t0),
@@ -329,7 +355,12 @@ def main():
                     help="only solve the batched workload and form its 2D energy-loss spectra")
     ap.add_argument("--cocg-probe", action="store_true",
                     help="only run the batched workload by COCG (block and diagonal preconditioners)")
+    ap.add_argument("--ecd-probe", action="store_true",
+                    help="only run the ECD86 workload (512 solves, row blocks and the diagonal)")
     args = ap.parse_args()
+    if args.ecd_probe:
+        print(json.dumps({"ecd86": ecd86_batched()}), flush=True)
+        return
     if args.co2_probe:
         from paper_2307_13483_amd import vdc
         print(json.dumps({"co2like": co2like(args), "co2like_cocg": co2like(args, vdc.COCG)}),

@@ -90,9 +90,20 @@ typedef struct {
 
 /* Right preconditioners (Sec. III.B), each a block-diagonal section of A:
  * JACOBI its diagonal; BLOCK the blocks of one n_u column and 8 consecutive
- * n_g (the paper's M^u cut into segments), factored once per job by complex
- * symmetric LDL^T; a block with a vanishing pivot falls back to its diagonal. */
-typedef enum { VDC_PREC_NONE = 0, VDC_PREC_JACOBI = 1, VDC_PREC_BLOCK = 2 } vdc_precond;
+ * n_g (the paper's M^u cut into segments); ROWS one block per n_g holding
+ * its whole n_u row with both states (the paper's M^g, 2 N_u x 2 N_u, of
+ * which each symmetry block holds one half).  Blocks are factored once per
+ * job by complex symmetric LDL^T; a block with a vanishing pivot falls back
+ * to its diagonal.  ROWS factors and applies each row serially (one thread
+ * per row, N_g threads of a job): cheap per step, but its worth is the
+ * iteration count, which it cuts most where lam q_u is the strong coupling.
+ * The CO2-like model takes NONE, JACOBI or BLOCK (its own block choice). */
+typedef enum {
+  VDC_PREC_NONE = 0,
+  VDC_PREC_JACOBI = 1,
+  VDC_PREC_BLOCK = 2,
+  VDC_PREC_ROWS = 3
+} vdc_precond;
 typedef enum {
   VDC_FP64 = 0,              /* restarted GMRES in complex FP64                  */
   VDC_FP32_INNER = 1         /* FGMRES: FP64 outer (true residual, Givens,

@@ -195,6 +195,7 @@ __device__ void sweep_dA(const OpJob<double>& op, const DevJob& jb, const DevMod
   }
 }
 
+template <bool rows>
 __global__ void __launch_bounds__(kBlock)
 adjoint_kernel(SolveArgs a) {
   __shared__ AdjLds L;
@@ -215,7 +216,7 @@ adjoint_kernel(SolveArgs a) {
     const c64* tab = a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc;
     const OpJob<double> op = make_op<double>(md, jb, tab);
     const int Nc = md.Nc, out = jb.out;
-    fp64_prepare(op, L.S.sq, s, a.precond);
+    fp64_prepare<rows>(op, L.S.sq, s, a.precond);
     const c64* psi = a.psi_in + (size_t)out * a.psi_ld;
     for (int i = tid; i < Nc; i += kBlock) {
       const int act = ((i % md.Nu) + jb.parity) & 1;
@@ -244,7 +245,7 @@ adjoint_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    const BlockSolve r = gmres_fp64_block(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT,
+    const BlockSolve r = gmres_fp64_block<rows>(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT,
                                           a.precond);
     __syncthreads();
     // -zeta^T (dA/dp) psi
@@ -272,14 +273,16 @@ adjoint_kernel(SolveArgs a) {
 }
 
 hipError_t launch_adjoint(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  hipLaunchKernelGGL(adjoint_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  if (a.precond == VDC_PREC_ROWS)
+    hipLaunchKernelGGL(adjoint_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else
+    hipLaunchKernelGGL(adjoint_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int adjoint_occupancy(size_t dyn_lds) {
-  int n = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, adjoint_kernel, kBlock, dyn_lds);
-  return (e == hipSuccess && n > 0) ? n : 1;
+  return std::min(occupancy_of(adjoint_kernel<true>, dyn_lds),
+                  occupancy_of(adjoint_kernel<false>, dyn_lds));
 }
 
 }  // namespace vdc

@@ -143,7 +143,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (o->max_iter < 1) return fail(VDC_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (!(o->tol > 0.0)) return fail(VDC_ERR_INVALID_ARG, "tol must be > 0");
   if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI &&
-      o->precond != VDC_PREC_BLOCK)
+      o->precond != VDC_PREC_BLOCK && o->precond != VDC_PREC_ROWS)
     return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
   if (o->precision != VDC_FP64 && o->precision != VDC_FP32_INNER)
     return fail(VDC_ERR_INVALID_ARG, "unknown precision");
@@ -1003,6 +1003,8 @@ vdc_status co2_plan(vdc_co2_t model, const vdc_solve_opts* o, int n_jobs, const 
   if (o->max_iter < 1) return fail(VDC_ERR_INVALID_ARG, "max_iter must be >= 1");
   if (!(o->tol > 0.0)) return fail(VDC_ERR_INVALID_ARG, "tol must be > 0");
   if (o->precision != VDC_FP64) return fail(VDC_ERR_INVALID_ARG, "this model solves in FP64 only");
+  if (o->precond == VDC_PREC_ROWS)
+    return fail(VDC_ERR_UNSUPPORTED, "row blocks are the two-state model's M^g; use VDC_PREC_BLOCK here");
   if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI && o->precond != VDC_PREC_BLOCK)
     return fail(VDC_ERR_INVALID_ARG, "unknown preconditioner");
   if (o->method != VDC_GMRES && o->method != VDC_COCG)

@@ -36,6 +36,7 @@ struct CocgLds {
 // in and z out as well: 10), the next direction (diagonal: r, dinv, p in, p
 // out: 4; block: z, p in, p out: 3); a true-residual check 6 (+ the setup's
 // z, rho and p passes on a restart).
+template <bool rows>
 __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
   __shared__ CocgLds L;
   fill_sq<double>(L.sq);
@@ -58,9 +59,9 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
     const OpJob<double> op = make_op<double>(
         md, jb, a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc);
     const int Nc = md.Nc;
-    const bool blk = a.precond == VDC_PREC_BLOCK;
+    const bool blk = prec_has_factor(a.precond);
     const SegFactor<double> fac{s.l1, s.l2, s.dinv};
-    fp64_prepare(op, L.sq, s, a.precond);
+    fp64_prepare<rows>(op, L.sq, s, a.precond);
     __syncthreads();
     if (tid == 0) {
       PhiEntry e[6];
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
     auto restart_direction = [&]() -> c64 {
       double acc[2] = {0.0, 0.0};
       if (blk) {
-        seg_apply<double>(fac, op.Ng, op.Nu, r, 1.0, p, false);
+        prec_apply<rows, double>(fac, op.Ng, op.Nu, r, 1.0, p, false);
         __syncthreads();
         for (int i = tid; i < Nc; i += kBlock) {
           const c64 t = r[i] * p[i];
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
         // pass (block: by column blocks, z = K^{-1} r stored)
         double acc[3] = {0.0, 0.0, 0.0};
         if (blk) {
-          seg_cocg_step<double>(fac, op.Ng, op.Nu, alpha, p, q, s.x, r, z, acc);
+          prec_cocg_step<rows, double>(fac, op.Ng, op.Nu, alpha, p, q, s.x, r, z, acc);
         } else {
           for (int i = tid; i < Nc; i += kBlock) {
             s.x[i] = s.x[i] + alpha * p[i];
@@ -238,6 +239,7 @@ struct CocgMixedLds {
   int job;
 };
 
+template <bool rows>
 __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
   __shared__ CocgMixedLds L;
   fill_sq<double>(L.sq);
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
   c32* l2 = l1 + ld;
   c32* wA32 = l2 + ld;
   c32* wB32 = wA32 + ld;
-  const bool blk = a.precond == VDC_PREC_BLOCK;
+  const bool blk = prec_has_factor(a.precond);
   const SegFactor<float> fac{l1, l2, dinv};
   for (;;) {
     __syncthreads();
@@ -277,7 +279,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
     const OpJob<double> op = make_op<double>(md, jb, a.tables + toff);
     const OpJob<float> op32 = make_op<float>(md, jb, a.tables32 + toff);
     const int Nc = md.Nc;
-    if (blk) seg_factor<float>(op, L.sq, fac);
+    if (blk) prec_factor<rows, float>(op, L.sq, fac);
     for (int i = tid; i < Nc; i += kBlock) {
       if (!blk) {
         const c64 dd = a.precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i))
@@ -302,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
     // z = K^{-1} src (FP32), then a barrier
     auto kinv = [&](const c32* src, c32* dst) {
       if (blk) {
-        seg_apply<float>(fac, op.Ng, op.Nu, src, 1.0f, dst, false);
+        prec_apply<rows, float>(fac, op.Ng, op.Nu, src, 1.0f, dst, false);
         __syncthreads();
       } else {
         for (int i = tid; i < Nc; i += kBlock) dst[i] = dinv[i] * src[i];
@@ -378,7 +380,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
           // one pass (block: by column blocks, z = K^{-1} r stored)
           float acc[3] = {0.f, 0.f, 0.f};
           if (blk) {
-            seg_cocg_step<float>(fac, op.Ng, op.Nu, alpha, p, q, d, r, z, acc);
+            prec_cocg_step<rows, float>(fac, op.Ng, op.Nu, alpha, p, q, d, r, z, acc);
           } else {
             for (int i = tid; i < Nc; i += kBlock) {
               d[i] = d[i] + alpha * p[i];
@@ -430,25 +432,29 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
 }
 
 hipError_t launch_cocg_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  hipLaunchKernelGGL(cocg_mixed_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  if (a.precond == VDC_PREC_ROWS)
+    hipLaunchKernelGGL(cocg_mixed_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else
+    hipLaunchKernelGGL(cocg_mixed_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int cocg_mixed_occupancy(size_t dyn_lds) {
-  int n = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cocg_mixed_kernel, kBlock, dyn_lds);
-  return (e == hipSuccess && n > 0) ? n : 1;
+  return std::min(occupancy_of(cocg_mixed_kernel<true>, dyn_lds),
+                  occupancy_of(cocg_mixed_kernel<false>, dyn_lds));
 }
 
 hipError_t launch_cocg_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  hipLaunchKernelGGL(cocg_fp64_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  if (a.precond == VDC_PREC_ROWS)
+    hipLaunchKernelGGL(cocg_fp64_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else
+    hipLaunchKernelGGL(cocg_fp64_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int cocg_fp64_occupancy(size_t dyn_lds) {
-  int n = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cocg_fp64_kernel, kBlock, dyn_lds);
-  return (e == hipSuccess && n > 0) ? n : 1;
+  return std::min(occupancy_of(cocg_fp64_kernel<true>, dyn_lds),
+                  occupancy_of(cocg_fp64_kernel<false>, dyn_lds));
 }
 
 }  // namespace vdc

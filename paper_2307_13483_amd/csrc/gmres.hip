@@ -18,6 +18,7 @@
 
 namespace vdc {
 
+template <bool rows>
 __global__ void __launch_bounds__(kBlock)
 gmres_fp64_kernel(SolveArgs a) {
   __shared__ Fp64Lds L;
@@ -35,7 +36,7 @@ gmres_fp64_kernel(SolveArgs a) {
     const DevTable tb = a.tabs[jb.table];
     const OpJob<double> op = make_op<double>(
         md, jb, a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc);
-    fp64_prepare(op, L.sq, s, a.precond);
+    fp64_prepare<rows>(op, L.sq, s, a.precond);
     __syncthreads();
     // right-hand side Phi^{v_i mu_i} in the block (<= 5 nonzeros)
     if (tid == 0) {
@@ -45,7 +46,7 @@ gmres_fp64_kernel(SolveArgs a) {
     }
     __syncthreads();
     const BlockSolve r =
-        gmres_fp64_block(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT, a.precond);
+        gmres_fp64_block<rows>(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT, a.precond);
     __syncthreads();
     finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);
@@ -53,15 +54,16 @@ gmres_fp64_kernel(SolveArgs a) {
 }
 
 hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  hipLaunchKernelGGL(gmres_fp64_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  if (a.precond == VDC_PREC_ROWS)
+    hipLaunchKernelGGL(gmres_fp64_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else
+    hipLaunchKernelGGL(gmres_fp64_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int gmres_fp64_occupancy(size_t dyn_lds) {
-  int n = 0;
-  hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gmres_fp64_kernel, kBlock, dyn_lds);
-  return (e == hipSuccess && n > 0) ? n : 1;
+  return std::min(occupancy_of(gmres_fp64_kernel<true>, dyn_lds),
+                  occupancy_of(gmres_fp64_kernel<false>, dyn_lds));
 }
 
 }  // namespace vdc

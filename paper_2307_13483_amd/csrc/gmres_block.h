@@ -48,11 +48,13 @@ struct BlockSolve {
 
 // The preconditioner (dinv = 1/diag(A) or 1, or the block factors) and
 // x = 0, b = 0 over the block.  No barrier.
+template <bool rows>
 __device__ inline void fp64_prepare(const OpJob<double>& op, const double* sq, const Fp64Slot& s,
                                     int precond) {
-  if (precond == VDC_PREC_BLOCK) seg_factor<double>(op, sq, SegFactor<double>{s.l1, s.l2, s.dinv});
+  const bool blk = prec_has_factor(precond);
+  if (blk) prec_factor<rows, double>(op, sq, SegFactor<double>{s.l1, s.l2, s.dinv});
   for (int i = threadIdx.x; i < op.Nc; i += kBlock) {
-    if (precond != VDC_PREC_BLOCK)
+    if (!blk)
       s.dinv[i] = precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
     s.x[i] = c64{0.0, 0.0};
     s.b[i] = c64{0.0, 0.0};
@@ -73,11 +75,12 @@ extern __shared__ __align__(16) char vdc_tile_lds[];
 // dinv), 4 to the x update (sum written to zt and read back with the factor,
 // x in and out) and 3 to the setup (factor: one more table plane, three
 // planes written instead of one).
+template <bool rows>
 __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& op,
                                               const Fp64Slot& s, size_t ld, int m, double tol,
                                               int max_iter, int T, int precond) {
   const int Nc = op.Nc;
-  const bool blk = precond == VDC_PREC_BLOCK;
+  const bool blk = prec_has_factor(precond);
   const SegFactor<double> fac{s.l1, s.l2, s.dinv};
   c64* lds = reinterpret_cast<c64*>(vdc_tile_lds);
   BlockSolve r{VDC_NOT_CONVERGED, 0, 0, 0.0, 0.0, blk ? 11.0 : 8.0};
@@ -91,7 +94,7 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
   for (int i = threadIdx.x; i < Nc; i += kBlock) s.V[i] = s.b[i];
   auto apply = [&](int j, double sc, c64* out) {
     if (blk) {
-      seg_apply<double>(fac, op.Ng, op.Nu, s.V + (size_t)j * ld, sc, s.zt, false);
+      prec_apply<rows, double>(fac, op.Ng, op.Nu, s.V + (size_t)j * ld, sc, s.zt, false);
       apply_A<double>(op, L.sq, s.zt, 1.0, nullptr, out, lds, T, s.wA, s.wB);
     } else {
       apply_A<double>(op, L.sq, s.V + (size_t)j * ld, sc, s.dinv, out, lds, T, s.wA, s.wB);
@@ -109,7 +112,7 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
     if (blk) {
       // zt = V y (own elements), then x += M^{-1} zt (block ownership)
       update_x<double>(s.V, ld, cr.k, L.K.y, L.K.vs, nullptr, s.zt, Nc, true);
-      seg_apply<double>(fac, op.Ng, op.Nu, s.zt, 1.0, s.x, true);
+      prec_apply<rows, double>(fac, op.Ng, op.Nu, s.zt, 1.0, s.x, true, s.zt);
     } else {
       update_x<double>(s.V, ld, cr.k, L.K.y, L.K.vs, s.dinv, s.x, Nc);
     }

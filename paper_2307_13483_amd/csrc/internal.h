@@ -29,6 +29,15 @@ constexpr int kClus = 64;
 constexpr int kClusP = 30;
 constexpr int kClusStride = 2 + 2 * kNumF * (kClusP + 1);
 
+// Resident workgroups of kBlock threads per CU for a solver kernel with
+// dyn_lds bytes of dynamic LDS (1 when the runtime cannot tell).
+template <typename Kernel>
+inline int occupancy_of(Kernel k, size_t dyn_lds) {
+  int n = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kBlock, dyn_lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
 // Level-shift function index: mu-major, pairs (11, 12, 22).
 //   0: F[f1e f1e]  1: F[f1e f2e]  2: F[f2e f2e]
 //   3: F[f1o f1o]  4: F[f1o f2o]  5: F[f2o f2o]

@@ -28,6 +28,7 @@ struct MixedLds {
   int job;
 };
 
+template <bool rows>
 __global__ void __launch_bounds__(kBlock)
 fgmres_mixed_kernel(SolveArgs a) {
   __shared__ MixedLds L;
@@ -60,7 +61,7 @@ fgmres_mixed_kernel(SolveArgs a) {
   c32* zt = l2 + ld;                             // M^{-1} of the inner vector in work
   (void)w;
   (void)w32;
-  const bool blk = a.precond == VDC_PREC_BLOCK;
+  const bool blk = prec_has_factor(a.precond);
   const SegFactor<float> fac{l1, l2, dinv};
 
   for (;;) {
@@ -77,7 +78,7 @@ fgmres_mixed_kernel(SolveArgs a) {
     const OpJob<float> op32 = make_op<float>(md, jb, a.tables32 + toff);
     const int Nc = md.Nc;
 
-    if (blk) seg_factor<float>(op, L.sq, fac);
+    if (blk) prec_factor<rows, float>(op, L.sq, fac);
     for (int i = tid; i < Nc; i += kBlock) {
       if (!blk) {
         const c64 d = a.precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i))
@@ -121,7 +122,7 @@ fgmres_mixed_kernel(SolveArgs a) {
       // inner FP32 operator: A (s dinv v)
       auto apply_in = [&](int j, float sc, c32* out) {
         if (blk) {
-          seg_apply<float>(fac, md.Ng, md.Nu, Vi + (size_t)j * ld, sc, zt, false);
+          prec_apply<rows, float>(fac, md.Ng, md.Nu, Vi + (size_t)j * ld, sc, zt, false);
           apply_A<float>(op32, L.sqf, zt, 1.0f, nullptr, out, lds32, a.tileT32, wA32, wB32);
         } else {
           apply_A<float>(op32, L.sqf, Vi + (size_t)j * ld, sc, dinv, out, lds32, a.tileT32, wA32,
@@ -177,7 +178,7 @@ fgmres_mixed_kernel(SolveArgs a) {
             }
           }
           if (blk) {
-            seg_apply<float>(fac, md.Ng, md.Nu, zt, 1.0f, zt, false);
+            prec_apply<rows, float>(fac, md.Ng, md.Nu, zt, 1.0f, zt, false);
             __syncthreads();
             for (int i = tid; i < Nc; i += kBlock) z[i] = c64{(double)zt[i].x, (double)zt[i].y};
           }
@@ -230,15 +231,16 @@ fgmres_mixed_kernel(SolveArgs a) {
 }
 
 hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  hipLaunchKernelGGL(fgmres_mixed_kernel, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  if (a.precond == VDC_PREC_ROWS)
+    hipLaunchKernelGGL(fgmres_mixed_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else
+    hipLaunchKernelGGL(fgmres_mixed_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int fgmres_mixed_occupancy(size_t dyn_lds) {
-  int n = 0;
-  hipError_t e =
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fgmres_mixed_kernel, kBlock, dyn_lds);
-  return (e == hipSuccess && n > 0) ? n : 1;
+  return std::min(occupancy_of(fgmres_mixed_kernel<true>, dyn_lds),
+                  occupancy_of(fgmres_mixed_kernel<false>, dyn_lds));
 }
 
 }  // namespace vdc

@@ -47,20 +47,26 @@ __global__ void __launch_bounds__(kPT) p_init(PlainArgs a) {
   const int i = blockIdx.x * kPT + threadIdx.x;
   if (i >= a.md.Nc) return;
   const OpJob<double> op = plain_op(a);
-  if (a.precond != VDC_PREC_BLOCK)
+  if (!prec_has_factor(a.precond))
     a.dinv[i] = a.precond == VDC_PREC_JACOBI ? cinv<double>(op_diag<double>(op, i)) : c64{1.0, 0.0};
   a.x[i] = c64{0.0, 0.0};
   a.b[i] = c64{0.0, 0.0};
 }
 
-// block preconditioner factors (segprec.h), one thread per block
+// block preconditioner factors (segprec.h), one thread per column block or
+// per row
 __global__ void __launch_bounds__(kPT) p_factor(PlainArgs a) {
   __shared__ double sq[kSqMax + 1];
   fill_sq<double>(sq);
   __syncthreads();
   const int c = blockIdx.x * kPT + threadIdx.x;
+  const SegFactor<double> f{a.l1, a.l2, a.dinv};
+  if (a.precond == VDC_PREC_ROWS) {
+    if (c < a.md.Ng) row_factor_row<double>(plain_op(a), sq, f, c);
+    return;
+  }
   if (c >= seg_blocks(a.md.Ng, a.md.Nu)) return;
-  seg_factor_block<double>(plain_op(a), sq, SegFactor<double>{a.l1, a.l2, a.dinv}, c);
+  seg_factor_block<double>(plain_op(a), sq, f, c);
 }
 
 // z = M^{-1} v, or z += M^{-1} v with accumulate, one thread per block; the
@@ -70,9 +76,14 @@ __global__ void __launch_bounds__(kPT) p_papply(PlainArgs a, const c64* v, c64* 
                                                 int end_of_cycle) {
   if (end_of_cycle ? a.st->done : a.st->stop_cycle) return;
   const int c = blockIdx.x * kPT + threadIdx.x;
+  const SegFactor<double> f{a.l1, a.l2, a.dinv};
+  if (a.precond == VDC_PREC_ROWS) {
+    // accumulating calls pass v = zt, which parks the forward sweep
+    if (c < a.md.Ng) row_apply_row<double>(f, a.md.Nu, v, 1.0, z, accumulate != 0, a.zt, c);
+    return;
+  }
   if (c >= seg_blocks(a.md.Ng, a.md.Nu)) return;
-  seg_apply_block<double>(SegFactor<double>{a.l1, a.l2, a.dinv}, a.md.Ng, a.md.Nu, v, 1.0, z,
-                          accumulate != 0, c);
+  seg_apply_block<double>(f, a.md.Ng, a.md.Nu, v, 1.0, z, accumulate != 0, c);
 }
 
 __global__ void p_rhs(PlainArgs a) {
@@ -87,7 +98,7 @@ __global__ void p_rhs(PlainArgs a) {
   s.cycles = 0;
   s.breakdown = 0;
   s.stop_cycle = 0;
-  s.passes = a.precond == VDC_PREC_BLOCK ? 10.0 : 7.0;
+  s.passes = prec_has_factor(a.precond) ? 10.0 : 7.0;
 }
 
 // per-block partial sums of |v|^2 (the v is w or b)
@@ -279,7 +290,7 @@ __global__ void __launch_bounds__(kPT) p_update(PlainArgs a) {
   if (i >= a.md.Nc) return;
   c64 t = c64{0.0, 0.0};
   for (int l = 0; l < a.st->k; ++l) t = t + a.V[(size_t)l * a.ld + i] * a.st->y[l];
-  if (a.precond == VDC_PREC_BLOCK)
+  if (prec_has_factor(a.precond))
     a.zt[i] = t;
   else
     a.x[i] = a.x[i] + a.dinv[i] * t;
@@ -299,7 +310,7 @@ __global__ void p_status(PlainArgs a) {
   if (s.done) return;
   s.cycles += 1;
   s.passes += 7.0 * s.k + 2.0 * s.k * (s.k + 1.0) + s.k + 10.0 +
-              (a.precond == VDC_PREC_BLOCK ? 4.0 * s.k + 4.0 : 0.0);
+              (prec_has_factor(a.precond) ? 4.0 * s.k + 4.0 : 0.0);
   const double beta = s.beta;
   if (!isfinite(beta)) {
     s.status = VDC_NONFINITE;
@@ -379,8 +390,9 @@ vdc_status solve_plain_impl(const SolveArgs& sa, const std::vector<DevJob>& jobs
     a.tab = sa.tables + htabs[jb.table].offset + (size_t)(jb.parity * sa.planes) * a.md.Nc;
     a.nblk = (a.md.Nc + kPT - 1) / kPT;
     const dim3 g1(a.nblk), b1(kPT);
-    const bool blk = a.precond == VDC_PREC_BLOCK;
-    const dim3 gs((seg_blocks(a.md.Ng, a.md.Nu) + kPT - 1) / kPT);
+    const bool blk = prec_has_factor(a.precond);
+    const int n_fac = a.precond == VDC_PREC_ROWS ? a.md.Ng : seg_blocks(a.md.Ng, a.md.Nu);
+    const dim3 gs((n_fac + kPT - 1) / kPT);
     hipLaunchKernelGGL(p_init, g1, b1, 0, st, a);
     if (blk) hipLaunchKernelGGL(p_factor, gs, b1, 0, st, a);
     hipLaunchKernelGGL(p_rhs, dim3(1), dim3(1), 0, st, a);

@@ -204,4 +204,235 @@ __device__ inline void seg_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Row blocks: the paper's M^g (Sec. III.B), one block per n_g holding its
+// whole n_u row (both states; in the symmetry block one point per n_u).
+// Inside a row the state alternates with n_u; the couplings that stay in the
+// row are the direct -lam q_u, the q_u parts of the sandwiches next to their
+// (1 + lam_d q_g) partners (F_AB at either end of the step) and the
+// returning q_u F_BB q_u, which reaches n_u +- 2:
+//   A(u, u + 1) = -q(u+1) (lam + F_AB(u) + F_AB(u+1)),
+//   A(u, u + 2) = -q(u+1) q(u+2) F_BB(u+1),
+// with each point's F_AB, F_BB those of its own active state (op2d.h).  The
+// rows are factored whole (L D L^T, no pivoting, the same diagonal fallback
+// as the column blocks), one thread per row, and stored in the SegFactor
+// planes at the points' own positions: l1 = L(u+1, u), l2 = L(u+2, u).
+// A row is a serial recurrence of length N_u, so only N_g threads work; the
+// paper finds these blocks the most effective for models whose strongest
+// coupling runs along q_u (lam of Eq. (18)).
+
+__device__ inline c64 row_off1(const OpJob<double>& op, const double* sq, int i, int u) {
+  const double q = sq[u + 1];
+  const c64 f = op.AB[i] + op.AB[i + 1];
+  return c64{-q * (op.lam + f.x), -q * f.y};
+}
+
+__device__ inline c64 row_off2(const OpJob<double>& op, const double* sq, int i, int u) {
+  return (-sq[u + 1] * sq[u + 2]) * op.BB[i + 1];
+}
+
+// Factor row g (FP64 arithmetic, stored in precision R), one thread.
+template <typename R>
+__device__ inline void row_factor_row(const OpJob<double>& op, const double* sq,
+                                      const SegFactor<R>& f, int g) {
+  const int Nu = op.Nu, base = g * Nu;
+  c64 Dm1{0.0, 0.0}, Dm2{0.0, 0.0}, l1m1{0.0, 0.0}, l2m1{0.0, 0.0}, l2m2{0.0, 0.0};
+  bool ok = true;
+  for (int u = 0; u < Nu; ++u) {
+    const int i = base + u;
+    const c64 akk = op_diag<double>(op, i);
+    const c64 d = akk - (l1m1 * l1m1) * Dm1 - (l2m2 * l2m2) * Dm2;
+    const double nd = sqrt(norm2(d));
+    ok = ok && isfinite(nd) && nd > 1e-12 * sqrt(norm2(akk));
+    const c64 di = cinv<double>(d);
+    c64 l1{0.0, 0.0}, l2{0.0, 0.0};
+    if (u + 1 < Nu) l1 = (row_off1(op, sq, i, u) - (l2m1 * l1m1) * Dm1) * di;
+    if (u + 2 < Nu) l2 = row_off2(op, sq, i, u) * di;
+    f.l1[i] = narrow<R>(l1);
+    f.l2[i] = narrow<R>(l2);
+    f.dinv[i] = narrow<R>(di);
+    Dm2 = Dm1;
+    Dm1 = d;
+    l2m2 = l2m1;
+    l2m1 = l2;
+    l1m1 = l1;
+  }
+  if (!ok) {
+    for (int u = 0; u < Nu; ++u) {
+      const int i = base + u;
+      f.l1[i] = cz<R>();
+      f.l2[i] = cz<R>();
+      f.dinv[i] = narrow<R>(cinv<double>(op_diag<double>(op, i)));
+    }
+  }
+}
+
+// Factor every row, spread over the workgroup's threads.  No barrier.
+template <typename R>
+__device__ inline void row_factor(const OpJob<double>& op, const double* sq,
+                                  const SegFactor<R>& f) {
+  for (int g = threadIdx.x; g < op.Ng; g += blockDim.x) row_factor_row<R>(op, sq, f, g);
+}
+
+// Row g of z = M^{-1} (vscale v), or z += M^{-1} (vscale v) with accumulate,
+// one thread.  The forward sweep's L^{-1} values y are parked in z, or in the
+// vector park when accumulating (park may be v, which is then overwritten);
+// the backward sweep keeps its last two results in registers.  z may be v.
+// With dot, acc[0] + i acc[1] += sum_u y_u^2 / D_u = v^T M^{-1} v (vscale
+// 1), formed in the backward sweep from the values it loads anyway.
+// Every row has the same length, so the loops run in step across a
+// wavefront; the loads of kRowChunk points are issued together, so a sweep
+// waits for memory once per chunk rather than once per point.
+template <typename R>
+struct RowChunk { static constexpr int K = 4; };
+template <>
+struct RowChunk<float> { static constexpr int K = 8; };
+
+template <typename R, bool dot>
+__device__ inline void row_sweep(const SegFactor<R>& f, int Nu, const typename CT<R>::C* v,
+                                 R vscale, typename CT<R>::C* z, bool accumulate,
+                                 typename CT<R>::C* park, int g, R* acc) {
+  using C = typename CT<R>::C;
+  constexpr int K = RowChunk<R>::K;
+  if (!accumulate) park = z;
+  const int base = g * Nu, last = base + Nu - 1;
+  C y1 = cz<R>(), y2 = cz<R>();
+  for (int u0 = 0; u0 < Nu; u0 += K) {
+    C vv[K], a1[K], a2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = min(base + u0 + k, last);
+      vv[k] = v[i];
+      a1[k] = f.l1[max(i - 1, base)];
+      a2[k] = f.l2[max(i - 2, base)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int u = u0 + k;
+      if (u < Nu) {
+        C t = vscale * vv[k];
+        if (u >= 1) t = t - a1[k] * y1;
+        if (u >= 2) t = t - a2[k] * y2;
+        park[base + u] = t;
+        y2 = y1;
+        y1 = t;
+      }
+    }
+  }
+  C z1 = cz<R>(), z2 = cz<R>();
+  for (int u0 = Nu - 1; u0 >= 0; u0 -= K) {
+    C yy[K], dd[K], a1[K], a2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = max(base + u0 - k, base);
+      yy[k] = park[i];
+      dd[k] = f.dinv[i];
+      a1[k] = f.l1[i];
+      a2[k] = f.l2[i];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int u = u0 - k;
+      if (u >= 0) {
+        const C w = dd[k] * yy[k];
+        if (dot) {
+          const C yw = yy[k] * w;
+          acc[0] += yw.x;
+          acc[1] += yw.y;
+        }
+        C t = w;
+        if (u + 1 < Nu) t = t - a1[k] * z1;
+        if (u + 2 < Nu) t = t - a2[k] * z2;
+        const int i = base + u;
+        z[i] = accumulate ? z[i] + t : t;
+        z2 = z1;
+        z1 = t;
+      }
+    }
+  }
+}
+
+template <typename R>
+__device__ inline void row_apply_row(const SegFactor<R>& f, int Nu, const typename CT<R>::C* v,
+                                     R vscale, typename CT<R>::C* z, bool accumulate,
+                                     typename CT<R>::C* park, int g) {
+  row_sweep<R, false>(f, Nu, v, vscale, z, accumulate, park, g, nullptr);
+}
+
+// The whole vector, rows spread over the workgroup's threads.  Begins with a
+// barrier, ends without.
+template <typename R>
+__device__ inline void row_apply(const SegFactor<R>& f, int Ng, int Nu,
+                                 const typename CT<R>::C* v, R vscale, typename CT<R>::C* z,
+                                 bool accumulate, typename CT<R>::C* park) {
+  __syncthreads();
+  for (int g = threadIdx.x; g < Ng; g += blockDim.x)
+    row_apply_row<R>(f, Nu, v, vscale, z, accumulate, park, g);
+}
+
+// seg_cocg_step with rows: x += alpha p, r -= alpha q and acc[0] += ||r||^2
+// element by element over all threads, a barrier, then z = M^{-1} r row by
+// row with acc[1] + i acc[2] += <r|z>_S = r^T (L D L^T)^{-1} r, summed as
+// y^T D^{-1} y with y = L^{-1} r.  Begins with a barrier; x and r are read
+// once more by the rows than in the fused column version.
+template <typename R>
+__device__ inline void row_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
+                                     typename CT<R>::C alpha,
+                                     const typename CT<R>::C* __restrict__ p,
+                                     const typename CT<R>::C* __restrict__ q,
+                                     typename CT<R>::C* __restrict__ x,
+                                     typename CT<R>::C* __restrict__ r,
+                                     typename CT<R>::C* __restrict__ z, R* acc) {
+  using C = typename CT<R>::C;
+  __syncthreads();
+  const int Nc = Ng * Nu;
+  for (int i = threadIdx.x; i < Nc; i += blockDim.x) {
+    x[i] = x[i] + alpha * p[i];
+    const C ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc[0] += norm2(ri);
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < Ng; g += blockDim.x)
+    row_sweep<R, true>(f, Nu, r, R(1), z, false, nullptr, g, acc + 1);
+}
+
+// Dispatch on the preconditioner: VDC_PREC_BLOCK (column segments) or
+// VDC_PREC_ROWS (whole rows) share the factor planes.  The solver kernels are
+// instantiated per choice (rows true or false), so neither pays registers for
+// the other's code.
+__host__ __device__ inline bool prec_has_factor(int precond) {
+  return precond == VDC_PREC_BLOCK || precond == VDC_PREC_ROWS;
+}
+
+template <bool rows, typename R>
+__device__ inline void prec_factor(const OpJob<double>& op, const double* sq,
+                                   const SegFactor<R>& f) {
+  if constexpr (rows) row_factor<R>(op, sq, f);
+  else seg_factor<R>(op, sq, f);
+}
+
+// park: scratch for the row variant's forward sweep when accumulating (may
+// be v); unused otherwise.
+template <bool rows, typename R>
+__device__ inline void prec_apply(const SegFactor<R>& f, int Ng, int Nu,
+                                  const typename CT<R>::C* v, R vscale, typename CT<R>::C* z,
+                                  bool accumulate, typename CT<R>::C* park = nullptr) {
+  if constexpr (rows) row_apply<R>(f, Ng, Nu, v, vscale, z, accumulate, park);
+  else seg_apply<R>(f, Ng, Nu, v, vscale, z, accumulate);
+}
+
+template <bool rows, typename R>
+__device__ inline void prec_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
+                                      typename CT<R>::C alpha,
+                                      const typename CT<R>::C* __restrict__ p,
+                                      const typename CT<R>::C* __restrict__ q,
+                                      typename CT<R>::C* __restrict__ x,
+                                      typename CT<R>::C* __restrict__ r,
+                                      typename CT<R>::C* __restrict__ z, R* acc) {
+  if constexpr (rows) row_cocg_step<R>(f, Ng, Nu, alpha, p, q, x, r, z, acc);
+  else seg_cocg_step<R>(f, Ng, Nu, alpha, p, q, x, r, z, acc);
+}
+
 }  // namespace vdc

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvdc.so")
 
 VDC_OK, VDC_ERR_INVALID_ARG, VDC_ERR_WORKSPACE, VDC_ERR_HIP, VDC_ERR_UNSUPPORTED = range(5)
 CONVERGED, NOT_CONVERGED, BREAKDOWN, NONFINITE = range(4)
-PREC_NONE, PREC_JACOBI, PREC_BLOCK = 0, 1, 2
+PREC_NONE, PREC_JACOBI, PREC_BLOCK, PREC_ROWS = 0, 1, 2, 3
 FP64, FP32_INNER = 0, 1
 GMRES, COCG = 0, 1
 STATUS_NAMES = {CONVERGED: "converged", NOT_CONVERGED: "not_converged",

@@ -315,7 +315,8 @@ def _grad_case(Ng, Nu, eps, n_final=4):
 
 @pytest.mark.parametrize("Ng,Nu,eps,precond", [(9, 7, [0.57, 1.73, 2.61], 1),
                                                (20, 16, [0.83, 2.28], 1),
-                                               (20, 16, [0.83, 2.28], 2)])
+                                               (20, 16, [0.83, 2.28], 2),
+                                               (20, 16, [0.83, 2.28], 3)])
 def test_adjoint_gradient_matches_oracle(vdc, Ng, Nu, eps, precond):
     """GPU adjoint (one transposed solve per right-hand side + parameter
     sweep) against the oracle's explicit-derivative gradient; diagonal and
@@ -530,3 +531,96 @@ def test_cocg_mixed_precision_solves(vdc, Ng, Nu, precond):
     T, sigma, psi, infos = vdc.solve(model, jobs, finals, opts, want_psi=True)
     _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
                  psi.cpu().numpy(), infos)
+
+
+# ------------------------------------------------------------ row blocks (M^g), ECD86
+
+def _rows_params(which):
+    return inputs.ecd86_params() if which == "ecd86" else inputs.draw_params(21)
+
+
+@pytest.mark.parametrize("which", ["ecd86", "generalized"])
+def test_rows_iterations_track_textbook(vdc, which):
+    """GMRES right-preconditioned by whole n_g rows (the paper's M^g) against
+    the oracle's textbook GMRES with the blocks of fixed n_g taken as slices
+    of its assembled A and solved by LU."""
+    from oracle import precond as pc
+    p = _rows_params(which)
+    Ng, Nu = 30, 26
+    jobs = [(0.5, (0, 0), 0), (2.6, (1, 0), 1), (3.4, (0, 1), 0)]
+    model = vdc.Model2D(p, Ng, Nu)
+    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)], vdc.Opts(restart=15, precond=vdc.PREC_ROWS))
+    for k, (e, vi, mu) in enumerate(jobs):
+        mdl, A, b, _, _ = _oracle_job(p, Ng, Nu, e, vi, mu, [(0, 0)])
+        Minv = pc.BlockInverse(A, pc.paper_blocks(Ng, Nu, "g"))
+        _, info = solvers.gmres(A, b, m=15, tol=1e-10, psolve=Minv)
+        assert info["converged"]
+        assert abs(infos[k]["iters"] - info["iters"]) <= 2, (infos[k], info)
+
+
+@pytest.mark.parametrize("which", ["ecd86", "generalized"])
+def test_rows_cocg_iterations_track_oracle(vdc, which):
+    from oracle import precond as pc
+    p = _rows_params(which)
+    Ng, Nu = 30, 26
+    jobs = [(0.5, (0, 0), 0), (2.6, (1, 0), 1), (3.4, (0, 1), 0)]
+    model = vdc.Model2D(p, Ng, Nu)
+    _, _, _, infos = vdc.solve(model, jobs, [(0, 0)],
+                               vdc.Opts(precond=vdc.PREC_ROWS, method=vdc.COCG, max_iter=5000))
+    for k, (e, vi, mu) in enumerate(jobs):
+        mdl, A, b, _, _ = _oracle_job(p, Ng, Nu, e, vi, mu, [(0, 0)])
+        _, info = solvers.cocg(A, b, tol=1e-10, psolve=pc.BlockInverse(A, pc.paper_blocks(Ng, Nu, "g")))
+        assert info["converged"]
+        assert abs(infos[k]["iters"] - info["iters"]) <= max(3, 0.03 * info["iters"]), (infos[k], info)
+
+
+@pytest.mark.parametrize("Ng,Nu", [(1, 1), (2, 3), (13, 29), (30, 26)])
+@pytest.mark.parametrize("path", ["fp64", "fp32", "plain", "cocg", "cocg_fp32"])
+@pytest.mark.parametrize("which", ["ecd86", "generalized"])
+def test_rows_solves(vdc, Ng, Nu, path, which):
+    """Tiny, ragged and wide rows through every solver path with the row
+    preconditioner; every solve checked against the oracle."""
+    p = _rows_params(which)
+    jobs = [(0.8, (0, 0), 0), (2.1, (min(1, Ng - 1), 0), 1), (3.3, (0, min(1, Nu - 1)), 0)]
+    finals = [(0, 0), (min(2, Ng - 1), 0), (0, min(1, Nu - 1))]
+    model = vdc.Model2D(p, Ng, Nu)
+    prec = vdc.FP32_INNER if path in ("fp32", "cocg_fp32") else vdc.FP64
+    method = vdc.COCG if path.startswith("cocg") else vdc.GMRES
+    opts = vdc.Opts(restart=12, precond=vdc.PREC_ROWS, precision=prec, method=method,
+                    inner_restart=100 if method == vdc.COCG else 12, inner_tol=1e-4,
+                    outer_restart=8, max_iter=20000)
+    T, sigma, psi, infos = vdc.solve(model, jobs, finals, opts, plain=(path == "plain"),
+                                     want_psi=True)
+    _check_solve(p, Ng, Nu, jobs, finals, T.cpu().numpy(), sigma.cpu().numpy(),
+                 psi.cpu().numpy(), infos)
+
+
+def test_ecd86_workload_sampled(vdc):
+    """The ECD86 workload's model (Table I, 60 x 60) on a sample of its jobs
+    across the energy range, COCG with row blocks in FP64 and FP64 refinement
+    over FP32 COCG, both to 1e-12 (cond(A) reaches ~1e3 here, so the
+    amplitudes' 1e-8 bound needs the tighter residual); the rows need far
+    fewer steps than the diagonal."""
+    cfg = inputs.ecd86_jobs()
+    p = cfg["params"]
+    sample = [cfg["jobs"][k] for k in (0, 1, 101, 208, 330, 511)]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    for prec in (vdc.FP64, vdc.FP32_INNER):
+        opts = vdc.Opts(precond=vdc.PREC_ROWS, method=vdc.COCG, precision=prec, tol=1e-12,
+                        inner_restart=400, inner_tol=1e-5, max_iter=20000)
+        T, sigma, psi, infos = vdc.solve(model, sample, cfg["finals"], opts, want_psi=True)
+        _check_solve(p, cfg["Ng"], cfg["Nu"], sample, cfg["finals"], T.cpu().numpy(),
+                     sigma.cpu().numpy(), psi.cpu().numpy(), infos, tol=1e-12)
+    hi = [j for j in sample if j[0] > 3.0]
+    _, _, _, rinfos = vdc.solve(model, hi, cfg["finals"],
+                                vdc.Opts(precond=vdc.PREC_ROWS, method=vdc.COCG, max_iter=20000))
+    _, _, _, jinfos = vdc.solve(model, hi, cfg["finals"],
+                                vdc.Opts(precond=vdc.PREC_JACOBI, method=vdc.COCG, max_iter=20000))
+    assert 3 * sum(i["iters"] for i in rinfos) <= sum(i["iters"] for i in jinfos)
+
+
+def test_rows_rejected_for_the_co2_like_model(vdc):
+    model = vdc.Co2Model(inputs.co2like_params(), dict(s=2, x=3, y=3, a=2))
+    with pytest.raises(vdc.VdcError):
+        vdc.co2_solve(model, [(1.0, (0, 0, 0, 0), 0)], [(0, 0, 0, 0)],
+                      vdc.Opts(precond=vdc.PREC_ROWS))
