@@ -551,31 +551,39 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
       dm.glastx[f] = x[K - 1] * g[K - 1];
     }
   }
-  // far-field moments per cluster of nodes (see levelshift.hip)
+  // far-field moments per cluster of nodes and per super-cluster of kSup
+  // clusters (see levelshift.hip), summed in extended precision and rounded
+  // once: the super-clusters' sums run over 512 nodes
   const int nclust = (K + kClus - 1) / kClus;
-  std::vector<double> clus((size_t)nclust * kClusStride, 0.0);
-  for (int c = 0; c < nclust; ++c) {
-    const int k0 = c * kClus, k1 = std::min(K, k0 + kClus);
-    double* C = clus.data() + (size_t)c * kClusStride;
+  const int nsup = (nclust + kSup - 1) / kSup;
+  std::vector<double> clus((size_t)(nclust + nsup) * kClusStride, 0.0);
+  auto moments = [&](int k0, int k1, double* C) {
     const double xc = 0.5 * (x[k0] + x[k1 - 1]);
     C[0] = xc;
     C[1] = 0.5 * (x[k1 - 1] - x[k0]);
     for (int kind = 0; kind < 2; ++kind) {
       const std::vector<double>& cf = kind == 0 ? coef : coefx;
       for (int f = 0; f < kNumF; ++f) {
-        double* M = C + 2 + (kind * kNumF + f) * (kClusP + 1);
+        long double M[kClusP + 1] = {};
         for (int k = k0; k < k1; ++k) {
-          const double ck = cf[(size_t)k * kNumF + f], d = x[k] - xc;
-          double dn = 1.0;
+          const long double ck = cf[(size_t)k * kNumF + f], d = (long double)x[k] - xc;
+          long double dn = 1.0L;
           for (int n = 0; n <= kClusP; ++n) {
             M[n] += ck * dn;
             dn *= d;
           }
         }
-        for (int n = 2; n <= kClusP; ++n) M[n] /= (double)n * (n - 1);
+        double* out = C + 2 + (kind * kNumF + f) * (kClusP + 1);
+        for (int n = 0; n <= kClusP; ++n)
+          out[n] = (double)(n >= 2 ? M[n] / ((long double)n * (n - 1)) : M[n]);
       }
     }
-  }
+  };
+  for (int c = 0; c < nclust; ++c)
+    moments(c * kClus, std::min(K, (c + 1) * kClus), clus.data() + (size_t)c * kClusStride);
+  for (int sc = 0; sc < nsup; ++sc)
+    moments(sc * kSup * kClus, std::min(K, (sc + 1) * kSup * kClus),
+            clus.data() + (size_t)(nclust + sc) * kClusStride);
   hipError_t e = hipMalloc(&m->d_nodes, sizeof(double) * K);
   if (e == hipSuccess) e = hipMalloc(&m->d_coef, sizeof(double) * K * kNumF);
   if (e == hipSuccess) e = hipMalloc(&m->d_coefx, sizeof(double) * K * kNumF);
@@ -600,6 +608,8 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
   dm.coefx = m->d_coefx;
   dm.nclust = nclust;
   dm.clus = m->d_clus;
+  dm.nsup = nsup;
+  dm.sup = m->d_clus + (size_t)nclust * kClusStride;
   *out = m;
   return VDC_OK;
 }

@@ -25,7 +25,10 @@ constexpr int kNumF = 6;          // level-shift functions per energy
 // consecutive nodes, moments up to kClusP; per cluster: centre, half-width,
 // then for the 6 functions g and the 6 functions x g: M_0, M_1 and
 // mu_n = M_n / (n (n-1)), n = 2..kClusP.
+// kSup consecutive clusters form a super-cluster with moments of its own,
+// used where a whole wave's points are far from it.
 constexpr int kClus = 64;
+constexpr int kSup = 8;
 constexpr int kClusP = 30;
 constexpr int kClusStride = 2 + 2 * kNumF * (kClusP + 1);
 
@@ -62,6 +65,8 @@ struct DevModel {
   const double* coefx;   // [K][kNumF]     device: slope jumps of x g(x)
   int nclust;            // ceil(K / kClus)
   const double* clus;    // [nclust][kClusStride] device: far-field moments
+  int nsup;              // ceil(nclust / kSup)
+  const double* sup;     // [nsup][kClusStride] device: super-cluster moments
 };
 
 // One job as the kernels see it (host-filled, device-resident array).

@@ -19,10 +19,11 @@
 //                              + sum_{n>=2} M_n / (n (n-1)) t^-(n-1),
 // M_n = sum_k c_k d_k^n, d_k = x_k - x_c, truncated at n = 30 (remainder
 // below 3^-31 / 900 of the cluster's magnitude); its eps derivative follows
-// term by term.  Near clusters are summed node by node.  Points are processed
-// in order of eps (a permutation per offset rectangle), so the lanes of a wave
-// agree on which clusters are far; a cluster is expanded only if it is far
-// for every lane of the wave.
+// term by term.  Near clusters are summed node by node; groups of kSup
+// clusters have moments of their own for points far from the whole group.
+// Points are processed in order of eps (a permutation per offset
+// rectangle), so the lanes of a wave agree on which clusters are far; a
+// cluster is expanded only if it is far for every lane of the wave.
 //
 // Sharing across initial states: eps_nu = eps_i + w_g (v_g - n_g) + w_u (v_u - n_u)
 // depends on (n_g, n_u) only through the offsets (v_g - n_g, v_u - n_u), so
@@ -90,62 +91,81 @@ __device__ inline uniform_dptr uniform_ptr(const double* p) {
   return (uniform_dptr)(((uint64_t)hi << 32) | lo);
 }
 
+// Far-field terms of one cluster (or super-cluster) C at t = eps - x_c,
+// added to the sums (see the series above).
+template <bool DERIV>
+__device__ inline void far_terms(uniform_dptr C, double t, double* aF, double* aD, double* aX) {
+  const double L = ln_abs(t);
+  double u = __builtin_amdgcn_rcp(t);
+  u = fma(u, fma(-t, u, 1.0), u);
+  u = fma(u, fma(-t, u, 1.0), u);
+  const double tl = t * L, l1 = L + 1.0;
+#pragma unroll
+  for (int f = 0; f < kNumF; ++f) {
+    const uniform_dptr M = C + 2 + f * (kClusP + 1);
+    double ser = M[kClusP];
+    for (int n = kClusP - 1; n >= 2; --n) ser = fma(ser, u, M[n]);
+    aF[f] += fma(tl, M[0], fma(-l1, M[1], u * ser));
+    if (DERIV) {
+      double sd = (kClusP - 1) * M[kClusP];
+      for (int n = kClusP - 1; n >= 2; --n) sd = fma(sd, u, (n - 1) * M[n]);
+      aD[f] += fma(L, M[0], -u * fma(u, sd, M[1]));
+      const uniform_dptr MX = C + 2 + (kNumF + f) * (kClusP + 1);
+      double sx = MX[kClusP];
+      for (int n = kClusP - 1; n >= 2; --n) sx = fma(sx, u, MX[n]);
+      aX[f] += fma(tl, MX[0], fma(-l1, MX[1], u * sx));
+    }
+  }
+}
+
 // Sums over the nodes of the transform for one electron energy: aF[f] =
 // sum_k c_k psi(eps - x_k) (g's slope jumps), with DERIV also
 // aD[f] = sum_k c_k ln|eps - x_k| and aX[f] = sum_k cx_k psi(eps - x_k)
 // (x g's slope jumps).  Called by every lane of a wave (inactive lanes pass
-// active = false and vote "far").
+// active = false and vote "far").  Two levels: a super-cluster of kSup
+// clusters far for the whole wave takes one expansion (away from the nodes'
+// range, where most points of a workload lie, 8 instead of 64), else each of
+// its clusters is expanded or, where near, summed node by node.
 template <bool DERIV>
 __device__ inline void node_sums(const DevModel& m, double eps, bool active, double* aF,
                                  double* aD, double* aX) {
 #pragma unroll
   for (int f = 0; f < kNumF; ++f) aF[f] = aD[f] = aX[f] = 0.0;
   const uniform_dptr clus = uniform_ptr(m.clus);
+  const uniform_dptr sup = uniform_ptr(m.sup);
   const uniform_dptr nodes = uniform_ptr(m.nodes);
   const uniform_dptr coef = uniform_ptr(m.coef);
   const uniform_dptr coefx = uniform_ptr(m.coefx);
   const int nclust = __builtin_amdgcn_readfirstlane(m.nclust);
+  const int nsup = __builtin_amdgcn_readfirstlane(m.nsup);
   const int K = __builtin_amdgcn_readfirstlane(m.K);
-  for (int c = 0; c < nclust; ++c) {
-    const uniform_dptr C = clus + (size_t)c * kClusStride;
-    const double xc = C[0], r = C[1];
-    const double t = eps - xc;
-    const bool far = !active || (fabs(t) >= 3.0 * r && t != 0.0);
-    if (__all(far)) {
-      const double L = ln_abs(t);
-      double u = __builtin_amdgcn_rcp(t);
-      u = fma(u, fma(-t, u, 1.0), u);
-      u = fma(u, fma(-t, u, 1.0), u);
-      const double tl = t * L, l1 = L + 1.0;
+  for (int sc = 0; sc < nsup; ++sc) {
+    const uniform_dptr S = sup + (size_t)sc * kClusStride;
+    const double ts = eps - S[0];
+    if (__all(!active || (fabs(ts) >= 3.0 * S[1] && ts != 0.0))) {
+      far_terms<DERIV>(S, ts, aF, aD, aX);
+      continue;
+    }
+    const int c1 = min(nclust, (sc + 1) * kSup);
+    for (int c = sc * kSup; c < c1; ++c) {
+      const uniform_dptr C = clus + (size_t)c * kClusStride;
+      const double t = eps - C[0];
+      if (__all(!active || (fabs(t) >= 3.0 * C[1] && t != 0.0))) {
+        far_terms<DERIV>(C, t, aF, aD, aX);
+      } else if (active) {
+        const int k1 = min(K, (c + 1) * kClus);
+        for (int k = c * kClus; k < k1; ++k) {
+          const double tk = eps - nodes[k];
+          const double ln = (tk == 0.0) ? 0.0 : ln_abs(tk);
+          const double psi = tk * ln;
 #pragma unroll
-      for (int f = 0; f < kNumF; ++f) {
-        const uniform_dptr M = C + 2 + f * (kClusP + 1);
-        double ser = M[kClusP];
-        for (int n = kClusP - 1; n >= 2; --n) ser = fma(ser, u, M[n]);
-        aF[f] += fma(tl, M[0], fma(-l1, M[1], u * ser));
-        if (DERIV) {
-          double sd = (kClusP - 1) * M[kClusP];
-          for (int n = kClusP - 1; n >= 2; --n) sd = fma(sd, u, (n - 1) * M[n]);
-          aD[f] += fma(L, M[0], -u * fma(u, sd, M[1]));
-          const uniform_dptr MX = C + 2 + (kNumF + f) * (kClusP + 1);
-          double sx = MX[kClusP];
-          for (int n = kClusP - 1; n >= 2; --n) sx = fma(sx, u, MX[n]);
-          aX[f] += fma(tl, MX[0], fma(-l1, MX[1], u * sx));
-        }
-      }
-    } else if (active) {
-      const int k1 = min(K, (c + 1) * kClus);
-      for (int k = c * kClus; k < k1; ++k) {
-        const double tk = eps - nodes[k];
-        const double ln = (tk == 0.0) ? 0.0 : ln_abs(tk);
-        const double psi = tk * ln;
-#pragma unroll
-        for (int f = 0; f < kNumF; ++f) {
-          const double ck = coef[(size_t)k * kNumF + f];
-          aF[f] = fma(ck, psi, aF[f]);
-          if (DERIV) {
-            aD[f] = fma(ck, ln, aD[f]);
-            aX[f] = fma(coefx[(size_t)k * kNumF + f], psi, aX[f]);
+          for (int f = 0; f < kNumF; ++f) {
+            const double ck = coef[(size_t)k * kNumF + f];
+            aF[f] = fma(ck, psi, aF[f]);
+            if (DERIV) {
+              aD[f] = fma(ck, ln, aD[f]);
+              aX[f] = fma(coefx[(size_t)k * kNumF + f], psi, aX[f]);
+            }
           }
         }
       }
