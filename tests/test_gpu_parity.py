@@ -35,7 +35,7 @@ def vdc():
 
 def _cocg_steps_agree(gpu_iters, A, b, psolve, tol=1e-10):
     """COCG has no minimisation property (Sec. III.A) and its residual can
-    rise locally (Sec. IV), so where it lingers just above the target the
+    rise locally (Sec. III.C), so where it lingers just above the target the
     step that first crosses it moves with rounding.  The GPU's count must
     match the oracle's within max(3, 3 %) plus the length of the oracle's
     final plateau (trailing residuals within 10 x tol)."""

@@ -103,7 +103,7 @@ def _same(A, f1, f2, Ng, Nu):
 
 
 def test_ecd86_block_choices_that_coincide():
-    """Sec. IV on the ECD86 model: M^{dg} and M^{gu} hold only the diagonal
+    """Sec. III.C on the ECD86 model: M^{dg} and M^{gu} hold only the diagonal
     of A, and M^{du}, M^d and M^u hold the same elements (A has no term that
     the larger blocks would add)."""
     Ng, Nu = 7, 6
@@ -138,7 +138,7 @@ def test_ecd86_rows_hold_exactly_the_lam_coupling():
 
 
 def test_generalized_model_du_equals_u_and_dg_differs_from_gu():
-    """Sec. IV on the generalized model: M^{du} and M^u coincide (at fixed n_u
+    """Sec. III.C on the generalized model: M^{du} and M^u coincide (at fixed n_u
     the two states never meet), while the small blocks M^{dg} and M^{gu} are
     distinct (its q_u sandwiches put elements inside M^{dg})."""
     Ng, Nu = 6, 5
@@ -162,7 +162,7 @@ def test_rows_are_exact_without_g_couplings():
 
 
 def test_ecd86_rows_cut_the_iterations_where_the_paper_finds():
-    """Sec. IV, ECD86: convergence is fast at low energy and slows above
+    """Sec. III.C, ECD86: convergence is fast at low energy and slows above
     2 eV; M^g is the most effective block choice there, far ahead of the
     diagonal.  Small basis, GMRES(50) and COCG."""
     Ng = Nu = 30
