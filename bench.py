@@ -169,6 +169,33 @@ def ecd86_batched():
     return {name: batched_run(model, cfg, o) for name, o in runs}
 
 
+def graph_replay(model, cfg, opts, steps):
+    """The headline's jobs and options captured once as a HIP graph (counter
+    reset, level-shift tables and the persistent solver: vdc_batch_capture)
+    and replayed ``steps`` times back to back: solves/s over the replays, and
+    whether the outputs equal an eager vdc_solve's bit for bit."""
+    import torch
+    from paper_2307_13483_amd import vdc
+    ref = vdc.Solver(model, cfg["jobs"], cfg["finals"], opts).run()
+    torch.cuda.synchronize()
+    b = vdc.Batch(model, cfg["jobs"], cfg["finals"], opts)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    b.capture(s)
+    b.replay(s)
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.replay(s)
+    s.synchronize()
+    dt = time.perf_counter() - t0
+    infos = b.infos(s)
+    conv = sum(i["status"] == vdc.CONVERGED for i in infos)
+    same = bool(torch.equal(b.T, ref.T) and torch.equal(b.sigma, ref.sigma))
+    return dict(replays=steps, solves_per_s=conv * steps / dt, ms_per_replay=dt / steps * 1e3,
+                converged=conv, identical_to_eager=same)
+
+
 def batched_run(model, cfg, opts):
     """One timed vdc_solve call over the configuration's jobs (after one
     untimed call): solves/s of the whole call (tables included), step
@@ -355,6 +382,8 @@ def main():
                     help="only solve the batched workload and form its 2D energy-loss spectra")
     ap.add_argument("--cocg-probe", action="store_true",
                     help="only run the batched workload by COCG (block and diagonal preconditioners)")
+    ap.add_argument("--graph-probe", action="store_true",
+                    help="only run the headline configuration as a captured HIP graph (fixed options)")
     ap.add_argument("--ecd-probe", action="store_true",
                     help="only run the ECD86 workload (512 solves, row blocks and the diagonal)")
     args = ap.parse_args()
@@ -429,6 +458,11 @@ def main():
             from paper_2307_13483_amd.autotune import autotune
             opts, _ = autotune([model], cfg["jobs"], cfg["finals"], base=opts)
         return opts
+
+    if args.graph_probe:
+        print(json.dumps({"graph_replay": graph_replay(model, cfg, choose(args.precision),
+                                                       args.steps)}), flush=True)
+        return
 
     def run_mode(precision):
         opts = choose(precision)
@@ -525,6 +559,7 @@ def main():
             out["plain"] = dict(error=str(e))
     if args.extras:
         out["extras"] = extras(args, model, cfg)
+        out["extras"]["graph_replay"] = graph_replay(model, cfg, opts, args.steps)
     if args.cpu_sample > 0:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
     print(json.dumps(out), flush=True)

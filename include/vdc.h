@@ -185,6 +185,34 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                      double* T_out, double* sigma_out, double* psi_out,
                      vdc_job_info* info, void* stream);
 
+/* The batched solve as a reusable launch (for host loops that repeat the same
+ * jobs, and for capture into a HIP graph: the whole batch, tables included,
+ * becomes one graph launch).
+ * vdc_batch_create: the checks, plan and descriptor upload of vdc_solve, done
+ *   once; the batch keeps the workspace and output pointers (caller-owned,
+ *   they must stay allocated and unchanged until vdc_batch_destroy) and
+ *   synchronises the stream before returning.  Same arguments as vdc_solve
+ *   without info.  n_jobs >= 1.
+ * vdc_batch_launch: enqueues the counter reset, the level-shift table
+ *   kernels and the persistent solver on the stream: kernels only, no copy,
+ *   memset, allocation or host synchronisation, so the call may be captured.
+ * vdc_batch_capture: captures vdc_batch_launch on the stream (not the null
+ *   stream) into a HIP graph owned by the batch and instantiates it
+ *   (replacing an earlier one); vdc_batch_replay launches that graph.
+ * vdc_batch_info: per-job results of the last completed launch or replay
+ *   (synchronises the stream).
+ * Launches of one batch on several streams at once race on its workspace. */
+typedef struct vdc_batch* vdc_batch_t;
+vdc_status vdc_batch_create(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                            int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                            void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                            double* psi_out, void* stream, vdc_batch_t* out);
+vdc_status vdc_batch_launch(vdc_batch_t batch, void* stream);
+vdc_status vdc_batch_capture(vdc_batch_t batch, void* stream);
+vdc_status vdc_batch_replay(vdc_batch_t batch, void* stream);
+vdc_status vdc_batch_info(vdc_batch_t batch, vdc_job_info* info, void* stream);
+vdc_status vdc_batch_destroy(vdc_batch_t batch);
+
 /* The plain single-solve path: the same arithmetic, one job after another,
  * each GMRES step issued from the host as separate grid-wide kernels (matvec,
  * Gram-Schmidt projections, norm, Givens update) with one status read-back

@@ -328,14 +328,26 @@ struct AdjointIO {
   double* grad;
 };
 
-vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
-                     int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
-                     void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
-                     double* psi_out, vdc_job_info* info, void* stream, bool plain,
-                     const AdjointIO* adj = nullptr) {
+// A solve as it sits in the workspace: the plan, the kernels' arguments and
+// what the table kernels need.  Filled by prepare_solve, launched by
+// enqueue_solve (kernels only: no copy, no memset, no host synchronisation).
+struct Prepared {
   Plan P;
+  SolveArgs a{};
+  char* ws = nullptr;
+  bool mixed = false, cocg = false, plain = false, adjoint = false;
+  int n_jobs = 0;
+};
+
+vdc_status prepare_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                         int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                         void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                         double* psi_out, hipStream_t s, bool plain, const AdjointIO* adj,
+                         Prepared& R) {
+  Plan& P = R.P;
   vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, plain, P, adj != nullptr);
   if (st != VDC_OK) return st;
+  R.n_jobs = n_jobs;
   if (n_jobs == 0) return VDC_OK;
   if (!workspace) return fail(VDC_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
@@ -347,9 +359,13 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
     return fail(VDC_ERR_INVALID_ARG, "finals/T_out/sigma_out must be non-NULL when n_final > 0");
   if (adj && (!adj->psi || !adj->grad_jobs || (n_final > 0 && (!finals || !adj->T || !adj->dsig))))
     return fail(VDC_ERR_INVALID_ARG, "psi, T, dL_dsigma, finals and grad_jobs must be non-NULL");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  const bool mixed = opts->precision == VDC_FP32_INNER;
+  R.ws = ws;
+  R.mixed = opts->precision == VDC_FP32_INNER;
+  R.cocg = opts->method == VDC_COCG;
+  R.plain = plain;
+  R.adjoint = adj != nullptr;
+  const bool mixed = R.mixed;
 
   HIPCHK(hipMemcpyAsync(ws + P.off_models, P.models.data(), sizeof(DevModel) * n_models,
                         hipMemcpyHostToDevice, s));
@@ -364,9 +380,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (n_final > 0)
     HIPCHK(hipMemcpyAsync(ws + P.off_finals, finals, sizeof(int) * 2 * n_final,
                           hipMemcpyHostToDevice, s));
-  HIPCHK(launch_zero_int(reinterpret_cast<int*>(ws + P.off_counter), 64, s));
 
-  SolveArgs a{};
+  SolveArgs& a = R.a;
   a.models = reinterpret_cast<const DevModel*>(ws + P.off_models);
   a.jobs = reinterpret_cast<const DevJob*>(ws + P.off_jobs);
   a.n_jobs = n_jobs;
@@ -399,38 +414,95 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
     a.dsig = adj->dsig;
     a.grad = adj->grad_jobs;
   }
+  return VDC_OK;
+}
 
-  EventSet ev;
-  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+// The counter reset, the level-shift tables and the persistent solver kernel
+// (not the plain path, which reads status back between its kernels).  With
+// ev, events bracket the tables and the solver.
+vdc_status enqueue_solve(const Prepared& R, hipStream_t s, EventSet* ev) {
+  const Plan& P = R.P;
+  const SolveArgs& a = R.a;
+  char* ws = R.ws;
+  HIPCHK(launch_zero_int(reinterpret_cast<int*>(ws + P.off_counter), 64, s));
+  if (ev) HIPCHK(hipEventRecord(ev->e[0], s));
   HIPCHK(launch_level_shift_tables(a.models, reinterpret_cast<const DevGroup*>(ws + P.off_groups),
                                    (int)P.groups.size(), P.max_group_pts,
                                    reinterpret_cast<const int*>(ws + P.off_perm), a.tabs,
                                    (int)P.tabs.size(), P.max_nc,
                                    reinterpret_cast<c64*>(ws + P.off_shift),
                                    reinterpret_cast<c64*>(ws + P.off_tables),
-                                   mixed ? reinterpret_cast<c32*>(ws + P.off_tables32) : nullptr, s,
-                                   P.deriv));
-  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
-  if (adj) {
+                                   R.mixed ? reinterpret_cast<c32*>(ws + P.off_tables32) : nullptr,
+                                   s, P.deriv));
+  if (ev) HIPCHK(hipEventRecord(ev->e[1], s));
+  if (R.adjoint) {
     HIPCHK(launch_adjoint(a, P.n_groups, P.dyn_lds, s));
-  } else if (plain) {
-    std::string err;
-    st = solve_plain_impl(a, P.jobs, P.models, s, err);
-    if (st != VDC_OK) return fail(st, err);
-  } else if (mixed && opts->method == VDC_COCG) {
+  } else if (R.mixed && R.cocg) {
     HIPCHK(launch_cocg_mixed(a, P.n_groups, P.dyn_lds, s));
-  } else if (mixed) {
+  } else if (R.mixed) {
     HIPCHK(launch_fgmres_mixed(a, P.n_groups, P.dyn_lds, s));
-  } else if (opts->method == VDC_COCG) {
+  } else if (R.cocg) {
     HIPCHK(launch_cocg_fp64(a, P.n_groups, P.dyn_lds, s));
   } else {
     HIPCHK(launch_gmres_fp64(a, P.n_groups, P.dyn_lds, s));
   }
-  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
-  std::vector<DevInfo> hinfo(n_jobs);
-  HIPCHK(hipMemcpyAsync(hinfo.data(), ws + P.off_info, sizeof(DevInfo) * n_jobs,
+  if (ev) HIPCHK(hipEventRecord(ev->e[2], s));
+  return VDC_OK;
+}
+
+// Per-job results from the workspace (synchronises the stream).
+vdc_status read_info(const Prepared& R, vdc_job_info* info, hipStream_t s) {
+  std::vector<DevInfo> hinfo(R.n_jobs);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), R.ws + R.P.off_info, sizeof(DevInfo) * R.n_jobs,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  if (info) {
+    for (int j = 0; j < R.n_jobs; ++j) {
+      info[j].status = hinfo[j].status;
+      info[j].iters = hinfo[j].iters;
+      info[j].restarts = hinfo[j].restarts;
+      info[j].outer_iters = hinfo[j].outer;
+      info[j].rel_res = hinfo[j].rel_res;
+      info[j].alg_bytes = hinfo[j].alg_bytes;
+    }
+  }
+  return VDC_OK;
+}
+
+vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                     int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                     void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                     double* psi_out, vdc_job_info* info, void* stream, bool plain,
+                     const AdjointIO* adj = nullptr) {
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Prepared R;
+  vdc_status st = prepare_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace,
+                                ws_bytes, T_out, sigma_out, psi_out, s, plain, adj, R);
+  if (st != VDC_OK || n_jobs == 0) return st;
+  EventSet ev;
+  if (plain) {
+    HIPCHK(launch_zero_int(reinterpret_cast<int*>(R.ws + R.P.off_counter), 64, s));
+    if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+    const Plan& P = R.P;
+    const SolveArgs& a = R.a;
+    HIPCHK(launch_level_shift_tables(a.models, reinterpret_cast<const DevGroup*>(R.ws + P.off_groups),
+                                     (int)P.groups.size(), P.max_group_pts,
+                                     reinterpret_cast<const int*>(R.ws + P.off_perm), a.tabs,
+                                     (int)P.tabs.size(), P.max_nc,
+                                     reinterpret_cast<c64*>(R.ws + P.off_shift),
+                                     reinterpret_cast<c64*>(R.ws + P.off_tables), nullptr, s,
+                                     P.deriv));
+    if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+    std::string err;
+    st = solve_plain_impl(a, P.jobs, P.models, s, err);
+    if (st != VDC_OK) return fail(st, err);
+    if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  } else {
+    st = enqueue_solve(R, s, ev.ok ? &ev : nullptr);
+    if (st != VDC_OK) return st;
+  }
+  st = read_info(R, info, s);
+  if (st != VDC_OK) return st;
   if (ev.ok) {
     float t1 = 0.f, t2 = 0.f;
     HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
@@ -448,20 +520,22 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
       adj->grad[p] = t;
     }
   }
-  if (info) {
-    for (int j = 0; j < n_jobs; ++j) {
-      info[j].status = hinfo[j].status;
-      info[j].iters = hinfo[j].iters;
-      info[j].restarts = hinfo[j].restarts;
-      info[j].outer_iters = hinfo[j].outer;
-      info[j].rel_res = hinfo[j].rel_res;
-      info[j].alg_bytes = hinfo[j].alg_bytes;
-    }
-  }
   return VDC_OK;
 }
 
 }  // namespace
+
+struct vdc_batch {
+  Prepared R;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+};
 
 extern "C" {
 
@@ -648,6 +722,74 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                      double* psi_out, vdc_job_info* info, void* stream) {
   return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
                    T_out, sigma_out, psi_out, info, stream, false);
+}
+
+vdc_status vdc_batch_create(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                            int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                            void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                            double* psi_out, void* stream, vdc_batch_t* out) {
+  if (!out) return fail(VDC_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_jobs < 1) return fail(VDC_ERR_INVALID_ARG, "a batch needs at least one job");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  vdc_batch* b = new vdc_batch();
+  vdc_status st = prepare_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace,
+                                ws_bytes, T_out, sigma_out, psi_out, s, false, nullptr, b->R);
+  if (st == VDC_OK && hipStreamSynchronize(s) != hipSuccess)
+    st = fail(VDC_ERR_HIP, "batch upload failed");
+  if (st != VDC_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return VDC_OK;
+}
+
+vdc_status vdc_batch_launch(vdc_batch_t b, void* stream) {
+  if (!b) return fail(VDC_ERR_INVALID_ARG, "NULL batch");
+  return enqueue_solve(b->R, reinterpret_cast<hipStream_t>(stream), nullptr);
+}
+
+vdc_status vdc_batch_capture(vdc_batch_t b, void* stream) {
+  if (!b) return fail(VDC_ERR_INVALID_ARG, "NULL batch");
+  if (!stream) return fail(VDC_ERR_INVALID_ARG, "capture needs a stream other than the null stream");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  b->drop_graph();
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const vdc_status st = enqueue_solve(b->R, s, nullptr);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (st != VDC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  b->graph = g;
+  const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    b->drop_graph();
+    return hip_fail(ei, "hipGraphInstantiate");
+  }
+  return VDC_OK;
+}
+
+vdc_status vdc_batch_replay(vdc_batch_t b, void* stream) {
+  if (!b) return fail(VDC_ERR_INVALID_ARG, "NULL batch");
+  if (!b->exec) return fail(VDC_ERR_INVALID_ARG, "no captured graph: call vdc_batch_capture first");
+  HIPCHK(hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+  return VDC_OK;
+}
+
+vdc_status vdc_batch_info(vdc_batch_t b, vdc_job_info* info, void* stream) {
+  if (!b) return fail(VDC_ERR_INVALID_ARG, "NULL batch");
+  return read_info(b->R, info, reinterpret_cast<hipStream_t>(stream));
+}
+
+vdc_status vdc_batch_destroy(vdc_batch_t b) {
+  if (!b) return VDC_OK;
+  b->drop_graph();
+  delete b;
+  return VDC_OK;
 }
 
 vdc_status vdc_solve_plain(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,

@@ -97,6 +97,14 @@ def lib():
         "vdc_solve_plain": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
                                 ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, S, P, P,
                                 P, ctypes.POINTER(JobInfo), P]),
+        "vdc_batch_create": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                 ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, S, P, P,
+                                 P, P, ctypes.POINTER(P)]),
+        "vdc_batch_launch": (I, [P, P]),
+        "vdc_batch_capture": (I, [P, P]),
+        "vdc_batch_replay": (I, [P, P]),
+        "vdc_batch_info": (I, [P, ctypes.POINTER(JobInfo), P]),
+        "vdc_batch_destroy": (I, [P]),
         "vdc_adjoint_workspace_size": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
                                            ctypes.POINTER(Job), ctypes.POINTER(S)]),
         "vdc_solve_adjoint": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
@@ -345,6 +353,44 @@ class Solver:
                      restarts=self.info[k].restarts, outer_iters=self.info[k].outer_iters,
                      rel_res=self.info[k].rel_res, alg_bytes=self.info[k].alg_bytes)
                 for k in range(self.n_jobs)]
+
+
+class Batch(Solver):
+    """vdc_batch_*: the Solver's jobs prepared once; ``launch`` enqueues the
+    whole solve (kernels only), ``capture`` records that into a HIP graph on
+    a stream of its own and ``replay`` launches the graph.  ``infos`` reads
+    the per-job results of the last completed launch or replay."""
+
+    def __init__(self, models, jobs, finals, opts=None, want_psi=False, stream=None):
+        super().__init__(models, jobs, finals, opts, want_psi)
+        self.handle = ctypes.c_void_p()
+        _check(lib().vdc_batch_create(len(self.models), self.handles, ctypes.byref(self.copts),
+                                      self.n_jobs, self.jobs, self.n_final, self.finals,
+                                      _ptr(self.ws), self.ws_bytes, _ptr(self.T), _ptr(self.sigma),
+                                      _ptr(self.psi), _stream_ptr(stream), ctypes.byref(self.handle)))
+
+    def launch(self, stream=None):
+        _check(lib().vdc_batch_launch(self.handle, _stream_ptr(stream)))
+        return self
+
+    def capture(self, stream):
+        """Capture on ``stream`` (a torch.cuda.Stream, not the default one)."""
+        _check(lib().vdc_batch_capture(self.handle, _stream_ptr(stream)))
+        return self
+
+    def replay(self, stream=None):
+        _check(lib().vdc_batch_replay(self.handle, _stream_ptr(stream)))
+        return self
+
+    def infos(self, stream=None):
+        _check(lib().vdc_batch_info(self.handle, self.info, _stream_ptr(stream)))
+        return super().infos()
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.vdc_batch_destroy(h)
+            self.handle = None
 
 
 def solve(models, jobs, finals, opts=None, plain=False, want_psi=False):

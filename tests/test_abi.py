@@ -51,6 +51,10 @@ def test_null_arguments_rejected():
     assert L.vdc_model2d_create(None, None) == vdc.VDC_ERR_INVALID_ARG
     assert L.vdc_level_shift(None, 1, None, None, None) == vdc.VDC_ERR_INVALID_ARG
     assert L.vdc_model_destroy(None) == vdc.VDC_OK
+    for f in (L.vdc_batch_launch, L.vdc_batch_capture, L.vdc_batch_replay):
+        assert f(None, None) == vdc.VDC_ERR_INVALID_ARG
+    assert L.vdc_batch_info(None, None, None) == vdc.VDC_ERR_INVALID_ARG
+    assert L.vdc_batch_destroy(None) == vdc.VDC_OK
 
 
 def test_invalid_co2_model_rejected_before_device_work():

@@ -639,3 +639,49 @@ def test_rows_rejected_for_the_co2_like_model(vdc):
     with pytest.raises(vdc.VdcError):
         vdc.co2_solve(model, [(1.0, (0, 0, 0, 0), 0)], [(0, 0, 0, 0)],
                       vdc.Opts(precond=vdc.PREC_ROWS))
+
+
+# ------------------------------------------------------------ batch launch, graph capture
+
+def test_batch_launch_and_graph_replay_match_vdc_solve(vdc):
+    """vdc_batch_launch, and a HIP graph captured from it, give vdc_solve's
+    results bit for bit on a sample of the batched workload (FP32 COCG inside
+    FP64 refinement, column blocks).  The graph is replayed three times with
+    the outputs cleared before and eager solves between the replays; every
+    replay is checked."""
+    import torch
+    cfg = inputs.batched_jobs(n_energies=512)
+    p = cfg["params"]
+    sample = [cfg["jobs"][k] for k in range(0, 3072, 97)]
+    model = vdc.Model2D(p, cfg["Ng"], cfg["Nu"])
+    opts = vdc.Opts(precond=vdc.PREC_BLOCK, method=vdc.COCG, precision=vdc.FP32_INNER,
+                    inner_restart=200, inner_tol=1e-5, max_iter=20000)
+    ref = vdc.Solver(model, sample, cfg["finals"], opts, want_psi=True).run()
+    torch.cuda.synchronize()
+    ref_it = [i["iters"] for i in ref.infos()]
+    assert all(i["status"] == 0 for i in ref.infos())
+
+    def same(b):
+        assert torch.equal(b.T, ref.T) and torch.equal(b.sigma, ref.sigma)
+        assert torch.equal(b.psi, ref.psi)
+
+    b = vdc.Batch(model, sample, cfg["finals"], opts, want_psi=True)
+    b.launch()
+    torch.cuda.synchronize()
+    same(b)
+    assert [i["iters"] for i in b.infos()] == ref_it
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    b.capture(s)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            b.T.zero_()
+            b.sigma.zero_()
+            b.psi.zero_()
+        b.replay(s)
+        s.synchronize()
+        same(b)
+        assert [i["iters"] for i in b.infos(s)] == ref_it, rep
+        other = vdc.Solver(model, sample[:3], cfg["finals"], opts).run()
+        torch.cuda.synchronize()
+        assert all(i["status"] == 0 for i in other.infos())
