@@ -125,6 +125,33 @@ def co2like(args, method=None):
                 frac=alg / (ms_sol * 1e-3) / 1e9 / HBM_PEAK_GBS)
 
 
+def co2_matvec(nv=512):
+    """The CO2-like model's operator (vdc_co2_apply, y = A x) on nv random
+    sector vectors at E = 2.0 eV, sectors alternating: algorithmic bytes 32 B
+    per grid point and vector (x in, y out) plus the level-shift rows of the
+    energy once, over the operator kernel's HIP-event time (best of 3)."""
+    import torch
+    from paper_2307_13483_amd import inputs, vdc
+    cfg = inputs.co2like_jobs()
+    model = vdc.Co2Model(cfg["params"], cfg["sizes"])
+    sz = cfg["sizes"]
+    npts = sz["s"] * sz["x"] * sz["y"] * sz["a"]
+    g = torch.Generator(device="cuda").manual_seed(2)
+    x = torch.randn((nv, npts), dtype=torch.complex128, device="cuda", generator=g)
+    sectors = [(k % 2, (k // 2) % 2) for k in range(nv)]
+    vdc.co2_apply(model, 2.0, x, sectors)
+    ms = []
+    for _ in range(3):
+        vdc.co2_apply(model, 2.0, x, sectors)
+        ms.append(vdc.last_kernel_times()[1])
+    t = min(ms) * 1e-3
+    ntab = sz["s"] * (sz["x"] + sz["y"] - 1) * sz["a"]
+    alg = nv * 32.0 * npts + ntab * 6 * 16.0
+    return dict(vectors=nv, points_per_vector=npts, kernel_ms=t * 1e3,
+                achieved_GBs=alg / t / 1e9, frac=alg / t / 1e9 / HBM_PEAK_GBS,
+                algorithmic_bytes=alg)
+
+
 def solver_name(opts, precond):
     from paper_2307_13483_amd import vdc
     pc = PREC_NAMES[precond]
@@ -330,6 +357,7 @@ def extras(args, model, cfg):
     from paper_2307_13483_amd import vdc as _v
     ex["co2like"] = co2like(args)
     ex["co2like_cocg"] = co2like(args, _v.COCG)
+    ex["co2_matvec"] = co2_matvec()
     ex["eels_batched"] = eels_batched(model, cfg)
     ex["cocg_batched"] = {name: cocg_batched(model, cfg, pc, mx) for name, pc, mx in
                           (("block", _v.PREC_BLOCK, False), ("jacobi", _v.PREC_JACOBI, False),
@@ -392,8 +420,8 @@ def main():
         return
     if args.co2_probe:
         from paper_2307_13483_amd import vdc
-        print(json.dumps({"co2like": co2like(args), "co2like_cocg": co2like(args, vdc.COCG)}),
-              flush=True)
+        print(json.dumps({"co2like": co2like(args), "co2like_cocg": co2like(args, vdc.COCG),
+                          "co2_matvec": co2_matvec()}), flush=True)
         return
     if args.eels_probe:
         from paper_2307_13483_amd import inputs, vdc
