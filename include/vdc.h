@@ -201,6 +201,9 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
  *   (replacing an earlier one); vdc_batch_replay launches that graph.
  * vdc_batch_info: per-job results of the last completed launch or replay
  *   (synchronises the stream).
+ * vdc_batch_kernel_times: milliseconds of the level-shift table kernels and
+ *   of the solver kernel in the last vdc_batch_launch, from HIP events
+ *   recorded on its stream (waits for them); replays are not timed.
  * Launches of one batch on several streams at once race on its workspace. */
 typedef struct vdc_batch* vdc_batch_t;
 vdc_status vdc_batch_create(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
@@ -211,6 +214,7 @@ vdc_status vdc_batch_launch(vdc_batch_t batch, void* stream);
 vdc_status vdc_batch_capture(vdc_batch_t batch, void* stream);
 vdc_status vdc_batch_replay(vdc_batch_t batch, void* stream);
 vdc_status vdc_batch_info(vdc_batch_t batch, vdc_job_info* info, void* stream);
+vdc_status vdc_batch_kernel_times(vdc_batch_t batch, double* ms_tables, double* ms_solver);
 vdc_status vdc_batch_destroy(vdc_batch_t batch);
 
 /* The plain single-solve path: the same arithmetic, one job after another,

@@ -527,6 +527,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
 
 struct vdc_batch {
   Prepared R;
+  EventSet ev;             // bracket the tables and the solver of each eager launch
+  bool timed = false;      // an eager launch has recorded them
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void drop_graph() {
@@ -747,7 +749,22 @@ vdc_status vdc_batch_create(int n_models, const vdc_model_t* models, const vdc_s
 
 vdc_status vdc_batch_launch(vdc_batch_t b, void* stream) {
   if (!b) return fail(VDC_ERR_INVALID_ARG, "NULL batch");
-  return enqueue_solve(b->R, reinterpret_cast<hipStream_t>(stream), nullptr);
+  const vdc_status st =
+      enqueue_solve(b->R, reinterpret_cast<hipStream_t>(stream), b->ev.ok ? &b->ev : nullptr);
+  b->timed = st == VDC_OK && b->ev.ok;
+  return st;
+}
+
+vdc_status vdc_batch_kernel_times(vdc_batch_t b, double* ms_tables, double* ms_solver) {
+  if (!b) return fail(VDC_ERR_INVALID_ARG, "NULL batch");
+  if (!b->timed) return fail(VDC_ERR_INVALID_ARG, "no timed launch: call vdc_batch_launch first");
+  HIPCHK(hipEventSynchronize(b->ev.e[2]));
+  float t1 = 0.f, t2 = 0.f;
+  HIPCHK(hipEventElapsedTime(&t1, b->ev.e[0], b->ev.e[1]));
+  HIPCHK(hipEventElapsedTime(&t2, b->ev.e[1], b->ev.e[2]));
+  if (ms_tables) *ms_tables = t1;
+  if (ms_solver) *ms_solver = t2;
+  return VDC_OK;
 }
 
 vdc_status vdc_batch_capture(vdc_batch_t b, void* stream) {

@@ -104,6 +104,7 @@ def lib():
         "vdc_batch_capture": (I, [P, P]),
         "vdc_batch_replay": (I, [P, P]),
         "vdc_batch_info": (I, [P, ctypes.POINTER(JobInfo), P]),
+        "vdc_batch_kernel_times": (I, [P, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "vdc_batch_destroy": (I, [P]),
         "vdc_adjoint_workspace_size": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
                                            ctypes.POINTER(Job), ctypes.POINTER(S)]),
@@ -385,6 +386,12 @@ class Batch(Solver):
     def infos(self, stream=None):
         _check(lib().vdc_batch_info(self.handle, self.info, _stream_ptr(stream)))
         return super().infos()
+
+    def kernel_times(self):
+        """(ms of the table kernels, ms of the solver) of the last launch."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(lib().vdc_batch_kernel_times(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -54,6 +54,7 @@ def test_null_arguments_rejected():
     for f in (L.vdc_batch_launch, L.vdc_batch_capture, L.vdc_batch_replay):
         assert f(None, None) == vdc.VDC_ERR_INVALID_ARG
     assert L.vdc_batch_info(None, None, None) == vdc.VDC_ERR_INVALID_ARG
+    assert L.vdc_batch_kernel_times(None, None, None) == vdc.VDC_ERR_INVALID_ARG
     assert L.vdc_batch_destroy(None) == vdc.VDC_OK
 
 
