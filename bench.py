@@ -271,6 +271,33 @@ def eels_batched(model, cfg):
                 total=float(S.sum().item()) * 0.001)
 
 
+def adjoint_gradient(opts):
+    """The adjoint workload (base model, 120 x 120, 256 energies, v_i = 0,
+    finals 0..5): one forward solve of its 512 right-hand sides and one
+    transposed solve each for dL/dsigma = 1, timed after an untimed pair."""
+    import torch
+    from paper_2307_13483_amd import inputs, vdc
+    aw = inputs.adjoint_workload()
+    ma = vdc.Model2D(aw["params"], aw["Ng"], aw["Nu"])
+    ajobs = [(float(e), (0, 0), mu) for e in aw["eps"] for mu in (0, 1)]
+    s = vdc.Solver(ma, ajobs, aw["finals"], opts, want_psi=True)
+    dsig = torch.ones((len(ajobs), len(aw["finals"])), dtype=torch.float64, device="cuda")
+    s.run()
+    s.adjoint(dsig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.adjoint(dsig)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return dict(energies=len(aw["eps"]), right_hand_sides=len(ajobs),
+                forward_ms=(t1 - t0) * 1e3, adjoint_ms=(t2 - t1) * 1e3,
+                gradient_evals_per_s=1.0 / (t2 - t0),
+                adjoint_converged=sum(s.adj_info[k].status == 0 for k in range(len(ajobs))))
+
+
 def uneven_mixed(pc, finals):
     """64 instances of the two-state model (own parameter draws, n x n basis
     with n in 40..160, one energy each), both partial waves, in one launch."""
@@ -354,22 +381,6 @@ def extras(args, model, cfg):
             (time.perf_counter() - t0) / 5 * 1e3
     ex["uneven_mixed"] = uneven_mixed(PRECONDS[args.precond], cfg["finals"])
     pc = PRECONDS[args.precond]
-    # adjoint: 120 x 120 base model, 256 energies, v_i = 0, finals 0..5
-    aw = inputs.adjoint_workload()
-    ma = vdc.Model2D(aw["params"], aw["Ng"], aw["Nu"])
-    ajobs = [(float(e), (0, 0), mu) for e in aw["eps"] for mu in (0, 1)]
-    s = vdc.Solver(ma, ajobs, aw["finals"], vdc.Opts(restart=6, precond=pc), want_psi=True)
-    dsig = torch.ones((len(ajobs), len(aw["finals"])), dtype=torch.float64, device="cuda")
-    s.run()
-    s.adjoint(dsig)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.run()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s.adjoint(dsig)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
     from paper_2307_13483_amd import vdc as _v
     ex["co2like"] = co2like(args)
     ex["co2like_cocg"] = co2like(args, _v.COCG)
@@ -379,10 +390,9 @@ def extras(args, model, cfg):
                           (("block", _v.PREC_BLOCK, False), ("jacobi", _v.PREC_JACOBI, False),
                            ("block_fp32_inner", _v.PREC_BLOCK, True))}
     ex["ecd86"] = ecd86_batched()
-    ex["adjoint"] = dict(energies=len(aw["eps"]), right_hand_sides=len(ajobs),
-                         forward_ms=(t1 - t0) * 1e3, adjoint_ms=(t2 - t1) * 1e3,
-                         gradient_evals_per_s=1.0 / (t2 - t0),
-                         adjoint_converged=sum(s.adj_info[k].status == 0 for k in range(len(ajobs))))
+    ex["adjoint"] = {name: adjoint_gradient(o) for name, o in
+                     (("gmres6", _v.Opts(restart=6, precond=pc)),
+                      ("cocg", _v.Opts(precond=pc, method=_v.COCG)))}
     return ex
 
 

@@ -111,15 +111,15 @@ typedef enum {
                                 accumulation as the variable preconditioner   */
 } vdc_precision;
 
-/* Krylov method of vdc_solve (Sec. III.A): restarted GMRES (with the
- * precision above), or COCG, conjugate gradients with the bilinear form
- * <a|b>_S = sum a_i b_i for the complex symmetric A, preconditioned as
- * M^{-1} A M^{-T} with M M^T the JACOBI or BLOCK section (both symmetric).
- * COCG with VDC_FP32_INNER (vdc_solve only) is FP64 iterative refinement
+/* Krylov method of vdc_solve, the batch entry points, vdc_solve_adjoint and
+ * vdc_co2_solve (Sec. III.A): restarted GMRES (with the precision above), or
+ * COCG, conjugate gradients with the bilinear form <a|b>_S = sum a_i b_i for
+ * the complex symmetric A, preconditioned as M^{-1} A M^{-T} with M M^T the
+ * JACOBI, BLOCK or ROWS section (all symmetric).  Not for vdc_solve_plain.
+ * COCG with VDC_FP32_INNER (not for the adjoint) is FP64 iterative refinement
  * whose correction equations are solved by COCG entirely in FP32 to the
  * relative residual inner_tol or inner_restart steps; iters then counts the
- * FP32 steps, outer_iters the refinements.  In FP64 (vdc_solve and
- * vdc_co2_solve) restart is ignored, max_iter counts COCG steps, and the
+ * FP32 steps, outer_iters the refinements.  In FP64 restart is ignored, max_iter counts COCG steps, and the
  * true residual decides convergence (the iteration restarts from it when the
  * updated residual has converged but it has not).  A vanishing bilinear
  * form at a fresh start is VDC_BREAKDOWN. */
@@ -245,7 +245,8 @@ vdc_status vdc_solve_plain(int n_models, const vdc_model_t* models, const vdc_so
  *   grad_jobs  device double [n_jobs][16]: each job's contribution
  *   grad       host double[16] or NULL: sum over jobs (in job order)
  *   info       host vdc_job_info[n_jobs] or NULL: the adjoint solves
- * FP64 only.  Workspace: vdc_adjoint_workspace_size().  Synchronises. */
+ * FP64 only; the transposed solves use opts->method (GMRES or COCG).
+ * Workspace: vdc_adjoint_workspace_size().  Synchronises. */
 vdc_status vdc_adjoint_workspace_size(int n_models, const vdc_model_t* models,
                                       const vdc_solve_opts* opts, int n_jobs,
                                       const vdc_job* jobs, size_t* bytes);

@@ -14,7 +14,7 @@
 // diagonal E - E_nu - E_d (w_g, w_u, gap), the direct couplings (k_d, lam),
 // the (1 + lam_d q_g) factors of the sandwich (lam_d), and the level-shift
 // diagonals through dF/deps (w_g, w_u), F/A (A) and the transform of x g (B).
-#include "gmres_block.h"
+#include "cocg_block.h"
 #include "solve_args.h"
 
 namespace vdc {
@@ -24,6 +24,7 @@ constexpr int kRedA = kWaves * 16 + 16;
 
 struct AdjLds {
   Fp64Lds S;
+  double dot[2];
   double redA[kRedA];
   c64 W[2 * kMaxFinal];
   int job;
@@ -245,8 +246,12 @@ adjoint_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    const BlockSolve r = gmres_fp64_block<rows>(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT,
-                                          a.precond);
+    const BlockSolve r =
+        a.method == VDC_COCG
+            ? cocg_fp64_block<rows>(L.S.red, L.dot, L.S.sq, op, s, a.ncap, a.tol, a.max_iter,
+                                    a.tileT, a.precond)
+            : gmres_fp64_block<rows>(L.S, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT,
+                                     a.precond);
     __syncthreads();
     // -zeta^T (dA/dp) psi
     sweep_dA(op, jb, md, L.S.sq, z, s.x, tab, L.redA, G);

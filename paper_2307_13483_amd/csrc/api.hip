@@ -151,8 +151,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     return fail(VDC_ERR_INVALID_ARG, "unknown method");
   const bool mixed = o->precision == VDC_FP32_INNER;
   const bool cocg = o->method == VDC_COCG;
-  if (cocg && (plain || adjoint))
-    return fail(VDC_ERR_UNSUPPORTED, "COCG runs in the batched solve only");
+  if (cocg && plain) return fail(VDC_ERR_UNSUPPORTED, "COCG runs in the batched solves only");
   if (mixed && adjoint) return fail(VDC_ERR_UNSUPPORTED, "the adjoint solve is FP64 only");
   P.deriv = adjoint;
   const int planes = adjoint ? kPlanesDeriv : kPlanesSolve;
@@ -396,6 +395,7 @@ vdc_status prepare_solve(int n_models, const vdc_model_t* models, const vdc_solv
   a.max_iter = opts->max_iter;
   a.tol = opts->tol;
   a.precond = opts->precond;
+  a.method = opts->method;
   a.m_in = opts->inner_restart;
   a.tol_in = opts->inner_tol;
   a.n_final = n_final;

@@ -1,20 +1,7 @@
 // Persistent batched COCG in complex FP64 (Sec. III.A), one job per
-// workgroup at a time, the whole solve on chip: conjugate gradients with the
-// symmetrized bilinear form <a|b>_S = sum_i a_i b_i, for the complex
-// symmetric A of the model, preconditioned as M^{-1} A M^{-T} (Sec. III.B)
-// with K = M M^T the diagonal of A or its column blocks (segprec.h; both
-// symmetric), in the coupled two-term form:
-//   r = b, z = K^{-1} r, p = z, rho = <r|z>_S;
-//   repeat: q = A p, mu = <p|q>_S (in the operator's pass), alpha = rho/mu,
-//           x += alpha p, r -= alpha q, z = K^{-1} r, rho' = <r|z>_S,
-//           p = z + (rho'/rho) p.
-// Short recurrences: no basis is stored and no orthogonalisation pass is
-// made.  When ||r|| <= tol ||b|| the FP64 true residual b - A x decides
-// (stopping rule of Sec. III); if it is larger the iteration restarts from
-// it.  A vanishing <p|q>_S or <r|z>_S (the form is not definite) restarts
-// from the true residual once, and is reported as a breakdown if it recurs
-// at once.  Every wave reaches the queue-exhausted exit.
-#include "gmres_block.h"
+// workgroup at a time, the whole solve on chip (cocg_block.h).  Every wave
+// reaches the queue-exhausted exit.
+#include "cocg_block.h"
 #include "solve_args.h"
 
 namespace vdc {
@@ -26,27 +13,12 @@ struct CocgLds {
   int job;
 };
 
-// Byte model (passes over a block vector of Nc complex FP64 values):
-// setup: the preconditioner and x, b (as the FP64 GMRES: 5, block 8), ||b||
-// (1), r = b (2), z = K^{-1} r into p with rho (diagonal: r, dinv in, p out:
-// 3; block: r and 3 factor planes in, p out, then r, p for rho: 7);
-// iteration: the operator (p and 3 table planes in, q out: 5, <p|q>_S from
-// the staged p), the update of x and r with rho' (x, p, r, q in, x, r out,
-// and dinv in: 7; block, by column blocks with z = K^{-1} r: 3 factor planes
-// in and z out as well: 10), the next direction (diagonal: r, dinv, p in, p
-// out: 4; block: z, p in, p out: 3); a true-residual check 6 (+ the setup's
-// z, rho and p passes on a restart).
 template <bool rows>
 __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
   __shared__ CocgLds L;
   fill_sq<double>(L.sq);
   const int tid = threadIdx.x;
   const Fp64Slot s = fp64_slot(a.scratch + (size_t)blockIdx.x * a.slot_elems, a.ncap, 4);
-  c64* lds = reinterpret_cast<c64*>(vdc_tile_lds);
-  c64* r = s.V;
-  c64* p = s.V + a.ncap;
-  c64* q = s.V + 2 * a.ncap;
-  c64* z = s.V + 3 * a.ncap;
   for (;;) {
     __syncthreads();
     if (tid == 0) L.job = atomicAdd(a.counter, 1);
@@ -58,9 +30,6 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
     const DevTable tb = a.tabs[jb.table];
     const OpJob<double> op = make_op<double>(
         md, jb, a.tables + tb.offset + (size_t)(jb.parity * a.planes) * md.Nc);
-    const int Nc = md.Nc;
-    const bool blk = prec_has_factor(a.precond);
-    const SegFactor<double> fac{s.l1, s.l2, s.dinv};
     fp64_prepare<rows>(op, L.sq, s, a.precond);
     __syncthreads();
     if (tid == 0) {
@@ -69,146 +38,11 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
       for (int k = 0; k < n; ++k) s.b[e[k].g * md.Nu + e[k].u] = c64{e[k].val, 0.0};
     }
     __syncthreads();
-    double passes = blk ? 9.0 : 6.0;
-    const double bnorm = sqrt(norm_sq<double>(s.b, Nc, L.red));
-    for (int i = tid; i < Nc; i += kBlock) r[i] = s.b[i];
-    passes += 2.0;
-    // p = z = K^{-1} r and rho = <r|z>_S (own elements; block: after its
-    // own barrier)
-    auto restart_direction = [&]() -> c64 {
-      double acc[2] = {0.0, 0.0};
-      if (blk) {
-        prec_apply<rows, double>(fac, op.Ng, op.Nu, r, 1.0, p, false);
-        __syncthreads();
-        for (int i = tid; i < Nc; i += kBlock) {
-          const c64 t = r[i] * p[i];
-          acc[0] += t.x;
-          acc[1] += t.y;
-        }
-        passes += 7.0;
-      } else {
-        for (int i = tid; i < Nc; i += kBlock) {
-          const c64 zi = s.dinv[i] * r[i];
-          p[i] = zi;
-          const c64 t = r[i] * zi;
-          acc[0] += t.x;
-          acc[1] += t.y;
-        }
-        passes += 3.0;
-      }
-      block_sum<2, double>(acc, L.red, L.red + kWaves * 2);
-      const c64 rho = c64{L.red[kWaves * 2], L.red[kWaves * 2 + 1]};
-      __syncthreads();
-      return rho;
-    };
-    int iters = 0, restarts = 0, status = VDC_NOT_CONVERGED;
-    double beta_true = bnorm;
-    if (!(bnorm > 0.0) || !isfinite(bnorm)) {
-      status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
-      beta_true = 0.0;
-    } else {
-      c64 rho = restart_direction();
-      bool fresh = true;   // p was just reset from the true residual
-      for (;;) {
-        // q = A p and mu = <p|q>_S
-        double mu[2] = {0.0, 0.0};
-        if (a.tileT > 0) {
-          matvec_tiled<double>(op, L.sq, p, 1.0, nullptr, q, lds, a.tileT, nullptr, L.red, L.dot);
-          mu[0] = L.dot[0];
-          mu[1] = L.dot[1];
-        } else {
-          matvec_block<double>(op, L.sq, p, nullptr, s.wA, s.wB, q);
-          double acc[2] = {0.0, 0.0};
-          for (int i = tid; i < Nc; i += kBlock) {
-            const c64 t = p[i] * q[i];
-            acc[0] += t.x;
-            acc[1] += t.y;
-          }
-          block_sum<2, double>(acc, L.red, L.red + kWaves * 2);
-          mu[0] = L.red[kWaves * 2];
-          mu[1] = L.red[kWaves * 2 + 1];
-          __syncthreads();
-          passes += 2.0;
-        }
-        passes += 5.0;
-        const c64 muc = c64{mu[0], mu[1]};
-        const double mn = norm2(muc), rn = norm2(rho);
-        if (!(mn > 0.0) || !(rn > 0.0) || !isfinite(mn) || !isfinite(rn)) {
-          // breakdown of the bilinear form: restart from the true residual
-          // once; at once again, give up
-          if (fresh) {
-            status = (isfinite(mn) && isfinite(rn)) ? VDC_BREAKDOWN : VDC_NONFINITE;
-            break;
-          }
-          beta_true = sqrt(residual_A<double>(op, L.sq, s.x, s.b, r, lds, a.tileT, s.wA, s.wB, L.red));
-          passes += 6.0;
-          if (beta_true <= a.tol * bnorm) {
-            status = VDC_CONVERGED;
-            break;
-          }
-          rho = restart_direction();
-          ++restarts;
-          fresh = true;
-          continue;
-        }
-        const c64 alpha = cdiv(rho, muc);
-        // x += alpha p, r -= alpha q, ||r||^2 and rho' = <r|K^{-1} r>_S in one
-        // pass (block: by column blocks, z = K^{-1} r stored)
-        double acc[3] = {0.0, 0.0, 0.0};
-        if (blk) {
-          prec_cocg_step<rows, double>(fac, op.Ng, op.Nu, alpha, p, q, s.x, r, z, acc);
-        } else {
-          for (int i = tid; i < Nc; i += kBlock) {
-            s.x[i] = s.x[i] + alpha * p[i];
-            const c64 ri = r[i] - alpha * q[i];
-            r[i] = ri;
-            acc[0] += norm2(ri);
-            const c64 t = ri * (s.dinv[i] * ri);
-            acc[1] += t.x;
-            acc[2] += t.y;
-          }
-        }
-        block_sum<3, double>(acc, L.red, L.red + kWaves * 3);
-        const double rr = L.red[kWaves * 3];
-        const c64 rho_new = c64{L.red[kWaves * 3 + 1], L.red[kWaves * 3 + 2]};
-        __syncthreads();
-        passes += blk ? 10.0 : 7.0;
-        ++iters;
-        fresh = false;
-        if (!isfinite(rr)) {
-          status = VDC_NONFINITE;
-          break;
-        }
-        if (sqrt(rr) <= a.tol * bnorm || iters >= a.max_iter) {
-          // the true residual decides; restart from it if needed
-          beta_true = sqrt(residual_A<double>(op, L.sq, s.x, s.b, r, lds, a.tileT, s.wA, s.wB, L.red));
-          passes += 6.0;
-          if (beta_true <= a.tol * bnorm) {
-            status = VDC_CONVERGED;
-            break;
-          }
-          if (!isfinite(beta_true)) {
-            status = VDC_NONFINITE;
-            break;
-          }
-          if (iters >= a.max_iter) break;
-          rho = restart_direction();
-          ++restarts;
-          fresh = true;
-          continue;
-        }
-        const c64 beta = cdiv(rho_new, rho);
-        rho = rho_new;
-        for (int i = tid; i < Nc; i += kBlock) {
-          const c64 zi = blk ? z[i] : s.dinv[i] * r[i];
-          p[i] = zi + beta * p[i];
-        }
-        passes += blk ? 3.0 : 4.0;
-      }
-    }
+    const BlockSolve r = cocg_fp64_block<rows>(L.red, L.dot, L.sq, op, s, a.ncap, a.tol,
+                                               a.max_iter, a.tileT, a.precond);
     __syncthreads();
-    finish_job(a, md, jb, s.x, tid, status, iters, restarts, 0,
-               bnorm > 0.0 ? beta_true / bnorm : 0.0, passes * 16.0 * md.Nc);
+    finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
+               r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);
   }
 }
 

@@ -20,6 +20,7 @@ struct SolveArgs {
   int max_iter;
   double tol;
   int precond;
+  int method;               // VDC_GMRES or VDC_COCG (the adjoint's solve)
   int m_in;                 // FP32_INNER: inner restart length
   double tol_in;            // FP32_INNER: inner relative tolerance
   int n_final;

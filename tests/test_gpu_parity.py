@@ -360,6 +360,30 @@ def test_adjoint_gradient_matches_oracle(vdc, Ng, Nu, eps, precond):
         assert abs(g[k] - g_ref[k]) <= 1e-8 * scale, (name, g[k], g_ref[k])
 
 
+@pytest.mark.parametrize("precond", [1, 2, 3])
+def test_adjoint_by_cocg_matches_oracle(vdc, precond):
+    """The same gradient with COCG for both the forward and the transposed
+    solves (A^T = A), diagonal, column-block or row-block preconditioner."""
+    from oracle import adjoint as adj
+    Ng, Nu, eps = 20, 16, [0.83, 2.28]
+    p, finals, sig_t = _grad_case(Ng, Nu, eps)
+    L, g_ref, sig_ref = adj.loss_and_grad(p, Ng, Nu, eps, (0, 0), finals, sig_t)
+    model = vdc.Model2D(p, Ng, Nu)
+    jobs = [(e, (0, 0), mu) for e in eps for mu in (0, 1)]
+    s = vdc.Solver(model, jobs, finals,
+                   vdc.Opts(tol=1e-12, precond=precond, method=vdc.COCG, max_iter=5000),
+                   want_psi=True).run()
+    sig = s.sigma.cpu().numpy().reshape(len(eps), 2, len(finals)).sum(axis=1)
+    assert np.allclose(sig, sig_ref, rtol=1e-9, atol=0)
+    import torch
+    dsig_jobs = torch.tensor(np.repeat(2.0 * (sig - sig_t), 2, axis=0))
+    g, _ = s.adjoint(dsig_jobs)
+    assert all(i.status == 0 for i in s.adj_info[:s.n_jobs])
+    scale = np.max(np.abs(g_ref))
+    for k, name in enumerate(vdc.PARAM_NAMES):
+        assert abs(g[k] - g_ref[k]) <= 1e-8 * scale, (name, g[k], g_ref[k])
+
+
 def test_autograd_function_dense_lu_reference(vdc):
     """The torch.autograd.Function on a 30 x 30 basis against the oracle's
     dense-LU gradient of the same loss."""
