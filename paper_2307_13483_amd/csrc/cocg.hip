@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
 // r out: p64 6), its cast (p64 1, p32 1), the inner start (r, dinv in, p
 // out: p32 3; block: p32 7) and x += ||r|| d (p64 2, p32 1); per inner step
 // the operator (p32 5), the update of d and r with rho' (diagonal: d, p, r,
-// q, dinv in, d, r out: p32 7; block, by column blocks with z = K^{-1} r:
+// q, dinv in, d, r out: p32 7; block, by column blocks (or rows) with z = K^{-1} r:
 // the same and 3 factor planes in, z out: p32 10) and the next direction
 // (diagonal: r, dinv, p in, p out: p32 4; block: z, p in, p out: p32 3).
 struct CocgMixedLds {
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
           }
           const c32 alpha = cinv<float>(mu) * rho;
           // d += alpha p, r -= alpha q, ||r||^2 and rho' = <r|K^{-1} r>_S in
-          // one pass (block: by column blocks, z = K^{-1} r stored)
+          // one pass (block: by column blocks or rows, z = K^{-1} r stored)
           float acc[3] = {0.f, 0.f, 0.f};
           if (blk) {
             prec_cocg_step<rows, float>(fac, op.Ng, op.Nu, alpha, p, q, d, r, z, acc);

@@ -25,7 +25,7 @@ namespace vdc {
 // 3; block: r and 3 factor planes in, p out, then r, p for rho: 7);
 // iteration: the operator (p and 3 table planes in, q out: 5, <p|q>_S from
 // the staged p), the update of x and r with rho' (x, p, r, q in, x, r out,
-// and dinv in: 7; block, by column blocks with z = K^{-1} r: 3 factor planes
+// and dinv in: 7; block, by column blocks (or rows) with z = K^{-1} r: 3 factor planes
 // in and z out as well: 10), the next direction (diagonal: r, dinv, p in, p
 // out: 4; block: z, p in, p out: 3); a true-residual check 6 (+ the setup's
 // z, rho and p passes on a restart).
@@ -133,7 +133,7 @@ __device__ inline BlockSolve cocg_fp64_block(double* red, double* dot, const dou
       }
       const c64 alpha = cdiv(rho, muc);
       // x += alpha p, r -= alpha q, ||r||^2 and rho' = <r|K^{-1} r>_S in one
-      // pass (block: by column blocks, z = K^{-1} r stored)
+      // pass (block: by column blocks or rows, z = K^{-1} r stored)
       double acc[3] = {0.0, 0.0, 0.0};
       if (blk) {
         prec_cocg_step<rows, double>(fac, op.Ng, op.Nu, alpha, p, q, s.x, r, z, acc);

@@ -4,7 +4,7 @@
 // Each workgroup pops jobs from a device counter (the host orders the job
 // array longest-first), then for its job:
 //   1. the preconditioner (Sec. III.B: 1/diag(A), or the LDL^T factors of the
-//      column blocks of segprec.h) and the right-hand side Phi^{v_i mu_i}
+//      column or row blocks of segprec.h) and the right-hand side Phi^{v_i mu_i}
 //      (Eq. (25)) in the job's symmetry block;
 //   2. restarted GMRES(m) with right preconditioning (krylov.h), then
 //      x += M^{-1} V y and the FP64 true residual b - A x, which decides

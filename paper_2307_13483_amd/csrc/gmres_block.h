@@ -1,6 +1,6 @@
 // Restarted GMRES(m) in complex FP64 on one symmetry block, run by a whole
 // workgroup (Sec. III.A, right preconditioning of Sec. III.B by the diagonal
-// of A or by its column blocks, segprec.h): cycles of krylov_cycle,
+// of A or by its column or row blocks, segprec.h): cycles of krylov_cycle,
 // x += M^{-1} V y, and the FP64 true residual b - A x deciding convergence
 // (the stopping rule of Sec. III).  Shared by the forward solver and the
 // adjoint (transposed) solve: A^T = A, and M^T = M for both preconditioners.

@@ -2,7 +2,7 @@
 // variable right preconditioner is one cycle of GMRES run entirely in complex
 // FP32 (inner: FP32 basis, FP32 level-shift tables, FP32 stencil, FP32 dot
 // products accumulated in FP32, FP32 preconditioner: the diagonal or the
-// column-block factors of segprec.h).  The outer level keeps
+// column- or row-block factors of segprec.h).  The outer level keeps
 // everything that decides the answer in FP64: the operator applied to the
 // inner results, its Gram-Schmidt, the Hessenberg least squares by Givens, the
 // solution update, the true residual b - A x and the amplitudes.  Because

@@ -1,8 +1,9 @@
-// Block-diagonal preconditioner built from sections of A (Sec. III.B): the
-// blocks hold the points of one n_u column and kSegRows consecutive n_g, in
-// the job's symmetry block.  With the segment as long as the column this is
-// the paper's M^u; the segmentation keeps every block small enough for one
-// thread's registers.
+// Block-diagonal preconditioners built from sections of A (Sec. III.B), in
+// the job's symmetry block.  Column blocks (VDC_PREC_BLOCK): the points of
+// one n_u column and kSegRows consecutive n_g; with the segment as long as
+// the column this is the paper's M^u, and the segmentation keeps every block
+// small enough for one thread's registers.  Row blocks (VDC_PREC_ROWS, the
+// second half of this file): the whole n_u row of one n_g, the paper's M^g.
 //
 // Band of A inside a column (one active state a along it, op2d.h): the
 // direct terms give -k_a q_g, and the sandwich (1 + lam_a q_g) F_AA
@@ -282,8 +283,9 @@ __device__ inline void row_factor(const OpJob<double>& op, const double* sq,
 // With dot, acc[0] + i acc[1] += sum_u y_u^2 / D_u = v^T M^{-1} v (vscale
 // 1), formed in the backward sweep from the values it loads anyway.
 // Every row has the same length, so the loops run in step across a
-// wavefront; the loads of kRowChunk points are issued together, so a sweep
-// waits for memory once per chunk rather than once per point.
+// wavefront; the loads of RowChunk<R>::K points (4 in FP64, 8 in FP32) are
+// issued together, so a sweep waits for memory once per chunk rather than
+// once per point.
 template <typename R>
 struct RowChunk { static constexpr int K = 4; };
 template <>
