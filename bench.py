@@ -482,7 +482,7 @@ def main():
         print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "repeats": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (jobs would be sharded across GPUs by estimated cost); --gpus must be 1"}))
         sys.exit(2)
     if args.matvec_probe > 0:
         import torch

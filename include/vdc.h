@@ -42,7 +42,7 @@ typedef enum {
   VDC_ERR_INVALID_ARG = 1,   /* a size, pointer or parameter is out of range   */
   VDC_ERR_WORKSPACE = 2,     /* workspace smaller than vdc_workspace_size()     */
   VDC_ERR_HIP = 3,           /* a HIP runtime call failed                       */
-  VDC_ERR_UNSUPPORTED = 4    /* a valid request this build does not implement   */
+  VDC_ERR_UNSUPPORTED = 4    /* a valid request the library does not implement */
 } vdc_status;
 
 typedef enum {
