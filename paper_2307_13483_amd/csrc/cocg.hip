@@ -91,8 +91,8 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
   c32* r = reinterpret_cast<c32*>(wB + ld);   // FP32
   c32* p = r + ld;
   c32* q = p + ld;
-  c32* z = q + ld;
-  c32* d = z + ld;
+  c32* z = q;                         // K^{-1} r over q, which the update has consumed
+  c32* d = q + ld;
   c32* dinv = d + ld;
   c32* l1 = dinv + ld;
   c32* l2 = l1 + ld;
@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
           const float rr = L.redf[3 * kWaves];
           const c32 rho_new = c32{L.redf[3 * kWaves + 1], L.redf[3 * kWaves + 2]};
           __syncthreads();
-          p32 += blk ? 10.0 : 7.0;
+          p32 += blk ? (rows ? 15.0 : 11.0) : 7.0;
           ++k;
           ++iters;
           if (rr <= (float)(a.tol_in * a.tol_in) || k >= a.m_in || iters >= a.max_iter ||
@@ -238,7 +238,18 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
             break;
           const c32 bt = cinv<float>(rho) * rho_new;
           rho = rho_new;
-          for (int i = tid; i < Nc; i += kBlock) p[i] = (blk ? z[i] : dinv[i] * r[i]) + bt * p[i];
+          for (int i0 = tid; i0 < Nc; i0 += kBatch * kBlock) {
+            c32 zv[kBatch], pv[kBatch];
+#pragma unroll
+            for (int e = 0; e < kBatch; ++e) {
+              const int i = min(i0 + e * kBlock, Nc - 1);
+              zv[e] = blk ? z[i] : dinv[i] * r[i];
+              pv[e] = p[i];
+            }
+#pragma unroll
+            for (int e = 0; e < kBatch; ++e)
+              if (i0 + e * kBlock < Nc) p[i0 + e * kBlock] = zv[e] + bt * pv[e];
+          }
           p32 += blk ? 3.0 : 4.0;
         }
         if (bad) {

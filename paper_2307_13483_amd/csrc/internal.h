@@ -12,6 +12,9 @@ namespace vdc {
 constexpr double kHartreeEV = 27.211386245988;
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kBlock = 1024;      // threads per workgroup of the persistent solver
+// elements per thread whose loads a streaming loop issues together before it
+// stores any: one wait for memory per batch instead of one per element
+constexpr int kBatch = 4;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxRestart = 128;
 // Slot vectors of length ncap besides the basis: FP64 solver (x, b, dinv, w,

@@ -157,15 +157,16 @@ __device__ inline void seg_apply(const SegFactor<R>& f, int Ng, int Nu,
 // acc[1] + i acc[2] += <r|z>_S (no conjugate) over the thread's blocks.
 // Begins with a barrier (p, q may have just been written by other threads);
 // x, r and z are then owned by blocks, so a barrier must precede element
-// ownership again.
+// ownership again.  z may be q: a block reads all of its q before it writes
+// any of its z, and no block reads another block's q.
 template <typename R>
 __device__ inline void seg_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
                                      typename CT<R>::C alpha,
                                      const typename CT<R>::C* __restrict__ p,
-                                     const typename CT<R>::C* __restrict__ q,
+                                     const typename CT<R>::C* q,
                                      typename CT<R>::C* __restrict__ x,
                                      typename CT<R>::C* __restrict__ r,
-                                     typename CT<R>::C* __restrict__ z, R* acc) {
+                                     typename CT<R>::C* z, R* acc) {
   using C = typename CT<R>::C;
   __syncthreads();
   const int nb = seg_blocks(Ng, Nu);
@@ -205,6 +206,85 @@ __device__ inline void seg_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
   }
 }
 
+
+// The same step split in two (the FP32 solvers' form): x += alpha p,
+// r -= alpha q and acc[0] += ||r||^2 element by element over all threads
+// (kBatch elements per thread in flight; elements past the end re-load the
+// last one and store nothing), a barrier, then block by block z = M^{-1} r with acc[1] + i acc[2] +=
+// <r|z>_S.  A block's r and factor entries are all loaded before its
+// recurrences start (rows past a short block's end re-load its last row and
+// are not used), so a thread waits for memory once per block instead of once
+// per row; the update pass keeps every wavefront's loads independent.  r is
+// read once more than in the fused form.  Begins with a barrier; z may be q.
+template <typename R>
+__device__ inline void seg_cocg_step_split(const SegFactor<R>& f, int Ng, int Nu,
+                                           typename CT<R>::C alpha,
+                                           const typename CT<R>::C* __restrict__ p,
+                                           const typename CT<R>::C* q,
+                                           typename CT<R>::C* __restrict__ x,
+                                           typename CT<R>::C* __restrict__ r,
+                                           typename CT<R>::C* z, R* acc) {
+  using C = typename CT<R>::C;
+  __syncthreads();
+  const int Nc = Ng * Nu;
+  // kBatch elements per thread at a time, all loads before any store
+  for (int i0 = threadIdx.x; i0 < Nc; i0 += kBatch * kBlock) {
+    C xv[kBatch], pv[kBatch], rv[kBatch], qv[kBatch];
+#pragma unroll
+    for (int e = 0; e < kBatch; ++e) {
+      const int i = min(i0 + e * kBlock, Nc - 1);
+      xv[e] = x[i];
+      pv[e] = p[i];
+      rv[e] = r[i];
+      qv[e] = q[i];
+    }
+#pragma unroll
+    for (int e = 0; e < kBatch; ++e) {
+      const int i = i0 + e * kBlock;
+      if (i < Nc) {
+        x[i] = xv[e] + alpha * pv[e];
+        const C ri = rv[e] - alpha * qv[e];
+        r[i] = ri;
+        acc[0] += norm2(ri);
+      }
+    }
+  }
+  __syncthreads();
+  const int nb = seg_blocks(Ng, Nu);
+  for (int c = threadIdx.x; c < nb; c += kBlock) {
+    const int u = c % Nu, g0 = (c / Nu) * kSegRows, L = min(kSegRows, Ng - g0);
+    C rv[kSegRows], a1[kSegRows], a2[kSegRows], di[kSegRows];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k) {
+      const int i = (g0 + min(k, L - 1)) * Nu + u;
+      rv[k] = r[i];
+      a1[k] = f.l1[i];
+      a2[k] = f.l2[i];
+      di[k] = f.dinv[i];
+    }
+    C y[kSegRows];
+#pragma unroll
+    for (int k = 0; k < kSegRows; ++k) {
+      C t = rv[k];
+      if (k >= 1) t = t - a1[k - 1] * y[k - 1];
+      if (k >= 2) t = t - a2[k - 2] * y[k - 2];
+      y[k] = t;
+    }
+#pragma unroll
+    for (int k = kSegRows - 1; k >= 0; --k) {
+      if (k < L) {
+        C t = di[k] * y[k];
+        if (k + 1 < L) t = t - a1[k] * y[k + 1];
+        if (k + 2 < L) t = t - a2[k] * y[k + 2];
+        y[k] = t;
+        z[(g0 + k) * Nu + u] = t;
+        const C rz = rv[k] * t;
+        acc[1] += rz.x;
+        acc[2] += rz.y;
+      }
+    }
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Row blocks: the paper's M^g (Sec. III.B), one block per n_g holding its
@@ -377,15 +457,16 @@ __device__ inline void row_apply(const SegFactor<R>& f, int Ng, int Nu,
 // element by element over all threads, a barrier, then z = M^{-1} r row by
 // row with acc[1] + i acc[2] += <r|z>_S = r^T (L D L^T)^{-1} r, summed as
 // y^T D^{-1} y with y = L^{-1} r.  Begins with a barrier; x and r are read
-// once more by the rows than in the fused column version.
+// once more by the rows than in the fused column version.  z may be q (q is
+// read only before the barrier).
 template <typename R>
 __device__ inline void row_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
                                      typename CT<R>::C alpha,
                                      const typename CT<R>::C* __restrict__ p,
-                                     const typename CT<R>::C* __restrict__ q,
+                                     const typename CT<R>::C* q,
                                      typename CT<R>::C* __restrict__ x,
                                      typename CT<R>::C* __restrict__ r,
-                                     typename CT<R>::C* __restrict__ z, R* acc) {
+                                     typename CT<R>::C* z, R* acc) {
   using C = typename CT<R>::C;
   __syncthreads();
   const int Nc = Ng * Nu;
@@ -429,11 +510,12 @@ template <bool rows, typename R>
 __device__ inline void prec_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
                                       typename CT<R>::C alpha,
                                       const typename CT<R>::C* __restrict__ p,
-                                      const typename CT<R>::C* __restrict__ q,
+                                      const typename CT<R>::C* q,
                                       typename CT<R>::C* __restrict__ x,
                                       typename CT<R>::C* __restrict__ r,
-                                      typename CT<R>::C* __restrict__ z, R* acc) {
+                                      typename CT<R>::C* z, R* acc) {
   if constexpr (rows) row_cocg_step<R>(f, Ng, Nu, alpha, p, q, x, r, z, acc);
+  else if constexpr (sizeof(R) == 4) seg_cocg_step_split<R>(f, Ng, Nu, alpha, p, q, x, r, z, acc);
   else seg_cocg_step<R>(f, Ng, Nu, alpha, p, q, x, r, z, acc);
 }
 
