@@ -61,9 +61,12 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
 // r out: p64 6), its cast (p64 1, p32 1), the inner start (r, dinv in, p
 // out: p32 3; block: p32 7) and x += ||r|| d (p64 2, p32 1); per inner step
 // the operator (p32 5), the update of d and r with rho' (diagonal: d, p, r,
-// q, dinv in, d, r out: p32 7; block, by column blocks (or rows) with z = K^{-1} r:
-// the same and 3 factor planes in, z out: p32 10) and the next direction
-// (diagonal: r, dinv, p in, p out: p32 4; block: z, p in, p out: p32 3).
+// q, dinv in, d, r out: p32 7; column blocks: d, p, r, q in, d, r out, then
+// the sweeps with r and 3 factor planes in, z out: p32 11; rows: the same
+// update, then the forward sweeps (r, 2 factor planes in, L^{-1} r parked in
+// z) and the backward sweeps (z, 3 factor planes in, z out): p32 15) and the
+// next direction (diagonal: r, dinv, p in, p out: p32 4; block: z, p in, p
+// out: p32 3).
 struct CocgMixedLds {
   double red[kRedSize];
   float redf[kRedSize];

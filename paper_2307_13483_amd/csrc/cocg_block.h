@@ -25,8 +25,10 @@ namespace vdc {
 // 3; block: r and 3 factor planes in, p out, then r, p for rho: 7);
 // iteration: the operator (p and 3 table planes in, q out: 5, <p|q>_S from
 // the staged p), the update of x and r with rho' (x, p, r, q in, x, r out,
-// and dinv in: 7; block, by column blocks (or rows) with z = K^{-1} r: 3 factor planes
-// in and z out as well: 10), the next direction (diagonal: r, dinv, p in, p
+// and dinv in: 7; column blocks, fused with z = K^{-1} r: 3 factor planes
+// in and z out as well: 10; rows: the update element by element, then the
+// row sweeps (r and 2 factor planes in, L^{-1} r parked in z; z and 3 factor
+// planes in, z out): 15), the next direction (diagonal: r, dinv, p in, p
 // out: 4; block: z, p in, p out: 3); a true-residual check 6 (+ the setup's
 // z, rho and p passes on a restart).
 //
@@ -152,7 +154,7 @@ __device__ inline BlockSolve cocg_fp64_block(double* red, double* dot, const dou
       const double rr = red[kWaves * 3];
       const c64 rho_new = c64{red[kWaves * 3 + 1], red[kWaves * 3 + 2]};
       __syncthreads();
-      passes += blk ? 10.0 : 7.0;
+      passes += blk ? (rows ? 15.0 : 10.0) : 7.0;
       ++iters;
       fresh = false;
       if (!isfinite(rr)) {
