@@ -197,9 +197,6 @@ __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* 
                                    c64* y, c64* wA, c64* wB, const c64* bsub = nullptr,
                                    double* red = nullptr, double* bdot = nullptr);
 
-// Complex FP16 (the stored multipliers of the block factor).
-struct c16 { _Float16 x, y; };
-
 // One job's block factor storage in bytes, for planes of n points and W1 =
 // 2 Ny + 1: L by columns (F) and by rows (G), complex FP16 [planes][n][W1];
 // 1/D, complex FP32 [planes][n]; the band staging of the factor kernel,

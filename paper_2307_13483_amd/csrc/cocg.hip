@@ -56,17 +56,20 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
 // refinement steps.
 //
 // Byte model (p64: passes of complex FP64, p32 of complex FP32): setup as the
-// FP64 COCG's preconditioner (p64 5, block: p64 1 and p32 3 for the FP32
-// factors) plus x, b; per outer step the residual (x, 3 table planes, b in,
-// r out: p64 6), its cast (p64 1, p32 1), the inner start (r, dinv in, p
-// out: p32 3; block: p32 7) and x += ||r|| d (p64 2, p32 1); per inner step
-// the operator (p32 5), the update of d and r with rho' (diagonal: d, p, r,
-// q, dinv in, d, r out: p32 7; column blocks: d, p, r, q in, d, r out, then
-// the sweeps with r and 3 factor planes in, z out: p32 11; rows: the same
-// update, then the forward sweeps (r, 2 factor planes in, L^{-1} r parked in
-// z) and the backward sweeps (z, 3 factor planes in, z out): p32 15) and the
-// next direction (diagonal: r, dinv, p in, p out: p32 4; block: z, p in, p
-// out: p32 3).
+// FP64 COCG's preconditioner (p64 5, block: p64 1 and p32 2 for the FP32
+// factors: 1/D, and the two FP16 multiplier planes, each half a p32) plus
+// x, b; per outer step the residual (x, 3 table planes, b in, r out: p64 6),
+// its cast (p64 1, p32 1), the inner start (r, dinv in, p out, then r, p for
+// rho: p32 3; column blocks: r and the factor in, p out, r and p: 6; rows:
+// the forward sweeps parking L^{-1} r in p and the backward sweeps, then r
+// and p: 9) and x += ||r|| d (p64 2, p32 1); per inner step the operator
+// (p32 5), the update of d and r with rho' (diagonal: d, p, r, q, dinv in, d,
+// r out: p32 7; column blocks: d, p, r, q in, d, r out, then the sweeps with
+// r and the factor (2) in, z out: p32 10; rows: the same update, then the
+// forward sweeps (r and the multipliers in, L^{-1} r parked in z: 3) and the
+// backward sweeps (z and the factor in, z out: 4): p32 13) and the next
+// direction (diagonal: r, dinv, p in, p out: p32 4; block: z, p in, p out:
+// p32 3).
 struct CocgMixedLds {
   double red[kRedSize];
   float redf[kRedSize];
@@ -97,9 +100,9 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
   c32* z = q;                         // K^{-1} r over q, which the update has consumed
   c32* d = q + ld;
   c32* dinv = d + ld;
-  c32* l1 = dinv + ld;
-  c32* l2 = l1 + ld;
-  c32* wA32 = l2 + ld;
+  c16* l1 = reinterpret_cast<c16*>(dinv + ld);   // FP16 multipliers: both in one plane
+  c16* l2 = l1 + ld;
+  c32* wA32 = dinv + 2 * ld;
   c32* wB32 = wA32 + ld;
   const bool blk = prec_has_factor(a.precond);
   const SegFactor<float> fac{l1, l2, dinv};
@@ -133,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
       for (int k = 0; k < n; ++k) b[e[k].g * md.Nu + e[k].u] = c64{e[k].val, 0.0};
     }
     __syncthreads();
-    double p64 = blk ? 6.0 : 7.0, p32 = blk ? 3.0 : 1.0;
+    double p64 = blk ? 6.0 : 7.0, p32 = blk ? 2.0 : 1.0;
     const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
     p64 += 1.0;
     int iters = 0, outer = 0, status = VDC_NOT_CONVERGED;
@@ -185,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
         // inner COCG on A d = r (unit norm) in FP32
         kinv(r, p);
         c32 rho = bilin(r, p);
-        p32 += blk ? 7.0 : 3.0;
+        p32 += blk ? (rows ? 9.0 : 6.0) : 3.0;
         int k = 0;
         bool bad = false;
         for (;;) {
@@ -233,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
           const float rr = L.redf[3 * kWaves];
           const c32 rho_new = c32{L.redf[3 * kWaves + 1], L.redf[3 * kWaves + 2]};
           __syncthreads();
-          p32 += blk ? (rows ? 15.0 : 11.0) : 7.0;
+          p32 += blk ? (rows ? 13.0 : 10.0) : 7.0;
           ++k;
           ++iters;
           if (rr <= (float)(a.tol_in * a.tol_in) || k >= a.m_in || iters >= a.max_iter ||

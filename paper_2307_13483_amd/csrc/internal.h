@@ -51,6 +51,9 @@ __host__ __device__ constexpr int fidx(int mu, int pair) { return 3 * mu + pair;
 
 // Model parameters in the form the kernels read them (plain values + device
 // pointers to the transform data owned by the model).
+// Complex FP16: stored multipliers of the block factors.
+struct c16 { _Float16 x, y; };
+
 struct DevModel {
   int Ng, Nu, Nc;        // Nc = Ng*Nu unknowns per symmetry block
   int K;                 // transform nodes

@@ -56,9 +56,9 @@ fgmres_mixed_kernel(SolveArgs a) {
   c32* w32 = dinv + ld;
   c32* wA32 = w32 + ld;
   c32* wB32 = wA32 + ld;
-  c32* l1 = wB32 + ld;                           // block factors (segprec.h)
-  c32* l2 = l1 + ld;
-  c32* zt = l2 + ld;                             // M^{-1} of the inner vector in work
+  c16* l1 = reinterpret_cast<c16*>(wB32 + ld);  // block multipliers (segprec.h), FP16:
+  c16* l2 = l1 + ld;                             //   both in one plane
+  c32* zt = wB32 + 2 * ld;                             // M^{-1} of the inner vector in work
   (void)w;
   (void)w32;
   const bool blk = prec_has_factor(a.precond);
@@ -107,13 +107,13 @@ fgmres_mixed_kernel(SolveArgs a) {
     //     cycle of k steps (cycle_passes(k) p32), z_j = dinv V y (k + 1 p32,
     //     1 p64)
     //   outer cycle of k_o steps: x += Z y (k_o + 2 p64), residual (6 p64)
-    // The block preconditioner adds: setup one more FP64 table plane and two
-    // more FP32 planes written (p64 1, p32 2); every inner step M^{-1} (vector
-    // and three factor planes read, zt written) before an operator that reads
-    // zt but no dinv (p32 4); z_j: the sum written to zt, M^{-1} in place
-    // (zt and three factor planes read, zt written), zt read for the
-    // widening (p32 7 instead of 1).
-    double p64 = blk ? 8.0 : 7.0, p32 = blk ? 3.0 : 1.0;
+    // The block preconditioner adds: setup one more FP64 table plane and the
+    // two FP16 multiplier planes written (p64 1, p32 1); every inner step
+    // M^{-1} (vector, 1/D and the multipliers read: 2, zt written) before an
+    // operator that reads zt but no dinv (p32 3); z_j: the sum written to
+    // zt, M^{-1} in place (zt and the factor read, zt written), zt read for
+    // the widening (p32 6 instead of 1).
+    double p64 = blk ? 8.0 : 7.0, p32 = blk ? 2.0 : 1.0;
     if (!(bnorm > 0.0) || !isfinite(bnorm)) {
       status = isfinite(bnorm) ? VDC_CONVERGED : VDC_NONFINITE;
       beta = 0.0;
@@ -183,7 +183,7 @@ fgmres_mixed_kernel(SolveArgs a) {
             for (int i = tid; i < Nc; i += kBlock) z[i] = c64{(double)zt[i].x, (double)zt[i].y};
           }
           p32 += cycle_passes(ci.k, ci.reorth_passes) + ci.k + 1.0 +
-                 (blk ? 4.0 * ci.k + 6.0 : 0.0);
+                 (blk ? 3.0 * ci.k + 5.0 : 0.0);
         } else {
           for (int i = tid; i < Nc; i += kBlock) z[i] = c64{0.0, 0.0};
         }

@@ -14,8 +14,8 @@
 //   A(g, g + 1) = -k_a q(g+1) - lam_a q(g+1) (F_AA(g) + F_AA(g+1)),
 //   A(g, g + 2) = -lam_a^2 q(g+1) q(g+2) F_AA(g+1).
 // A block is complex symmetric (A^T = A), factored as L D L^T without
-// pivoting; a block whose pivot falls below 1e-12 of its diagonal entry is
-// replaced by its diagonal.
+// pivoting; a block whose pivot falls below 1e-12 of its diagonal entry, or
+// whose multipliers do not fit their storage, is replaced by its diagonal.
 #pragma once
 #include "op2d.h"
 
@@ -23,11 +23,40 @@ namespace vdc {
 
 constexpr int kSegRows = 8;
 
+// Storage of the multipliers: complex FP64 for the FP64 solvers, complex
+// FP16 for the FP32 ones (halves the bytes and registers of their sweeps;
+// the stored values define the preconditioner exactly, so it stays
+// symmetric).  D^{-1} keeps the solver's precision.
+template <typename R> struct FacT { using S = typename CT<R>::C; };
+template <> struct FacT<float> { using S = c16; };
+
+template <typename R>
+__device__ inline typename CT<R>::C lw(typename CT<R>::C a) { return a; }
+template <typename R>
+__device__ inline typename CT<R>::C lw(c16 a) {
+  return typename CT<R>::C{R((float)a.x), R((float)a.y)};
+}
+template <typename R>
+__device__ inline typename FacT<R>::S lnarrow(c64 a) {
+  if constexpr (sizeof(typename FacT<R>::S) == sizeof(c16))
+    return c16{(_Float16)(float)a.x, (_Float16)(float)a.y};
+  else
+    return cfrom<R>(a);
+}
+// Whether a multiplier is representable in the storage: FP16 ends at 65504.
+template <typename R>
+__device__ inline bool lfits(c64 a) {
+  if constexpr (sizeof(typename FacT<R>::S) == sizeof(c16))
+    return fabs(a.x) < 6.0e4 && fabs(a.y) < 6.0e4;
+  else
+    return true;
+}
+
 // L and D^{-1} of every block, one entry per point (block layout).
 template <typename R>
 struct SegFactor {
-  typename CT<R>::C* l1;     // L(g + 1, g) inside the block (0 at its last row)
-  typename CT<R>::C* l2;     // L(g + 2, g)
+  typename FacT<R>::S* l1;   // L(g + 1, g) inside the block (0 at its last row)
+  typename FacT<R>::S* l2;   // L(g + 2, g)
   typename CT<R>::C* dinv;   // 1 / D(g)
 };
 
@@ -78,6 +107,7 @@ __device__ inline void seg_factor_block(const OpJob<double>& op, const double* s
         l1[k] = t * di;
       }
       if (k + 2 < L) l2[k] = col_off2(op, sq, g, u, a) * di;
+      ok = ok && lfits<R>(l1[k]) && lfits<R>(l2[k]);
     }
   }
 #pragma unroll
@@ -85,12 +115,12 @@ __device__ inline void seg_factor_block(const OpJob<double>& op, const double* s
     if (k < L) {
       const int i = (g0 + k) * Nu + u;
       if (ok) {
-        f.l1[i] = narrow<R>(l1[k]);
-        f.l2[i] = narrow<R>(l2[k]);
+        f.l1[i] = lnarrow<R>(l1[k]);
+        f.l2[i] = lnarrow<R>(l2[k]);
         f.dinv[i] = narrow<R>(cinv<double>(D[k]));
       } else {
-        f.l1[i] = cz<R>();
-        f.l2[i] = cz<R>();
+        f.l1[i] = lnarrow<R>(c64{0.0, 0.0});
+        f.l2[i] = lnarrow<R>(c64{0.0, 0.0});
         f.dinv[i] = narrow<R>(cinv<double>(op_diag<double>(op, i)));
       }
     }
@@ -121,8 +151,8 @@ __device__ inline void seg_apply_block(const SegFactor<R>& f, int Ng, int Nu,
     if (k < L) {
       const int i = (g0 + k) * Nu + u;
       C t = vscale * v[i];
-      if (k >= 1) t = t - f.l1[i - Nu] * y[k - 1];
-      if (k >= 2) t = t - f.l2[i - 2 * Nu] * y[k - 2];
+      if (k >= 1) t = t - lw<R>(f.l1[i - Nu]) * y[k - 1];
+      if (k >= 2) t = t - lw<R>(f.l2[i - 2 * Nu]) * y[k - 2];
       y[k] = t;
     }
   }
@@ -131,8 +161,8 @@ __device__ inline void seg_apply_block(const SegFactor<R>& f, int Ng, int Nu,
     if (k < L) {
       const int i = (g0 + k) * Nu + u;
       C t = f.dinv[i] * y[k];
-      if (k + 1 < L) t = t - f.l1[i] * y[k + 1];
-      if (k + 2 < L) t = t - f.l2[i] * y[k + 2];
+      if (k + 1 < L) t = t - lw<R>(f.l1[i]) * y[k + 1];
+      if (k + 2 < L) t = t - lw<R>(f.l2[i]) * y[k + 2];
       y[k] = t;
       z[i] = accumulate ? z[i] + t : t;
     }
@@ -184,8 +214,8 @@ __device__ inline void seg_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
         rv[k] = ri;
         acc[0] += norm2(ri);
         C t = ri;
-        if (k >= 1) t = t - f.l1[i - Nu] * y[k - 1];
-        if (k >= 2) t = t - f.l2[i - 2 * Nu] * y[k - 2];
+        if (k >= 1) t = t - lw<R>(f.l1[i - Nu]) * y[k - 1];
+        if (k >= 2) t = t - lw<R>(f.l2[i - 2 * Nu]) * y[k - 2];
         y[k] = t;
       }
     }
@@ -194,8 +224,8 @@ __device__ inline void seg_cocg_step(const SegFactor<R>& f, int Ng, int Nu,
       if (k < L) {
         const int i = (g0 + k) * Nu + u;
         C t = f.dinv[i] * y[k];
-        if (k + 1 < L) t = t - f.l1[i] * y[k + 1];
-        if (k + 2 < L) t = t - f.l2[i] * y[k + 2];
+        if (k + 1 < L) t = t - lw<R>(f.l1[i]) * y[k + 1];
+        if (k + 2 < L) t = t - lw<R>(f.l2[i]) * y[k + 2];
         y[k] = t;
         z[i] = t;
         const C rz = rv[k] * t;
@@ -258,8 +288,8 @@ __device__ inline void seg_cocg_step_split(const SegFactor<R>& f, int Ng, int Nu
     for (int k = 0; k < kSegRows; ++k) {
       const int i = (g0 + min(k, L - 1)) * Nu + u;
       rv[k] = r[i];
-      a1[k] = f.l1[i];
-      a2[k] = f.l2[i];
+      a1[k] = lw<R>(f.l1[i]);
+      a2[k] = lw<R>(f.l2[i]);
       di[k] = f.dinv[i];
     }
     C y[kSegRows];
@@ -330,8 +360,9 @@ __device__ inline void row_factor_row(const OpJob<double>& op, const double* sq,
     c64 l1{0.0, 0.0}, l2{0.0, 0.0};
     if (u + 1 < Nu) l1 = (row_off1(op, sq, i, u) - (l2m1 * l1m1) * Dm1) * di;
     if (u + 2 < Nu) l2 = row_off2(op, sq, i, u) * di;
-    f.l1[i] = narrow<R>(l1);
-    f.l2[i] = narrow<R>(l2);
+    ok = ok && lfits<R>(l1) && lfits<R>(l2);
+    f.l1[i] = lnarrow<R>(l1);
+    f.l2[i] = lnarrow<R>(l2);
     f.dinv[i] = narrow<R>(di);
     Dm2 = Dm1;
     Dm1 = d;
@@ -342,8 +373,8 @@ __device__ inline void row_factor_row(const OpJob<double>& op, const double* sq,
   if (!ok) {
     for (int u = 0; u < Nu; ++u) {
       const int i = base + u;
-      f.l1[i] = cz<R>();
-      f.l2[i] = cz<R>();
+      f.l1[i] = lnarrow<R>(c64{0.0, 0.0});
+      f.l2[i] = lnarrow<R>(c64{0.0, 0.0});
       f.dinv[i] = narrow<R>(cinv<double>(op_diag<double>(op, i)));
     }
   }
@@ -386,8 +417,8 @@ __device__ inline void row_sweep(const SegFactor<R>& f, int Nu, const typename C
     for (int k = 0; k < K; ++k) {
       const int i = min(base + u0 + k, last);
       vv[k] = v[i];
-      a1[k] = f.l1[max(i - 1, base)];
-      a2[k] = f.l2[max(i - 2, base)];
+      a1[k] = lw<R>(f.l1[max(i - 1, base)]);
+      a2[k] = lw<R>(f.l2[max(i - 2, base)]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -410,8 +441,8 @@ __device__ inline void row_sweep(const SegFactor<R>& f, int Nu, const typename C
       const int i = max(base + u0 - k, base);
       yy[k] = park[i];
       dd[k] = f.dinv[i];
-      a1[k] = f.l1[i];
-      a2[k] = f.l2[i];
+      a1[k] = lw<R>(f.l1[i]);
+      a2[k] = lw<R>(f.l2[i]);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
