@@ -93,7 +93,10 @@ typedef struct {
  * n_g (the paper's M^u cut into segments); ROWS one block per n_g holding
  * its whole n_u row with both states (the paper's M^g, 2 N_u x 2 N_u, of
  * which each symmetry block holds one half).  Blocks are factored once per
- * job by complex symmetric LDL^T; a block with a vanishing pivot falls back
+ * job by complex symmetric LDL^T (in FP64; with VDC_FP32_INNER the inner
+ * solves apply a factor whose multipliers are stored in FP16 and 1/D in
+ * FP32, exactly as stored, so it stays symmetric); a block with a vanishing
+ * pivot, or whose multipliers leave the FP16 range in that mode, falls back
  * to its diagonal.  ROWS factors and applies each row serially (one thread
  * per row, N_g threads of a job): cheap per step, but its worth is the
  * iteration count, which it cuts most where lam q_u is the strong coupling.
