@@ -369,3 +369,44 @@ def test_textbook_gmres_reaches_lu_solution():
         assert info["converged"]
         assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
         assert np.linalg.norm(x - xl) <= 1e-7 * np.linalg.norm(xl)
+
+
+# ---------------------------------------------------------------- cross section
+
+def _single_channel_params():
+    """One open channel: only state 1 couples to the continuum, and only to
+    the even partial wave; both frequencies above 1 eV, so for eps_i < 1 eV
+    no vibrational excitation is open; the anion state sits at 0.3 eV."""
+    p = inputs.base_params()
+    p.update(omega_g=1.0, omega_u=1.2, E1=0.3, A2e=0.0, A1o=0.0, A2o=0.0)
+    return p
+
+
+def test_cross_section_prefactor_unitarity_limit():
+    """With a single open channel the optical theorem (pinned above) gives
+    -Im T = pi |T|^2, so |T| <= 1/pi, with equality where Re T = 0.  The
+    cross section of Eq. (16), 2 pi^3/eps_i |T|^2, must then be the s-wave
+    partial-wave bound 4 pi/k^2 times pi^2 |T|^2, with k^2 = 2 eps_i in
+    hartree (atomic units): sigma k^2 / (4 pi) <= 1 at every energy and = 1
+    at the sign change of Re T.  This fixes the prefactor 2 pi^3 and the
+    eV -> hartree conversion of eps_i; a cross section with eps_i left in eV
+    is 27.2 times too small and fails."""
+    from scipy.optimize import brentq
+    p = _single_channel_params()
+    Ng, Nu = 6, 5
+
+    def T_of(e):
+        _, T = ob.solve_job(p, Ng, Nu, e, (0, 0), "e", [(0, 0)])
+        return T[0, 0]
+
+    def ratio(e):
+        sig = ob.cross_sections(p, Ng, Nu, e, (0, 0), [(0, 0)])[0]
+        return sig * (2.0 * e / ls.HARTREE_EV) / (4.0 * math.pi)
+
+    for e in np.linspace(0.05, 0.95, 10):
+        T = T_of(e)
+        assert abs(-T.imag - math.pi * abs(T) ** 2) <= 1e-12 * abs(T)
+        assert ratio(e) <= 1.0 + 1e-12
+    assert T_of(0.25).real < 0 < T_of(0.30).real
+    e0 = brentq(lambda e: T_of(e).real, 0.25, 0.30, xtol=1e-15, rtol=1e-15)
+    assert abs(ratio(e0) - 1.0) <= 1e-10
