@@ -7,9 +7,11 @@
  * two-state, two-mode model of Sec. II.C and, for each job (incident energy
  * eps_i, initial vibrational state v_i, incoming partial wave mu_i), solves
  *     (E - H_ef(E)) Psi = Phi^{v_i mu_i},   E = eps_i + E_{v_i}     (Eqs. (2), (26))
- * by a Krylov method (restarted GMRES, Sec. III.A) with the diagonal
- * preconditioner of Sec. III.B, then projects the T-matrix amplitudes
- * (Eqs. (15), (24)) and cross sections (Eq. (16)).
+ * by a Krylov method of Sec. III.A (restarted GMRES, or COCG with the
+ * symmetrized bilinear form), right-preconditioned by a block-diagonal
+ * section of A (Sec. III.B: its diagonal, column blocks or rows), in FP64 or
+ * with FP32 inner solves inside an FP64 outer iteration, then projects the
+ * T-matrix amplitudes (Eqs. (15), (24)) and cross sections (Eq. (16)).
  *
  * Conventions shared by every entry point
  *  - Energies in eV.  T is dimensionless; sigma is in bohr^2 with eps_i
@@ -108,10 +110,14 @@ typedef enum {
   VDC_PREC_ROWS = 3
 } vdc_precond;
 typedef enum {
-  VDC_FP64 = 0,              /* restarted GMRES in complex FP64                  */
-  VDC_FP32_INNER = 1         /* FGMRES: FP64 outer (true residual, Givens,
-                                solution, amplitudes), GMRES in FP32 with FP32
-                                accumulation as the variable preconditioner   */
+  VDC_FP64 = 0,              /* the whole Krylov solve in complex FP64           */
+  VDC_FP32_INNER = 1         /* FP64 outer iteration (true residual, Givens,
+                                solution, amplitudes) around inner solves in
+                                complex FP32 with FP32 accumulation: with
+                                VDC_GMRES, FGMRES whose variable preconditioner
+                                is FP32 GMRES; with VDC_COCG, FP64 iterative
+                                refinement whose correction equations are
+                                solved by FP32 COCG (see vdc_method)          */
 } vdc_precision;
 
 /* Krylov method of vdc_solve, the batch entry points, vdc_solve_adjoint and
@@ -154,6 +160,12 @@ typedef struct {
                                 design (vector passes x element size; see the
                                 byte model in the solver sources), excluding
                                 the level-shift tables' construction           */
+  int retried;               /* vdc_solve with VDC_FP32_INNER: 1 if the job did
+                                not converge in the mixed-precision solve and
+                                was solved again in FP64 (the other fields then
+                                describe the FP64 solve), 2 if that re-solve
+                                did not fit the workspace, else 0             */
+  int reserved;
 } vdc_job_info;
 
 /* Build a model (host call; allocates and fills its small device tables:
@@ -181,7 +193,13 @@ vdc_status vdc_workspace_size(int n_models, const vdc_model_t* models,
  *   psi_out  device c16 [n_jobs][N] or NULL: the solution Psi, full layout
  *   info     host vdc_job_info[n_jobs] or NULL
  * Requirements: workspace device, >= vdc_workspace_size() bytes, 256-byte
- * aligned.  Synchronises the stream before returning. */
+ * aligned.  Synchronises the stream before returning.
+ * With VDC_FP32_INNER, every job that does not converge (FP32 stagnation, a
+ * breakdown or a non-finite FP32 value) is solved again in FP64 with the same
+ * method, preconditioner and limits, in the same workspace (with fewer
+ * resident workgroups if needed), and marked in info[j].retried; its outputs
+ * are then those of the FP64 solve.  The batch entry points do not retry
+ * (they never synchronise): check vdc_batch_info. */
 vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
                      int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
                      void* workspace, size_t ws_bytes,

@@ -132,9 +132,20 @@ int cu_count() {
   return n > 0 ? n : 256;
 }
 
+// Optional plan settings: an output index per job (a re-solve of some jobs
+// of a larger call writes their rows of the caller's arrays), the length of
+// those arrays, and a cap on the resident workgroups (fewer slots, so that a
+// plan fits a given amount of memory).
+struct PlanExtra {
+  const int* out_map = nullptr;
+  int n_out = -1;
+  int max_groups = 0;
+};
+
 vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_opts* o,
                      int n_jobs, const vdc_job* jobs, int n_final, bool plain, Plan& P,
-                     bool adjoint = false) {
+                     bool adjoint = false, const PlanExtra* ex = nullptr) {
+  const int n_out = (ex && ex->out_map) ? ex->n_out : n_jobs;
   if (n_models <= 0 || !models) return fail(VDC_ERR_INVALID_ARG, "no models");
   if (!o) return fail(VDC_ERR_INVALID_ARG, "opts is NULL");
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(VDC_ERR_INVALID_ARG, "bad job list");
@@ -256,7 +267,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
     o2.mu = jb.mu_i;
     o2.parity = (jb.vi_u + jb.mu_i) & 1;
     o2.model = jb.model;
-    o2.out = j;
+    o2.out = (ex && ex->out_map) ? ex->out_map[j] : j;
     o2.pad = 0;
     auto key = std::make_pair(jb.model, o2.E);
     auto it = tab_index.find(key);
@@ -283,7 +294,13 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   });
   const int m = cocg ? 4 : (mixed ? o->outer_restart : o->restart);
   P.ncap = (size_t)((P.max_nc + 63) / 64) * 64;
-  if (mixed) {
+  if (mixed && cocg) {
+    // FP64 refinement over FP32 COCG (cocg_mixed_kernel): FP64 x, b, r, wA,
+    // wB; FP32 (in c64 units) r, p, q, d, 1/D, the two FP16 multiplier
+    // planes (one FP32 plane together), wA, wB.  No basis and no Hessenberg:
+    // inner_restart is only a step limit and does not enter the size.
+    P.slot_elems = (size_t)5 * P.ncap + ((size_t)8 * P.ncap + 1) / 2;
+  } else if (mixed) {
     // FP64: Vout (m+1), Z (m), x, b, w, wA, wB, R_out, R_in;
     // FP32 (in c64 units): Vin (m_in+1) and the inner solver's vectors
     const int mi = o->inner_restart;
@@ -302,6 +319,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
                   : (mixed ? (cocg ? cocg_mixed_occupancy(P.dyn_lds) : fgmres_mixed_occupancy(P.dyn_lds))
                            : (cocg ? cocg_fp64_occupancy(P.dyn_lds) : gmres_fp64_occupancy(P.dyn_lds)));
   P.n_groups = plain ? 1 : std::max(1, std::min(n_jobs, cu_count() * occ));
+  if (ex && ex->max_groups > 0) P.n_groups = std::min(P.n_groups, ex->max_groups);
   size_t off = 0;
   P.off_counter = off; off += 256;
   P.off_models = off; off = align256(off + sizeof(DevModel) * n_models);
@@ -310,7 +328,7 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   P.off_groups = off; off = align256(off + sizeof(DevGroup) * std::max<size_t>(1, P.groups.size()));
   P.off_perm = off; off = align256(off + sizeof(int) * std::max<size_t>(1, P.perm.size()));
   P.off_finals = off; off = align256(off + sizeof(int) * 2 * std::max(1, n_final));
-  P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
+  P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_out));
   P.off_shift = off; off = align256(off + sizeof(c64) * P.shift_elems);
   P.off_tables = off; off = align256(off + sizeof(c64) * P.table_elems);
   P.off_tables32 = off; off = align256(off + (mixed ? sizeof(c32) * P.table_elems : 0));
@@ -336,17 +354,25 @@ struct Prepared {
   char* ws = nullptr;
   bool mixed = false, cocg = false, plain = false, adjoint = false;
   int n_jobs = 0;
+  std::vector<int> out_map;   // caller index of each job (empty: the identity)
+  int n_out = 0;              // entries of the info array in the workspace
 };
 
 vdc_status prepare_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
                          int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
                          void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
                          double* psi_out, hipStream_t s, bool plain, const AdjointIO* adj,
-                         Prepared& R) {
+                         Prepared& R, const PlanExtra* ex = nullptr) {
   Plan& P = R.P;
-  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, plain, P, adj != nullptr);
+  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, plain, P, adj != nullptr,
+                            ex);
   if (st != VDC_OK) return st;
   R.n_jobs = n_jobs;
+  R.n_out = n_jobs;
+  if (ex && ex->out_map) {
+    R.out_map.assign(ex->out_map, ex->out_map + n_jobs);
+    R.n_out = ex->n_out;
+  }
   if (n_jobs == 0) return VDC_OK;
   if (!workspace) return fail(VDC_ERR_INVALID_ARG, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
@@ -452,12 +478,14 @@ vdc_status enqueue_solve(const Prepared& R, hipStream_t s, EventSet* ev) {
 
 // Per-job results from the workspace (synchronises the stream).
 vdc_status read_info(const Prepared& R, vdc_job_info* info, hipStream_t s) {
-  std::vector<DevInfo> hinfo(R.n_jobs);
-  HIPCHK(hipMemcpyAsync(hinfo.data(), R.ws + R.P.off_info, sizeof(DevInfo) * R.n_jobs,
+  std::vector<DevInfo> hinfo(R.n_out);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), R.ws + R.P.off_info, sizeof(DevInfo) * R.n_out,
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (info) {
-    for (int j = 0; j < R.n_jobs; ++j) {
+    for (int k = 0; k < R.n_jobs; ++k) {
+      const int j = R.out_map.empty() ? k : R.out_map[k];
+      info[j].retried = 0;
       info[j].status = hinfo[j].status;
       info[j].iters = hinfo[j].iters;
       info[j].restarts = hinfo[j].restarts;
@@ -473,11 +501,11 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                      int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
                      void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
                      double* psi_out, vdc_job_info* info, void* stream, bool plain,
-                     const AdjointIO* adj = nullptr) {
+                     const AdjointIO* adj = nullptr, const PlanExtra* ex = nullptr) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Prepared R;
   vdc_status st = prepare_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace,
-                                ws_bytes, T_out, sigma_out, psi_out, s, plain, adj, R);
+                                ws_bytes, T_out, sigma_out, psi_out, s, plain, adj, R, ex);
   if (st != VDC_OK || n_jobs == 0) return st;
   EventSet ev;
   if (plain) {
@@ -520,6 +548,52 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
       adj->grad[p] = t;
     }
   }
+  return VDC_OK;
+}
+
+// FP32-inner jobs that did not converge (stagnation, breakdown or a
+// non-finite value in FP32) are solved again in FP64 with the same method,
+// preconditioner and limits, into their own rows of the caller's outputs,
+// using the caller's workspace (the first solve is complete: read_info
+// synchronised the stream).  With fewer slots when the FP64 plan of these jobs
+// does not fit the workspace; a job is marked retried = 1, or 2 when not even
+// one slot fits.  The kernel timings of the first solve are kept.
+vdc_status retry_fp64(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                      int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                      void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                      double* psi_out, vdc_job_info* info, void* stream) {
+  std::vector<int> idx;
+  for (int j = 0; j < n_jobs; ++j)
+    if (info[j].status != VDC_CONVERGED) idx.push_back(j);
+  if (idx.empty()) return VDC_OK;
+  std::vector<vdc_job> sub(idx.size());
+  for (size_t k = 0; k < idx.size(); ++k) sub[k] = jobs[idx[k]];
+  vdc_solve_opts o64 = *opts;
+  o64.precision = VDC_FP64;
+  PlanExtra ex;
+  ex.out_map = idx.data();
+  ex.n_out = n_jobs;
+  Plan P;
+  vdc_status st = make_plan(n_models, models, &o64, (int)sub.size(), sub.data(), n_final, false, P,
+                            false, &ex);
+  if (st != VDC_OK) return st;
+  if (P.total > ws_bytes) {
+    const size_t slot = sizeof(c64) * P.slot_elems;
+    const size_t avail = ws_bytes > P.off_scratch + 256 ? ws_bytes - P.off_scratch - 256 : 0;
+    const int g = (int)std::min<size_t>(avail / slot, (size_t)P.n_groups);
+    if (g < 1) {
+      for (int j : idx) info[j].retried = 2;
+      return VDC_OK;
+    }
+    ex.max_groups = g;
+  }
+  const double t1 = g_ms_tables, t2 = g_ms_solver;
+  st = run_solve(n_models, models, &o64, (int)sub.size(), sub.data(), n_final, finals, workspace,
+                 ws_bytes, T_out, sigma_out, psi_out, info, stream, false, nullptr, &ex);
+  g_ms_tables = t1;
+  g_ms_solver = t2;
+  if (st != VDC_OK) return st;
+  for (int j : idx) info[j].retried = 1;
   return VDC_OK;
 }
 
@@ -575,6 +649,8 @@ vdc_status vdc_model2d_create(const vdc_model2d_desc* d, vdc_model_t* out) {
     if (!std::isfinite(v)) return fail(VDC_ERR_INVALID_ARG, "non-finite model parameter");
   if (!(d->omega_g > 0.0) || !(d->omega_u > 0.0))
     return fail(VDC_ERR_INVALID_ARG, "vibrational frequencies must be > 0");
+  if (!std::isfinite(d->E1 + d->gap))
+    return fail(VDC_ERR_INVALID_ARG, "E1 + gap overflows");
   if ((size_t)d->Ng * d->Nu > (size_t)1 << 26) return fail(VDC_ERR_INVALID_ARG, "basis too large");
 
   vdc_model* m = new vdc_model();
@@ -722,8 +798,17 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                      int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
                      void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
                      double* psi_out, vdc_job_info* info, void* stream) {
-  return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
-                   T_out, sigma_out, psi_out, info, stream, false);
+  const bool mixed = opts && opts->precision == VDC_FP32_INNER;
+  std::vector<vdc_job_info> own;
+  if (mixed && !info && n_jobs > 0) {
+    own.resize(n_jobs);
+    info = own.data();
+  }
+  const vdc_status st = run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace,
+                                  ws_bytes, T_out, sigma_out, psi_out, info, stream, false);
+  if (st != VDC_OK || !mixed || n_jobs == 0) return st;
+  return retry_fp64(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
+                    T_out, sigma_out, psi_out, info, stream);
 }
 
 vdc_status vdc_batch_create(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,

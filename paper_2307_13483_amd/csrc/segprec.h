@@ -37,7 +37,7 @@ __device__ inline typename CT<R>::C lw(c16 a) {
   return typename CT<R>::C{R((float)a.x), R((float)a.y)};
 }
 template <typename R>
-__device__ inline typename FacT<R>::S lnarrow(c64 a) {
+__host__ __device__ inline typename FacT<R>::S lnarrow(c64 a) {
   if constexpr (sizeof(typename FacT<R>::S) == sizeof(c16))
     return c16{(_Float16)(float)a.x, (_Float16)(float)a.y};
   else
@@ -45,7 +45,7 @@ __device__ inline typename FacT<R>::S lnarrow(c64 a) {
 }
 // Whether a multiplier is representable in the storage: FP16 ends at 65504.
 template <typename R>
-__device__ inline bool lfits(c64 a) {
+__host__ __device__ inline bool lfits(c64 a) {
   if constexpr (sizeof(typename FacT<R>::S) == sizeof(c16))
     return fabs(a.x) < 6.0e4 && fabs(a.y) < 6.0e4;
   else

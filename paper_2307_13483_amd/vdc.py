@@ -7,6 +7,7 @@ turns status codes into exceptions.  Loading fails loudly when the library
 has not been built: there is no fallback.
 """
 import ctypes
+import logging
 import os
 from dataclasses import dataclass
 
@@ -14,6 +15,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
+_log = logging.getLogger("vdc")
 LIB_PATH = os.path.join(_HERE, "libvdc.so")
 
 VDC_OK, VDC_ERR_INVALID_ARG, VDC_ERR_WORKSPACE, VDC_ERR_HIP, VDC_ERR_UNSUPPORTED = range(5)
@@ -57,7 +59,8 @@ class SolveOpts(ctypes.Structure):
 class JobInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("outer_iters", ctypes.c_int), ("rel_res", ctypes.c_double),
-                ("alg_bytes", ctypes.c_double)]
+                ("alg_bytes", ctypes.c_double), ("retried", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
 
 
 class Co2Desc(ctypes.Structure):
@@ -350,10 +353,16 @@ class Solver:
         return self
 
     def infos(self):
-        return [dict(status=self.info[k].status, iters=self.info[k].iters,
-                     restarts=self.info[k].restarts, outer_iters=self.info[k].outer_iters,
-                     rel_res=self.info[k].rel_res, alg_bytes=self.info[k].alg_bytes)
-                for k in range(self.n_jobs)]
+        out = [dict(status=self.info[k].status, iters=self.info[k].iters,
+                    restarts=self.info[k].restarts, outer_iters=self.info[k].outer_iters,
+                    rel_res=self.info[k].rel_res, alg_bytes=self.info[k].alg_bytes,
+                    retried=self.info[k].retried)
+               for k in range(self.n_jobs)]
+        n_retry = sum(1 for i in out if i["retried"])
+        if n_retry:
+            _log.warning("%d of %d FP32-inner solves did not converge and were solved again "
+                         "in FP64", n_retry, self.n_jobs)
+        return out
 
 
 class Batch(Solver):

@@ -70,3 +70,20 @@ def test_invalid_co2_model_rejected_before_device_work():
     assert e.value.code == vdc.VDC_ERR_INVALID_ARG
     assert vdc.lib().vdc_co2_create(None, None) == vdc.VDC_ERR_INVALID_ARG
     assert vdc.lib().vdc_co2_destroy(None) == vdc.VDC_OK
+
+
+@pytest.mark.parametrize("name,value", [("kappa1", float("nan")), ("omega_u", float("inf")),
+                                        ("A2o", float("nan")), ("gap", 1.7e308),
+                                        ("lam", float("-inf"))])
+def test_nonfinite_parameter_rejected_before_device_work(name, value):
+    """A NaN or infinite model parameter, or one whose derived state energy
+    E_2 = E_1 + gap overflows, is a call error (VDC_ERR_INVALID_ARG) raised by
+    the host checks of vdc_model2d_create, before any device call."""
+    from paper_2307_13483_amd import vdc
+    p = dict(inputs.base_params())
+    p[name] = value
+    if name == "gap":
+        p["E1"] = 1.7e308
+    with pytest.raises(vdc.VdcError) as e:
+        vdc.Model2D(p, 4, 4)
+    assert e.value.code == vdc.VDC_ERR_INVALID_ARG

@@ -37,8 +37,9 @@ def _cocg_steps_agree(gpu_iters, A, b, psolve, tol=1e-10):
     """COCG has no minimisation property (Sec. III.A) and its residual can
     rise locally (Sec. III.C), so where it lingers just above the target the
     step that first crosses it moves with rounding.  The GPU's count must
-    match the oracle's within max(3, 3 %) plus the length of the oracle's
-    final plateau (trailing residuals within 10 x tol)."""
+    match the oracle's within max(3, 5 %) plus the length of the oracle's
+    final plateau (trailing residuals within 10 x tol), the plateau counted
+    up to 10 steps (the longest on these cases is 11)."""
     _, info = solvers.cocg(A, b, tol=tol, psolve=psolve, history=True)
     assert info["converged"]
     bn = np.linalg.norm(b)
@@ -48,7 +49,7 @@ def _cocg_steps_agree(gpu_iters, A, b, psolve, tol=1e-10):
         if v > 10 * tol:
             break
         plateau += 1
-    slack = max(3, 0.03 * info["iters"]) + plateau
+    slack = max(3, 0.05 * info["iters"]) + min(plateau, 10)
     assert abs(gpu_iters - info["iters"]) <= slack, (gpu_iters, info["iters"], plateau)
 
 
