@@ -3,11 +3,13 @@
 Workload (one "step"): the generalized two-state model of Sec. II.C at one
 seeded +-20 % parameter draw, 120 x 120 basis per state (28800 unknowns),
 512 incident energies on [0.1, 3.0] eV x initial states v_i = 0, 1, 2 x
-both partial waves = 3072 right-hand sides, each solved to a relative true
-residual of 1e-10 (restarted GMRES, diagonal preconditioner), followed by the
-amplitudes to v_f = 0..5 and the cross-section shares.  The per-energy
-level-shift tables are built inside the step.  Inputs are synthetic (seeded
-parameters; the paper uses no dataset).
+both partial waves = 3072 right-hand sides, each solved to a relative FP64
+true residual of 1e-10 by the Krylov method the autotuner picks (GMRES,
+FGMRES with FP32 inner cycles, COCG, or FP64 refinement over FP32 COCG) with
+the column-block preconditioner, followed by the amplitudes to v_f = 0..5 and
+the cross-section shares.  The per-energy level-shift tables are built inside
+the step.  Inputs are synthetic (seeded parameters; the paper uses no
+dataset).
 
 Prints one JSON line (see DESIGN.md for the byte model behind "roofline").
 """
@@ -86,27 +88,159 @@ def _warm(_):
     return os.getpid()
 
 
+def host_info():
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return dict(nproc=os.cpu_count(), usable_cpus=affinity, cpu_model=model)
+
+
+def _pool(workers):
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    return ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
 def cpu_baseline(cfg, n_sample):
     """The oracle as it stands over a bounded, evenly spaced sample of the
     same jobs, one job per worker process (one thread each, at most 16
     workers: the host cores given to one GPU), timed from submission to the
-    last result after the workers have imported the oracle."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
+    last result after the workers have imported the oracle.  Also returns
+    the oracle's amplitudes of the sampled jobs (index -> T[f][mu_f])."""
     p, Ng, Nu = cfg["params"], cfg["Ng"], cfg["Nu"]
     jobs = cfg["jobs"]
     idx = [int(round(k * (len(jobs) - 1) / max(1, n_sample - 1))) for k in range(n_sample)]
     workers = max(1, min(16, os.cpu_count() or 1, len(idx)))
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+    with _pool(workers) as ex:
         list(ex.map(_warm, range(workers)))
         t0 = time.perf_counter()
-        list(ex.map(_oracle_job, [p] * len(idx), [Ng] * len(idx), [Nu] * len(idx),
-                    [jobs[k] for k in idx], [cfg["finals"]] * len(idx)))
+        Ts = list(ex.map(_oracle_job, [p] * len(idx), [Ng] * len(idx), [Nu] * len(idx),
+                         [jobs[k] for k in idx], [cfg["finals"]] * len(idx)))
         dt = time.perf_counter() - t0
-    return dict(value=len(idx) / dt, unit="solves/s", cores=workers, kind="oracle",
-                sample=f"{len(idx)} of the {len(jobs)} right-hand sides (evenly spaced), one per "
-                       f"single-threaded worker process ({workers} workers), sparse LU of the "
-                       f"assembled {2 * Ng * Nu}-unknown matrix, {dt:.1f} s")
+    out = dict(value=len(idx) / dt, unit="solves/s", cores=workers, kind="oracle",
+               sample=f"{len(idx)} of the {len(jobs)} right-hand sides (evenly spaced), one per "
+                      f"single-threaded worker process ({workers} workers), sparse LU of the "
+                      f"assembled {2 * Ng * Nu}-unknown matrix, {dt:.1f} s",
+               host=host_info())
+    return out, dict(zip(idx, Ts))
+
+
+def amplitude_error(T_gpu, T_ref):
+    """max over the sampled jobs of max_f |T_gpu - T_ref| / max_f |T_ref|."""
+    import numpy as np
+    errs = []
+    for k, Tr in T_ref.items():
+        Tr = np.asarray(Tr).reshape(-1)
+        Tg = np.asarray(T_gpu[k]).reshape(-1)
+        errs.append(float(np.max(np.abs(Tg - Tr)) / max(1e-300, np.max(np.abs(Tr)))))
+    return max(errs), float(np.median(errs))
+
+
+# GPU results the oracle leg compares against (not printed)
+_KEEP = {}
+
+
+def _oracle_co2_job(p, sizes, job, finals, psi_full):
+    """The oracle's ||b - A psi|| / ||b|| of a CO2-like GPU solution with its
+    own assembled matrix (the level-shift functions evaluated once per
+    distinct eps_nu), and its amplitudes Phi_f^T psi; one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import poly
+    with threadpool_limits(limits=1):
+        eps_i, v, mu = job
+        E = poly.total_energy(p, eps_i, v)
+
+        def tables(pp, eps):
+            u, inv = np.unique(np.asarray(eps, dtype=np.float64), return_inverse=True)
+            return {k: t[inv] for k, t in poly.pair_tables(pp, u).items()}
+
+        M = poly.PolyModel(p, sizes, E, tables=tables)
+        A = M.matrix()
+        b = M.phi(v, poly.WAVES[mu])
+        res = float(np.linalg.norm(b - A @ psi_full) / np.linalg.norm(b))
+        return res, [[complex(M.phi(vf, w) @ psi_full) for w in poly.WAVES] for vf in finals]
+
+
+def cpu_baseline_configs(cfg_c1):
+    """The oracle on the other configurations, as far as it gets in bounded
+    time, and the GPU results' errors against it:
+      c0: both right-hand sides (LU of 3200 unknowns), GPU run with the C0
+          options (GMRES(50), diagonal preconditioner);
+      c3: 16 of the 128 uneven right-hand sides (both of the largest basis,
+          158 x 158, and 14 spread), LU, against every GPU run of the batch;
+      c2: no oracle solve fits a bounded sample at 331 776 unknowns (sparse
+          LU fill-in; the dense bend blocks take 9 GB per energy), so the
+          oracle checks the residual of two GPU solutions with its own
+          assembled matrix and projects their amplitudes: a check, timed."""
+    import numpy as np
+    out, acc = {}, {}
+    if "c0" in _KEEP:
+        c0 = _KEEP["c0"]
+        t0 = time.perf_counter()
+        Ts = [_oracle_job(c0["params"], c0["Ng"], c0["Nu"], j, c0["finals"]) for j in c0["jobs"]]
+        dt = time.perf_counter() - t0
+        out["c0"] = dict(value=len(Ts) / dt, unit="solves/s", cores=1,
+                         sample="both right-hand sides, sparse LU of 3200 unknowns, one thread")
+        mx, med = amplitude_error(c0["T"], dict(enumerate(Ts)))
+        acc["c0"] = dict(jobs=len(Ts), max_rel_amplitude_error=mx, reference="oracle LU",
+                         solver="GMRES(50), diagonal preconditioner, FP64")
+    if "c3" in _KEEP:
+        c3 = _KEEP["c3"]
+        insts, jobs = c3["insts"], c3["jobs"]
+        big = int(np.argmax([i["Ng"] for i in insts]))
+        pick = [2 * big, 2 * big + 1] + [k for k in range(0, len(jobs), 9)
+                                         if k // 2 != big][:14]
+        workers = max(1, min(16, os.cpu_count() or 1, len(pick)))
+        with _pool(workers) as ex:
+            list(ex.map(_warm, range(workers)))
+            t0 = time.perf_counter()
+            Ts = list(ex.map(_oracle_job, [insts[jobs[k][3]]["params"] for k in pick],
+                             [insts[jobs[k][3]]["Ng"] for k in pick],
+                             [insts[jobs[k][3]]["Nu"] for k in pick],
+                             [jobs[k][:3] for k in pick], [c3["finals"]] * len(pick)))
+            dt = time.perf_counter() - t0
+        out["c3"] = dict(value=len(pick) / dt, unit="solves/s", cores=workers,
+                         sample=f"{len(pick)} of the 128 uneven right-hand sides (both of the "
+                                f"{insts[big]['Ng']} x {insts[big]['Ng']} instance), sparse LU, "
+                                f"{dt:.1f} s")
+        ref = dict(zip(pick, Ts))
+        acc["c3"] = {name: dict(zip(("max_rel_amplitude_error", "median_rel_amplitude_error"),
+                                    amplitude_error(T, ref)))
+                     for name, T in c3["T"].items()}
+        acc["c3"]["jobs"] = len(pick)
+        acc["c3"]["reference"] = "oracle LU"
+    if "c2" in _KEEP:
+        c2 = _KEEP["c2"]
+        workers = max(1, min(16, os.cpu_count() or 1, len(c2["jobs"])))
+        with _pool(workers) as ex:
+            t0 = time.perf_counter()
+            rs = list(ex.map(_oracle_co2_job, [c2["params"]] * len(c2["jobs"]),
+                             [c2["sizes"]] * len(c2["jobs"]), c2["jobs"],
+                             [c2["finals"]] * len(c2["jobs"]), c2["psi"]))
+            dt = time.perf_counter() - t0
+        out["c2"] = dict(value=len(rs) / dt, unit="residual checks/s", cores=workers,
+                         sample=f"{len(rs)} GPU solutions of 331 776 unknowns: the oracle's "
+                                f"assembly and residual, not a solve, {dt:.1f} s")
+        errs = []
+        for (res, T), Tg in zip(rs, c2["T"]):
+            T = np.asarray(T)
+            errs.append(float(np.max(np.abs(np.asarray(Tg) - T)) / max(1e-300, np.max(np.abs(T)))))
+        acc["c2"] = dict(jobs=len(rs), worst_oracle_rel_residual=max(r for r, _ in rs),
+                         max_rel_amplitude_difference=max(errs),
+                         reference="oracle's own assembled matrix (residual), its Phi (T)")
+    return out, acc
 
 
 PRECONDS = {"jacobi": 1, "block": 2, "rows": 3}
@@ -135,12 +269,41 @@ def co2like(args, method=None):
     ms_tab, ms_sol = vdc.last_kernel_times()
     it = [i["iters"] for i in infos]
     alg = sum(i["alg_bytes"] for i in infos)
+    if method is None:
+        _keep_co2(model, cfg, opts, T)
     return dict(right_hand_sides=len(infos), sizes=cfg["sizes"], solves_per_s=len(infos) / dt,
                 converged=sum(i["status"] == vdc.CONVERGED for i in infos),
                 worst_rel_res=max(i["rel_res"] for i in infos), iters_mean=sum(it) / len(it),
                 iters_max=max(it), ms_tables=ms_tab, ms_solver=ms_sol,
                 algorithmic_bytes=alg, achieved_GBs=alg / (ms_sol * 1e-3) / 1e9,
                 frac=alg / (ms_sol * 1e-3) / 1e9 / HBM_PEAK_GBS)
+
+
+def _keep_co2(model, cfg, opts, T):
+    """Two right-hand sides of the CO2-like batch (lowest energy s wave, a
+    high-energy p_x wave) solved again with their solutions, in the oracle's
+    full layout, for the oracle leg; T from the timed batch."""
+    import numpy as np
+    from paper_2307_13483_amd import vdc
+    pick = [0, 373]
+    jobs = [cfg["jobs"][k] for k in pick]
+    _, _, psi, _ = vdc.co2_solve(model, jobs, cfg["finals"], opts, want_psi=True)
+    sz = cfg["sizes"]
+    Ns, Nx, Ny, Na = (sz[k] for k in ("s", "x", "y", "a"))
+    n = Ns * Nx * Ny * Na
+    s, a, x, y = np.meshgrid(np.arange(Ns), np.arange(Na), np.arange(Nx), np.arange(Ny),
+                             indexing="ij")
+    fulls = []
+    for q, (eps_i, v, mu) in enumerate(jobs):
+        px, py = vdc.co2_sector(v, mu)
+        t = (((x + px) & 1) | (((y + py) & 1) << 1)).ravel()
+        idx = (t * n + (((s * Nx + x) * Ny + y) * Na + a).ravel())
+        z = psi[q].cpu().numpy()
+        full = np.zeros(3 * n, dtype=complex)
+        full[idx[t != 3]] = z[t != 3]
+        fulls.append(full)
+    _KEEP["c2"] = dict(params=cfg["params"], sizes=sz, jobs=jobs, finals=cfg["finals"],
+                       psi=fulls, T=[T[k].cpu().numpy() for k in pick])
 
 
 def co2_matvec(nv=512):
@@ -346,6 +509,8 @@ def uneven_mixed(pc, finals):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[name] = (s.T.cpu().numpy().copy(), s.infos(), len(jobs) / dt)
+    _KEEP["c3"] = dict(insts=insts, jobs=jobs, finals=finals,
+                       T={name: r[0] for name, r in res.items()})
     T64 = res["fp64_cocg"][0]
     um = dict(instances=len(insts), solves=len(jobs))
     for name, (T, infos, rate) in res.items():
@@ -383,12 +548,13 @@ def extras(args, model, cfg):
     ex["matvec"] = dict(vectors=nv, unknowns_per_vector=nc, kernel_ms=t * 1e3,
                         achieved_GBs=alg / t / 1e9, frac=alg / t / 1e9 / HBM_PEAK_GBS,
                         algorithmic_bytes=alg)
-    # single energy, 40 x 40 basis, 2 right-hand sides: latency of one call
+    # single energy, 40 x 40 basis, 2 right-hand sides, GMRES(50) with the
+    # diagonal preconditioner: latency of one call
     sc = inputs.single_jobs()
     m0 = vdc.Model2D(sc["params"], sc["Ng"], sc["Nu"])
     for plain in (False, True):
         s = vdc.Solver(m0, sc["jobs"], sc["finals"],
-                       vdc.Opts(restart=50, tol=1e-10, precond=PRECONDS[args.precond]))
+                       vdc.Opts(restart=50, tol=1e-10, precond=vdc.PREC_JACOBI))
         s.run(plain=plain)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -397,6 +563,9 @@ def extras(args, model, cfg):
         torch.cuda.synchronize()
         ex["single_energy_plain_ms" if plain else "single_energy_batched_ms"] = \
             (time.perf_counter() - t0) / 5 * 1e3
+        if not plain:
+            _KEEP["c0"] = dict(sc, T=s.T.cpu().numpy())
+            ex["single_energy_solver"] = "GMRES(50), diagonal preconditioner, FP64"
     ex["uneven_mixed"] = uneven_mixed(PRECONDS[args.precond], cfg["finals"])
     pc = PRECONDS[args.precond]
     from paper_2307_13483_amd import vdc as _v
@@ -587,7 +756,7 @@ def main():
                     iters_mean=sum(iters) / len(iters), iters_max=max(iters),
                     outer_mean=(sum(i["outer_iters"] for i in infos) / len(infos)),
                     ms_tables=sum(ms_tables) / len(ms_tables), ms_solver=solver_ms,
-                    roofline=roof, opts=opts)
+                    roofline=roof, opts=opts, T=solver.T.cpu().numpy())
 
     head = run_mode(args.precision)
     other = run_mode("fp64" if args.precision == "fp32" else "fp32") if args.both else None
@@ -611,8 +780,22 @@ def main():
         "ms_tables": head["ms_tables"], "ms_solver": head["ms_solver"],
         "roofline": head["roofline"],
     }
+    out["roofline"]["scope"] = ("the whole solver kernel: operator, preconditioner sweeps and "
+                                "vector updates; the operator alone is under 'matvec'")
     if other is not None:
-        out["other_precision"] = {k: v for k, v in other.items() if k != "opts"}
+        out["other_precision"] = {k: v for k, v in other.items() if k not in ("opts", "T")}
+    gmres_runs = {}
+    if args.extras:
+        # the C1 jobs by GMRES as well (restart lengths as tuned on this workload)
+        pc = PRECONDS[args.precond]
+        for name, o in (("gmres_fp64", vdc.Opts(restart=5, precond=pc, max_iter=20000)),
+                        ("fgmres_fp32_inner", vdc.Opts(precision=vdc.FP32_INNER, precond=pc,
+                                                       inner_restart=8, inner_tol=1e-3,
+                                                       outer_restart=16, max_iter=20000))):
+            r = batched_run(model, cfg, o)
+            r["solver"] = solver_name(o, args.precond)
+            gmres_runs[name] = r
+        out["c1_gmres"] = gmres_runs
     if args.plain_sample > 0:
         # the plain single-solve path at its own best restart length (its
         # per-step cost is launch latency, so it prefers long cycles)
@@ -635,13 +818,30 @@ def main():
             out["plain"] = dict(sample=k, plain_fp64_solves_per_s=rates[best_m], plain_restart=best_m,
                                 plain_by_restart={str(m): r for m, r in rates.items()},
                                 speedup_batched_vs_plain=head["value"] / rates[best_m])
+            if "gmres_fp64" in gmres_runs:
+                # the same method and precision batched: batching alone
+                out["plain"]["speedup_batched_gmres_fp64_vs_plain"] = (
+                    gmres_runs["gmres_fp64"]["solves_per_s"] / rates[best_m])
         except vdc.VdcError as e:
             out["plain"] = dict(error=str(e))
+    acc = {}
     if args.extras:
         out["extras"] = extras(args, model, cfg)
         out["extras"]["graph_replay"] = graph_replay(model, cfg, opts, args.steps)
+        ex = out["extras"]
+        out["matvec"] = {k: ex["matvec"][k] for k in ("achieved_GBs", "frac", "kernel_ms")}
+        out["matvec"]["kernel"] = "matvec_strip_kernel (the batched operator on its own)"
     if args.cpu_sample > 0:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+        cb, Tref = cpu_baseline(cfg, args.cpu_sample)
+        cb["configs"], acc_other = cpu_baseline_configs(cfg)
+        acc.update(acc_other)
+        mx, med = amplitude_error(head["T"], Tref)
+        acc["c1"] = dict(jobs=len(Tref), max_rel_amplitude_error=mx,
+                         median_rel_amplitude_error=med,
+                         reference="oracle sparse LU of the cpu_baseline sample")
+        out["cpu_baseline"] = cb
+    if acc:
+        out["accuracy_vs_oracle"] = acc
     print(json.dumps(out), flush=True)
 
 
