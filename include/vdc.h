@@ -206,6 +206,28 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                      double* T_out, double* sigma_out, double* psi_out,
                      vdc_job_info* info, void* stream);
 
+/* vdc_solve for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc, code running while another stream
+ * captures a HIP graph): the same plan, kernels and outputs as vdc_solve, with no
+ * workspace argument.  The library keeps one static device array of
+ * VDC_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU it runs on, held until the
+ * process ends, and runs the call in it: with fewer resident workgroups when
+ * the plan does not fit, and VDC_ERR_WORKSPACE (message names the bytes
+ * needed) when even one workgroup's slot, the level-shift tables and the job
+ * descriptors do not fit - e.g. a 120 x 120 batch over hundreds of energies;
+ * use vdc_solve there.  No hipMalloc, hipFree or event is created; the
+ * job descriptors are copied into the array with hipMemcpyAsync.  Kernel
+ * times are not recorded (vdc_last_kernel_times keeps the previous call's).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (each call initialises what it reads): calls that overlap on one
+ * GPU, from several host threads or streams, race and must be serialised
+ * by the caller.  Synchronises the stream before returning. */
+#define VDC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+vdc_status vdc_solve_noalloc(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                             int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                             double* T_out, double* sigma_out, double* psi_out,
+                             vdc_job_info* info, void* stream);
+
 /* The batched solve as a reusable launch (for host loops that repeat the same
  * jobs, and for capture into a HIP graph: the whole batch, tables included,
  * becomes one graph launch).

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <utility>
@@ -46,6 +47,12 @@ vdc_status solve_plain_impl(const SolveArgs& a, const std::vector<DevJob>& jobs,
 
 using namespace vdc;
 
+// Device memory of vdc_solve_noalloc: one array per GPU, allocated when the
+// code object is loaded on it and held until the process ends.  Host code
+// never uses the name as an address (it is a host-side stand-in); it takes
+// the device address from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[VDC_NOALLOC_SCRATCH_BYTES];
+
 struct vdc_model {
   vdc_model2d_desc desc;
   DevModel dev;
@@ -64,7 +71,8 @@ thread_local double g_ms_tables = 0.0, g_ms_solver = 0.0;
 struct EventSet {
   hipEvent_t e[3] = {nullptr, nullptr, nullptr};
   bool ok = false;
-  EventSet() {
+  explicit EventSet(bool want = true) {
+    if (!want) return;   // no events: nothing is created
     ok = true;
     for (auto& x : e) ok = ok && hipEventCreate(&x) == hipSuccess;
   }
@@ -140,6 +148,7 @@ struct PlanExtra {
   const int* out_map = nullptr;
   int n_out = -1;
   int max_groups = 0;
+  bool untimed = false;   // record no kernel-time events (creates none)
 };
 
 vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_opts* o,
@@ -507,7 +516,7 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   vdc_status st = prepare_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace,
                                 ws_bytes, T_out, sigma_out, psi_out, s, plain, adj, R, ex);
   if (st != VDC_OK || n_jobs == 0) return st;
-  EventSet ev;
+  EventSet ev(!(ex && ex->untimed));
   if (plain) {
     HIPCHK(launch_zero_int(reinterpret_cast<int*>(R.ws + R.P.off_counter), 64, s));
     if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
@@ -561,7 +570,8 @@ vdc_status run_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
 vdc_status retry_fp64(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
                       int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
                       void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
-                      double* psi_out, vdc_job_info* info, void* stream) {
+                      double* psi_out, vdc_job_info* info, void* stream,
+                      bool untimed = false) {
   std::vector<int> idx;
   for (int j = 0; j < n_jobs; ++j)
     if (info[j].status != VDC_CONVERGED) idx.push_back(j);
@@ -573,6 +583,7 @@ vdc_status retry_fp64(int n_models, const vdc_model_t* models, const vdc_solve_o
   PlanExtra ex;
   ex.out_map = idx.data();
   ex.n_out = n_jobs;
+  ex.untimed = untimed;
   Plan P;
   vdc_status st = make_plan(n_models, models, &o64, (int)sub.size(), sub.data(), n_final, false, P,
                             false, &ex);
@@ -594,6 +605,27 @@ vdc_status retry_fp64(int n_models, const vdc_model_t* models, const vdc_solve_o
   g_ms_solver = t2;
   if (st != VDC_OK) return st;
   for (int j : idx) info[j].retried = 1;
+  return VDC_OK;
+}
+
+// Device address of this GPU's scratch array (looked up with the device
+// current, once per device, then cached).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+vdc_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(VDC_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(VDC_ERR_HIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
   return VDC_OK;
 }
 
@@ -809,6 +841,43 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (st != VDC_OK || !mixed || n_jobs == 0) return st;
   return retry_fp64(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
                     T_out, sigma_out, psi_out, info, stream);
+}
+
+vdc_status vdc_solve_noalloc(int n_models, const vdc_model_t* models,
+                             const vdc_solve_opts* opts, int n_jobs, const vdc_job* jobs,
+                             int n_final, const int* finals, double* T_out, double* sigma_out,
+                             double* psi_out, vdc_job_info* info, void* stream) {
+  const size_t cap = VDC_NOALLOC_SCRATCH_BYTES;
+  Plan P;
+  vdc_status st = make_plan(n_models, models, opts, n_jobs, jobs, n_final, false, P);
+  if (st != VDC_OK || n_jobs == 0) return st;
+  PlanExtra ex;
+  ex.untimed = true;
+  if (P.total > cap) {
+    // fewer resident workgroups (slots) until the plan fits, if one does
+    const size_t slot = sizeof(c64) * P.slot_elems;
+    const size_t fixed = P.off_scratch + 256;
+    if (fixed + slot > cap)
+      return fail(VDC_ERR_WORKSPACE,
+                  "vdc_solve_noalloc: this call needs " + std::to_string(fixed + slot) +
+                      " bytes of device scratch with one resident workgroup, more than the " +
+                      std::to_string(cap) + " bytes the library holds; use vdc_solve");
+    ex.max_groups = (int)std::min<size_t>((cap - fixed) / slot, (size_t)P.n_groups);
+  }
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != VDC_OK) return st;
+  const bool mixed = opts->precision == VDC_FP32_INNER;
+  std::vector<vdc_job_info> own;
+  if (mixed && !info) {
+    own.resize(n_jobs);
+    info = own.data();
+  }
+  st = run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, ws, cap, T_out, sigma_out,
+                 psi_out, info, stream, false, nullptr, &ex);
+  if (st != VDC_OK || !mixed) return st;
+  return retry_fp64(n_models, models, opts, n_jobs, jobs, n_final, finals, ws, cap, T_out,
+                    sigma_out, psi_out, info, stream, true);
 }
 
 vdc_status vdc_batch_create(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,

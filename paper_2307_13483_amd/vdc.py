@@ -97,6 +97,9 @@ def lib():
         "vdc_solve": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I, ctypes.POINTER(Job),
                           I, ctypes.POINTER(ctypes.c_int), P, S, P, P, P,
                           ctypes.POINTER(JobInfo), P]),
+        "vdc_solve_noalloc": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                  ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, P, P,
+                                  ctypes.POINTER(JobInfo), P]),
         "vdc_solve_plain": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
                                 ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, S, P, P,
                                 P, ctypes.POINTER(JobInfo), P]),
@@ -344,6 +347,15 @@ class Solver:
                                        self.adj_bytes, _ptr(self.grad_jobs), g, self.adj_info,
                                        _stream_ptr(stream)))
         return np.array(list(g)), self.grad_jobs
+
+    def run_noalloc(self, stream=None):
+        """vdc_solve_noalloc: the same solve in the library's static device
+        scratch (this object's workspace is not used)."""
+        _check(lib().vdc_solve_noalloc(len(self.models), self.handles, ctypes.byref(self.copts),
+                                       self.n_jobs, self.jobs, self.n_final, self.finals,
+                                       _ptr(self.T), _ptr(self.sigma), _ptr(self.psi), self.info,
+                                       _stream_ptr(stream)))
+        return self
 
     def run(self, plain=False, stream=None):
         f = lib().vdc_solve_plain if plain else lib().vdc_solve
