@@ -36,6 +36,11 @@ KERNEL_SOURCES = {"gmres_fp64_kernel": "gmres.hip", "fgmres_mixed_kernel": "mixe
                   "co2_factor_kernel": "co2.hip"}
 
 
+def log(msg):
+    """Progress on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_hash(kernel):
     """Hash of the kernel's source file and every header it includes
     (transitively): counters taken on other sources are not used."""
@@ -567,16 +572,20 @@ def extras(args, model, cfg):
             _KEEP["c0"] = dict(sc, T=s.T.cpu().numpy())
             ex["single_energy_solver"] = "GMRES(50), diagonal preconditioner, FP64"
     ex["uneven_mixed"] = uneven_mixed(PRECONDS[args.precond], cfg["finals"])
+    log("uneven_mixed done")
     pc = PRECONDS[args.precond]
     from paper_2307_13483_amd import vdc as _v
     ex["co2like"] = co2like(args)
+    log("co2like done")
     ex["co2like_cocg"] = co2like(args, _v.COCG)
     ex["co2_matvec"] = co2_matvec()
     ex["eels_batched"] = eels_batched(model, cfg)
+    log("eels_batched done")
     ex["cocg_batched"] = {name: cocg_batched(model, cfg, pc, mx) for name, pc, mx in
                           (("block", _v.PREC_BLOCK, False), ("jacobi", _v.PREC_JACOBI, False),
                            ("block_fp32_inner", _v.PREC_BLOCK, True))}
     ex["ecd86"] = ecd86_batched()
+    log("ecd86 done")
     ex["adjoint"] = {name: adjoint_gradient(o) for name, o in
                      (("gmres6", _v.Opts(restart=6, precond=pc)),
                       ("cocg", _v.Opts(precond=pc, method=_v.COCG)))}
@@ -759,7 +768,10 @@ def main():
                     roofline=roof, opts=opts, T=solver.T.cpu().numpy())
 
     head = run_mode(args.precision)
+    log(f"headline: {head['value']:.0f} solves/s")
     other = run_mode("fp64" if args.precision == "fp32" else "fp32") if args.both else None
+    if other is not None:
+        log(f"other precision: {other['value']:.0f} solves/s")
     opts = head["opts"]
     out = {
         "metric": METRIC, "value": head["value"], "unit": "solves/s", "n_gpus": 1,
@@ -795,6 +807,7 @@ def main():
             r = batched_run(model, cfg, o)
             r["solver"] = solver_name(o, args.precond)
             gmres_runs[name] = r
+            log(f"C1 {name}: {r['solves_per_s']:.0f} solves/s")
         out["c1_gmres"] = gmres_runs
     if args.plain_sample > 0:
         # the plain single-solve path at its own best restart length (its
@@ -824,15 +837,18 @@ def main():
                     gmres_runs["gmres_fp64"]["solves_per_s"] / rates[best_m])
         except vdc.VdcError as e:
             out["plain"] = dict(error=str(e))
+        log("plain path done")
     acc = {}
     if args.extras:
         out["extras"] = extras(args, model, cfg)
+        log("extras done")
         out["extras"]["graph_replay"] = graph_replay(model, cfg, opts, args.steps)
         ex = out["extras"]
         out["matvec"] = {k: ex["matvec"][k] for k in ("achieved_GBs", "frac", "kernel_ms")}
         out["matvec"]["kernel"] = "matvec_strip_kernel (the batched operator on its own)"
     if args.cpu_sample > 0:
         cb, Tref = cpu_baseline(cfg, args.cpu_sample)
+        log("oracle C1 sample done")
         cb["configs"], acc_other = cpu_baseline_configs(cfg)
         acc.update(acc_other)
         mx, med = amplitude_error(head["T"], Tref)
