@@ -23,6 +23,8 @@ observables  T-matrix and cross sections, Eqs. (15), (16), (24)
 adjoint      d(loss)/d(parameters) by explicit derivative matrices and LU
 poly         the CO2-like three-state, four-mode polynomial model (Sec. III.C)
              assembled the same way, and its bend-block preconditioner
+terms        any model of the class given by polynomial term lists (D states,
+             M modes, P partial waves), assembled the same way
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py``; none is "parity unpinned".

@@ -158,3 +158,79 @@ def co2like_jobs(n_energies=128, sizes=None, seed=SEED + 2):
     jobs = [(float(e), (0, 0, 0, 0), mu) for e in eps for mu in (0, 1, 2)]
     return dict(params=co2like_params(seed), sizes=dict(sizes or CO2_SIZES), jobs=jobs,
                 finals=[(v, 0, 0, 0) for v in range(4)] + [(0, 2, 0, 0), (0, 0, 0, 2)])
+
+
+# ---------------------------------------------------------------- term lists
+#
+# Models written as polynomial term lists (the general descriptor): a dict
+# with omega [M], nbasis [M], e_state [D], uterms / vterms as lists of
+# (d, d' or mu, coeff, powers [M]), width {(d, mu): (A, B)}, l [P], K, X.
+
+def terms_from_2d(p, Ng, Nu):
+    """The generalized two-state model (modes g, u; waves e, o) as terms."""
+    return dict(omega=[p["omega_g"], p["omega_u"]], nbasis=[Ng, Nu],
+                e_state=[p["E1"], p["E1"] + p["gap"]],
+                uterms=[(0, 0, p["kappa1"], [1, 0]), (1, 1, p["kappa2"], [1, 0]),
+                        (0, 1, p["lam"], [0, 1])],
+                vterms=[(0, 0, 1.0, [0, 0]), (0, 0, p["lam1"], [1, 0]), (1, 0, 1.0, [0, 1]),
+                        (0, 1, 1.0, [0, 1]), (1, 1, 1.0, [0, 0]), (1, 1, p["lam2"], [1, 0])],
+                width={(0, 0): (p["A1e"], p["B1e"]), (1, 0): (p["A2e"], p["B2e"]),
+                       (0, 1): (p["A1o"], p["B1o"]), (1, 1): (p["A2o"], p["B2o"])},
+                l=[p["l_e"], p["l_o"]], K=p["K"], X=p["X"])
+
+
+def terms_from_co2(p, sizes):
+    """The CO2-like model (states sigma, Pi_x, Pi_y; modes s, x, y, a;
+    waves s, p_x, p_y) as terms."""
+    def m(s=0, x=0, y=0, a=0):
+        return [s, x, y, a]
+    u = [(0, 0, p["k_sigma"], m(s=1)), (0, 0, p["gs_sigma"], m(s=2)), (0, 0, p["gb_sigma"], m(x=2)),
+         (0, 0, p["gb_sigma"], m(y=2)), (0, 0, p["ga_sigma"], m(a=2))]
+    for d, sgn in ((1, 1.0), (2, -1.0)):
+        u += [(d, d, p["k_pi"], m(s=1)), (d, d, p["gs_pi"], m(s=2)), (d, d, p["gb_pi"], m(x=2)),
+              (d, d, p["gb_pi"], m(y=2)), (d, d, p["ga_pi"], m(a=2)),
+              (d, d, sgn * p["c_rt"], m(x=2)), (d, d, -sgn * p["c_rt"], m(y=2))]
+    u += [(1, 2, 2.0 * p["c_rt"], m(x=1, y=1)),
+          (0, 1, p["c_sp"], m(x=1)), (0, 1, p["c_sp"] * p["c_sp2"], m(s=1, x=1)),
+          (0, 2, p["c_sp"], m(y=1)), (0, 2, p["c_sp"] * p["c_sp2"], m(s=1, y=1))]
+    v = [(0, 0, 1.0, m()), (0, 0, p["l_sigma"], m(s=1)), (1, 0, p["h_pi"], m(x=1)),
+         (2, 0, p["h_pi"], m(y=1)), (0, 1, p["h_sigma"], m(x=1)), (1, 1, 1.0, m()),
+         (1, 1, p["l_pi"], m(s=1)), (0, 2, p["h_sigma"], m(y=1)), (2, 2, 1.0, m()),
+         (2, 2, p["l_pi"], m(s=1))]
+    width = {}
+    for d, c in ((0, "sigma"), (1, "pi"), (2, "pi")):
+        for mu, w in ((0, "s"), (1, "p"), (2, "p")):
+            width[(d, mu)] = (p["A_%s_%s" % (c, w)], p["B_%s_%s" % (c, w)])
+    return dict(omega=[p["omega_s"], p["omega_b"], p["omega_b"], p["omega_a"]],
+                nbasis=[sizes["s"], sizes["x"], sizes["y"], sizes["a"]],
+                e_state=[p["E_sigma"], p["E_pi"], p["E_pi"]], uterms=u, vterms=v, width=width,
+                l=[0, 1, 1], K=p["K"], X=p["X"])
+
+
+def quartic_model(seed=SEED + 4, nbasis=(14, 11, 6)):
+    """A third model of the class, with the higher-order terms the paper's CO2
+    model has (Sec. III.C): three states, three modes (w = 0.12, 0.09, 0.2
+    eV), two partial waves (l = 0, 1).  U: state energies 0.9, 1.6, 2.4 eV,
+    linear, quadratic and quartic terms on the diagonal, the states coupled
+    by q_1, q_0 q_1 and q_2^2; O: 1 + a q_0 + b q_0^2 for state 0 in the
+    first wave, q_1 and q_0 q_2 for the others.  Coefficient magnitudes
+    10^U(-3, -1) eV (linear), 10^U(-3, -2) (quadratic, cross), 10^U(-4, -3)
+    (quartic), random signs; widths A = 0.2 U(0.5, 1.5), B = U(0.8, 1.2)."""
+    rng = np.random.default_rng(seed)
+
+    def c(lo, hi):
+        return float(rng.choice((-1.0, 1.0)) * 10.0 ** rng.uniform(lo, hi))
+    u = [(0, 0, c(-3, -1), [1, 0, 0]), (0, 0, c(-3, -2), [2, 0, 0]), (0, 0, c(-4, -3), [4, 0, 0]),
+         (1, 1, c(-3, -1), [1, 0, 0]), (1, 1, c(-3, -2), [0, 2, 0]), (1, 1, c(-4, -3), [0, 4, 0]),
+         (2, 2, c(-3, -1), [0, 0, 1]), (2, 2, c(-4, -3), [2, 2, 0]),
+         (0, 1, c(-3, -1), [0, 1, 0]), (0, 1, c(-3, -2), [1, 1, 0]), (1, 2, c(-3, -2), [0, 0, 2]),
+         (0, 2, c(-3, -2), [1, 0, 1])]
+    v = [(0, 0, 1.0, [0, 0, 0]), (0, 0, c(-2, -1), [1, 0, 0]), (0, 0, c(-3, -2), [2, 0, 0]),
+         (1, 0, 1.0, [0, 1, 0]), (2, 0, 0.7, [1, 0, 1]),
+         (1, 1, 1.0, [0, 0, 0]), (1, 1, c(-2, -1), [0, 0, 1]), (0, 1, 0.8, [0, 1, 0])]
+    width = {}
+    for d in range(3):
+        for mu in range(2):
+            width[(d, mu)] = (float(0.2 * rng.uniform(0.5, 1.5)), float(rng.uniform(0.8, 1.2)))
+    return dict(omega=[0.12, 0.09, 0.2], nbasis=list(nbasis), e_state=[0.9, 1.6, 2.4],
+                uterms=u, vterms=v, width=width, l=[0, 1], K=4096, X=40.0)
