@@ -451,6 +451,115 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
                          const double* x, double* y, void* workspace, size_t ws_bytes,
                          void* stream);
 
+/* ------------------------------------------------------------------------
+ * The general model of the class, given by polynomial term lists (Sec. II.A-C
+ * written for D discrete states, M vibrational modes and P partial waves;
+ * the paper's CO2 model, Sec. III.C, is of this form with higher-order terms):
+ *   H_0 = sum_k omega_k (n_k + 1/2)                                  (Eq. (21))
+ *   U_dd' = e_state[d] delta_dd' + sum of U terms c prod_k q_k^p_k   (Eq. (18))
+ *     (a U term names a pair (d, e) and adds to U_de and U_ed: U is symmetric)
+ *   V_d^mu(eps) = f_d^mu(eps) O_d^mu, O_d^mu = sum of V terms (d, mu, c, p),
+ *     2 pi (f_d^mu)^2 = Gamma_d^mu = A eps^(l + 1/2) exp(-eps/B)      (Eq. (22))
+ *   F_dd' = sum_mu (O_d^mu)^T diag(F[f_d^mu f_d'^mu](E - E_nu)) O_d'^mu  (Eqs. (19), (23))
+ *   A = E - H_0 - U - F,   Phi^{v mu}_d = f_d^mu(E - E_v) O_d^mu |v>  (Eqs. (25), (28))
+ * with q_k = (a_k + a_k^+)/sqrt 2 truncated to the basis of mode k and every
+ * monomial a product of truncated matrices.  Full vectors hold D blocks of
+ * npts = prod_k nbasis[k] values, the block of state d at d * npts, point
+ * index with the last mode fastest; N = D npts.
+ * Limits: D <= 4, M <= 8, P <= 4, powers <= 4 per mode, nbasis 1..1024,
+ * N <= 2^26; l belongs to the partial wave (equal for every state with
+ * A > 0 on it), 0..4. */
+#define VDC_MAX_STATES 4
+#define VDC_MAX_MODES 8
+#define VDC_MAX_WAVES 4
+#define VDC_MAX_POWER 4
+
+typedef struct {
+  int d, e;                  /* U: the pair of states; V: state d, partial wave e */
+  double coeff;              /* eV for U terms; dimensionless for V terms        */
+  int pow[VDC_MAX_MODES];    /* power of q_k, 0..4 (0 past n_modes)             */
+} vdc_term;
+
+typedef struct {
+  double A, B;               /* Gamma = A eps^(l+1/2) exp(-eps/B); A >= 0, B > 0 */
+  int l;                     /* 0..4                                             */
+} vdc_width;
+
+typedef struct {             /* caller-owned; copied at creation                 */
+  int n_states, n_modes, n_pw;
+  const double* omega;       /* [n_modes] eV, > 0                                */
+  const int* nbasis;         /* [n_modes]                                        */
+  const double* e_state;     /* [n_states] eV                                    */
+  int n_uterms;
+  const vdc_term* uterms;
+  int n_vterms;
+  const vdc_term* vterms;
+  const vdc_width* width;    /* [n_states][n_pw]; A = 0: no coupling            */
+  int hilbert_nodes;         /* 16..65536                                        */
+  double hilbert_xmax;       /* > 0 eV                                           */
+  int dispatch;              /* non-zero: when the terms are exactly those of
+                                vdc_model2d_desc (two states, modes g and u,
+                                waves e and o), solve with the two-state
+                                kernels (vdc_model_kind then reports 0)        */
+} vdc_model_desc;
+
+/* One right-hand side of a model built by vdc_model_create. */
+typedef struct {
+  double eps_i;              /* > 0                                              */
+  int v[VDC_MAX_MODES];      /* initial vibrational state (0 past n_modes)       */
+  int mu_i;                  /* incoming partial wave, 0..n_pw-1                 */
+  int model;                 /* index into the call's models[]                   */
+} vdc_mjob;
+
+/* Build a model from term lists (host call; allocates its device tables).
+ * The handle also serves vdc_model_destroy; the two-state entry points
+ * (vdc_solve, vdc_matvec, ...) accept it only when vdc_model_kind is 0. */
+vdc_status vdc_model_create(const vdc_model_desc* desc, vdc_model_t* out);
+
+/* 0: the two-state kernels solve it (dispatch), 1: the term-list kernels. */
+vdc_status vdc_model_kind(vdc_model_t model, int* kind);
+
+/* Workspace bytes of vdc_model_solve (room for up to 64 finals).  Host call. */
+vdc_status vdc_model_workspace_size(int n_models, const vdc_model_t* models,
+                                    const vdc_solve_opts* opts, int n_jobs, const vdc_mjob* jobs,
+                                    size_t* bytes);
+
+/* Solve Eq. (26) for every job and project T and the sigma shares.  Models
+ * of kind 0 go to vdc_solve (every option of it, including its FP64 re-solve
+ * of FP32-inner jobs); models of kind 1 run one persistent launch (after
+ * one launch for the level-shift planes of every distinct (model, E)): one
+ * workgroup per job, COCG or restarted GMRES(restart) in complex FP64,
+ * right-preconditioned by diag(A) (VDC_PREC_JACOBI) or not (VDC_PREC_NONE);
+ * FP32_INNER, BLOCK and ROWS are VDC_ERR_UNSUPPORTED there.
+ *   finals   host int [n_final][VDC_MAX_MODES] final states v_f
+ *   T_out    device c16 [n_jobs][n_final][P], P = the largest n_pw of the
+ *            models (kind 0: 2), T_{mu_f v_f <- mu_i v_i}, 0 for closed channels
+ *   sigma_out device double [n_jobs][n_final]: the job's share of Eq. (16)
+ *            (sum over mu_f); vdc_sum_partial_waves adds the mu_i shares
+ *   psi_out  device c16 [n_jobs][max N] or NULL (full layout)
+ *   info     host [n_jobs] or NULL.  Synchronises the stream. */
+vdc_status vdc_model_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                           int n_jobs, const vdc_mjob* jobs, int n_final, const int* finals,
+                           void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                           double* psi_out, vdc_job_info* info, void* stream);
+
+/* y = A(E) x on n_vec full-layout vectors (device c16 [n_vec][N] each, not
+ * overlapping) with the term-list kernels (any model from
+ * vdc_model_create): the level-shift planes at E, then the two stencil
+ * passes.  Kernel times by vdc_last_kernel_times.  Synchronises. */
+vdc_status vdc_model_apply_workspace_size(vdc_model_t model, int n_vec, size_t* bytes);
+vdc_status vdc_model_apply(vdc_model_t model, double E, int n_vec, const double* x, double* y,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/* The cross section of Eq. (16) summed over the incoming partial waves:
+ * sigma[c][f] = sum over jobs j with collision[j] = c of share[j][f]
+ * (shares from a solve call; jobs of one (eps_i, v_i) differ in mu_i),
+ * added in job order.  collision: device int [n_jobs] (indices outside
+ * 0..n_coll-1 are skipped); share: device double [n_jobs][n_final]; sigma:
+ * device double [n_coll][n_final].  Asynchronous on the stream. */
+vdc_status vdc_sum_partial_waves(int n_jobs, const int* collision, int n_coll, int n_final,
+                                 const double* share, double* sigma, void* stream);
+
 /* Thread-local text of the last error (never NULL). */
 const char* vdc_last_error(void);
 

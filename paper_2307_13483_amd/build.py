@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvdc.so")
 SOURCES = ["api.hip", "levelshift.hip", "matvec.hip", "gmres.hip", "mixed.hip", "plain.hip", "co2.hip",
-           "adjoint.hip", "cocg.hip", "eels.hip"]
+           "adjoint.hip", "cocg.hip", "eels.hip", "terms.hip"]
 ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

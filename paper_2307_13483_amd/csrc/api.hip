@@ -1,5 +1,6 @@
 // C ABI of libvdc: model build, workspace layout, job ordering and launches.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -16,6 +17,7 @@
 #include "blockops.h"
 #include "solve_args.h"
 #include "strip.h"
+#include "terms_args.h"
 
 namespace vdc {
 hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s);
@@ -53,6 +55,16 @@ using namespace vdc;
 // the device address from hipGetSymbolAddress, once per device.
 static __device__ __align__(256) unsigned char scratch[VDC_NOALLOC_SCRATCH_BYTES];
 
+// Term-list form of a model (vdc_model_create): the device model of the
+// general kernels and the device memory it points to.
+struct GenHost {
+  DevGen dev{};
+  int N = 0;                       // D npts
+  std::vector<void*> mem;          // device allocations
+  std::vector<vdc_model_t> ls;     // two-state transform models of the level shifts
+  ~GenHost();
+};
+
 struct vdc_model {
   vdc_model2d_desc desc;
   DevModel dev;
@@ -60,7 +72,15 @@ struct vdc_model {
   double* d_coef = nullptr;
   double* d_coefx = nullptr;
   double* d_clus = nullptr;
+  int kind = 0;                    // 0: two-state kernels available; 1: term lists only
+  GenHost* gen = nullptr;          // term-list form (models from vdc_model_create)
 };
+
+GenHost::~GenHost() {
+  for (void* p : mem)
+    if (p) (void)hipFree(p);
+  for (vdc_model_t m : ls) vdc_model_destroy(m);
+}
 
 namespace {
 
@@ -188,6 +208,9 @@ vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_op
   P.models.resize(n_models);
   for (int k = 0; k < n_models; ++k) {
     if (!models[k]) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+    if (models[k]->kind != 0)
+      return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form: "
+                                       "use vdc_model_solve");
     P.models[k] = models[k]->dev;
     P.max_nc = std::max(P.max_nc, models[k]->dev.Nc);
     P.max_nu = std::max(P.max_nu, models[k]->dev.Nu);
@@ -804,6 +827,7 @@ vdc_status vdc_model_destroy(vdc_model_t m) {
   if (m->d_coef) (void)hipFree(m->d_coef);
   if (m->d_coefx) (void)hipFree(m->d_coefx);
   if (m->d_clus) (void)hipFree(m->d_clus);
+  delete m->gen;
   delete m;
   return VDC_OK;
 }
@@ -994,6 +1018,7 @@ vdc_status vdc_solve_adjoint(int n_models, const vdc_model_t* models, const vdc_
 
 vdc_status vdc_level_shift(vdc_model_t m, int n_eps, const double* eps, double* out, void* stream) {
   if (!m) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+  if (m->kind != 0) return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form");
   if (n_eps < 0) return fail(VDC_ERR_INVALID_ARG, "n_eps < 0");
   if (n_eps == 0) return VDC_OK;
   if (!eps || !out) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
@@ -1018,6 +1043,7 @@ static size_t matvec_ws(const vdc_model* m, int n_vec) {
 
 vdc_status vdc_matvec_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
   if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  if (m->kind != 0) return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form");
   *bytes = matvec_ws(m, n_vec);
   return VDC_OK;
 }
@@ -1050,6 +1076,7 @@ static int strip_slab_rows(int Ng, int Nu, int n_vec) {
 
 vdc_status vdc_matvec_block_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
   if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  if (m->kind != 0) return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form");
   *bytes = matvec_block_ws(m) + align256(sizeof(int) * std::max(1, n_vec));
   return VDC_OK;
 }
@@ -1058,6 +1085,7 @@ vdc_status vdc_matvec_block(vdc_model_t m, double E, int n_vec, const int* parit
                             const double* x, double* y, void* workspace, size_t ws_bytes,
                             void* stream) {
   if (!m) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+  if (m->kind != 0) return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form");
   if (n_vec < 0 || !std::isfinite(E)) return fail(VDC_ERR_INVALID_ARG, "bad n_vec or E");
   if (n_vec == 0) return VDC_OK;
   if (!parity || !x || !y || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
@@ -1121,6 +1149,7 @@ vdc_status vdc_matvec_block(vdc_model_t m, double E, int n_vec, const int* parit
 vdc_status vdc_matvec(vdc_model_t m, double E, int n_vec, const int* parity, const double* x,
                       double* y, void* workspace, size_t ws_bytes, void* stream) {
   if (!m) return fail(VDC_ERR_INVALID_ARG, "NULL model");
+  if (m->kind != 0) return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form");
   if (n_vec < 0 || !std::isfinite(E)) return fail(VDC_ERR_INVALID_ARG, "bad n_vec or E");
   if (n_vec == 0) return VDC_OK;
   if (!parity || !x || !y || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
@@ -1190,6 +1219,7 @@ size_t eels_groups(int n_jobs) { return (size_t)std::max(1, std::min(n_jobs, cu_
 
 vdc_status vdc_eels_workspace_size(vdc_model_t model, int n_jobs, size_t* bytes) {
   if (!model || !bytes || n_jobs < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  if (model->kind != 0) return fail(VDC_ERR_INVALID_ARG, "a model built from term lists without the two-state form");
   const int Nc = model->dev.Nc;
   size_t off = 0;
   off = align256(off + sizeof(DevModel));
@@ -1680,3 +1710,721 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
   }
   return VDC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// The general model given by polynomial term lists (vdc_model_create etc.)
+
+namespace {
+
+using PowKey = std::array<int, kGenMaxModes>;
+
+// Canonical form of a term list: coefficients summed per (state pair or
+// state and wave, powers); zero sums dropped.
+struct Canon {
+  std::map<std::tuple<int, int, PowKey>, double> u;   // (d <= e, powers)
+  std::map<std::tuple<int, int, PowKey>, double> v;   // (d, mu, powers)
+};
+
+PowKey powkey(const vdc_term& t) {
+  PowKey k{};
+  for (int i = 0; i < kGenMaxModes; ++i) k[i] = t.pow[i];
+  return k;
+}
+
+vdc_status check_desc(const vdc_model_desc* d, Canon& c) {
+  if (d->n_states < 1 || d->n_states > VDC_MAX_STATES)
+    return fail(VDC_ERR_INVALID_ARG, "n_states must be 1..4");
+  if (d->n_modes < 1 || d->n_modes > VDC_MAX_MODES)
+    return fail(VDC_ERR_INVALID_ARG, "n_modes must be 1..8");
+  if (d->n_pw < 1 || d->n_pw > VDC_MAX_WAVES) return fail(VDC_ERR_INVALID_ARG, "n_pw must be 1..4");
+  if (!d->omega || !d->nbasis || !d->e_state || !d->width)
+    return fail(VDC_ERR_INVALID_ARG, "omega, nbasis, e_state and width must be non-NULL");
+  if (d->n_uterms < 0 || d->n_vterms < 0 || (d->n_uterms > 0 && !d->uterms) ||
+      (d->n_vterms > 0 && !d->vterms))
+    return fail(VDC_ERR_INVALID_ARG, "bad term list");
+  if (d->hilbert_nodes < 16 || d->hilbert_nodes > 65536)
+    return fail(VDC_ERR_INVALID_ARG, "hilbert_nodes must be 16..65536");
+  if (!(d->hilbert_xmax > 0.0) || !std::isfinite(d->hilbert_xmax))
+    return fail(VDC_ERR_INVALID_ARG, "hilbert_xmax must be > 0");
+  size_t npts = 1;
+  for (int k = 0; k < d->n_modes; ++k) {
+    if (!(d->omega[k] > 0.0) || !std::isfinite(d->omega[k]))
+      return fail(VDC_ERR_INVALID_ARG, "vibrational frequencies must be finite and > 0");
+    if (d->nbasis[k] < 1 || d->nbasis[k] > kSqMax)
+      return fail(VDC_ERR_INVALID_ARG, "basis sizes must be 1..1024");
+    npts *= (size_t)d->nbasis[k];
+  }
+  if (npts * d->n_states > ((size_t)1 << 26)) return fail(VDC_ERR_INVALID_ARG, "basis too large");
+  for (int s = 0; s < d->n_states; ++s)
+    if (!std::isfinite(d->e_state[s])) return fail(VDC_ERR_INVALID_ARG, "non-finite state energy");
+  for (int mu = 0; mu < d->n_pw; ++mu) {
+    int lmu = -1;
+    for (int s = 0; s < d->n_states; ++s) {
+      const vdc_width& w = d->width[s * d->n_pw + mu];
+      if (!(w.A >= 0.0) || !std::isfinite(w.A))
+        return fail(VDC_ERR_INVALID_ARG, "width amplitudes A must be finite and >= 0");
+      if (!(w.B > 0.0) || !std::isfinite(w.B))
+        return fail(VDC_ERR_INVALID_ARG, "width scales B must be finite and > 0");
+      if (w.l < 0 || w.l > 4) return fail(VDC_ERR_INVALID_ARG, "l must be 0..4");
+      if (w.A > 0.0) {
+        if (lmu >= 0 && w.l != lmu)
+          return fail(VDC_ERR_INVALID_ARG, "the threshold exponent l belongs to the partial wave: "
+                                           "equal for every state coupled to it");
+        lmu = w.l;
+      }
+    }
+  }
+  auto check_term = [&](const vdc_term& t, int emax) -> bool {
+    if (t.d < 0 || t.d >= d->n_states || t.e < 0 || t.e >= emax) return false;
+    if (!std::isfinite(t.coeff)) return false;
+    for (int k = 0; k < kGenMaxModes; ++k) {
+      if (t.pow[k] < 0 || t.pow[k] > VDC_MAX_POWER) return false;
+      if (k >= d->n_modes && t.pow[k] != 0) return false;
+    }
+    return true;
+  };
+  for (int i = 0; i < d->n_uterms; ++i) {
+    const vdc_term& t = d->uterms[i];
+    if (!check_term(t, d->n_states))
+      return fail(VDC_ERR_INVALID_ARG, "bad U term " + std::to_string(i) +
+                                           ": states, finite coefficient, powers 0..4 on the modes");
+    c.u[std::make_tuple(std::min(t.d, t.e), std::max(t.d, t.e), powkey(t))] += t.coeff;
+  }
+  for (int i = 0; i < d->n_vterms; ++i) {
+    const vdc_term& t = d->vterms[i];
+    if (!check_term(t, d->n_pw))
+      return fail(VDC_ERR_INVALID_ARG, "bad V term " + std::to_string(i) +
+                                           ": state, wave, finite coefficient, powers 0..4");
+    c.v[std::make_tuple(t.d, t.e, powkey(t))] += t.coeff;
+  }
+  for (auto it = c.u.begin(); it != c.u.end();) it = it->second == 0.0 ? c.u.erase(it) : std::next(it);
+  for (auto it = c.v.begin(); it != c.v.end();) it = it->second == 0.0 ? c.v.erase(it) : std::next(it);
+  return VDC_OK;
+}
+
+// The two-state generalized model in the descriptor (and the caller allows
+// its kernels): fill the two-state descriptor.
+bool as_two_state(const vdc_model_desc* d, const Canon& c, vdc_model2d_desc& o) {
+  if (!d->dispatch || d->n_states != 2 || d->n_modes != 2 || d->n_pw != 2) return false;
+  const PowKey g{1, 0}, u{0, 1}, one{};
+  double kap[2] = {0.0, 0.0}, lam = 0.0;
+  for (const auto& t : c.u) {
+    const int a = std::get<0>(t.first), b = std::get<1>(t.first);
+    const PowKey& p = std::get<2>(t.first);
+    if (a == b && p == g) kap[a] = t.second;
+    else if (a == 0 && b == 1 && p == u) lam = t.second;
+    else return false;
+  }
+  double lamd[2] = {0.0, 0.0};
+  int seen = 0;
+  for (const auto& t : c.v) {
+    const int a = std::get<0>(t.first), mu = std::get<1>(t.first);
+    const PowKey& p = std::get<2>(t.first);
+    if (a == mu && p == one && t.second == 1.0) seen |= 1 << (2 * a + mu);
+    else if (a == mu && p == g) lamd[a] = t.second;
+    else if (a != mu && p == u && t.second == 1.0) seen |= 1 << (2 * a + mu);
+    else return false;
+  }
+  if (seen != 15) return false;
+  o = vdc_model2d_desc{};
+  o.omega_g = d->omega[0];
+  o.omega_u = d->omega[1];
+  o.kappa1 = kap[0];
+  o.kappa2 = kap[1];
+  o.lam = lam;
+  o.lam1 = lamd[0];
+  o.lam2 = lamd[1];
+  o.E1 = d->e_state[0];
+  o.gap = d->e_state[1] - d->e_state[0];
+  for (int s = 0; s < 2; ++s)
+    for (int mu = 0; mu < 2; ++mu) {
+      o.A[s][mu] = d->width[s * 2 + mu].A;
+      o.B[s][mu] = d->width[s * 2 + mu].B;
+    }
+  for (int mu = 0; mu < 2; ++mu)
+    o.l[mu] = d->width[0 * 2 + mu].A > 0.0 ? d->width[mu].l : d->width[2 + mu].l;
+  o.Ng = d->nbasis[0];
+  o.Nu = d->nbasis[1];
+  o.hilbert_nodes = d->hilbert_nodes;
+  o.hilbert_xmax = d->hilbert_xmax;
+  return true;
+}
+
+template <typename T>
+vdc_status upload(GenHost& G, const std::vector<T>& h, const T** out) {
+  void* p = nullptr;
+  const size_t n = std::max<size_t>(1, h.size()) * sizeof(T);
+  HIPCHK(hipMalloc(&p, n));
+  G.mem.push_back(p);
+  if (!h.empty()) HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = reinterpret_cast<const T*>(p);
+  return VDC_OK;
+}
+
+// Rows of (P q P)^p for p = 0..4 on an n-function basis: table[(p n + m) kGenQW
+// + delta + 4] = <m|(P q P)^p|m + delta>.
+std::vector<double> power_rows(int n) {
+  std::vector<double> t((size_t)(kGenMaxPow + 1) * n * kGenQW, 0.0);
+  auto at = [&](int p, int m, int dl) -> double& {
+    return t[((size_t)p * n + m) * kGenQW + dl + kGenMaxPow];
+  };
+  for (int m = 0; m < n; ++m) at(0, m, 0) = 1.0;
+  // (M q)[m][j] = sum_i M[m][i] q[i][j], q[i][i+1] = q[i+1][i] = sqrt((i+1)/2)
+  for (int p = 1; p <= kGenMaxPow; ++p)
+    for (int m = 0; m < n; ++m)
+      for (int dl = -p; dl <= p; ++dl) {
+        const int j = m + dl;
+        if (j < 0 || j >= n) continue;
+        double s = 0.0;
+        for (int dd = -(p - 1); dd <= p - 1; ++dd) {
+          const int i = m + dd;
+          if (i < 0 || i >= n || std::abs(i - j) != 1) continue;
+          s += at(p - 1, m, dd) * std::sqrt(0.5 * std::max(i, j));
+        }
+        at(p, m, dl) = s;
+      }
+  return t;
+}
+
+// Compile one operator (monomials with their coefficients) into stencil
+// points: the distinct offset vectors, each with the monomials reaching it.
+GenOp compile_op(const std::vector<std::pair<PowKey, double>>& mono, const DevGen& g,
+                 std::vector<GenPoint>& pts, std::vector<GenTerm>& terms) {
+  std::map<std::array<int, kGenMaxModes>, std::vector<int>> by_off;
+  for (size_t t = 0; t < mono.size(); ++t) {
+    const PowKey& p = mono[t].first;
+    std::array<int, kGenMaxModes> dl{};
+    // odometer over delta_k in {-p_k, -p_k + 2, ..., p_k}
+    for (int k = 0; k < kGenMaxModes; ++k) dl[k] = -p[k];
+    for (;;) {
+      by_off[dl].push_back((int)t);
+      int k = g.M - 1;
+      while (k >= 0) {
+        dl[k] += 2;
+        if (dl[k] <= p[k]) break;
+        dl[k] = -p[k];
+        --k;
+      }
+      if (k < 0) break;
+    }
+  }
+  GenOp op{(int)pts.size(), (int)by_off.size()};
+  for (const auto& e : by_off) {
+    GenPoint pt{};
+    pt.off = 0;
+    pt.zero = 1;
+    for (int k = 0; k < kGenMaxModes; ++k) {
+      pt.dl[k] = (signed char)e.first[k];
+      if (k < g.M) pt.off += e.first[k] * g.stride[k];
+      if (e.first[k] != 0) pt.zero = 0;
+    }
+    pt.t0 = (int)terms.size();
+    pt.nt = (int)e.second.size();
+    for (int t : e.second) {
+      GenTerm tm{};
+      tm.c = mono[t].second;
+      for (int k = 0; k < kGenMaxModes; ++k) tm.pw[k] = (signed char)mono[t].first[k];
+      terms.push_back(tm);
+    }
+    pts.push_back(pt);
+  }
+  return op;
+}
+
+vdc_status build_gen(const vdc_model_desc* d, const Canon& c, GenHost& G) {
+  DevGen& g = G.dev;
+  g.D = d->n_states;
+  g.M = d->n_modes;
+  g.P = d->n_pw;
+  g.npts = 1;
+  for (int k = 0; k < g.M; ++k) {
+    g.n[k] = d->nbasis[k];
+    g.omega[k] = d->omega[k];
+    g.npts *= g.n[k];
+  }
+  int st = 1;
+  for (int k = g.M - 1; k >= 0; --k) {
+    g.stride[k] = st;
+    st *= g.n[k];
+  }
+  G.N = g.D * g.npts;
+  for (int s = 0; s < g.D; ++s) g.e_state[s] = d->e_state[s];
+  for (int s = 0; s < g.D; ++s)
+    for (int mu = 0; mu < g.P; ++mu) {
+      g.A[s][mu] = d->width[s * g.P + mu].A;
+      g.B[s][mu] = d->width[s * g.P + mu].B;
+    }
+  for (int mu = 0; mu < g.P; ++mu) {
+    g.l[mu] = 0;
+    for (int s = 0; s < g.D; ++s)
+      if (d->width[s * g.P + mu].A > 0.0) g.l[mu] = d->width[s * g.P + mu].l;
+  }
+  // operators
+  std::vector<GenPoint> pts;
+  std::vector<GenTerm> terms;
+  for (int a = 0; a < g.D; ++a)
+    for (int b = a; b < g.D; ++b) {
+      std::vector<std::pair<PowKey, double>> mono;
+      for (const auto& t : c.u)
+        if (std::get<0>(t.first) == a && std::get<1>(t.first) == b)
+          mono.emplace_back(std::get<2>(t.first), t.second);
+      GenOp op{0, 0};
+      if (!mono.empty()) op = compile_op(mono, g, pts, terms);
+      g.uop[a][b] = g.uop[b][a] = op;
+    }
+  for (int a = 0; a < g.D; ++a)
+    for (int mu = 0; mu < g.P; ++mu) {
+      std::vector<std::pair<PowKey, double>> mono;
+      for (const auto& t : c.v)
+        if (std::get<0>(t.first) == a && std::get<1>(t.first) == mu)
+          mono.emplace_back(std::get<2>(t.first), t.second);
+      g.vop[a][mu] = mono.empty() ? GenOp{0, 0} : compile_op(mono, g, pts, terms);
+    }
+  // level-shift planes F^mu_de: both states couple to mu (O != 0, A > 0)
+  g.nplanes = 0;
+  auto couples = [&](int s, int mu) { return g.vop[s][mu].np > 0 && g.A[s][mu] > 0.0; };
+  for (int mu = 0; mu < kGenMaxWaves; ++mu)
+    for (int a = 0; a < kGenMaxStates; ++a)
+      for (int b = 0; b < kGenMaxStates; ++b) g.fplane[mu][a][b] = -1;
+  for (int mu = 0; mu < g.P; ++mu)
+    for (int a = 0; a < g.D; ++a)
+      for (int b = a; b < g.D; ++b)
+        if (couples(a, mu) && couples(b, mu)) g.fplane[mu][a][b] = g.fplane[mu][b][a] = g.nplanes++;
+  g.nw = 0;
+  for (int mu = 0; mu < kGenMaxWaves; ++mu)
+    for (int a = 0; a < kGenMaxStates; ++a) g.wplane[mu][a] = -1;
+  for (int mu = 0; mu < g.P; ++mu)
+    for (int a = 0; a < g.D; ++a)
+      if (couples(a, mu)) g.wplane[mu][a] = g.nw++;
+  // two-state transform models: slots (mu, a, b) covering F_aa, F_ab, F_bb,
+  // two slots (waves mu' = 0, 1 of the descriptor) per model
+  struct Slot { int mu, a, b; };
+  std::vector<Slot> slots;
+  std::vector<char> covered(g.nplanes > 0 ? g.nplanes : 1, 0);
+  for (int mu = 0; mu < g.P; ++mu) {
+    for (int a = 0; a < g.D; ++a)
+      for (int b = a + 1; b < g.D; ++b)
+        if (g.fplane[mu][a][b] >= 0) slots.push_back(Slot{mu, a, b});
+    for (int a = 0; a < g.D; ++a)
+      if (g.fplane[mu][a][a] >= 0) slots.push_back(Slot{mu, a, a});
+  }
+  std::vector<DevModel> lsm;
+  std::vector<int> lsmap;
+  for (size_t s0 = 0; s0 < slots.size(); s0 += 2) {
+    vdc_model2d_desc ld{};
+    ld.omega_g = ld.omega_u = 1.0;
+    ld.Ng = ld.Nu = 1;
+    ld.hilbert_nodes = d->hilbert_nodes;
+    ld.hilbert_xmax = d->hilbert_xmax;
+    std::array<int, kNumF> map;
+    map.fill(-1);
+    for (int w = 0; w < 2; ++w) {
+      ld.A[0][w] = ld.A[1][w] = 0.0;
+      ld.B[0][w] = ld.B[1][w] = 1.0;
+      ld.l[w] = 0;
+      if (s0 + w >= slots.size()) continue;
+      const Slot& sl = slots[s0 + w];
+      ld.A[0][w] = g.A[sl.a][sl.mu];
+      ld.B[0][w] = g.B[sl.a][sl.mu];
+      ld.A[1][w] = g.A[sl.b][sl.mu];
+      ld.B[1][w] = g.B[sl.b][sl.mu];
+      ld.l[w] = g.l[sl.mu];
+      const int pairs[3][2] = {{sl.a, sl.a}, {sl.a, sl.b}, {sl.b, sl.b}};
+      for (int pq = 0; pq < 3; ++pq) {
+        const int pl = g.fplane[sl.mu][pairs[pq][0]][pairs[pq][1]];
+        if (pl >= 0 && !covered[pl]) {
+          covered[pl] = 1;
+          map[fidx(w, pq)] = pl;
+        }
+      }
+    }
+    vdc_model_t m2 = nullptr;
+    const vdc_status st2 = vdc_model2d_create(&ld, &m2);
+    if (st2 != VDC_OK) return st2;
+    G.ls.push_back(m2);
+    lsm.push_back(m2->dev);
+    for (int f = 0; f < kNumF; ++f) lsmap.push_back(map[f]);
+  }
+  g.nlsm = (int)lsm.size();
+  // tables of powers of the truncated coordinate, E_nu and the point order
+  std::vector<double> qtab;
+  for (int k = 0; k < g.M; ++k) {
+    g.qoff[k] = (int)qtab.size();
+    const std::vector<double> t = power_rows(g.n[k]);
+    qtab.insert(qtab.end(), t.begin(), t.end());
+  }
+  std::vector<double> Enu(g.npts);
+  for (int i = 0; i < g.npts; ++i) {
+    int r = i;
+    double e = 0.0;
+    for (int k = g.M - 1; k >= 0; --k) {
+      const int nk = r % g.n[k];
+      r /= g.n[k];
+      e += g.omega[k] * (nk + 0.5);
+    }
+    Enu[i] = e;
+  }
+  std::vector<int> perm(g.npts);
+  for (int i = 0; i < g.npts; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return Enu[a] < Enu[b]; });
+  vdc_status st3;
+  if ((st3 = upload(G, qtab, &g.qtab)) != VDC_OK) return st3;
+  if ((st3 = upload(G, pts, &g.pts)) != VDC_OK) return st3;
+  if ((st3 = upload(G, terms, &g.terms)) != VDC_OK) return st3;
+  if ((st3 = upload(G, Enu, &g.Enu)) != VDC_OK) return st3;
+  if ((st3 = upload(G, perm, &g.perm)) != VDC_OK) return st3;
+  if ((st3 = upload(G, lsm, &g.lsm)) != VDC_OK) return st3;
+  if ((st3 = upload(G, lsmap, &g.lsmap)) != VDC_OK) return st3;
+  return VDC_OK;
+}
+
+// Plan of a batched solve of term-list models (workspace layout).
+struct GenPlan {
+  std::vector<DevGen> models;
+  std::vector<GenJob> jobs;
+  std::vector<GenTab> tabs;
+  size_t table_elems = 0, ld = 0, wld = 0, slot_elems = 0;
+  int n_groups = 0, max_npts = 0, max_nlsm = 0, n_pw = 0;
+  size_t off_counter, off_models, off_jobs, off_tabs, off_finals, off_info, off_tables,
+      off_scratch, total;
+};
+
+vdc_status gen_plan(int n_models, const vdc_model_t* models, const vdc_solve_opts* o, int n_jobs,
+                    const vdc_mjob* jobs, int n_final, GenPlan& P) {
+  if (n_models <= 0 || !models) return fail(VDC_ERR_INVALID_ARG, "no models");
+  if (!o) return fail(VDC_ERR_INVALID_ARG, "opts is NULL");
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(VDC_ERR_INVALID_ARG, "bad job list");
+  if (n_final < 0 || n_final > kMaxFinal) return fail(VDC_ERR_INVALID_ARG, "n_final must be 0..64");
+  if (o->method != VDC_GMRES && o->method != VDC_COCG)
+    return fail(VDC_ERR_INVALID_ARG, "unknown method");
+  if (o->method == VDC_GMRES && (o->restart < 1 || o->restart > kMaxRestart))
+    return fail(VDC_ERR_INVALID_ARG, "restart must be 1..128");
+  if (o->max_iter < 1) return fail(VDC_ERR_INVALID_ARG, "max_iter must be >= 1");
+  if (!(o->tol > 0.0)) return fail(VDC_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->precision != VDC_FP64)
+    return fail(VDC_ERR_UNSUPPORTED, "term-list models are solved in FP64 only");
+  if (o->precond != VDC_PREC_NONE && o->precond != VDC_PREC_JACOBI)
+    return fail(VDC_ERR_UNSUPPORTED, "term-list models take VDC_PREC_NONE or VDC_PREC_JACOBI");
+  size_t maxN = 1, maxW = 1;
+  for (int k = 0; k < n_models; ++k) {
+    if (!models[k] || !models[k]->gen)
+      return fail(VDC_ERR_INVALID_ARG, "every model must come from vdc_model_create");
+    const DevGen& g = models[k]->gen->dev;
+    P.models.push_back(g);
+    maxN = std::max(maxN, (size_t)g.D * g.npts);
+    maxW = std::max(maxW, (size_t)g.nw * g.npts);
+    P.max_npts = std::max(P.max_npts, g.npts);
+    P.max_nlsm = std::max(P.max_nlsm, g.nlsm);
+    P.n_pw = std::max(P.n_pw, g.P);
+  }
+  std::map<std::pair<int, double>, int> tab_index;
+  P.jobs.resize(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) {
+    const vdc_mjob& jb = jobs[j];
+    if (jb.model < 0 || jb.model >= n_models)
+      return fail(VDC_ERR_INVALID_ARG, "job model index out of range");
+    const DevGen& g = P.models[jb.model];
+    if (!(jb.eps_i > 0.0) || !std::isfinite(jb.eps_i))
+      return fail(VDC_ERR_INVALID_ARG, "eps_i must be > 0 (open entrance channel)");
+    if (jb.mu_i < 0 || jb.mu_i >= g.P) return fail(VDC_ERR_INVALID_ARG, "mu_i outside the model's waves");
+    GenJob& o2 = P.jobs[j];
+    for (int k = 0; k < kGenMaxModes; ++k) {
+      o2.v[k] = k < g.M ? jb.v[k] : 0;
+      if (k >= g.M && jb.v[k] != 0) return fail(VDC_ERR_INVALID_ARG, "v_i has entries past n_modes");
+    }
+    if (gen_flat(g, o2.v) < 0) return fail(VDC_ERR_INVALID_ARG, "v_i outside the basis");
+    o2.eps_i = jb.eps_i;
+    o2.E = jb.eps_i + gen_vib_energy(g, o2.v);
+    o2.mu = jb.mu_i;
+    o2.model = jb.model;
+    o2.out = j;
+    auto key = std::make_pair(jb.model, o2.E);
+    auto it = tab_index.find(key);
+    if (it == tab_index.end()) {
+      GenTab t{};
+      t.E = o2.E;
+      t.model = jb.model;
+      t.offset = P.table_elems;
+      P.table_elems += (size_t)g.nplanes * g.npts;
+      it = tab_index.emplace(key, (int)P.tabs.size()).first;
+      P.tabs.push_back(t);
+    }
+    o2.table = it->second;
+  }
+  if (P.tabs.size() > 65535) return fail(VDC_ERR_INVALID_ARG, "more than 65535 distinct energies");
+  // longest first: unknowns x energy
+  std::stable_sort(P.jobs.begin(), P.jobs.end(), [&](const GenJob& a, const GenJob& b) {
+    const DevGen& ga = P.models[a.model];
+    const DevGen& gb = P.models[b.model];
+    return (double)ga.D * ga.npts * (0.5 + a.E) > (double)gb.D * gb.npts * (0.5 + b.E);
+  });
+  P.ld = (maxN + 63) / 64 * 64;
+  P.wld = (maxW + 63) / 64 * 64;
+  const int m = o->method == VDC_COCG ? 3 : o->restart + 1;
+  P.slot_elems = 4 * P.ld + P.wld + (size_t)m * P.ld +
+                 (o->method == VDC_COCG ? 0 : (size_t)(o->restart + 1) * o->restart);
+  P.slot_elems = (P.slot_elems + 31) / 32 * 32;
+  P.n_groups = std::max(1, std::min(n_jobs, cu_count() * gen_solve_occupancy()));
+  size_t off = 0;
+  P.off_counter = off; off += 256;
+  P.off_models = off; off = align256(off + sizeof(DevGen) * n_models);
+  P.off_jobs = off; off = align256(off + sizeof(GenJob) * std::max(1, n_jobs));
+  P.off_tabs = off; off = align256(off + sizeof(GenTab) * std::max<size_t>(1, P.tabs.size()));
+  P.off_finals = off; off = align256(off + sizeof(int) * kGenMaxModes * std::max(1, n_final));
+  P.off_info = off; off = align256(off + sizeof(DevInfo) * std::max(1, n_jobs));
+  P.off_tables = off; off = align256(off + sizeof(c64) * P.table_elems);
+  P.off_scratch = off; off = align256(off + sizeof(c64) * P.slot_elems * P.n_groups);
+  P.total = off;
+  return VDC_OK;
+}
+
+// All models have the two-state form: the job list in that form.
+bool all_two_state(int n_models, const vdc_model_t* models) {
+  for (int k = 0; k < n_models; ++k)
+    if (!models[k] || models[k]->kind != 0) return false;
+  return true;
+}
+
+vdc_status to_two_state_jobs(int n_jobs, const vdc_mjob* jobs, int n_final, const int* finals,
+                             std::vector<vdc_job>& j2, std::vector<int>& f2) {
+  j2.resize(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) {
+    for (int k = 2; k < VDC_MAX_MODES; ++k)
+      if (jobs[j].v[k] != 0) return fail(VDC_ERR_INVALID_ARG, "v_i has entries past n_modes");
+    j2[j] = vdc_job{jobs[j].eps_i, jobs[j].v[0], jobs[j].v[1], jobs[j].mu_i, jobs[j].model};
+  }
+  f2.resize(2 * std::max(1, n_final));
+  for (int f = 0; f < n_final; ++f) {
+    f2[2 * f] = finals[f * VDC_MAX_MODES];
+    f2[2 * f + 1] = finals[f * VDC_MAX_MODES + 1];
+  }
+  return VDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vdc_status vdc_model_create(const vdc_model_desc* d, vdc_model_t* out) {
+  if (!d || !out) return fail(VDC_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  Canon c;
+  vdc_status st = check_desc(d, c);
+  if (st != VDC_OK) return st;
+  vdc_model2d_desc d2;
+  vdc_model_t m = nullptr;
+  if (as_two_state(d, c, d2)) {
+    st = vdc_model2d_create(&d2, &m);
+    if (st != VDC_OK) return st;
+  } else {
+    m = new vdc_model();
+    m->desc = vdc_model2d_desc{};
+    m->dev = DevModel{};
+    m->kind = 1;
+  }
+  m->gen = new GenHost();
+  st = build_gen(d, c, *m->gen);
+  if (st != VDC_OK) {
+    vdc_model_destroy(m);
+    return st;
+  }
+  *out = m;
+  return VDC_OK;
+}
+
+vdc_status vdc_model_kind(vdc_model_t m, int* kind) {
+  if (!m || !kind) return fail(VDC_ERR_INVALID_ARG, "NULL argument");
+  *kind = m->kind;
+  return VDC_OK;
+}
+
+vdc_status vdc_model_workspace_size(int n_models, const vdc_model_t* models,
+                                    const vdc_solve_opts* opts, int n_jobs, const vdc_mjob* jobs,
+                                    size_t* bytes) {
+  if (!bytes) return fail(VDC_ERR_INVALID_ARG, "bytes is NULL");
+  if (n_models > 0 && models && all_two_state(n_models, models)) {
+    std::vector<vdc_job> j2;
+    std::vector<int> f2;
+    vdc_status st = to_two_state_jobs(n_jobs, jobs, 0, nullptr, j2, f2);
+    if (st != VDC_OK) return st;
+    return vdc_workspace_size(n_models, models, opts, n_jobs, j2.data(), bytes);
+  }
+  GenPlan P;
+  vdc_status st = gen_plan(n_models, models, opts, n_jobs, jobs, kMaxFinal, P);
+  if (st != VDC_OK) return st;
+  *bytes = P.total;
+  return VDC_OK;
+}
+
+vdc_status vdc_model_solve(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                           int n_jobs, const vdc_mjob* jobs, int n_final, const int* finals,
+                           void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                           double* psi_out, vdc_job_info* info, void* stream) {
+  if (n_final > 0 && !finals) return fail(VDC_ERR_INVALID_ARG, "finals is NULL");
+  if (n_models > 0 && models && all_two_state(n_models, models)) {
+    std::vector<vdc_job> j2;
+    std::vector<int> f2;
+    vdc_status st = to_two_state_jobs(n_jobs, jobs, n_final, finals, j2, f2);
+    if (st != VDC_OK) return st;
+    return vdc_solve(n_models, models, opts, n_jobs, j2.data(), n_final, f2.data(), workspace,
+                     ws_bytes, T_out, sigma_out, psi_out, info, stream);
+  }
+  GenPlan P;
+  vdc_status st = gen_plan(n_models, models, opts, n_jobs, jobs, n_final, P);
+  if (st != VDC_OK || n_jobs == 0) return st;
+  if (!workspace) return fail(VDC_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total)
+    return fail(VDC_ERR_WORKSPACE, "workspace too small: need " + std::to_string(P.total) +
+                                       " bytes, got " + std::to_string(ws_bytes));
+  if (n_final > 0 && (!T_out || !sigma_out))
+    return fail(VDC_ERR_INVALID_ARG, "T_out/sigma_out must be non-NULL when n_final > 0");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  std::vector<int> fin((size_t)kGenMaxModes * std::max(1, n_final), 0);
+  for (int f = 0; f < n_final; ++f)
+    for (int k = 0; k < kGenMaxModes; ++k) fin[(size_t)f * kGenMaxModes + k] = finals[f * VDC_MAX_MODES + k];
+  HIPCHK(hipMemcpyAsync(ws + P.off_models, P.models.data(), sizeof(DevGen) * n_models,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_jobs, P.jobs.data(), sizeof(GenJob) * n_jobs,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_tabs, P.tabs.data(), sizeof(GenTab) * P.tabs.size(),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + P.off_finals, fin.data(), sizeof(int) * fin.size(),
+                        hipMemcpyHostToDevice, s));
+  GenArgs a{};
+  a.models = reinterpret_cast<const DevGen*>(ws + P.off_models);
+  a.jobs = reinterpret_cast<const GenJob*>(ws + P.off_jobs);
+  a.n_jobs = n_jobs;
+  a.tabs = reinterpret_cast<const GenTab*>(ws + P.off_tabs);
+  a.tables = reinterpret_cast<const c64*>(ws + P.off_tables);
+  a.counter = reinterpret_cast<int*>(ws + P.off_counter);
+  a.scratch = reinterpret_cast<c64*>(ws + P.off_scratch);
+  a.slot_elems = P.slot_elems;
+  a.ld = P.ld;
+  a.wld = P.wld;
+  a.method = opts->method;
+  a.m = opts->restart;
+  a.max_iter = opts->max_iter;
+  a.tol = opts->tol;
+  a.precond = opts->precond;
+  a.n_final = n_final;
+  a.finals = reinterpret_cast<const int*>(ws + P.off_finals);
+  a.n_pw = P.n_pw;
+  a.T_out = reinterpret_cast<c64*>(T_out);
+  a.sigma_out = sigma_out;
+  a.psi_out = reinterpret_cast<c64*>(psi_out);
+  a.psi_ld = P.ld;
+  size_t maxN = 0;
+  for (const DevGen& g : P.models) maxN = std::max(maxN, (size_t)g.D * g.npts);
+  a.psi_ld = maxN;
+  a.info = reinterpret_cast<DevInfo*>(ws + P.off_info);
+  EventSet ev;
+  HIPCHK(launch_zero_int(a.counter, 64, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  HIPCHK(launch_gen_planes(a.models, a.tabs, (int)P.tabs.size(), P.max_npts, P.max_nlsm,
+                           reinterpret_cast<c64*>(ws + P.off_tables), s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  HIPCHK(launch_gen_solve(a, P.n_groups, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  std::vector<DevInfo> hinfo(n_jobs);
+  HIPCHK(hipMemcpyAsync(hinfo.data(), ws + P.off_info, sizeof(DevInfo) * n_jobs,
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t1 = 0.f, t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = t1;
+    g_ms_solver = t2;
+  }
+  if (info)
+    for (int j = 0; j < n_jobs; ++j)
+      info[j] = vdc_job_info{hinfo[j].status, hinfo[j].iters, hinfo[j].restarts, 0,
+                             hinfo[j].rel_res, hinfo[j].alg_bytes};
+  return VDC_OK;
+}
+
+static size_t gen_apply_ws(const GenHost& G, int n_vec, size_t* off_tab, size_t* off_tables,
+                           size_t* off_w) {
+  size_t off = align256(sizeof(DevGen));
+  *off_tab = off;
+  off = align256(off + sizeof(GenTab));
+  *off_tables = off;
+  off = align256(off + sizeof(c64) * (size_t)std::max(1, G.dev.nplanes) * G.dev.npts);
+  *off_w = off;
+  off = align256(off + sizeof(c64) * (size_t)std::max(1, G.dev.nw) * G.dev.npts *
+                           std::max(1, n_vec));
+  return off;
+}
+
+vdc_status vdc_model_apply_workspace_size(vdc_model_t m, int n_vec, size_t* bytes) {
+  if (!m || !bytes || n_vec < 0) return fail(VDC_ERR_INVALID_ARG, "bad argument");
+  if (!m->gen) return fail(VDC_ERR_UNSUPPORTED, "the model has no term-list form (vdc_model2d_create)");
+  size_t a, b, c;
+  *bytes = gen_apply_ws(*m->gen, n_vec, &a, &b, &c);
+  return VDC_OK;
+}
+
+vdc_status vdc_model_apply(vdc_model_t m, double E, int n_vec, const double* x, double* y,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  size_t need = 0;
+  vdc_status st = vdc_model_apply_workspace_size(m, n_vec, &need);
+  if (st != VDC_OK) return st;
+  if (n_vec == 0) return VDC_OK;
+  if (!std::isfinite(E)) return fail(VDC_ERR_INVALID_ARG, "E must be finite");
+  if (!x || !y || !workspace) return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(VDC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(VDC_ERR_WORKSPACE, "workspace too small");
+  const GenHost& G = *m->gen;
+  const size_t N = (size_t)G.N;
+  if (reinterpret_cast<const char*>(x) < reinterpret_cast<const char*>(y) + sizeof(c64) * N * n_vec &&
+      reinterpret_cast<const char*>(y) < reinterpret_cast<const char*>(x) + sizeof(c64) * N * n_vec)
+    return fail(VDC_ERR_INVALID_ARG, "x and y must not overlap");
+  size_t off_tab, off_tables, off_w;
+  gen_apply_ws(G, n_vec, &off_tab, &off_tables, &off_w);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  GenTab tb{};
+  tb.E = E;
+  tb.model = 0;
+  tb.offset = 0;
+  HIPCHK(hipMemcpyAsync(ws, &G.dev, sizeof(DevGen), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + off_tab, &tb, sizeof(GenTab), hipMemcpyHostToDevice, s));
+  const DevGen* gd = reinterpret_cast<const DevGen*>(ws);
+  c64* F = reinterpret_cast<c64*>(ws + off_tables);
+  EventSet ev;
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));
+  HIPCHK(launch_gen_planes(gd, reinterpret_cast<const GenTab*>(ws + off_tab), 1, G.dev.npts,
+                           G.dev.nlsm, F, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[1], s));
+  HIPCHK(launch_gen_apply(gd, G.dev.npts, E, F, n_vec, reinterpret_cast<const c64*>(x),
+                          reinterpret_cast<c64*>(ws + off_w), reinterpret_cast<c64*>(y), N,
+                          (size_t)std::max(1, G.dev.nw) * G.dev.npts, s));
+  if (ev.ok) HIPCHK(hipEventRecord(ev.e[2], s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (ev.ok) {
+    float t1 = 0.f, t2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t1, ev.e[0], ev.e[1]));
+    HIPCHK(hipEventElapsedTime(&t2, ev.e[1], ev.e[2]));
+    g_ms_tables = t1;
+    g_ms_solver = t2;
+  }
+  return VDC_OK;
+}
+
+vdc_status vdc_sum_partial_waves(int n_jobs, const int* collision, int n_coll, int n_final,
+                                 const double* share, double* sigma, void* stream) {
+  if (n_jobs < 0 || n_coll < 0 || n_final < 0)
+    return fail(VDC_ERR_INVALID_ARG, "negative size");
+  if (n_coll == 0 || n_final == 0) return VDC_OK;
+  if (!sigma || (n_jobs > 0 && (!collision || !share)))
+    return fail(VDC_ERR_INVALID_ARG, "NULL buffer");
+  HIPCHK(launch_sum_waves(n_jobs, collision, n_coll, n_final, share, sigma,
+                          reinterpret_cast<hipStream_t>(stream)));
+  return VDC_OK;
+}
+
+}  // extern "C"

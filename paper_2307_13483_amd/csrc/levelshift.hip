@@ -31,6 +31,7 @@
 // rectangle of offsets they need ("shift table"), and a gather pass writes
 // each total energy's block tables from it.
 #include "internal.h"
+#include "terms_args.h"
 
 namespace vdc {
 
@@ -352,6 +353,42 @@ level_shift_points_kernel(DevModel m, int n, const double* __restrict__ eps, c64
 #pragma unroll
     for (int f = 0; f < kNumF; ++f) out[(size_t)i * kNumF + f] = F[f];
   }
+}
+
+// Level-shift planes of the general model at total energy E (one table per
+// (model, E)): each of the model's two-state transform models c evaluates
+// its six functions at eps_nu = E - E_nu, and lsmap[c][f] names the plane
+// F^mu_dd' that function f of c supplies (-1: a duplicate, not stored).
+// Points are visited in order of E_nu (perm), so a wave's lanes agree on
+// which node clusters are far.
+__global__ void __launch_bounds__(kLsThreads)
+gen_planes_kernel(const DevGen* __restrict__ gens, const GenTab* __restrict__ tabs,
+                  c64* __restrict__ base) {
+  const GenTab tb = tabs[blockIdx.z];
+  const DevGen& g = gens[tb.model];
+  const int c = blockIdx.y;
+  if (c >= g.nlsm || blockIdx.x * blockDim.x >= g.npts) return;   // whole workgroup
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = s < g.npts;
+  const int i = active ? g.perm[s] : 0;
+  const double eps = active ? tb.E - g.Enu[i] : 0.0;
+  c64 F[kNumF];
+  level_shift6(g.lsm[c], eps, active, F);
+  if (active) {
+#pragma unroll
+    for (int f = 0; f < kNumF; ++f) {
+      const int pl = g.lsmap[c * kNumF + f];
+      if (pl >= 0) base[tb.offset + (size_t)pl * g.npts + i] = F[f];
+    }
+  }
+}
+
+hipError_t launch_gen_planes(const DevGen* gens, const GenTab* tabs, int n_tabs, int max_npts,
+                             int max_nlsm, c64* base, hipStream_t s) {
+  if (n_tabs <= 0 || max_nlsm <= 0) return hipSuccess;
+  const dim3 grid((max_npts + kLsThreads - 1) / kLsThreads, max_nlsm, n_tabs);
+  hipLaunchKernelGGL(gen_planes_kernel, grid, dim3(kLsThreads), 0, s, gens, tabs, base);
+  return hipGetLastError();
 }
 
 hipError_t launch_level_shift_tables(const DevModel* models_dev, const DevGroup* groups_dev,

@@ -77,6 +77,33 @@ class Co2Job(ctypes.Structure):
     _fields_ = [("eps_i", ctypes.c_double), ("v", ctypes.c_int * 4), ("mu_i", ctypes.c_int)]
 
 
+MAX_MODES = 8
+
+
+class Term(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("e", ctypes.c_int), ("coeff", ctypes.c_double),
+                ("pow", ctypes.c_int * MAX_MODES)]
+
+
+class Width(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_double), ("B", ctypes.c_double), ("l", ctypes.c_int)]
+
+
+class TermDesc(ctypes.Structure):
+    _fields_ = [("n_states", ctypes.c_int), ("n_modes", ctypes.c_int), ("n_pw", ctypes.c_int),
+                ("omega", ctypes.POINTER(ctypes.c_double)), ("nbasis", ctypes.POINTER(ctypes.c_int)),
+                ("e_state", ctypes.POINTER(ctypes.c_double)),
+                ("n_uterms", ctypes.c_int), ("uterms", ctypes.POINTER(Term)),
+                ("n_vterms", ctypes.c_int), ("vterms", ctypes.POINTER(Term)),
+                ("width", ctypes.POINTER(Width)), ("hilbert_nodes", ctypes.c_int),
+                ("hilbert_xmax", ctypes.c_double), ("dispatch", ctypes.c_int)]
+
+
+class MJob(ctypes.Structure):
+    _fields_ = [("eps_i", ctypes.c_double), ("v", ctypes.c_int * MAX_MODES), ("mu_i", ctypes.c_int),
+                ("model", ctypes.c_int)]
+
+
 _lib = None
 
 
@@ -134,6 +161,16 @@ def lib():
         "vdc_co2_apply": (I, [P, D, I, I, ctypes.POINTER(ctypes.c_int), P, P, P, S, P]),
         "vdc_eels_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
         "vdc_eels": (I, [P, I, ctypes.POINTER(Job), P, S, I, D, D, D, P, P, S, P]),
+        "vdc_model_create": (I, [ctypes.POINTER(TermDesc), ctypes.POINTER(P)]),
+        "vdc_model_kind": (I, [P, ctypes.POINTER(ctypes.c_int)]),
+        "vdc_model_workspace_size": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                         ctypes.POINTER(MJob), ctypes.POINTER(S)]),
+        "vdc_model_solve": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                ctypes.POINTER(MJob), I, ctypes.POINTER(ctypes.c_int), P, S, P, P,
+                                P, ctypes.POINTER(JobInfo), P]),
+        "vdc_model_apply_workspace_size": (I, [P, I, ctypes.POINTER(S)]),
+        "vdc_model_apply": (I, [P, D, I, P, P, P, S, P]),
+        "vdc_sum_partial_waves": (I, [I, P, I, I, P, P, P]),
         "vdc_last_error": (ctypes.c_char_p, []),
         "vdc_version": (ctypes.c_char_p, []),
     }
@@ -453,7 +490,8 @@ class CrossSections(torch.autograd.Function):
         s = Solver(model, jobs, spec["finals"], spec.get("opts"), want_psi=True).run()
         ctx.solver, ctx.model = s, model
         ctx.n_e, ctx.n_f = len(spec["eps"]), len(spec["finals"])
-        return s.sigma.view(ctx.n_e, 2, ctx.n_f).sum(dim=1)
+        # Eq. (16): the two mu_i shares of each energy, added by the library
+        return sum_partial_waves([k // 2 for k in range(len(jobs))], ctx.n_e, s.sigma)
 
     @staticmethod
     def backward(ctx, grad_sigma):
@@ -550,3 +588,127 @@ def co2_apply(model, E, x, sectors, which=0, stream=None):
     _check(lib().vdc_co2_apply(model.handle, float(E), int(which), n, sec, _ptr(x), _ptr(y),
                                _ptr(w), ws.value, _stream_ptr(stream)))
     return y
+
+
+# ---------------------------------------------------------------- term-list models
+
+class TermModel:
+    """A model given by polynomial term lists (vdc_model_create).  ``desc``:
+    dict with omega [M], nbasis [M], e_state [D], uterms / vterms as lists of
+    (d, d' or mu, coeff, powers), width {(d, mu): (A, B)}, l [P], K, X (as
+    paper_2307_13483_amd.inputs builds them).  dispatch: let the two-state
+    kernels solve it when its terms are those of the two-state model."""
+
+    def __init__(self, desc, dispatch=False):
+        D, M, P = len(desc["e_state"]), len(desc["nbasis"]), len(desc["l"])
+        self.D, self.M, self.P = D, M, P
+        self.nbasis = [int(n) for n in desc["nbasis"]]
+        self.npts = int(np.prod(self.nbasis))
+        self._omega = (ctypes.c_double * M)(*[float(w) for w in desc["omega"]])
+        self._nbasis = (ctypes.c_int * M)(*self.nbasis)
+        self._estate = (ctypes.c_double * D)(*[float(e) for e in desc["e_state"]])
+
+        def terms(lst):
+            arr = (Term * max(1, len(lst)))()
+            for k, (d, e, c, pw) in enumerate(lst):
+                arr[k].d, arr[k].e, arr[k].coeff = int(d), int(e), float(c)
+                for q, pq in enumerate(pw):
+                    arr[k].pow[q] = int(pq)
+            return arr
+        self._u, self._v = terms(desc["uterms"]), terms(desc["vterms"])
+        self._w = (Width * (D * P))()
+        for dd in range(D):
+            for mu in range(P):
+                A, B = desc["width"].get((dd, mu), (0.0, 1.0))
+                self._w[dd * P + mu] = Width(float(A), float(B), int(desc["l"][mu]))
+        d = TermDesc(D, M, P, self._omega, self._nbasis, self._estate, len(desc["uterms"]),
+                     self._u, len(desc["vterms"]), self._v, self._w, int(desc.get("K", 4096)),
+                     float(desc.get("X", 40.0)), 1 if dispatch else 0)
+        h = ctypes.c_void_p()
+        _check(lib().vdc_model_create(ctypes.byref(d), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def N(self):
+        return self.D * self.npts
+
+    def kind(self):
+        k = ctypes.c_int()
+        _check(lib().vdc_model_kind(self.handle, ctypes.byref(k)))
+        return k.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.vdc_model_destroy(self.handle)
+            self.handle = None
+
+
+def _mjobs(jobs):
+    arr = (MJob * max(1, len(jobs)))()
+    for k, jb in enumerate(jobs):
+        arr[k].eps_i = float(jb[0])
+        for q, vq in enumerate(jb[1]):
+            arr[k].v[q] = int(vq)
+        arr[k].mu_i = int(jb[2])
+        arr[k].model = int(jb[3]) if len(jb) > 3 else 0
+    return arr
+
+
+def model_solve(models, jobs, finals, opts=None, want_psi=False, stream=None):
+    """vdc_model_solve.  jobs: (eps_i, v (multi-index), mu_i[, model index]);
+    finals: multi-indices.  Returns (T [n_jobs, n_final, P], sigma shares
+    [n_jobs, n_final], psi [n_jobs, max N] or None, infos)."""
+    models = list(models) if isinstance(models, (list, tuple)) else [models]
+    opts = opts or Opts(precond=PREC_JACOBI)
+    n = len(jobs)
+    cj = _mjobs(jobs)
+    hs = (ctypes.c_void_p * len(models))(*[m.handle.value for m in models])
+    so = opts.c()
+    nb = ctypes.c_size_t()
+    _check(lib().vdc_model_workspace_size(len(models), hs, ctypes.byref(so), n, cj, ctypes.byref(nb)))
+    nf = len(finals)
+    fin = (ctypes.c_int * max(1, MAX_MODES * nf))()
+    for f, vf in enumerate(finals):
+        for q, vq in enumerate(vf):
+            fin[f * MAX_MODES + q] = int(vq)
+    two_state = all(m.kind() == 0 for m in models)
+    P = 2 if two_state else max(m.P for m in models)
+    T = torch.zeros((n, nf, P), dtype=torch.complex128, device="cuda")
+    sigma = torch.zeros((n, nf), dtype=torch.float64, device="cuda")
+    psi = (torch.zeros((n, max(m.N for m in models)), dtype=torch.complex128, device="cuda")
+           if want_psi else None)
+    info = (JobInfo * max(1, n))()
+    raw, ws = _aligned_workspace(nb.value, "cuda")
+    _check(lib().vdc_model_solve(len(models), hs, ctypes.byref(so), n, cj, nf, fin, _ptr(ws),
+                                 nb.value, _ptr(T), _ptr(sigma), _ptr(psi), info,
+                                 _stream_ptr(stream)))
+    infos = [dict(status=info[k].status, iters=info[k].iters, restarts=info[k].restarts,
+                  rel_res=info[k].rel_res, alg_bytes=info[k].alg_bytes, retried=info[k].retried)
+             for k in range(n)]
+    return T, sigma, psi, infos
+
+
+def model_apply(model, E, x, stream=None):
+    """vdc_model_apply: y = A(E) x for full-layout vectors x [n_vec, N]."""
+    x = torch.as_tensor(x, dtype=torch.complex128, device="cuda").contiguous()
+    if x.dim() == 1:
+        x = x[None]
+    n = x.shape[0]
+    nb = ctypes.c_size_t()
+    _check(lib().vdc_model_apply_workspace_size(model.handle, n, ctypes.byref(nb)))
+    raw, ws = _aligned_workspace(nb.value, "cuda")
+    y = torch.empty_like(x)
+    _check(lib().vdc_model_apply(model.handle, float(E), n, _ptr(x), _ptr(y), _ptr(ws), nb.value,
+                                 _stream_ptr(stream)))
+    return y
+
+
+def sum_partial_waves(collision, n_coll, share, stream=None):
+    """vdc_sum_partial_waves: sigma [n_coll, n_final] of Eq. (16) from the
+    per-job shares [n_jobs, n_final] (device) and each job's collision index."""
+    share = share.contiguous()
+    coll = torch.as_tensor(list(collision), dtype=torch.int32, device=share.device)
+    sig = torch.zeros((int(n_coll), share.shape[1]), dtype=torch.float64, device=share.device)
+    _check(lib().vdc_sum_partial_waves(share.shape[0], _ptr(coll), int(n_coll), share.shape[1],
+                                       _ptr(share), _ptr(sig), _stream_ptr(stream)))
+    return sig
