@@ -741,6 +741,7 @@ def main():
         infos = solver.infos()
         conv = sum(1 for i in infos if i["status"] == vdc.CONVERGED)
         worst = max(i["rel_res"] for i in infos)
+        worst_defect = max(i["optical_defect"] for i in infos)
         iters = [i["iters"] for i in infos]
         solver_ms = sum(ms_solver) / len(ms_solver)
         alg = sum(i["alg_bytes"] for i in infos)
@@ -761,7 +762,8 @@ def main():
                     chosen=dict(method="COCG" if cocg else "GMRES", restart=opts.restart,
                                 inner_restart=opts.inner_restart, inner_tol=opts.inner_tol,
                                 outer_restart=opts.outer_restart, tile_rows=opts.tile_rows),
-                    converged=conv, worst_rel_res=worst, n_jobs=solver.n_jobs,
+                    converged=conv, worst_rel_res=worst, worst_optical_defect=worst_defect,
+                    n_jobs=solver.n_jobs,
                     iters_mean=sum(iters) / len(iters), iters_max=max(iters),
                     outer_mean=(sum(i["outer_iters"] for i in infos) / len(infos)),
                     ms_tables=sum(ms_tables) / len(ms_tables), ms_solver=solver_ms,
@@ -787,6 +789,7 @@ def main():
                    "tol": "1e-10 relative FP64 true residual",
                    "precision": args.precision},
         "converged": head["converged"], "worst_rel_res": head["worst_rel_res"],
+        "worst_optical_defect": head["worst_optical_defect"],
         "iters_mean": head["iters_mean"], "iters_max": head["iters_max"],
         "outer_mean": head["outer_mean"],
         "ms_tables": head["ms_tables"], "ms_solver": head["ms_solver"],

@@ -166,6 +166,13 @@ typedef struct {
                                 describe the FP64 solve), 2 if that re-solve
                                 did not fit the workspace, else 0             */
   int reserved;
+  double optical_defect;     /* |-Im T_ii - pi sum |T_f|^2| / |T_ii| of the
+                                solution, the sum over every open final state
+                                and partial wave of the basis: the truncated-
+                                basis optical theorem, exact for the exact
+                                solution (two-state and term-list solves; -1
+                                where not computed: the CO2-like model and the
+                                adjoint)                                     */
 } vdc_job_info;
 
 /* Build a model (host call; allocates and fills its small device tables:

@@ -524,6 +524,7 @@ vdc_status read_info(const Prepared& R, vdc_job_info* info, hipStream_t s) {
       info[j].outer_iters = hinfo[j].outer;
       info[j].rel_res = hinfo[j].rel_res;
       info[j].alg_bytes = hinfo[j].alg_bytes;
+      info[j].optical_defect = hinfo[j].defect;
     }
   }
   return VDC_OK;
@@ -1609,7 +1610,7 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
   }
   for (int k = 0; k < n_jobs; ++k)
     info[k] = vdc_job_info{hinfo[k].status, hinfo[k].iters, hinfo[k].restarts, 0, hinfo[k].rel_res,
-                           hinfo[k].alg_bytes};
+                           hinfo[k].alg_bytes, 0, 0, -1.0};
   return VDC_OK;
 }
 
@@ -2342,7 +2343,7 @@ vdc_status vdc_model_solve(int n_models, const vdc_model_t* models, const vdc_so
   if (info)
     for (int j = 0; j < n_jobs; ++j)
       info[j] = vdc_job_info{hinfo[j].status, hinfo[j].iters, hinfo[j].restarts, 0,
-                             hinfo[j].rel_res, hinfo[j].alg_bytes};
+                             hinfo[j].rel_res, hinfo[j].alg_bytes, 0, 0, hinfo[j].defect};
   return VDC_OK;
 }
 

@@ -117,6 +117,7 @@ struct DevInfo {
   int status, iters, restarts, outer;
   double rel_res;
   double alg_bytes;
+  double defect = -1.0;  // optical-theorem defect of the solution (-1: not computed)
 };
 
 struct c64 { double x, y; };

@@ -5,6 +5,30 @@
 
 namespace vdc {
 
+// Sum of NV values over a workgroup of blockDim.x <= kBlock threads (a
+// multiple of 64): wave xor-butterflies, then the wave partials in wave
+// order (fixed order).  Result in out[0..NV-1] after a barrier.
+template <int NV>
+__device__ inline void block_sum_any(double (&v)[NV], double* red, double* out) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], s, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[wave * NV + q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[w * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
 struct SolveArgs {
   const DevModel* models;
   const DevJob* jobs;
@@ -40,14 +64,58 @@ struct SolveArgs {
   double* grad;             // [n_jobs][16] per-job gradient contributions
 };
 
+// Optical-theorem defect of the solution x of the job's symmetry block,
+// |-Im T_ii - pi sum_{open v_f} sum_{mu_f} |T_f|^2| / |T_ii|, where T_ii is the
+// job's elastic amplitude and the sum runs over every open final state of
+// the basis: the truncated-basis identity that follows from A = R + i pi
+// sum Phi Phi^T (Eqs. (19), (23), (25)), exact for the exact solution.  In
+// the block at a point where state a is active only the wave mu = a has an
+// amplitude, T = f_a^a(eps) (1 + lam_a q_g) x + f_b^a(eps) q_u x (b the
+// other state), from the same neighbours as the operator.  All threads,
+// after a barrier; returned to every thread.
+__device__ inline double optical_defect(const DevModel& md, const DevJob& jb, const c64* x,
+                                        double Tii_im, double Tii_abs) {
+  __shared__ double red[kWaves + 1];
+  double acc[1] = {0.0};
+  const int Nu = md.Nu;
+  for (int i = threadIdx.x; i < md.Nc; i += blockDim.x) {
+    const int ng = i / Nu, nu = i - ng * Nu;
+    const double eps = jb.E - (md.omega_g * (ng + 0.5) + md.omega_u * (nu + 0.5));
+    if (!(eps > 0.0)) continue;
+    const int act = (nu + jb.parity) & 1;
+    const double fa = coupling_f(md, act, act, eps), fb = coupling_f(md, 1 - act, act, eps);
+    c64 zg = c64{0.0, 0.0}, zu = c64{0.0, 0.0};
+    if (ng > 0) zg = sqrt(0.5 * ng) * x[i - Nu];
+    if (ng + 1 < md.Ng) zg = zg + sqrt(0.5 * (ng + 1)) * x[i + Nu];
+    if (nu > 0) zu = sqrt(0.5 * nu) * x[i - 1];
+    if (nu + 1 < Nu) zu = zu + sqrt(0.5 * (nu + 1)) * x[i + 1];
+    const c64 T = fa * (x[i] + md.lamd[act] * zg) + fb * zu;
+    acc[0] += norm2(T);
+  }
+  block_sum_any<1>(acc, red, red + kWaves);
+  const double S = red[kWaves];
+  __syncthreads();
+  return Tii_abs > 0.0 ? fabs(-Tii_im - kPi * S) / Tii_abs : 0.0;
+}
+
 // Amplitudes T_{mu_f v_f <- mu_i v_i} = Phi^{v_f mu_f T} Psi (Eq. (24)) for the
 // solution x of the job's symmetry block, the share 2 pi^3/eps_i sum_{mu_f}|T|^2
-// of sigma_{v_f <- v_i} (Eq. (16), eps_i in hartree), the full-layout Psi and
-// the status.  Called by all threads of the workgroup after a barrier.
+// of sigma_{v_f <- v_i} (Eq. (16), eps_i in hartree), the full-layout Psi, the
+// optical-theorem defect and the status.  Called by all threads of the
+// workgroup after a barrier.
 __device__ inline void finish_job(const SolveArgs& a, const DevModel& md, const DevJob& jb,
                                   const c64* x, int tid, int status, int iters, int cycles,
                                   int outer, double rel_res, double alg_bytes) {
   const int out = jb.out;
+  // the elastic amplitude T_ii (every thread, from the few entries of Phi_i)
+  c64 Tii = c64{0.0, 0.0};
+  {
+    PhiEntry e[6];
+    const int n = phi_entries(md, jb.mu, jb.eps_i, jb.vi_g, jb.vi_u, e);
+    for (int q = 0; q < n; ++q)
+      if (((e[q].u + jb.parity) & 1) == e[q].d) Tii = Tii + e[q].val * x[e[q].g * md.Nu + e[q].u];
+  }
+  const double defect = optical_defect(md, jb, x, Tii.y, sqrt(norm2(Tii)));
   if (tid < a.n_final) {
     const int g = a.finals[2 * tid], u = a.finals[2 * tid + 1];
     const double eps_f = jb.E - (md.omega_g * (g + 0.5) + md.omega_u * (u + 0.5));
@@ -74,7 +142,9 @@ __device__ inline void finish_job(const SolveArgs& a, const DevModel& md, const 
       psi[(size_t)(1 - act) * md.Nc + i] = c64{0.0, 0.0};
     }
   }
-  if (tid == 0) a.info[out] = DevInfo{status, iters, cycles, outer, rel_res, alg_bytes};
+  // the defect pass reads x once more (16 B per block unknown)
+  if (tid == 0)
+    a.info[out] = DevInfo{status, iters, cycles, outer, rel_res, alg_bytes + 16.0 * md.Nc, defect};
 }
 
 }  // namespace vdc

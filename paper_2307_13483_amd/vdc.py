@@ -60,7 +60,7 @@ class JobInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("outer_iters", ctypes.c_int), ("rel_res", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double), ("retried", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("reserved", ctypes.c_int), ("optical_defect", ctypes.c_double)]
 
 
 class Co2Desc(ctypes.Structure):
@@ -405,7 +405,7 @@ class Solver:
         out = [dict(status=self.info[k].status, iters=self.info[k].iters,
                     restarts=self.info[k].restarts, outer_iters=self.info[k].outer_iters,
                     rel_res=self.info[k].rel_res, alg_bytes=self.info[k].alg_bytes,
-                    retried=self.info[k].retried)
+                    retried=self.info[k].retried, optical_defect=self.info[k].optical_defect)
                for k in range(self.n_jobs)]
         n_retry = sum(1 for i in out if i["retried"])
         if n_retry:
@@ -683,7 +683,8 @@ def model_solve(models, jobs, finals, opts=None, want_psi=False, stream=None):
                                  nb.value, _ptr(T), _ptr(sigma), _ptr(psi), info,
                                  _stream_ptr(stream)))
     infos = [dict(status=info[k].status, iters=info[k].iters, restarts=info[k].restarts,
-                  rel_res=info[k].rel_res, alg_bytes=info[k].alg_bytes, retried=info[k].retried)
+                  rel_res=info[k].rel_res, alg_bytes=info[k].alg_bytes, retried=info[k].retried,
+                  optical_defect=info[k].optical_defect)
              for k in range(n)]
     return T, sigma, psi, infos
 

@@ -1,0 +1,104 @@
+"""The per-job optical-theorem check computed on the GPU (vdc_job_info.
+optical_defect): |-Im T_ii - pi sum over open (v_f, mu_f) |T_f|^2| / |T_ii|.
+It must agree with the same quantity computed by the oracle from the GPU's
+own solution (same psi, different summation order: within 1e-13), be small
+for converged solves (<= 1e-8: exact for the exact solution, the residual of
+1e-10 times cond(A) of O(10^2) bounds it) and large for a solve stopped
+early, on every two-state solve path and on the term-list path."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import model2d as m2
+from oracle import terms
+from paper_2307_13483_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vdc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_13483_amd import vdc as v
+    v.lib()
+    return v
+
+
+def _oracle_defect_2d(p, Ng, Nu, job, psi):
+    eps_i, vi, mu = job
+    mdl = m2.Model2D(p, Ng, Nu, m2.total_energy(p, eps_i, vi))
+    Tii = mdl.phi(vi, m2.MU[mu]) @ psi
+    opened = [(g, u) for g in range(Ng) for u in range(Nu)
+              if mdl.E - m2.vib_energy(p, (g, u)) > 0]
+    S = sum(abs(mdl.phi(v, mf) @ psi) ** 2 for v in opened for mf in m2.MU)
+    return abs(-Tii.imag - math.pi * S) / abs(Tii)
+
+
+PATHS = {
+    "gmres": dict(restart=20),
+    "cocg": dict(method=1),
+    "fgmres": dict(precision=1, inner_restart=8, inner_tol=1e-3, outer_restart=16),
+    "cocg_fp32": dict(method=1, precision=1, inner_restart=200, inner_tol=1e-5),
+    "rows_cocg": dict(method=1, precond=3),
+    "plain": dict(restart=20),
+}
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_two_state_defect(vdc, path):
+    p = inputs.draw_params(17)
+    Ng, Nu = 26, 22
+    model = vdc.Model2D(p, Ng, Nu)
+    jobs = [(0.45, (0, 0), 0), (1.6, (1, 0), 1), (2.8, (2, 0), 0), (2.1, (0, 1), 1)]
+    opts = vdc.Opts(**dict(dict(precond=vdc.PREC_BLOCK, max_iter=20000), **PATHS[path]))
+    s = vdc.Solver(model, jobs, [(0, 0)], opts, want_psi=True).run(plain=path == "plain")
+    infos = s.infos()
+    psi = s.psi.cpu().numpy()
+    for k, job in enumerate(jobs):
+        assert infos[k]["status"] == vdc.CONVERGED
+        d = infos[k]["optical_defect"]
+        assert 0.0 <= d <= 1e-8, (job, d)
+        assert abs(d - _oracle_defect_2d(p, Ng, Nu, job, psi[k])) <= 1e-13
+
+
+def test_defect_detects_an_unconverged_solution(vdc):
+    """One Arnoldi step instead of a converged solve: the defect rises above
+    the converged bound, by orders of magnitude over the converged value of
+    the same job, and matches the oracle's on the same solution."""
+    p = inputs.draw_params(18)
+    Ng, Nu = 30, 24
+    model = vdc.Model2D(p, Ng, Nu)
+    jobs = [(2.4, (0, 0), 0), (2.9, (1, 0), 1)]
+    good = vdc.Solver(model, jobs, [(0, 0)], vdc.Opts(restart=30, precond=vdc.PREC_JACOBI)).run()
+    s = vdc.Solver(model, jobs, [(0, 0)], vdc.Opts(restart=1, max_iter=1, precond=vdc.PREC_JACOBI),
+                   want_psi=True).run()
+    psi = s.psi.cpu().numpy()
+    for k, (info, ref) in enumerate(zip(s.infos(), good.infos())):
+        assert info["status"] == vdc.NOT_CONVERGED and ref["status"] == vdc.CONVERGED
+        assert info["optical_defect"] > 1e-8
+        assert info["optical_defect"] > 1e3 * ref["optical_defect"], (info, ref)
+        d_or = _oracle_defect_2d(p, Ng, Nu, jobs[k], psi[k])
+        assert abs(info["optical_defect"] - d_or) <= 1e-12 * max(1.0, d_or)
+
+
+def test_term_list_defect(vdc):
+    desc = inputs.quartic_model()
+    gm = vdc.TermModel(desc)
+    jobs = [(0.6, (0, 0, 0), 0), (1.7, (1, 0, 0), 1), (2.5, (0, 1, 0), 0)]
+    T, sig, psi, infos = vdc.model_solve(gm, jobs, [(0, 0, 0)],
+                                         vdc.Opts(restart=30, precond=vdc.PREC_JACOBI), want_psi=True)
+    psi = psi.cpu().numpy()
+    grid = list(itertools.product(*[range(n) for n in desc["nbasis"]]))
+    for k, (eps_i, vi, mu) in enumerate(jobs):
+        assert infos[k]["status"] == vdc.CONVERGED
+        tm = terms.TermModel(desc, terms.total_energy(desc, eps_i, vi))
+        Tii = tm.phi(vi, mu) @ psi[k]
+        opened = [v for v in grid if tm.E - terms.vib_energy(desc, v) > 0]
+        S = sum(abs(tm.phi(v, mf) @ psi[k]) ** 2 for v in opened for mf in range(2))
+        d_or = abs(-Tii.imag - math.pi * S) / abs(Tii)
+        assert infos[k]["optical_defect"] <= 1e-8
+        assert abs(infos[k]["optical_defect"] - d_or) <= 1e-13
