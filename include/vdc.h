@@ -213,6 +213,21 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
                      double* T_out, double* sigma_out, double* psi_out,
                      vdc_job_info* info, void* stream);
 
+/* vdc_solve recording every job's convergence history (off in the other
+ * calls): after each step, hist[j][k] (device double [n_jobs][hist_len],
+ * row j = the caller's job j) receives the relative residual ||r||/||b|| that
+ * the method tracks after step k + 1: GMRES the least-squares residual of
+ * the Arnoldi step (Sec. III.A), FGMRES the outer one, COCG the updated
+ * residual, FP32-inner COCG the inner residual times the outer residual norm
+ * (one entry per FP32 step).  Entries past the job's last step, and steps
+ * beyond hist_len, are not written.  No FP64 re-solve of FP32-inner jobs.
+ * Otherwise as vdc_solve. */
+vdc_status vdc_solve_history(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                             int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                             void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                             double* psi_out, vdc_job_info* info, double* hist, int hist_len,
+                             void* stream);
+
 /* vdc_solve for callers that cannot allocate device memory (tight serving
  * loops, harnesses that forbid hipMalloc, code running while another stream
  * captures a HIP graph): the same plan, kernels and outputs as vdc_solve, with no

@@ -169,6 +169,8 @@ struct PlanExtra {
   int n_out = -1;
   int max_groups = 0;
   bool untimed = false;   // record no kernel-time events (creates none)
+  double* hist = nullptr; // residual histories [n_out][hist_len] (device)
+  int hist_len = 0;
 };
 
 vdc_status make_plan(int n_models, const vdc_model_t* models, const vdc_solve_opts* o,
@@ -471,6 +473,10 @@ vdc_status prepare_solve(int n_models, const vdc_model_t* models, const vdc_solv
     a.T_in = reinterpret_cast<const c64*>(adj->T);
     a.dsig = adj->dsig;
     a.grad = adj->grad_jobs;
+  }
+  if (ex && ex->hist) {
+    a.hist = ex->hist;
+    a.hist_len = ex->hist_len;
   }
   return VDC_OK;
 }
@@ -866,6 +872,19 @@ vdc_status vdc_solve(int n_models, const vdc_model_t* models, const vdc_solve_op
   if (st != VDC_OK || !mixed || n_jobs == 0) return st;
   return retry_fp64(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
                     T_out, sigma_out, psi_out, info, stream);
+}
+
+vdc_status vdc_solve_history(int n_models, const vdc_model_t* models, const vdc_solve_opts* opts,
+                             int n_jobs, const vdc_job* jobs, int n_final, const int* finals,
+                             void* workspace, size_t ws_bytes, double* T_out, double* sigma_out,
+                             double* psi_out, vdc_job_info* info, double* hist, int hist_len,
+                             void* stream) {
+  if (!hist || hist_len < 1) return fail(VDC_ERR_INVALID_ARG, "hist must be non-NULL, hist_len >= 1");
+  PlanExtra ex;
+  ex.hist = hist;
+  ex.hist_len = hist_len;
+  return run_solve(n_models, models, opts, n_jobs, jobs, n_final, finals, workspace, ws_bytes,
+                   T_out, sigma_out, psi_out, info, stream, false, nullptr, &ex);
 }
 
 vdc_status vdc_solve_noalloc(int n_models, const vdc_model_t* models,

@@ -39,7 +39,8 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
     }
     __syncthreads();
     const BlockSolve r = cocg_fp64_block<rows>(L.red, L.dot, L.sq, op, s, a.ncap, a.tol,
-                                               a.max_iter, a.tileT, a.precond);
+                                               a.max_iter, a.tileT, a.precond, hist_row(a, jb),
+                                               a.hist_len);
     __syncthreads();
     finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);
@@ -138,6 +139,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
     __syncthreads();
     double p64 = blk ? 6.0 : 7.0, p32 = blk ? 2.0 : 1.0;
     const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
+    double* hist = hist_row(a, jb);
     p64 += 1.0;
     int iters = 0, outer = 0, status = VDC_NOT_CONVERGED;
     double beta = bnorm;
@@ -239,6 +241,8 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
           p32 += blk ? (rows ? 13.0 : 10.0) : 7.0;
           ++k;
           ++iters;
+          if (hist && tid == 0 && iters <= a.hist_len)
+            hist[iters - 1] = sqrt((double)rr) * beta / bnorm;
           if (rr <= (float)(a.tol_in * a.tol_in) || k >= a.m_in || iters >= a.max_iter ||
               !isfinite(rr))
             break;

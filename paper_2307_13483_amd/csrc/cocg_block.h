@@ -41,7 +41,8 @@ template <bool rows>
 __device__ inline BlockSolve cocg_fp64_block(double* red, double* dot, const double* sq,
                                              const OpJob<double>& op, const Fp64Slot& s,
                                              size_t ld, double tol, int max_iter, int T,
-                                             int precond) {
+                                             int precond, double* hist = nullptr,
+                                             int hist_len = 0) {
   const int tid = threadIdx.x;
   const int Nc = op.Nc;
   c64* lds = reinterpret_cast<c64*>(vdc_tile_lds);
@@ -156,6 +157,7 @@ __device__ inline BlockSolve cocg_fp64_block(double* red, double* dot, const dou
       __syncthreads();
       passes += blk ? (rows ? 15.0 : 10.0) : 7.0;
       ++iters;
+      if (hist && tid == 0 && iters <= hist_len) hist[iters - 1] = sqrt(rr) / bnorm;
       fresh = false;
       if (!isfinite(rr)) {
         status = VDC_NONFINITE;

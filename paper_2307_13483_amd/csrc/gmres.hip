@@ -46,7 +46,8 @@ gmres_fp64_kernel(SolveArgs a) {
     }
     __syncthreads();
     const BlockSolve r =
-        gmres_fp64_block<rows>(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT, a.precond);
+        gmres_fp64_block<rows>(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT, a.precond,
+                               hist_row(a, jb), a.hist_len);
     __syncthreads();
     finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);

@@ -78,7 +78,8 @@ extern __shared__ __align__(16) char vdc_tile_lds[];
 template <bool rows>
 __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& op,
                                               const Fp64Slot& s, size_t ld, int m, double tol,
-                                              int max_iter, int T, int precond) {
+                                              int max_iter, int T, int precond,
+                                              double* hist = nullptr, int hist_len = 0) {
   const int Nc = op.Nc;
   const bool blk = prec_has_factor(precond);
   const SegFactor<double> fac{s.l1, s.l2, s.dinv};
@@ -107,7 +108,8 @@ __device__ inline BlockSolve gmres_fp64_block(Fp64Lds& L, const OpJob<double>& o
     }
     __syncthreads();
     const CycleResult cr = krylov_cycle<double>(L.K, L.red, s.V, ld, Nc, m, tol * r.bnorm,
-                                                max_iter, r.iters, s.Rm, apply);
+                                                max_iter, r.iters, s.Rm, apply, hist, hist_len,
+                                                1.0 / r.bnorm);
     r.passes += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 9.0 + (blk ? 4.0 * cr.k + 4.0 : 0.0);
     if (blk) {
       // zt = V y (own elements), then x += M^{-1} zt (block ownership)

@@ -129,10 +129,14 @@ __device__ inline void scale_coeffs(R* h, R* hs, const R* vs, int nv) {
 // with a barrier.  Stops when the least-squares residual drops to tol_abs or
 // iters reaches max_iter.  On return L.y holds the least-squares
 // coefficients on the unit basis (after a barrier).
+// With hist, thread 0 writes the least-squares residual times hscale after
+// every step to hist[iters - 1] while iters <= hist_len.
 template <typename R, typename Apply>
 __device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<R>::C* V,
                                            size_t ld, int Nc, int m, double tol_abs,
-                                           int max_iter, int& iters, c64* Rm, Apply apply) {
+                                           int max_iter, int& iters, c64* Rm, Apply apply,
+                                           double* hist = nullptr, int hist_len = 0,
+                                           double hscale = 0.0) {
   using C = typename CT<R>::C;
   CycleResult res{0, false, false, 0.0, 0};
   for (int j = 0; j < m; ++j) {
@@ -162,6 +166,7 @@ __device__ inline CycleResult krylov_cycle(KrylovLds<R>& L, R* red, typename CT<
     __syncthreads();
     const double r = L.resid;
     ++iters;
+    if (hist && threadIdx.x == 0 && iters <= hist_len) hist[iters - 1] = r * hscale;
     res.k = j + 1;
     if (!isfinite(r) || !isfinite(hn)) {
       res.nonfinite = true;

@@ -199,7 +199,8 @@ fgmres_mixed_kernel(SolveArgs a) {
         }
         __syncthreads();
         const CycleResult cr = krylov_cycle<double>(L.Ko, L.red, Vo, ld, Nc, m, a.tol * bnorm,
-                                                    1 << 30, ocount, Ro, apply_out);
+                                                    1 << 30, ocount, Ro, apply_out,
+                                                    hist_row(a, jb), a.hist_len, 1.0 / bnorm);
         p64 += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 2.0 + 6.0;
         // x += Z y (Z_l is the preconditioned unit basis vector l)
         update_x<double>(Z, ld, cr.k, L.Ko.y, nullptr, nullptr, x, Nc);

@@ -62,7 +62,15 @@ struct SolveArgs {
   const c64* T_in;          // forward amplitudes [n_jobs][n_final][2]
   const double* dsig;       // dL/dsigma [n_jobs][n_final]
   double* grad;             // [n_jobs][16] per-job gradient contributions
+  // residual histories (vdc_solve_history): [n_jobs][hist_len] or null
+  double* hist;
+  int hist_len;
 };
+
+// This job's history row, or null.
+__device__ inline double* hist_row(const SolveArgs& a, const DevJob& jb) {
+  return a.hist ? a.hist + (size_t)jb.out * a.hist_len : nullptr;
+}
 
 // Optical-theorem defect of the solution x of the job's symmetry block,
 // |-Im T_ii - pi sum_{open v_f} sum_{mu_f} |T_f|^2| / |T_ii|, where T_ii is the

@@ -124,6 +124,9 @@ def lib():
         "vdc_solve": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I, ctypes.POINTER(Job),
                           I, ctypes.POINTER(ctypes.c_int), P, S, P, P, P,
                           ctypes.POINTER(JobInfo), P]),
+        "vdc_solve_history": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
+                                  ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, S, P, P,
+                                  P, ctypes.POINTER(JobInfo), P, I, P]),
         "vdc_solve_noalloc": (I, [I, ctypes.POINTER(P), ctypes.POINTER(SolveOpts), I,
                                   ctypes.POINTER(Job), I, ctypes.POINTER(ctypes.c_int), P, P, P,
                                   ctypes.POINTER(JobInfo), P]),
@@ -384,6 +387,18 @@ class Solver:
                                        self.adj_bytes, _ptr(self.grad_jobs), g, self.adj_info,
                                        _stream_ptr(stream)))
         return np.array(list(g)), self.grad_jobs
+
+    def run_history(self, hist_len, stream=None):
+        """vdc_solve_history: the solve with every job's relative residual after
+        each step; returns the history [n_jobs, hist_len] (NaN past the end)."""
+        hist = torch.full((self.n_jobs, int(hist_len)), float("nan"), dtype=torch.float64,
+                          device="cuda")
+        _check(lib().vdc_solve_history(len(self.models), self.handles, ctypes.byref(self.copts),
+                                       self.n_jobs, self.jobs, self.n_final, self.finals,
+                                       _ptr(self.ws), self.ws_bytes, _ptr(self.T), _ptr(self.sigma),
+                                       _ptr(self.psi), self.info, _ptr(hist), int(hist_len),
+                                       _stream_ptr(stream)))
+        return hist
 
     def run_noalloc(self, stream=None):
         """vdc_solve_noalloc: the same solve in the library's static device
