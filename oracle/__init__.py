@@ -25,6 +25,8 @@ poly         the CO2-like three-state, four-mode polynomial model (Sec. III.C)
              assembled the same way, and its bend-block preconditioner
 terms        any model of the class given by polynomial term lists (D states,
              M modes, P partial waves), assembled the same way
+polar        the 2D bend of the CO2-like model in the polar (circular) basis
+             of the isotropic oscillator, with H_0 + U in it
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py``; none is "parity unpinned".
