@@ -626,6 +626,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times "
                          "(calibrates the HBM byte counters of a profiler)")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only time plain device copies of footprints from 32 MiB to 2 GiB "
+                         "(read + write): the copy ceiling with and without the last-level cache")
+    ap.add_argument("--co2-matvec-probe", action="store_true",
+                    help="only run the CO2-like operator on 512 sector vectors (vdc_co2_apply)")
     ap.add_argument("--co2-probe", action="store_true",
                     help="only run the CO2-like workload (384 solves) and print its figures")
     ap.add_argument("--eels-probe", action="store_true",
@@ -666,6 +671,33 @@ def main():
                                             ("jacobi", vdc.PREC_JACOBI, False),
                                             ("block_fp32_inner", vdc.PREC_BLOCK, True))}}),
               flush=True)
+        return
+    if args.co2_matvec_probe:
+        print(json.dumps({"co2_matvec": co2_matvec()}), flush=True)
+        return
+    if args.stream_probe:
+        import torch
+        rows = []
+        for mib in (16, 32, 64, 96, 112, 128, 160, 256, 512, 1024):
+            n = (mib << 20) // 8
+            x = torch.ones(n, dtype=torch.float64, device="cuda")
+            y = torch.empty_like(x)
+            for _ in range(3):
+                y.copy_(x)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(5, int(4096 // mib))
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                y.copy_(x)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rows.append(dict(footprint_MiB=2 * mib, copy_MiB=mib, ms=ms,
+                             GBs=2 * (mib << 20) / (ms * 1e-3) / 1e9))
+            log(f"copy {mib} MiB: {rows[-1]['GBs']:.0f} GB/s")
+            del x, y
+        print(json.dumps({"stream_probe": rows}), flush=True)
         return
     if args.copy_probe:
         import torch

@@ -671,6 +671,62 @@ hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The operator on many sector vectors at once (vdc_co2_apply, which = 0) as
+// two grid-wide passes, one thread per (vector, point) in workgroups of
+// kCo2Threads: the first writes every point's (w_A, w_B), the second every
+// point's y from its neighbours' z and (w_A, w_B).  The same per-point
+// arithmetic as the solver's operator (co2_phase1, co2_phase2); here every
+// point of every vector is independent work, so the loads of many
+// wavefronts are in flight per CU instead of those of one workgroup per
+// vector.  Vectors are taken in batches (the w planes of a batch are
+// scratch): vector v0 + blockIdx.y.
+constexpr int kCo2Threads = 256;
+
+__device__ inline void fill_sq_small(double* sq, int nmax) {
+  for (int n = threadIdx.x; n <= nmax; n += blockDim.x) sq[n] = sqrt(0.5 * n);
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kCo2Threads) co2_w_kernel(Co2OpsArgs a, int v0) {
+  __shared__ double sq[kSqMax + 1];
+  const Co2Model& md = *a.model;
+  fill_sq_small(sq, max(max(md.Ns, md.Nx), max(md.Ny, md.Na)) + 2);
+  const int i = blockIdx.x * kCo2Threads + threadIdx.x;
+  if (i >= md.npts) return;
+  const int v = v0 + blockIdx.y;
+  const Co2Op op{a.model, a.tab, a.E, a.sectors[2 * v], a.sectors[2 * v + 1]};
+  c64 wa, wb;
+  co2_phase1(op, sq, a.x + (size_t)v * md.npts, 1.0, i, wa, wb);
+  c64* w = a.scratch + (size_t)blockIdx.y * 2 * md.npts;
+  w[i] = wa;
+  w[md.npts + i] = wb;
+}
+
+__global__ void __launch_bounds__(kCo2Threads) co2_y_kernel(Co2OpsArgs a, int v0) {
+  __shared__ double sq[kSqMax + 1];
+  const Co2Model& md = *a.model;
+  fill_sq_small(sq, max(max(md.Ns, md.Nx), max(md.Ny, md.Na)) + 2);
+  const int i = blockIdx.x * kCo2Threads + threadIdx.x;
+  if (i >= md.npts) return;
+  const int v = v0 + blockIdx.y;
+  const Co2Op op{a.model, a.tab, a.E, a.sectors[2 * v], a.sectors[2 * v + 1]};
+  const c64* w = a.scratch + (size_t)blockIdx.y * 2 * md.npts;
+  a.y[(size_t)v * md.npts + i] =
+      co2_phase2(op, sq, a.x + (size_t)v * md.npts, 1.0, w, w + md.npts, i);
+}
+
+// npts: points per vector (host copy of the model's), batch: vectors whose w
+// planes fit the scratch.
+hipError_t launch_co2_apply_split(const Co2OpsArgs& a, int npts, int batch, hipStream_t s) {
+  for (int v0 = 0; v0 < a.n_vec; v0 += batch) {
+    const int nb = min(batch, a.n_vec - v0);
+    const dim3 grid((npts + kCo2Threads - 1) / kCo2Threads, nb);
+    hipLaunchKernelGGL(co2_w_kernel, grid, dim3(kCo2Threads), 0, s, a, v0);
+    hipLaunchKernelGGL(co2_y_kernel, grid, dim3(kCo2Threads), 0, s, a, v0);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, hipStream_t s) {
   hipLaunchKernelGGL(co2_ops_kernel, dim3(n_groups), dim3(kBlock), 0, s, a);
   return hipGetLastError();
