@@ -484,6 +484,11 @@ def adjoint_gradient(opts):
                 adjoint_converged=sum(s.adj_info[k].status == 0 for k in range(len(ajobs))))
 
 
+UNEVEN_OFF = ("not run: a launch of this batch with FP32-inner COCG ended in a GPU memory fault "
+              "whose cause is not identified (a CPU emulation of the same launch under "
+              "AddressSanitizer is clean)")
+
+
 def uneven_mixed(pc, finals):
     """64 instances of the two-state model (own parameter draws, n x n basis
     with n in 40..160, one energy each), both partial waves, in one launch."""
@@ -571,8 +576,7 @@ def extras(args, model, cfg):
         if not plain:
             _KEEP["c0"] = dict(sc, T=s.T.cpu().numpy())
             ex["single_energy_solver"] = "GMRES(50), diagonal preconditioner, FP64"
-    ex["uneven_mixed"] = uneven_mixed(PRECONDS[args.precond], cfg["finals"])
-    log("uneven_mixed done")
+    ex["uneven_mixed"] = dict(skipped=UNEVEN_OFF)
     pc = PRECONDS[args.precond]
     from paper_2307_13483_amd import vdc as _v
     ex["co2like"] = co2like(args)
@@ -645,9 +649,7 @@ def main():
                     help="only run the ECD86 workload (512 solves, row blocks and the diagonal)")
     args = ap.parse_args()
     if args.uneven_probe:
-        print(json.dumps({"uneven_mixed": uneven_mixed(PRECONDS[args.precond],
-                                                       [(k, 0) for k in range(6)])}), flush=True)
-        return
+        raise SystemExit("--uneven-probe: " + UNEVEN_OFF)
     if args.ecd_probe:
         print(json.dumps({"ecd86": ecd86_batched()}), flush=True)
         return
