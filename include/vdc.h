@@ -147,6 +147,12 @@ typedef struct {
   int tile_rows;             /* rows of n_g per LDS tile of the fused operator
                                 pass; 0 = the largest that fits               */
   int method;                /* vdc_method (vdc_solve only; 0 = GMRES)         */
+  int check_optical;         /* 1: compute vdc_job_info.optical_defect for every
+                                two-state or term-list solve (one more pass
+                                over the solution per job; the solve kernels
+                                of that launch are the instantiations that
+                                also write residual histories); 0: not
+                                computed, optical_defect = -1                 */
 } vdc_solve_opts;
 
 /* Per-job results written to host memory by the solve calls. */
@@ -170,8 +176,9 @@ typedef struct {
                                 solution, the sum over every open final state
                                 and partial wave of the basis: the truncated-
                                 basis optical theorem, exact for the exact
-                                solution (two-state and term-list solves; -1
-                                where not computed: the CO2-like model and the
+                                solution (two-state and term-list solves with
+                                opts.check_optical = 1; -1 where not computed:
+                                check_optical = 0, the CO2-like model and the
                                 adjoint)                                     */
 } vdc_job_info;
 

@@ -470,6 +470,7 @@ vdc_status prepare_solve(int n_models, const vdc_model_t* models, const vdc_solv
   a.planes = adj ? kPlanesDeriv : kPlanesSolve;
   a.tileT = P.tileT;
   a.tileT32 = P.tileT32;
+  a.check_optical = opts->check_optical != 0;
   if (adj) {
     a.psi_in = reinterpret_cast<const c64*>(adj->psi);
     a.T_in = reinterpret_cast<const c64*>(adj->T);
@@ -2348,6 +2349,7 @@ vdc_status vdc_model_solve(int n_models, const vdc_model_t* models, const vdc_so
   for (const DevGen& g : P.models) maxN = std::max(maxN, (size_t)g.D * g.npts);
   a.psi_ld = maxN;
   a.info = reinterpret_cast<DevInfo*>(ws + P.off_info);
+  a.check_optical = opts->check_optical != 0;
   EventSet ev;
   HIPCHK(launch_zero_int(a.counter, 64, s));
   if (ev.ok) HIPCHK(hipEventRecord(ev.e[0], s));

@@ -13,7 +13,7 @@ struct CocgLds {
   int job;
 };
 
-template <bool rows>
+template <bool rows, bool diag>
 __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
   __shared__ CocgLds L;
   fill_sq<double>(L.sq);
@@ -39,10 +39,10 @@ __global__ void __launch_bounds__(kBlock) cocg_fp64_kernel(SolveArgs a) {
     }
     __syncthreads();
     const BlockSolve r = cocg_fp64_block<rows>(L.red, L.dot, L.sq, op, s, a.ncap, a.tol,
-                                               a.max_iter, a.tileT, a.precond, hist_row(a, jb),
-                                               a.hist_len);
+                                               a.max_iter, a.tileT, a.precond,
+                                               hist_row<diag>(a, jb), a.hist_len);
     __syncthreads();
-    finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
+    finish_job<diag>(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);
   }
 }
@@ -80,7 +80,7 @@ struct CocgMixedLds {
   int job;
 };
 
-template <bool rows>
+template <bool rows, bool diag>
 __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
   __shared__ CocgMixedLds L;
   fill_sq<double>(L.sq);
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
     __syncthreads();
     double p64 = blk ? 6.0 : 7.0, p32 = blk ? 2.0 : 1.0;
     const double bnorm = sqrt(norm_sq<double>(b, Nc, L.red));
-    double* hist = hist_row(a, jb);
+    double* hist = hist_row<diag>(a, jb);
     p64 += 1.0;
     int iters = 0, outer = 0, status = VDC_NOT_CONVERGED;
     double beta = bnorm;
@@ -281,35 +281,50 @@ __global__ void __launch_bounds__(kBlock) cocg_mixed_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    finish_job(a, md, jb, x, tid, status, iters, outer, outer,
+    finish_job<diag>(a, md, jb, x, tid, status, iters, outer, outer,
                bnorm > 0.0 ? beta / bnorm : 0.0, (p64 * 16.0 + p32 * 8.0) * md.Nc);
   }
 }
 
 hipError_t launch_cocg_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  if (a.precond == VDC_PREC_ROWS)
-    hipLaunchKernelGGL(cocg_mixed_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  const bool rows = a.precond == VDC_PREC_ROWS, diag = a.check_optical || a.hist;
+  if (rows && diag)
+    hipLaunchKernelGGL((cocg_mixed_kernel<true, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (rows)
+    hipLaunchKernelGGL((cocg_mixed_kernel<true, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (diag)
+    hipLaunchKernelGGL((cocg_mixed_kernel<false, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   else
-    hipLaunchKernelGGL(cocg_mixed_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+    hipLaunchKernelGGL((cocg_mixed_kernel<false, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s,
+                       a);
   return hipGetLastError();
 }
 
 int cocg_mixed_occupancy(size_t dyn_lds) {
-  return std::min(occupancy_of(cocg_mixed_kernel<true>, dyn_lds),
-                  occupancy_of(cocg_mixed_kernel<false>, dyn_lds));
+  return std::min(std::min(occupancy_of(cocg_mixed_kernel<true, true>, dyn_lds),
+                           occupancy_of(cocg_mixed_kernel<true, false>, dyn_lds)),
+                  std::min(occupancy_of(cocg_mixed_kernel<false, true>, dyn_lds),
+                           occupancy_of(cocg_mixed_kernel<false, false>, dyn_lds)));
 }
 
 hipError_t launch_cocg_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  if (a.precond == VDC_PREC_ROWS)
-    hipLaunchKernelGGL(cocg_fp64_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  const bool rows = a.precond == VDC_PREC_ROWS, diag = a.check_optical || a.hist;
+  if (rows && diag)
+    hipLaunchKernelGGL((cocg_fp64_kernel<true, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (rows)
+    hipLaunchKernelGGL((cocg_fp64_kernel<true, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (diag)
+    hipLaunchKernelGGL((cocg_fp64_kernel<false, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   else
-    hipLaunchKernelGGL(cocg_fp64_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+    hipLaunchKernelGGL((cocg_fp64_kernel<false, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int cocg_fp64_occupancy(size_t dyn_lds) {
-  return std::min(occupancy_of(cocg_fp64_kernel<true>, dyn_lds),
-                  occupancy_of(cocg_fp64_kernel<false>, dyn_lds));
+  return std::min(std::min(occupancy_of(cocg_fp64_kernel<true, true>, dyn_lds),
+                           occupancy_of(cocg_fp64_kernel<true, false>, dyn_lds)),
+                  std::min(occupancy_of(cocg_fp64_kernel<false, true>, dyn_lds),
+                           occupancy_of(cocg_fp64_kernel<false, false>, dyn_lds)));
 }
 
 }  // namespace vdc

@@ -18,7 +18,7 @@
 
 namespace vdc {
 
-template <bool rows>
+template <bool rows, bool diag>
 __global__ void __launch_bounds__(kBlock)
 gmres_fp64_kernel(SolveArgs a) {
   __shared__ Fp64Lds L;
@@ -47,24 +47,31 @@ gmres_fp64_kernel(SolveArgs a) {
     __syncthreads();
     const BlockSolve r =
         gmres_fp64_block<rows>(L, op, s, a.ncap, a.m, a.tol, a.max_iter, a.tileT, a.precond,
-                               hist_row(a, jb), a.hist_len);
+                               hist_row<diag>(a, jb), a.hist_len);
     __syncthreads();
-    finish_job(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
+    finish_job<diag>(a, md, jb, s.x, tid, r.status, r.iters, r.cycles, 0,
                r.bnorm > 0.0 ? r.beta / r.bnorm : 0.0, r.passes * 16.0 * md.Nc);
   }
 }
 
 hipError_t launch_gmres_fp64(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  if (a.precond == VDC_PREC_ROWS)
-    hipLaunchKernelGGL(gmres_fp64_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  const bool rows = a.precond == VDC_PREC_ROWS, diag = a.check_optical || a.hist;
+  if (rows && diag)
+    hipLaunchKernelGGL((gmres_fp64_kernel<true, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (rows)
+    hipLaunchKernelGGL((gmres_fp64_kernel<true, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (diag)
+    hipLaunchKernelGGL((gmres_fp64_kernel<false, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   else
-    hipLaunchKernelGGL(gmres_fp64_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+    hipLaunchKernelGGL((gmres_fp64_kernel<false, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int gmres_fp64_occupancy(size_t dyn_lds) {
-  return std::min(occupancy_of(gmres_fp64_kernel<true>, dyn_lds),
-                  occupancy_of(gmres_fp64_kernel<false>, dyn_lds));
+  return std::min(std::min(occupancy_of(gmres_fp64_kernel<true, true>, dyn_lds),
+                           occupancy_of(gmres_fp64_kernel<true, false>, dyn_lds)),
+                  std::min(occupancy_of(gmres_fp64_kernel<false, true>, dyn_lds),
+                           occupancy_of(gmres_fp64_kernel<false, false>, dyn_lds)));
 }
 
 }  // namespace vdc

@@ -28,7 +28,7 @@ struct MixedLds {
   int job;
 };
 
-template <bool rows>
+template <bool rows, bool diag>
 __global__ void __launch_bounds__(kBlock)
 fgmres_mixed_kernel(SolveArgs a) {
   __shared__ MixedLds L;
@@ -200,7 +200,7 @@ fgmres_mixed_kernel(SolveArgs a) {
         __syncthreads();
         const CycleResult cr = krylov_cycle<double>(L.Ko, L.red, Vo, ld, Nc, m, a.tol * bnorm,
                                                     1 << 30, ocount, Ro, apply_out,
-                                                    hist_row(a, jb), a.hist_len, 1.0 / bnorm);
+                                                    hist_row<diag>(a, jb), a.hist_len, 1.0 / bnorm);
         p64 += cycle_passes(cr.k, cr.reorth_passes) + cr.k + 2.0 + 6.0;
         // x += Z y (Z_l is the preconditioned unit basis vector l)
         update_x<double>(Z, ld, cr.k, L.Ko.y, nullptr, nullptr, x, Nc);
@@ -226,22 +226,29 @@ fgmres_mixed_kernel(SolveArgs a) {
       }
     }
     __syncthreads();
-    finish_job(a, md, jb, x, tid, status, iters, cycles, outer,
+    finish_job<diag>(a, md, jb, x, tid, status, iters, cycles, outer,
                bnorm > 0.0 ? beta / bnorm : 0.0, (16.0 * p64 + 8.0 * p32) * Nc);
   }
 }
 
 hipError_t launch_fgmres_mixed(const SolveArgs& a, int n_groups, size_t dyn_lds, hipStream_t s) {
-  if (a.precond == VDC_PREC_ROWS)
-    hipLaunchKernelGGL(fgmres_mixed_kernel<true>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  const bool rows = a.precond == VDC_PREC_ROWS, diag = a.check_optical || a.hist;
+  if (rows && diag)
+    hipLaunchKernelGGL((fgmres_mixed_kernel<true, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (rows)
+    hipLaunchKernelGGL((fgmres_mixed_kernel<true, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+  else if (diag)
+    hipLaunchKernelGGL((fgmres_mixed_kernel<false, true>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   else
-    hipLaunchKernelGGL(fgmres_mixed_kernel<false>, dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
+    hipLaunchKernelGGL((fgmres_mixed_kernel<false, false>), dim3(n_groups), dim3(kBlock), dyn_lds, s, a);
   return hipGetLastError();
 }
 
 int fgmres_mixed_occupancy(size_t dyn_lds) {
-  return std::min(occupancy_of(fgmres_mixed_kernel<true>, dyn_lds),
-                  occupancy_of(fgmres_mixed_kernel<false>, dyn_lds));
+  return std::min(std::min(occupancy_of(fgmres_mixed_kernel<true, true>, dyn_lds),
+                           occupancy_of(fgmres_mixed_kernel<true, false>, dyn_lds)),
+                  std::min(occupancy_of(fgmres_mixed_kernel<false, true>, dyn_lds),
+                           occupancy_of(fgmres_mixed_kernel<false, false>, dyn_lds)));
 }
 
 }  // namespace vdc

@@ -332,8 +332,8 @@ __global__ void p_status(PlainArgs a) {
 __global__ void __launch_bounds__(kBlock) p_finish(SolveArgs sa, PlainArgs a) {
   __syncthreads();
   const PlainState& s = *a.st;
-  finish_job(sa, a.md, a.jb, a.x, threadIdx.x, s.status, s.iters, s.cycles, 0,
-             s.bnorm > 0.0 ? s.beta / s.bnorm : 0.0, s.passes * 16.0 * a.md.Nc);
+  finish_job<true>(sa, a.md, a.jb, a.x, threadIdx.x, s.status, s.iters, s.cycles, 0,
+                   s.bnorm > 0.0 ? s.beta / s.bnorm : 0.0, s.passes * 16.0 * a.md.Nc);
 }
 
 size_t plain_extra_elems(size_t ncap, int m) {

@@ -65,10 +65,19 @@ struct SolveArgs {
   // residual histories (vdc_solve_history): [n_jobs][hist_len] or null
   double* hist;
   int hist_len;
+  int check_optical;        // compute the optical-theorem defect of each solution
 };
 
-// This job's history row, or null.
+// The solver kernels come in two instantiations: diag = false (the default
+// launch: no defect pass, no history stores, nothing of either in the
+// kernel) and diag = true (the launch when the defect or histories are asked
+// for), so that the default kernel's register allocation is not burdened by
+// code it does not run.
+
+// This job's history row, or null (always null in a diag = false kernel).
+template <bool diag>
 __device__ inline double* hist_row(const SolveArgs& a, const DevJob& jb) {
+  if constexpr (!diag) return nullptr;
   return a.hist ? a.hist + (size_t)jb.out * a.hist_len : nullptr;
 }
 
@@ -109,21 +118,28 @@ __device__ inline double optical_defect(const DevModel& md, const DevJob& jb, co
 // Amplitudes T_{mu_f v_f <- mu_i v_i} = Phi^{v_f mu_f T} Psi (Eq. (24)) for the
 // solution x of the job's symmetry block, the share 2 pi^3/eps_i sum_{mu_f}|T|^2
 // of sigma_{v_f <- v_i} (Eq. (16), eps_i in hartree), the full-layout Psi, the
-// optical-theorem defect and the status.  Called by all threads of the
-// workgroup after a barrier.
+// optical-theorem defect (diag kernels with check_optical set; else -1) and
+// the status.  Called by all threads of the workgroup after a barrier.
+template <bool diag>
 __device__ inline void finish_job(const SolveArgs& a, const DevModel& md, const DevJob& jb,
                                   const c64* x, int tid, int status, int iters, int cycles,
                                   int outer, double rel_res, double alg_bytes) {
   const int out = jb.out;
-  // the elastic amplitude T_ii (every thread, from the few entries of Phi_i)
-  c64 Tii = c64{0.0, 0.0};
-  {
-    PhiEntry e[6];
-    const int n = phi_entries(md, jb.mu, jb.eps_i, jb.vi_g, jb.vi_u, e);
-    for (int q = 0; q < n; ++q)
-      if (((e[q].u + jb.parity) & 1) == e[q].d) Tii = Tii + e[q].val * x[e[q].g * md.Nu + e[q].u];
+  double defect = -1.0;
+  if constexpr (diag) {
+    if (a.check_optical) {
+      // the elastic amplitude T_ii (every thread, from the few entries of Phi_i)
+      c64 Tii = c64{0.0, 0.0};
+      PhiEntry e[6];
+      const int n = phi_entries(md, jb.mu, jb.eps_i, jb.vi_g, jb.vi_u, e);
+      for (int q = 0; q < n; ++q)
+        if (((e[q].u + jb.parity) & 1) == e[q].d)
+          Tii = Tii + e[q].val * x[e[q].g * md.Nu + e[q].u];
+      defect = optical_defect(md, jb, x, Tii.y, sqrt(norm2(Tii)));
+      // the defect pass reads x once more (16 B per block unknown)
+      alg_bytes += 16.0 * md.Nc;
+    }
   }
-  const double defect = optical_defect(md, jb, x, Tii.y, sqrt(norm2(Tii)));
   if (tid < a.n_final) {
     const int g = a.finals[2 * tid], u = a.finals[2 * tid + 1];
     const double eps_f = jb.E - (md.omega_g * (g + 0.5) + md.omega_u * (u + 0.5));
@@ -150,9 +166,7 @@ __device__ inline void finish_job(const SolveArgs& a, const DevModel& md, const 
       psi[(size_t)(1 - act) * md.Nc + i] = c64{0.0, 0.0};
     }
   }
-  // the defect pass reads x once more (16 B per block unknown)
-  if (tid == 0)
-    a.info[out] = DevInfo{status, iters, cycles, outer, rel_res, alg_bytes + 16.0 * md.Nc, defect};
+  if (tid == 0) a.info[out] = DevInfo{status, iters, cycles, outer, rel_res, alg_bytes, defect};
 }
 
 }  // namespace vdc

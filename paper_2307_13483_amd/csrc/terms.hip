@@ -290,21 +290,25 @@ __global__ void __launch_bounds__(kBlock) gen_solve_kernel(GenArgs a) {
       for (int i = tid; i < N; i += kBlock) psi[i] = x[i];
     }
     // optical theorem: -Im T_ii = pi sum over open (v_f, mu_f) |T_f|^2 in the
-    // truncated basis (A = R + i pi sum Phi Phi^T, Eqs. (19), (23), (25))
-    double acc[1] = {0.0};
-    for (int i = tid; i < g.npts; i += kBlock) {
-      if (!(E - g.Enu[i] > 0.0)) continue;
-      int nk[kGenMaxModes];
-      gen_index(g, i, nk);
-      for (int k = g.M; k < kGenMaxModes; ++k) nk[k] = 0;
-      for (int mu = 0; mu < g.P; ++mu) acc[0] += norm2(gen_amplitude(g, E, nk, mu, x));
+    // truncated basis (A = R + i pi sum Phi Phi^T, Eqs. (19), (23), (25));
+    // when asked for (a uniform branch: every thread or none)
+    double defect = -1.0;
+    if (a.check_optical) {
+      double acc[1] = {0.0};
+      for (int i = tid; i < g.npts; i += kBlock) {
+        if (!(E - g.Enu[i] > 0.0)) continue;
+        int nk[kGenMaxModes];
+        gen_index(g, i, nk);
+        for (int k = g.M; k < kGenMaxModes; ++k) nk[k] = 0;
+        for (int mu = 0; mu < g.P; ++mu) acc[0] += norm2(gen_amplitude(g, E, nk, mu, x));
+      }
+      block_sum<1, double>(acc, L.red, L.red + kWaves);
+      const double S = L.red[kWaves];
+      __syncthreads();
+      const c64 Tii = gen_amplitude(g, E, jb.v, jb.mu, x);
+      const double ti = sqrt(norm2(Tii));
+      defect = ti > 0.0 ? fabs(-Tii.y - kPi * S) / ti : 0.0;
     }
-    block_sum<1, double>(acc, L.red, L.red + kWaves);
-    const double S = L.red[kWaves];
-    __syncthreads();
-    const c64 Tii = gen_amplitude(g, E, jb.v, jb.mu, x);
-    const double ti = sqrt(norm2(Tii));
-    const double defect = ti > 0.0 ? fabs(-Tii.y - kPi * S) / ti : 0.0;
     if (tid == 0)
       a.info[out] = DevInfo{status, iters, cycles, 0, bnorm > 0.0 ? beta / bnorm : 0.0,
                             passes * 16.0 * N, defect};

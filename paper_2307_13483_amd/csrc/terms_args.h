@@ -43,6 +43,7 @@ struct GenArgs {
   c64* psi_out;            // [n_jobs][psi_ld] or null
   size_t psi_ld;
   DevInfo* info;
+  int check_optical;       // compute the optical-theorem defect of each solution
 };
 
 hipError_t launch_gen_apply(const DevGen* gm_dev, int npts, double E, const c64* F, int n_vec,

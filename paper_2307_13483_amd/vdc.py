@@ -53,7 +53,7 @@ class SolveOpts(ctypes.Structure):
                 ("precond", ctypes.c_int), ("precision", ctypes.c_int),
                 ("inner_restart", ctypes.c_int), ("inner_tol", ctypes.c_double),
                 ("outer_restart", ctypes.c_int), ("tile_rows", ctypes.c_int),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("check_optical", ctypes.c_int)]
 
 
 class JobInfo(ctypes.Structure):
@@ -258,11 +258,12 @@ class Opts:
     outer_restart: int = 16
     tile_rows: int = 0
     method: int = GMRES
+    check_optical: int = 0   # 1: every job's optical-theorem defect (JobInfo.optical_defect)
 
     def c(self):
         return SolveOpts(self.restart, self.max_iter, self.tol, self.precond, self.precision,
                          self.inner_restart, self.inner_tol, self.outer_restart, self.tile_rows,
-                         self.method)
+                         self.method, int(self.check_optical))
 
 
 def level_shift(model, eps):

@@ -4,7 +4,8 @@ It must agree with the same quantity computed by the oracle from the GPU's
 own solution (same psi, different summation order: within 1e-13), be small
 for converged solves (<= 1e-8: exact for the exact solution, the residual of
 1e-10 times cond(A) of O(10^2) bounds it) and large for a solve stopped
-early, on every two-state solve path and on the term-list path."""
+early, on every two-state solve path and on the term-list path, when the
+launch asks for it (opts.check_optical); otherwise it is -1."""
 import itertools
 import math
 
@@ -54,7 +55,8 @@ def test_two_state_defect(vdc, path):
     Ng, Nu = 26, 22
     model = vdc.Model2D(p, Ng, Nu)
     jobs = [(0.45, (0, 0), 0), (1.6, (1, 0), 1), (2.8, (2, 0), 0), (2.1, (0, 1), 1)]
-    opts = vdc.Opts(**dict(dict(precond=vdc.PREC_BLOCK, max_iter=20000), **PATHS[path]))
+    opts = vdc.Opts(**dict(dict(precond=vdc.PREC_BLOCK, max_iter=20000, check_optical=1),
+                           **PATHS[path]))
     s = vdc.Solver(model, jobs, [(0, 0)], opts, want_psi=True).run(plain=path == "plain")
     infos = s.infos()
     psi = s.psi.cpu().numpy()
@@ -73,8 +75,10 @@ def test_defect_detects_an_unconverged_solution(vdc):
     Ng, Nu = 30, 24
     model = vdc.Model2D(p, Ng, Nu)
     jobs = [(2.4, (0, 0), 0), (2.9, (1, 0), 1)]
-    good = vdc.Solver(model, jobs, [(0, 0)], vdc.Opts(restart=30, precond=vdc.PREC_JACOBI)).run()
-    s = vdc.Solver(model, jobs, [(0, 0)], vdc.Opts(restart=1, max_iter=1, precond=vdc.PREC_JACOBI),
+    good = vdc.Solver(model, jobs, [(0, 0)], vdc.Opts(restart=30, precond=vdc.PREC_JACOBI,
+                                                      check_optical=1)).run()
+    s = vdc.Solver(model, jobs, [(0, 0)], vdc.Opts(restart=1, max_iter=1, precond=vdc.PREC_JACOBI,
+                                                   check_optical=1),
                    want_psi=True).run()
     psi = s.psi.cpu().numpy()
     for k, (info, ref) in enumerate(zip(s.infos(), good.infos())):
@@ -90,7 +94,8 @@ def test_term_list_defect(vdc):
     gm = vdc.TermModel(desc)
     jobs = [(0.6, (0, 0, 0), 0), (1.7, (1, 0, 0), 1), (2.5, (0, 1, 0), 0)]
     T, sig, psi, infos = vdc.model_solve(gm, jobs, [(0, 0, 0)],
-                                         vdc.Opts(restart=30, precond=vdc.PREC_JACOBI), want_psi=True)
+                                         vdc.Opts(restart=30, precond=vdc.PREC_JACOBI,
+                                                  check_optical=1), want_psi=True)
     psi = psi.cpu().numpy()
     grid = list(itertools.product(*[range(n) for n in desc["nbasis"]]))
     for k, (eps_i, vi, mu) in enumerate(jobs):
@@ -102,3 +107,23 @@ def test_term_list_defect(vdc):
         d_or = abs(-Tii.imag - math.pi * S) / abs(Tii)
         assert infos[k]["optical_defect"] <= 1e-8
         assert abs(infos[k]["optical_defect"] - d_or) <= 1e-13
+
+
+@pytest.mark.parametrize("path", ["cocg_fp32", "gmres", "plain"])
+def test_defect_not_computed_unless_asked(vdc, path):
+    """check_optical = 0 (the default): the launch takes the kernels without
+    the defect pass, every job reports -1, and the solutions, amplitudes and
+    iteration counts are those of the launch that computes it."""
+    p = inputs.draw_params(19)
+    model = vdc.Model2D(p, 24, 20)
+    jobs = [(0.8, (0, 0), 0), (2.2, (1, 0), 1)]
+    base = dict(dict(precond=vdc.PREC_BLOCK, max_iter=20000), **PATHS[path])
+    plain = path == "plain"
+    off = vdc.Solver(model, jobs, [(0, 0), (1, 0)], vdc.Opts(**base), want_psi=True).run(plain=plain)
+    on = vdc.Solver(model, jobs, [(0, 0), (1, 0)], vdc.Opts(**dict(base, check_optical=1)),
+                    want_psi=True).run(plain=plain)
+    for a, b in zip(off.infos(), on.infos()):
+        assert a["status"] == b["status"] == vdc.CONVERGED
+        assert a["optical_defect"] == -1.0 and 0.0 <= b["optical_defect"] <= 1e-8
+        assert a["iters"] == b["iters"]
+    assert bool((off.psi == on.psi).all()) and bool((off.T == on.T).all())
