@@ -9,8 +9,10 @@ batch; the oracle side runs in worker processes, tests/_oracle_pool.py):
   * CO2-like: 24 x 24 x 24 x 8 (331 776 unknowns), 384 right-hand sides,
     FP64 GMRES(20) with the bend-block preconditioner: the oracle recomputes
     ||b - A psi|| / ||b|| with its own assembled A (no LU at this size);
-  * uneven mixed precision: the 64 instances in one launch, eight of them
-    (the largest basis among them) against LU (skipped: see UNEVEN_FAULT);
+  * uneven mixed precision: the 64 instances in one launch by FGMRES with
+    FP32 inner GMRES (the configuration's method), eight of them (the
+    largest basis among them) against LU; the same by FP32-inner COCG is
+    skipped (see UNEVEN_FAULT);
   * adjoint: 120 x 120, two incident energies of the gradient workload's
     grid, every parameter against the oracle's explicit-derivative gradient.
 
@@ -167,6 +169,39 @@ def test_uneven_config_instances(vdc):
     sizes = np.array([i["Ng"] for i in insts])
     big = int(np.argmax(sizes))
     chosen = [big] + [k for k in range(0, 64, 9) if k != big][:7]
+    picks = [2 * k + (q % 2) for q, k in enumerate(chosen)]
+    args, jl = [], []
+    for j in picks:
+        eps_i, vi, mu, k = jobs[j]
+        ins = insts[k]
+        N = 2 * ins["Ng"] * ins["Nu"]
+        args.append((ins["params"], ins["Ng"], ins["Nu"], (eps_i, vi, mu), finals,
+                     s.psi[j, :N].cpu().numpy()))
+        jl.append((eps_i, vi, mu))
+    checks = op.pool_map(op.check_2d_job, args)
+    _assert_2d(checks, s.T[picks].cpu().numpy(), s.sigma[picks].cpu().numpy(), jl)
+    assert max(sizes[chosen]) == max(sizes)
+
+
+@pytest.mark.timeout(900)
+def test_uneven_config_fgmres(vdc):
+    """The uneven configuration as specified: the 64 instances (both partial
+    waves, 128 right-hand sides) in one launch by FGMRES whose inner GMRES
+    (matvec and orthogonalisation) runs in FP32, FP64 outer residual, Givens
+    and amplitudes, tol 1e-10; eight instances, the largest basis among them,
+    against the oracle's LU."""
+    insts = inputs.uneven_instances()
+    models = [vdc.Model2D(i["params"], i["Ng"], i["Nu"]) for i in insts]
+    jobs = [(i["eps"], (0, 0), mu, k) for k, i in enumerate(insts) for mu in (0, 1)]
+    finals = [(k, 0) for k in range(6)]
+    opts = vdc.Opts(precision=vdc.FP32_INNER, precond=vdc.PREC_BLOCK, method=vdc.GMRES,
+                    outer_restart=16, inner_restart=8, inner_tol=1e-3, max_iter=20000)
+    s = vdc.Solver(models, jobs, finals, opts, want_psi=True).run()
+    infos = s.infos()
+    assert all(i["status"] == vdc.CONVERGED for i in infos)
+    sizes = np.array([i["Ng"] for i in insts])
+    big = int(np.argmax(sizes))
+    chosen = [big] + [k for k in range(3, 64, 9) if k != big][:7]
     picks = [2 * k + (q % 2) for q, k in enumerate(chosen)]
     args, jl = [], []
     for j in picks:
