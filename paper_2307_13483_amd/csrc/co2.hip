@@ -78,17 +78,21 @@ __device__ inline c64 co2_plane_entry(const Co2Op& o, const double* sq, int s, i
 // points without a state carry the identity).  Then the elimination runs
 // with the active part of the band in registers: lane (R mod 64) holds row
 // R, register c the column j0 + c (j0 the first pivot of the current group
-// of kFacU pivots), so a pivot needs no LDS and no barrier: the pivot column
-// reaches every lane by readlane and each lane updates its own row.  After
+// of kFacU pivots), and each lane updates its own row.  After
 // kFacU pivots the registers move down by kFacU (the columns just eliminated
 // leave) and the kFacU rows that become active enter through LDS; their
-// band entries were fetched one group earlier.
+// band entries were fetched one group earlier.  The pivot column reaches
+// the lanes through LDS (each lane writes its entry, every lane reads the
+// entries after the pivot as broadcast loads) rather than by readlane: 48
+// complex values per pivot as scalars would not fit the scalar registers.
 
 constexpr int kFacU = 4;                          // pivots per register shift
 constexpr int kFacMaxW = 48;                      // largest half bandwidth: Ny <= 24
 constexpr int kFacSlots = kFacMaxW + kFacU;       // register columns per row
 constexpr int kFacWaves = 4;                      // planes per workgroup
 constexpr int kFacStencil = 7;                    // stencil offsets per column
+constexpr int kFacChunk = 16;                     // pivot-row entries per load chunk
+static_assert(kFacMaxW % kFacChunk == 0, "the pivot row is read in whole chunks");
 // a pivot below this fraction of its original diagonal entry (squared
 // magnitudes) sends the plane to its diagonal
 constexpr double kFacPivotTol = 1e-10;
@@ -121,6 +125,9 @@ __device__ inline void wave_lds_sync() {
 __global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArgs a) {
   __shared__ double sq[kSqMax + 1];
   __shared__ c32 stage[kFacWaves][kFacU * kFacSlots];
+  // the pivot column of each wavefront, twice over (lanes 0..63 at k and
+  // k + 64), in two buffers used by alternate pivots
+  __shared__ c32 colbuf[kFacWaves][2][128];
   fill_sq<double>(sq);
   __syncthreads();
   const Co2Model& m = *a.model;
@@ -197,7 +204,15 @@ __global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArg
 #pragma unroll
     for (int t = 0; t < kFacU; ++t) {
       const int j = j0 + t;
-      const c64 D = to64(rlane(A[t], j & 63));
+      // every lane's entry of column j, A(R, j) of its row R, into LDS: the
+      // pivot row's entries A(j, j + c') = A(j + c', j) (A is symmetric) are
+      // then read back by every lane as broadcast loads, pc[c' - 1]
+      c32* col = colbuf[wv][t & 1];
+      col[lane] = A[t];
+      col[lane + 64] = A[t];
+      wave_lds_sync();
+      const c32* pc = col + ((j + 1) & 63);
+      const c64 D = to64(col[j & 63]);
       const double nd = norm2(D);
       if (j < n) ok = ok && isfinite(nd) && nd > kFacPivotTol * (double)rlane(d0, j & 63);
       const c64 Di = cinv<double>(D);
@@ -215,14 +230,24 @@ __global__ void __launch_bounds__(64 * kFacWaves) co2_factor_kernel(Co2FactorArg
       // entries right of a row's diagonal land in registers no live row
       // uses)
       const c32 Lf = to32(L);
+      // (in chunks of kFacChunk: their broadcast loads, then their updates;
+      // the scheduling barrier keeps the chunks' loads from all being hoisted
+      // ahead, which would take kFacMaxW complex registers at once)
 #pragma unroll
-      for (int cp = 1; cp <= kFacMaxW; ++cp) {
-        const c32 sc = rlane(A[t], (j + cp) & 63);
-        c32& e = A[t + cp];
-        e.x = fmaf(-Lf.x, sc.x, e.x);
-        e.x = fmaf(Lf.y, sc.y, e.x);
-        e.y = fmaf(-Lf.x, sc.y, e.y);
-        e.y = fmaf(-Lf.y, sc.x, e.y);
+      for (int c0 = 1; c0 <= kFacMaxW; c0 += kFacChunk) {
+        c32 scv[kFacChunk];
+#pragma unroll
+        for (int q = 0; q < kFacChunk; ++q) scv[q] = pc[c0 - 1 + q];
+#pragma unroll
+        for (int q = 0; q < kFacChunk; ++q) {
+          const c32 sc = scv[q];
+          c32& e = A[t + c0 + q];
+          e.x = fmaf(-Lf.x, sc.x, e.x);
+          e.x = fmaf(Lf.y, sc.y, e.x);
+          e.y = fmaf(-Lf.x, sc.y, e.y);
+          e.y = fmaf(-Lf.y, sc.x, e.y);
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
 #pragma unroll
