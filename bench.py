@@ -492,6 +492,56 @@ UNEVEN_COCG_OFF = ("not run: a launch of this batch with FP32-inner COCG ended i
                    "AddressSanitizer is clean)")
 
 
+def terms_batched():
+    """The general (term-list) path, vdc_model_create + vdc_model_solve: the
+    two-state model at 120 x 120 written as term lists (2 energies of the
+    batched workload x v_i x mu = 12 jobs) solved by the term-list kernels
+    and, for comparison, dispatched to the two-state kernels; and the quartic
+    three-state, three-mode model at 30 x 24 x 12 (25 920 unknowns, 5 jobs).
+    FP64 COCG with the diagonal preconditioner; wall time of a second call."""
+    import numpy as np
+    import torch
+    from paper_2307_13483_amd import inputs, vdc
+    out = {}
+    cfg = inputs.batched_jobs(n_energies=2)
+    d2 = inputs.terms_from_2d(cfg["params"], cfg["Ng"], cfg["Nu"])
+    jobs = [(j[0], tuple(j[1]), j[2]) for j in cfg["jobs"]]
+    finals = [tuple(f) for f in cfg["finals"]]
+    opts = vdc.Opts(restart=30, precond=vdc.PREC_JACOBI, method=vdc.COCG, max_iter=20000)
+    Ts = {}
+    for name, dispatch in (("generic", False), ("dispatched", True)):
+        m = vdc.TermModel(d2, dispatch=dispatch)
+        vdc.model_solve(m, jobs, finals, opts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T, sig, _, infos = vdc.model_solve(m, jobs, finals, opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        Ts[name] = T.cpu().numpy()
+        out["two_state_120x120_" + name] = dict(
+            jobs=len(jobs), solves_per_s=len(jobs) / dt, kind=m.kind(),
+            converged=sum(i["status"] == 0 for i in infos),
+            worst_rel_res=max(i["rel_res"] for i in infos))
+    a, b = Ts["generic"], Ts["dispatched"]
+    out["two_state_max_rel_amplitude_diff"] = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+    dq = inputs.quartic_model(nbasis=(30, 24, 12))
+    qjobs = [(0.35, (0, 0, 0), 0), (1.2, (1, 0, 0), 1), (2.6, (0, 1, 0), 0), (1.9, (0, 0, 1), 1),
+             (2.9, (0, 0, 0), 1)]
+    qfin = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (2, 0, 1)]
+    m = vdc.TermModel(dq)
+    vdc.model_solve(m, qjobs, qfin, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T, sig, _, infos = vdc.model_solve(m, qjobs, qfin, opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["quartic_30x24x12"] = dict(jobs=len(qjobs), unknowns=m.N, solves_per_s=len(qjobs) / dt,
+                                   converged=sum(i["status"] == 0 for i in infos),
+                                   worst_rel_res=max(i["rel_res"] for i in infos),
+                                   iters_mean=float(np.mean([i["iters"] for i in infos])))
+    return out
+
+
 def uneven_mixed(pc, finals):
     """64 instances of the two-state model (own parameter draws, n x n basis
     with n in 40..160, one energy each), both partial waves, in one launch."""
@@ -590,6 +640,8 @@ def extras(args, model, cfg):
                            ("block_fp32_inner", _v.PREC_BLOCK, True))}
     ex["ecd86"] = ecd86_batched()
     log("ecd86 done")
+    ex["terms"] = terms_batched()
+    log("terms done")
     ex["adjoint"] = {name: adjoint_gradient(o) for name, o in
                      (("gmres6", _v.Opts(restart=6, precond=pc)),
                       ("cocg", _v.Opts(precond=pc, method=_v.COCG)))}
@@ -645,12 +697,17 @@ def main():
                     help="only run the headline configuration as a captured HIP graph (fixed options)")
     ap.add_argument("--uneven-probe", action="store_true",
                     help="only run the uneven mixed-precision batch (64 instances, 128 solves)")
+    ap.add_argument("--terms-probe", action="store_true",
+                    help="only run the term-list (general model) workloads")
     ap.add_argument("--ecd-probe", action="store_true",
                     help="only run the ECD86 workload (512 solves, row blocks and the diagonal)")
     args = ap.parse_args()
     if args.uneven_probe:
         print(json.dumps({"uneven_mixed": uneven_mixed(PRECONDS[args.precond],
                                                        [(k, 0) for k in range(6)])}), flush=True)
+        return
+    if args.terms_probe:
+        print(json.dumps({"terms": terms_batched()}), flush=True)
         return
     if args.ecd_probe:
         print(json.dumps({"ecd86": ecd86_batched()}), flush=True)
