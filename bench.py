@@ -11,7 +11,11 @@ the cross-section shares.  The per-energy level-shift tables are built inside
 the step.  Inputs are synthetic (seeded parameters; the paper uses no
 dataset).
 
-Prints one JSON line (see DESIGN.md for the byte model behind "roofline").
+Prints one JSON line.  "roofline" divides the solver kernel's algorithmic
+bytes (the byte model each solver kernel applies to its own passes,
+vdc_job_info.alg_bytes) by that kernel's time from HIP events on its launch
+stream, against 8 TB/s; "traffic" comes from committed byte-counter
+summaries when they were taken on the current kernel sources.
 """
 import argparse
 import dataclasses
