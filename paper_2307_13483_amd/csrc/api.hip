@@ -42,6 +42,8 @@ hipError_t launch_co2_factor(const Co2FactorArgs& a, int Ns, int Na, hipStream_t
 hipError_t launch_co2_gmres(const Co2Args& a, int n_groups, hipStream_t s);
 hipError_t launch_co2_ops(const Co2OpsArgs& a, int n_groups, hipStream_t s);
 hipError_t launch_co2_apply_split(const Co2OpsArgs& a, int npts, int batch, hipStream_t s);
+hipError_t launch_co2_march(const Co2OpsArgs& a, int Ns, int Nx, int Ny, int Na, hipStream_t s);
+bool co2_march_fits(int Ns, int Nx, int Ny, int Na);
 constexpr int kCo2ApplyBatch = 128;   // vectors per pass pair of the split operator
 int co2_factor_max_ny();
 vdc_status solve_plain_impl(const SolveArgs& a, const std::vector<DevJob>& jobs,
@@ -1642,9 +1644,11 @@ vdc_status vdc_co2_ops_workspace_size(vdc_co2_t model, int n_vec, int which, siz
   const Co2Model& md = model->dev;
   if (which == 1 && md.Ny > co2_factor_max_ny())
     return fail(VDC_ERR_UNSUPPORTED, "the block preconditioner needs Ny <= 24");
-  // which = 0: the split operator's w planes for a batch of vectors;
-  // which = 1: one slot per workgroup (the block apply needs none, kept small)
-  const int groups = which == 0 ? std::max(1, std::min(n_vec, kCo2ApplyBatch))
+  // which = 0: none for the march along n_s (co2_march_fits), else the
+  // split operator's w planes for a batch of vectors; which = 1: one slot per
+  // workgroup (the block apply needs none, kept small)
+  const bool march = co2_march_fits(md.Ns, md.Nx, md.Ny, md.Na);
+  const int groups = which == 0 ? (march ? 0 : std::max(1, std::min(n_vec, kCo2ApplyBatch)))
                                 : std::max(1, std::min(n_vec, cu_count()));
   const size_t fac = which == 1 ? co2_fac_bytes(md) : 0;
   size_t off = 0;
@@ -1724,7 +1728,9 @@ vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const 
   a.slot_elems = 2 * (size_t)md.npts;
   a.fac = d_fac;
   a.fac_job_bytes = fac_job;
-  if (which == 0)
+  if (which == 0 && co2_march_fits(md.Ns, md.Nx, md.Ny, md.Na))
+    HIPCHK(launch_co2_march(a, md.Ns, md.Nx, md.Ny, md.Na, s));
+  else if (which == 0)
     HIPCHK(launch_co2_apply_split(a, md.npts, std::max(1, std::min(n_vec, kCo2ApplyBatch)), s));
   else
     HIPCHK(launch_co2_ops(a, groups, s));

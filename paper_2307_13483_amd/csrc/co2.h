@@ -64,6 +64,26 @@ __host__ __device__ inline int co2_type(int x, int y, int px, int py) {
 __host__ __device__ inline int co2_sector_x(const int* v, int mu) { return (v[1] + (mu == 1)) & 1; }
 __host__ __device__ inline int co2_sector_y(const int* v, int mu) { return (v[2] + (mu == 2)) & 1; }
 
+// c ? a : b on complex values, component by component (keeps the choice a
+// choice of values, never of the addresses they were read from)
+__device__ __forceinline__ c64 co2_sel(bool c, c64 a, c64 b) {
+  return c64{c ? a.x : b.x, c ? a.y : b.y};
+}
+
+// A model coefficient as a wavefront-uniform value.  Choices between two
+// coefficients by a lane's class are made between such values: a choice
+// between the fields themselves is compiled into a per-lane choice of
+// address and a vector load.
+__device__ inline double co2_uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double co2_pick(bool first, double a, double b) {
+  return first ? co2_uniform(a) : co2_uniform(b);
+}
+
 // (q^2)_{n n} and (q^2)_{n, n+2} of the truncated product
 __device__ inline double q2_diag(int n, int N) { return 0.5 * n + (n + 1 < N ? 0.5 * (n + 1) : 0.0); }
 
@@ -105,27 +125,48 @@ __device__ inline c64 co2_tab(const Co2Op& o, int s, int x, int y, int a, int t,
 // weights are sqrt(n/2) read at index 0 = 0), so that all loads of a point
 // can be in flight together.  Terms are added in the same order as a
 // branchy evaluation would add them (a skipped term adds zero).
+//
+// The point arithmetic takes its neighbours from an accessor: z(ok, ds, da,
+// dx, dy) is vs v at the point offset by (ds, da, dx, dy) in (n_s, n_a, n_x,
+// n_y) when ok, else at the point itself; w(ok, ds, dx, dy) the level-shift
+// product of the point's own channel class (w_A at a sigma point, w_B at a Pi
+// point) at the offset point, else at the point itself; tab(o, p, t, k) the
+// level-shift value co2_tab at the point.  Co2Flat reads a whole vector and
+// its w planes from memory.
+struct Co2Flat {
+  const c64* v;
+  double vs;
+  const c64* wc;             // w_A or w_B, by the point's class (phase 2)
+  int i, ss, sa, sx, sy;
+  __device__ c64 z(bool ok, int ds, int da, int dx, int dy) const {
+    return vs * v[ok ? i + ds * ss + da * sa + dx * sx + dy * sy : i];
+  }
+  __device__ c64 w(bool ok, int ds, int dx, int dy) const {
+    return wc[ok ? i + ds * ss + dx * sx + dy * sy : i];
+  }
+  __device__ c64 tab(const Co2Op& o, const Co2Point& p, int t, int k) const {
+    return co2_tab(o, p.s, p.x, p.y, p.a, t, k);
+  }
+};
 
-// Phase 1 at point i: the pointwise level-shift products (w_A, w_B) of the
+// Phase 1 at point p: the pointwise level-shift products (w_A, w_B) of the
 // channel that reaches the point.
-__device__ inline void co2_phase1(const Co2Op& o, const double* sq, const c64* v, double vs,
-                                  int i, c64& wa, c64& wb) {
+template <typename Acc>
+__device__ inline void co2_point1(const Co2Op& o, const double* sq, const Acc& Z, const Co2Point& p,
+                                  c64& wa, c64& wb) {
   const Co2Model& m = *o.m;
-  const Co2Point p = co2_point(m, i);
   const int t = co2_type(p.x, p.y, o.px, o.py);
-  const int sy = 1, sx = m.Ny, ss = m.Na * m.Nx * m.Ny;
-  auto Z = [&](bool ok, int d) { return vs * v[ok ? i + d : i]; };
   // sqrt(n/2) z(n - 1) + sqrt((n + 1)/2) z(n + 1) along one mode
-  auto pair = [&](int n, int N, int st) {
-    const bool lo = n > 0, hi = n + 1 < N;
-    return sq[lo ? n : 0] * Z(lo, -st) + sq[hi ? n + 1 : 0] * Z(hi, st);
-  };
-  const c64 z0 = vs * v[i];
-  const c64 qs = pair(p.s, m.Ns, ss), qx = pair(p.x, m.Nx, sx), qy = pair(p.y, m.Ny, sy);
+  const bool slo = p.s > 0, shi = p.s + 1 < m.Ns, xlo = p.x > 0, xhi = p.x + 1 < m.Nx;
+  const bool ylo = p.y > 0, yhi = p.y + 1 < m.Ny;
+  const c64 z0 = Z.z(true, 0, 0, 0, 0);
+  const c64 qs = sq[slo ? p.s : 0] * Z.z(slo, -1, 0, 0, 0) + sq[shi ? p.s + 1 : 0] * Z.z(shi, 1, 0, 0, 0);
+  const c64 qx = sq[xlo ? p.x : 0] * Z.z(xlo, 0, 0, -1, 0) + sq[xhi ? p.x + 1 : 0] * Z.z(xhi, 0, 0, 1, 0);
+  const c64 qy = sq[ylo ? p.y : 0] * Z.z(ylo, 0, 0, 0, -1) + sq[yhi ? p.y + 1 : 0] * Z.z(yhi, 0, 0, 0, 1);
   const int tt = t == 3 ? 0 : t;
-  const c64 T0 = co2_tab(o, p.s, p.x, p.y, p.a, tt, 0);
-  const c64 T1 = co2_tab(o, p.s, p.x, p.y, p.a, tt, 1);
-  const c64 T2 = co2_tab(o, p.s, p.x, p.y, p.a, tt, 2);
+  const c64 T0 = Z.tab(o, p, tt, 0);
+  const c64 T1 = Z.tab(o, p, tt, 1);
+  const c64 T2 = Z.tab(o, p, tt, 2);
   const c64 us = t == 0 ? z0 + m.l_sigma * qs : m.h_sigma * (t == 1 ? qx : qy);
   const c64 up = t == 0 ? m.h_pi * (qx + qy) : z0 + m.l_pi * qs;
   wa = T0 * us + T1 * up;
@@ -133,59 +174,75 @@ __device__ inline void co2_phase1(const Co2Op& o, const double* sq, const c64* v
   if (t == 3) wa = wb = c64{0.0, 0.0};
 }
 
-// Phase 2 at point i: y = (E - E_nu) z - U z - F z.
-__device__ inline c64 co2_phase2(const Co2Op& o, const double* sq, const c64* v, double vs,
-                                 const c64* wA, const c64* wB, int i) {
+// Phase 2 at point p: y = (E - E_nu) z - U z - F z.
+template <typename Acc>
+__device__ inline c64 co2_point2(const Co2Op& o, const double* sq, const Acc& Z, const Co2Point& p) {
   const Co2Model& m = *o.m;
-  const Co2Point p = co2_point(m, i);
   const int t = co2_type(p.x, p.y, o.px, o.py);
-  const int sy = 1, sx = m.Ny, sa = m.Nx * m.Ny, ss = m.Na * m.Nx * m.Ny;
   const int s = p.s, a = p.a, x = p.x, y = p.y;
-  auto Z = [&](bool ok, int d) { return vs * v[ok ? i + d : i]; };
-  const c64 z0 = vs * v[i];
+  const c64 z0 = Z.z(true, 0, 0, 0, 0);
   const int c = t == 0 ? 0 : 1;
-  const double rt = t == 0 ? 0.0 : (t == 1 ? m.c_rt : -m.c_rt);
+  const double rt = t == 0 ? 0.0 : co2_pick(t == 1, m.c_rt, -m.c_rt);
   // diagonal-state polynomial: E_d + k q_s + g_s q_s^2 + (g_b + rt) q_x^2 + (g_b - rt) q_y^2 + g_a q_a^2
   const bool s_lo = s > 0, s_hi = s + 1 < m.Ns;
   const double ws_lo = sq[s_lo ? s : 0], ws_hi = sq[s_hi ? s + 1 : 0];
-  const c64 qs1 = ws_lo * Z(s_lo, -ss) + ws_hi * Z(s_hi, ss);
-  auto q2 = [&](int n, int N, int st) {
+  const c64 qs1 = ws_lo * Z.z(s_lo, -1, 0, 0, 0) + ws_hi * Z.z(s_hi, 1, 0, 0, 0);
+  // (q^2 z) along mode k: n, its basis size N, unit offset (ds, da, dx, dy)
+  auto q2 = [&](int n, int N, int us, int ua, int ux, int uy) {
     const bool lo = n >= 2, hi = n + 2 < N;
-    return q2_diag(n, N) * z0 + (sq[lo ? n - 1 : 0] * sq[lo ? n : 0]) * Z(lo, -2 * st) +
-           (sq[hi ? n + 1 : 0] * sq[hi ? n + 2 : 0]) * Z(hi, 2 * st);
+    return q2_diag(n, N) * z0 + (sq[lo ? n - 1 : 0] * sq[lo ? n : 0]) * Z.z(lo, -2 * us, -2 * ua, -2 * ux, -2 * uy) +
+           (sq[hi ? n + 1 : 0] * sq[hi ? n + 2 : 0]) * Z.z(hi, 2 * us, 2 * ua, 2 * ux, 2 * uy);
   };
-  c64 U = (c == 0 ? m.E_sigma : m.E_pi) * z0 + (c == 0 ? m.k_sigma : m.k_pi) * qs1 +
-          m.gs[c] * q2(s, m.Ns, ss) + (m.gb[c] + rt) * q2(x, m.Nx, sx) +
-          (m.gb[c] - rt) * q2(y, m.Ny, sy) + m.ga[c] * q2(a, m.Na, sa);
+  const double gs = co2_pick(c == 0, m.gs[0], m.gs[1]), gb = co2_pick(c == 0, m.gb[0], m.gb[1]);
+  const double ga = co2_pick(c == 0, m.ga[0], m.ga[1]);
+  c64 U = co2_pick(c == 0, m.E_sigma, m.E_pi) * z0 + co2_pick(c == 0, m.k_sigma, m.k_pi) * qs1 +
+          gs * q2(s, m.Ns, 1, 0, 0, 0) + (gb + rt) * q2(x, m.Nx, 0, 0, 1, 0) +
+          (gb - rt) * q2(y, m.Ny, 0, 0, 0, 1) + ga * q2(a, m.Na, 0, 1, 0, 0);
   // sigma - Pi couplings c (1 + c' q_s) q_x and c (1 + c' q_s) q_y, at the
   // point's s - 1, s, s + 1
   const bool x_lo = x > 0, x_hi = x + 1 < m.Nx, y_lo = y > 0, y_hi = y + 1 < m.Ny;
   const double wx_lo = sq[x_lo ? x : 0], wx_hi = sq[x_hi ? x + 1 : 0];
   const double wy_lo = sq[y_lo ? y : 0], wy_hi = sq[y_hi ? y + 1 : 0];
   auto qx_at = [&](bool ok, int ds) {
-    return wx_lo * Z(ok && x_lo, ds - sx) + wx_hi * Z(ok && x_hi, ds + sx);
+    return wx_lo * Z.z(ok && x_lo, ds, 0, -1, 0) + wx_hi * Z.z(ok && x_hi, ds, 0, 1, 0);
   };
   auto qy_at = [&](bool ok, int ds) {
-    return wy_lo * Z(ok && y_lo, ds - sy) + wy_hi * Z(ok && y_hi, ds + sy);
+    return wy_lo * Z.z(ok && y_lo, ds, 0, 0, -1) + wy_hi * Z.z(ok && y_hi, ds, 0, 0, 1);
   };
-  const c64 cx = m.c_sp * (qx_at(true, 0) + m.c_sp2 * (ws_lo * qx_at(s_lo, -ss) + ws_hi * qx_at(s_hi, ss)));
-  const c64 cy = m.c_sp * (qy_at(true, 0) + m.c_sp2 * (ws_lo * qy_at(s_lo, -ss) + ws_hi * qy_at(s_hi, ss)));
+  const c64 cx = m.c_sp * (qx_at(true, 0) + m.c_sp2 * (ws_lo * qx_at(s_lo, -1) + ws_hi * qx_at(s_hi, 1)));
+  const c64 cy = m.c_sp * (qy_at(true, 0) + m.c_sp2 * (ws_lo * qy_at(s_lo, -1) + ws_hi * qy_at(s_hi, 1)));
   // Pi_x - Pi_y: 2 c_rt q_x q_y
-  const c64 xy = (wx_lo * wy_lo) * Z(x_lo && y_lo, -sx - sy) + (wx_lo * wy_hi) * Z(x_lo && y_hi, -sx + sy) +
-                 (wx_hi * wy_lo) * Z(x_hi && y_lo, sx - sy) + (wx_hi * wy_hi) * Z(x_hi && y_hi, sx + sy);
+  const c64 xy = (wx_lo * wy_lo) * Z.z(x_lo && y_lo, 0, 0, -1, -1) + (wx_lo * wy_hi) * Z.z(x_lo && y_hi, 0, 0, -1, 1) +
+                 (wx_hi * wy_lo) * Z.z(x_hi && y_lo, 0, 0, 1, -1) + (wx_hi * wy_hi) * Z.z(x_hi && y_hi, 0, 0, 1, 1);
   U = t == 0 ? (U + cx) + cy : (U + (t == 1 ? cx : cy)) + (2.0 * m.c_rt) * xy;
   // F z: transposed sandwich of the neighbours' (w_A, w_B)
-  const c64* w = t == 0 ? wA : wB;
-  auto W = [&](bool ok, int d) { return w[ok ? i + d : i]; };
-  const c64 sl = ws_lo * W(s_lo, -ss) + ws_hi * W(s_hi, ss);
-  const c64 rx = wx_lo * W(x_lo, -sx) + wx_hi * W(x_hi, sx);
-  const c64 ry = wy_lo * W(y_lo, -sy) + wy_hi * W(y_hi, sy);
-  c64 Fz = w[i] + (t == 0 ? m.l_sigma : m.l_pi) * sl;
-  if (t == 0 || t == 1) Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * rx;
-  if (t == 0 || t == 2) Fz = Fz + (t == 0 ? m.h_sigma : m.h_pi) * ry;
+  const c64 sl = ws_lo * Z.w(s_lo, -1, 0, 0) + ws_hi * Z.w(s_hi, 1, 0, 0);
+  const c64 rx = wx_lo * Z.w(x_lo, 0, -1, 0) + wx_hi * Z.w(x_hi, 0, 1, 0);
+  const c64 ry = wy_lo * Z.w(y_lo, 0, 0, -1) + wy_hi * Z.w(y_hi, 0, 0, 1);
+  c64 Fz = Z.w(true, 0, 0, 0) + co2_pick(t == 0, m.l_sigma, m.l_pi) * sl;
+  const double h = co2_pick(t == 0, m.h_sigma, m.h_pi);
+  if (t == 0 || t == 1) Fz = Fz + h * rx;
+  if (t == 0 || t == 2) Fz = Fz + h * ry;
   const double Ev = m.omega_s * (s + 0.5) + m.omega_b * (x + y + 1.0) + m.omega_a * (a + 0.5);
   const c64 out = (o.E - Ev) * z0 - U - Fz;
   return t == 3 ? c64{0.0, 0.0} : out;
+}
+
+// The two phases at flat point i of a vector v in memory (wA, wB its w planes).
+__device__ inline void co2_phase1(const Co2Op& o, const double* sq, const c64* v, double vs,
+                                  int i, c64& wa, c64& wb) {
+  const Co2Model& m = *o.m;
+  const Co2Flat Z{v, vs, nullptr, i, m.Na * m.Nx * m.Ny, m.Nx * m.Ny, m.Ny, 1};
+  co2_point1(o, sq, Z, co2_point(m, i), wa, wb);
+}
+
+__device__ inline c64 co2_phase2(const Co2Op& o, const double* sq, const c64* v, double vs,
+                                 const c64* wA, const c64* wB, int i) {
+  const Co2Model& m = *o.m;
+  const Co2Point p = co2_point(m, i);
+  const int t = co2_type(p.x, p.y, o.px, o.py);
+  const Co2Flat Z{v, vs, t == 0 ? wA : wB, i, m.Na * m.Nx * m.Ny, m.Nx * m.Ny, m.Ny, 1};
+  return co2_point2(o, sq, Z, p);
 }
 
 // y = A (vs v) over the whole vector by one workgroup; wA, wB are scratch

@@ -740,6 +740,221 @@ __global__ void __launch_bounds__(kCo2Threads) co2_y_kernel(Co2OpsArgs a, int v0
       co2_phase2(op, sq, a.x + (size_t)v * md.npts, 1.0, w, w + md.npts, i);
 }
 
+// The operator on many sector vectors at once by marching along n_s
+// (vdc_co2_apply, which = 0, for bend planes of Nx Ny <= kMarchMaxPlane
+// points): one workgroup per (vector, n_a), one thread per bend point
+// j = n_x Ny + n_y.  Step s of the march
+//   stores z and the level-shift rows of plane s + 1 into LDS rings (four
+//   z planes, two planes of rows),
+//   computes (w_A, w_B) at s + 1 (co2_point1; its bend neighbours from LDS),
+//   stores the component the point's bend neighbours read into a ring of two
+//   LDS planes,
+//   computes y at s (co2_point2; the bend neighbours of z at s - 1 .. s + 1
+//   and of w at s from LDS, the own column and z at n_a -+ 2 from
+//   registers) and stores it,
+// with one barrier per step: a z slot written in step s was last read in
+// step s - 2, a w or row slot in step s - 1, before the barrier of step s.
+// A bend neighbour (n_x +- 1 or n_y +- 1) flips one parity, so it is of the
+// other class or carries no state: each point stores only the component of
+// the other class (w_B at sigma points, w_A at Pi points).  Every x value is
+// read from memory three times (own column, and as the n_a +- 2 neighbour of
+// two workgroups of the same vector), y written once, and no w leaves the
+// chip.  Loads run ahead: the own column three planes, the level-shift rows
+// one plane, z at n_a -+ 2 from the top of the step that uses it.
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod
+// 8); the workgroups of one vector are numbered so that they share an XCD and
+// follow each other there, and their n_a +- 2 reads meet one L2.  The same
+// per-point arithmetic as the solver's operator and the split passes.
+constexpr int kMarchMaxPlane = 1024;
+
+// Neighbour accessor of the march for a centre at plane s (see co2_point1,
+// co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
+// of the neighbour components of w at s and the point's level-shift values;
+// in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
+// class's w at s - 1 .. s + 1.  A neighbour that is not in the basis reads
+// the centre, as in Co2Flat; the LDS is read at the own point then and the
+// value discarded.
+struct Co2Ring {
+  const c64* zm2;
+  const c64* zp[3];
+  const c64* wn;
+  const c64* T;
+  c64 z0, z1, z2, za[2], wc[3];
+  int j, sx;
+  __device__ c64 z(bool ok, int ds, int da, int dx, int dy) const {
+    if (da != 0) return co2_sel(ok, za[da > 0 ? 1 : 0], z0);
+    if (dx == 0 && dy == 0) {
+      if (ds == 0) return z0;
+      if (ds == 1) return co2_sel(ok, z1, z0);
+      if (ds == 2) return co2_sel(ok, z2, z0);
+      return co2_sel(ok, ds == -1 ? zp[0][j] : zm2[j], z0);
+    }
+    return co2_sel(ok, zp[1 + ds][ok ? j + dx * sx + dy : j], z0);
+  }
+  __device__ c64 w(bool ok, int ds, int dx, int dy) const {
+    if (dx == 0 && dy == 0) return co2_sel(ok, wc[1 + ds], wc[1]);
+    return co2_sel(ok, wn[ok ? j + dx * sx + dy : j], wc[1]);
+  }
+  __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return T[k]; }
+};
+
+// Doubles of sqrt(n/2) at the head of the march's dynamic LDS (even, so the
+// planes after them stay 16-byte aligned), and the whole dynamic LDS: sqrt
+// values, z ring [4][Nx Ny], w ring [2][Nx Ny], row ring [2][6 (Nx + Ny - 1)].
+__host__ __device__ inline int co2_march_sq(int Ns, int Nx, int Ny, int Na) {
+  const int nmax = max(max(Ns, Nx), max(Ny, Na));
+  return (nmax + 4) & ~1;
+}
+
+__host__ __device__ inline size_t co2_march_lds(int Ns, int Nx, int Ny, int Na) {
+  return (size_t)co2_march_sq(Ns, Nx, Ny, Na) * sizeof(double) +
+         ((size_t)6 * Nx * Ny + (size_t)2 * kNumF * (Nx + Ny - 1)) * sizeof(c64);
+}
+
+// The model, vectors and rows come as separate kernel arguments, none aliasing
+// another, so that the model's fields are read once into scalar registers
+// and no store of y orders the loads of x.
+template <int kThreads>
+__global__ void __launch_bounds__(kThreads)
+    co2_march_kernel(const Co2Model* __restrict__ model, const c64* __restrict__ tab,
+                     const int* __restrict__ sectors, int n_vec, double E,
+                     const c64* __restrict__ x_in, c64* __restrict__ y_out) {
+  const Co2Model& md = *model;
+  const int Ns = md.Ns, Na = md.Na, Ny = md.Ny, NP = md.Nx * md.Ny;
+  const int b = blockIdx.x, slot = b >> 3;
+  const int ia = slot % Na;
+  const int v = (slot / Na) * 8 + (b & 7);
+  if (v >= n_vec) return;
+  const int tid = threadIdx.x;
+  const int nsq = co2_march_sq(Ns, md.Nx, Ny, Na);
+  const int ntp = kNumF * md.nb;              // level-shift values of one plane's rows
+  double* sq = reinterpret_cast<double*>(vdc_tile_lds);
+  c64* zl = reinterpret_cast<c64*>(vdc_tile_lds + nsq * sizeof(double));   // [4][NP]
+  c64* wl = zl + 4 * NP;                                                   // [2][NP]
+  c64* tl = wl + 2 * NP;                                                   // [2][ntp]
+  for (int n = tid; n < nsq; n += blockDim.x) sq[n] = sqrt(0.5 * n);
+  // lanes past the plane compute point 0 and store nothing
+  const bool live = tid < NP;
+  const int j = live ? tid : 0;
+  const int x = j / Ny, y = j - x * Ny;
+  const Co2Op op{model, tab, E, sectors[2 * v], sectors[2 * v + 1]};
+  const int t = co2_type(x, y, op.px, op.py);
+  const int trow_off = (x + y) * kNumF + (t == 0 || t == 3 ? 0 : 3);   // co2_tab's row and class
+  const int ss = Na * NP;                     // stride of n_s
+  // this workgroup's column block of the vector: point (s, n_a, j) at s ss + j
+  const c64* xv = x_in + (size_t)v * md.npts + (size_t)ia * NP;
+  c64* yv = y_out + (size_t)v * md.npts + (size_t)ia * NP;
+  const c64* tab_a = tab + (size_t)ia * kNumF;
+  const bool alo = ia >= 2, ahi = ia + 2 < Na;
+  const c64 zero{0.0, 0.0};
+  // z of the own column at plane s (0 past the last), and at s, n_a + da
+  auto zat = [&](int s) {
+    c64 r{0.0, 0.0};
+    if (s < Ns) r = xv[s * ss + j];
+    return r;
+  };
+  auto zna = [&](bool ok, int s, int da) {
+    c64 r{0.0, 0.0};
+    if (ok && s < Ns) r = xv[s * ss + da * NP + j];
+    return r;
+  };
+  // value i of the level-shift rows of plane s (co2_tab at n_x + n_y = i / 6)
+  auto trow = [&](int s, int i) {
+    return tab_a[(size_t)(s * md.nb + i / kNumF) * Na * kNumF + i % kNumF];
+  };
+  auto trow_ahead = [&](int s) {
+    c64 r{0.0, 0.0};
+    if (tid < ntp && s < Ns) r = trow(s, tid);
+    return r;
+  };
+  // z(s), z(s + 1), z(s + 2) of the own column and z(s + 3), z(s + 4) in
+  // flight; z(s, n_a -+ 2); the own class's w(s - 1), w(s); the rows of plane
+  // s + 1 in flight.  The loads of a step are issued at its top and waited
+  // for at its end, where the registers move down.
+  c64 z0 = zat(0), z1 = zat(1), z2 = zat(2);
+  c64 q1 = zat(3), q2 = zat(4);
+  c64 zam = zna(alo, 0, -2), zap = zna(ahi, 0, 2);
+  c64 wo0 = zero, wo1 = zero;
+  for (int i = tid; i < ntp; i += blockDim.x) tl[i] = trow(0, i);
+  c64 tq = trow_ahead(1);
+  // plane 0 and its w
+  if (live) zl[j] = z0;
+  __syncthreads();
+  {
+    const Co2Ring R{zl, {zl, zl, zl}, wl, tl + trow_off, z0, z1, zero, {zero, zero}, {zero, zero, zero},
+                    j, Ny};
+    c64 wa, wb;
+    co2_point1(op, sq, R, Co2Point{0, ia, x, y, 0}, wa, wb);
+    wo1 = co2_sel(t == 0, wa, wb);
+    if (live) wl[j] = co2_sel(t == 0, wb, wa);
+  }
+#pragma unroll 1
+  for (int s = 0; s < Ns; ++s) {
+    c64* zs1 = zl + ((s + 1) & 3) * NP;
+    c64* w1 = wl + ((s + 1) & 1) * NP;
+    c64* t1 = tl + ((s + 1) & 1) * ntp;
+    if (s + 1 < Ns) {
+      if (live) zs1[j] = z1;
+      if (tid < ntp) t1[tid] = tq;
+      for (int i = tid + blockDim.x; i < ntp; i += blockDim.x) t1[i] = trow(s + 1, i);
+    }
+    const c64 tq2 = trow_ahead(s + 2);
+    const c64 zam2 = zna(alo, s + 1, -2), zap2 = zna(ahi, s + 1, 2);
+    const c64 q3 = zat(s + 5);
+    __syncthreads();
+    c64 wn1 = zero;
+    if (s + 1 < Ns) {
+      const Co2Ring R{zl, {zl + (s & 3) * NP, zs1, zs1}, w1, t1 + trow_off, z1, z2, zero, {zero, zero},
+                      {zero, zero, zero}, j, Ny};
+      c64 wa, wb;
+      co2_point1(op, sq, R, Co2Point{s + 1, ia, x, y, 0}, wa, wb);
+      wn1 = co2_sel(t == 0, wa, wb);
+      if (live) w1[j] = co2_sel(t == 0, wb, wa);
+    }
+    {
+      const Co2Ring R{zl + ((s + 2) & 3) * NP, {zl + ((s + 3) & 3) * NP, zl + (s & 3) * NP, zs1},
+                      wl + (s & 1) * NP, tl, z0, z1, z2, {zam, zap}, {wo0, wo1, wn1}, j, Ny};
+      const c64 out = co2_point2(op, sq, R, Co2Point{s, ia, x, y, 0});
+      if (live) yv[s * ss + j] = out;
+    }
+    z0 = z1;
+    z1 = z2;
+    z2 = q1;
+    q1 = q2;
+    q2 = q3;
+    zam = zam2;
+    zap = zap2;
+    tq = tq2;
+    wo0 = wo1;
+    wo1 = wn1;
+  }
+}
+
+// Whether the march takes a model: planes up to kMarchMaxPlane points and
+// its rings within 96 KiB of LDS.
+bool co2_march_fits(int Ns, int Nx, int Ny, int Na) {
+  return Nx * Ny <= kMarchMaxPlane && co2_march_lds(Ns, Nx, Ny, Na) <= 96 * 1024;
+}
+
+// Groups of the march: eight per (n_a, group of eight vectors).
+hipError_t launch_co2_march(const Co2OpsArgs& a, int Ns, int Nx, int Ny, int Na, hipStream_t s) {
+  if (a.n_vec == 0) return hipSuccess;
+  const size_t groups = (size_t)8 * Na * ((a.n_vec + 7) / 8);
+  if (!co2_march_fits(Ns, Nx, Ny, Na) || groups > 0x7fffffff) return hipErrorInvalidValue;
+  const int threads = (Nx * Ny + 63) / 64 * 64;
+  // planes up to 640 points (10 wavefronts, at most 3 per SIMD) may use 168
+  // VGPRs, wider ones 128
+  if (threads <= 640)
+    hipLaunchKernelGGL(co2_march_kernel<640>, dim3((unsigned)groups), dim3(threads),
+                       co2_march_lds(Ns, Nx, Ny, Na), s, a.model, a.tab, a.sectors, a.n_vec, a.E,
+                       a.x, a.y);
+  else
+    hipLaunchKernelGGL(co2_march_kernel<kMarchMaxPlane>, dim3((unsigned)groups), dim3(threads),
+                       co2_march_lds(Ns, Nx, Ny, Na), s, a.model, a.tab, a.sectors, a.n_vec, a.E,
+                       a.x, a.y);
+  return hipGetLastError();
+}
+
 // npts: points per vector (host copy of the model's), batch: vectors whose w
 // planes fit the scratch.
 hipError_t launch_co2_apply_split(const Co2OpsArgs& a, int npts, int batch, hipStream_t s) {

@@ -35,10 +35,10 @@ def build(outdir, jobs=8):
     for f in os.listdir(CSRC):
         if f.endswith((".h", ".hip")):
             shutil.copy(os.path.join(CSRC, f), src)
-    gb = os.path.join(src, "gmres_block.h")
+    gb = os.path.join(src, "internal.h")
     text, n = _DYN_LDS.subn("#define vdc_tile_lds emu_dyn_lds", open(gb).read())
     if n != 1:
-        raise RuntimeError("the dynamic LDS declaration was not found in gmres_block.h")
+        raise RuntimeError("the dynamic LDS declaration was not found in internal.h")
     open(gb, "w").write(text)
     inc = ["-I", os.path.join(EMU, "include"), "-I", os.path.join(ROOT, "include"), "-I", src]
     units = [os.path.join(src, f) for f in sorted(os.listdir(src)) if f.endswith(".hip")]

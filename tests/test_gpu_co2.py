@@ -81,8 +81,12 @@ def _bound_tables(p, eps):
     return out
 
 
+# the march along n_s (planes up to 1024 points): n_a +- 2 neighbours on
+# one side or both, rings wrapping, planes of one or several wavefronts; a
+# single plane; and a plane past the march's limit (the split passes)
 @pytest.mark.parametrize("sizes,eps", [(dict(s=5, x=6, y=7, a=4), 1.7), (dict(s=3, x=9, y=4, a=3), 3.1),
-                                       (dict(s=1, x=2, y=3, a=1), 0.6)])
+                                       (dict(s=1, x=2, y=3, a=1), 0.6), (dict(s=7, x=9, y=11, a=6), 2.2),
+                                       (dict(s=2, x=35, y=30, a=1), 1.1)])
 def test_operator_matches_assembled_matrix(vdc, sizes, eps):
     E = poly.total_energy(P, eps, (0, 0, 0, 0))
     M = poly.PolyModel(P, sizes, E)
