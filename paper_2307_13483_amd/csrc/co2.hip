@@ -874,7 +874,7 @@ __global__ void __launch_bounds__(kThreads)
   c64 z0 = zat(0), z1 = zat(1), z2 = zat(2);
   c64 q1 = zat(3), q2 = zat(4);
   c64 zam = zna(alo, 0, -2), zap = zna(ahi, 0, 2);
-  c64 wo0 = zero, wo1 = zero;
+  c64 wo0 = zero, wo1 = zero, yprev = zero;
   for (int i = tid; i < ntp; i += blockDim.x) tl[i] = trow(0, i);
   c64 tq = trow_ahead(1);
   // plane 0 and its w
@@ -901,6 +901,10 @@ __global__ void __launch_bounds__(kThreads)
     const c64 tq2 = trow_ahead(s + 2);
     const c64 zam2 = zna(alo, s + 1, -2), zap2 = zna(ahi, s + 1, 2);
     const c64 q3 = zat(s + 5);
+    // y of the previous step, stored after this step's loads: a store counts
+    // with the loads, in order, so waiting for the loads then leaves it
+    // outstanding
+    if (live && s > 0) yv[(s - 1) * ss + j] = yprev;
     __syncthreads();
     c64 wn1 = zero;
     if (s + 1 < Ns) {
@@ -914,8 +918,7 @@ __global__ void __launch_bounds__(kThreads)
     {
       const Co2Ring R{zl + ((s + 2) & 3) * NP, {zl + ((s + 3) & 3) * NP, zl + (s & 3) * NP, zs1},
                       wl + (s & 1) * NP, tl, z0, z1, z2, {zam, zap}, {wo0, wo1, wn1}, j, Ny};
-      const c64 out = co2_point2(op, sq, R, Co2Point{s, ia, x, y, 0});
-      if (live) yv[s * ss + j] = out;
+      yprev = co2_point2(op, sq, R, Co2Point{s, ia, x, y, 0});
     }
     z0 = z1;
     z1 = z2;
@@ -928,6 +931,7 @@ __global__ void __launch_bounds__(kThreads)
     wo0 = wo1;
     wo1 = wn1;
   }
+  if (live) yv[(Ns - 1) * ss + j] = yprev;
 }
 
 // Whether the march takes a model: planes up to kMarchMaxPlane points and
