@@ -767,6 +767,9 @@ __global__ void __launch_bounds__(kCo2Threads) co2_y_kernel(Co2OpsArgs a, int v0
 // per-point arithmetic as the solver's operator and the split passes.
 constexpr int kMarchMaxPlane = 1024;
 
+// The launch's dynamic LDS (the same array the solver kernels tile into).
+extern __shared__ __align__(16) char vdc_tile_lds[];
+
 // Neighbour accessor of the march for a centre at plane s (see co2_point1,
 // co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
 // of the neighbour components of w at s and the point's level-shift values;

@@ -61,6 +61,9 @@ __device__ inline void fp64_prepare(const OpJob<double>& op, const double* sq, c
   }
 }
 
+// Dynamic LDS of the solver kernels: the tiles of matvec_tiled.
+extern __shared__ __align__(16) char vdc_tile_lds[];
+
 // Solves A x = b with b in s.b (complete and visible: call after a barrier).
 // Byte model (passes over a block vector of Nc complex FP64 values): setup 8
 // (two table planes read for the diagonal; dinv, x, b written; b read for its

@@ -35,10 +35,6 @@ constexpr int kSup = 8;
 constexpr int kClusP = 30;
 constexpr int kClusStride = 2 + 2 * kNumF * (kClusP + 1);
 
-// Dynamic LDS of the kernels that size it at launch: the solvers' tiles of
-// matvec_tiled, the plane rings of the CO2-like marching operator.
-extern __shared__ __align__(16) char vdc_tile_lds[];
-
 // Resident workgroups of kBlock threads per CU for a solver kernel with
 // dyn_lds bytes of dynamic LDS (1 when the runtime cannot tell).
 template <typename Kernel>

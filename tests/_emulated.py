@@ -35,11 +35,15 @@ def build(outdir, jobs=8):
     for f in os.listdir(CSRC):
         if f.endswith((".h", ".hip")):
             shutil.copy(os.path.join(CSRC, f), src)
-    gb = os.path.join(src, "internal.h")
-    text, n = _DYN_LDS.subn("#define vdc_tile_lds emu_dyn_lds", open(gb).read())
-    if n != 1:
-        raise RuntimeError("the dynamic LDS declaration was not found in internal.h")
-    open(gb, "w").write(text)
+    found = 0
+    for f in os.listdir(src):
+        path = os.path.join(src, f)
+        text, n = _DYN_LDS.subn("#define vdc_tile_lds emu_dyn_lds", open(path).read())
+        if n:
+            open(path, "w").write(text)
+            found += n
+    if found == 0:
+        raise RuntimeError("no dynamic LDS declaration found in the sources")
     inc = ["-I", os.path.join(EMU, "include"), "-I", os.path.join(ROOT, "include"), "-I", src]
     units = [os.path.join(src, f) for f in sorted(os.listdir(src)) if f.endswith(".hip")]
     units += [os.path.join(EMU, "emu_fiber.cpp"), os.path.join(EMU, "driver.cpp")]
