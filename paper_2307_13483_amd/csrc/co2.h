@@ -131,8 +131,9 @@ __device__ inline c64 co2_tab(const Co2Op& o, int s, int x, int y, int a, int t,
 // n_y) when ok, else at the point itself; w(ok, ds, dx, dy) the level-shift
 // product of the point's own channel class (w_A at a sigma point, w_B at a Pi
 // point) at the offset point, else at the point itself; tab(o, p, t, k) the
-// level-shift value co2_tab at the point.  Co2Flat reads a whole vector and
-// its w planes from memory.
+// level-shift value co2_tab at the point; pick(first, a, b) and cls(c2, c)
+// one of two model coefficients by the point's class.  Co2Flat reads a whole
+// vector and its w planes from memory.
 struct Co2Flat {
   const c64* v;
   double vs;
@@ -147,6 +148,8 @@ struct Co2Flat {
   __device__ c64 tab(const Co2Op& o, const Co2Point& p, int t, int k) const {
     return co2_tab(o, p.s, p.x, p.y, p.a, t, k);
   }
+  __device__ double pick(bool first, double a, double b) const { return first ? a : b; }
+  __device__ double cls(const double* c2, int c) const { return c2[c]; }
 };
 
 // Phase 1 at point p: the pointwise level-shift products (w_A, w_B) of the
@@ -182,7 +185,7 @@ __device__ inline c64 co2_point2(const Co2Op& o, const double* sq, const Acc& Z,
   const int s = p.s, a = p.a, x = p.x, y = p.y;
   const c64 z0 = Z.z(true, 0, 0, 0, 0);
   const int c = t == 0 ? 0 : 1;
-  const double rt = t == 0 ? 0.0 : co2_pick(t == 1, m.c_rt, -m.c_rt);
+  const double rt = t == 0 ? 0.0 : Z.pick(t == 1, m.c_rt, -m.c_rt);
   // diagonal-state polynomial: E_d + k q_s + g_s q_s^2 + (g_b + rt) q_x^2 + (g_b - rt) q_y^2 + g_a q_a^2
   const bool s_lo = s > 0, s_hi = s + 1 < m.Ns;
   const double ws_lo = sq[s_lo ? s : 0], ws_hi = sq[s_hi ? s + 1 : 0];
@@ -193,9 +196,8 @@ __device__ inline c64 co2_point2(const Co2Op& o, const double* sq, const Acc& Z,
     return q2_diag(n, N) * z0 + (sq[lo ? n - 1 : 0] * sq[lo ? n : 0]) * Z.z(lo, -2 * us, -2 * ua, -2 * ux, -2 * uy) +
            (sq[hi ? n + 1 : 0] * sq[hi ? n + 2 : 0]) * Z.z(hi, 2 * us, 2 * ua, 2 * ux, 2 * uy);
   };
-  const double gs = co2_pick(c == 0, m.gs[0], m.gs[1]), gb = co2_pick(c == 0, m.gb[0], m.gb[1]);
-  const double ga = co2_pick(c == 0, m.ga[0], m.ga[1]);
-  c64 U = co2_pick(c == 0, m.E_sigma, m.E_pi) * z0 + co2_pick(c == 0, m.k_sigma, m.k_pi) * qs1 +
+  const double gs = Z.cls(m.gs, c), gb = Z.cls(m.gb, c), ga = Z.cls(m.ga, c);
+  c64 U = Z.pick(c == 0, m.E_sigma, m.E_pi) * z0 + Z.pick(c == 0, m.k_sigma, m.k_pi) * qs1 +
           gs * q2(s, m.Ns, 1, 0, 0, 0) + (gb + rt) * q2(x, m.Nx, 0, 0, 1, 0) +
           (gb - rt) * q2(y, m.Ny, 0, 0, 0, 1) + ga * q2(a, m.Na, 0, 1, 0, 0);
   // sigma - Pi couplings c (1 + c' q_s) q_x and c (1 + c' q_s) q_y, at the
@@ -219,10 +221,9 @@ __device__ inline c64 co2_point2(const Co2Op& o, const double* sq, const Acc& Z,
   const c64 sl = ws_lo * Z.w(s_lo, -1, 0, 0) + ws_hi * Z.w(s_hi, 1, 0, 0);
   const c64 rx = wx_lo * Z.w(x_lo, 0, -1, 0) + wx_hi * Z.w(x_hi, 0, 1, 0);
   const c64 ry = wy_lo * Z.w(y_lo, 0, 0, -1) + wy_hi * Z.w(y_hi, 0, 0, 1);
-  c64 Fz = Z.w(true, 0, 0, 0) + co2_pick(t == 0, m.l_sigma, m.l_pi) * sl;
-  const double h = co2_pick(t == 0, m.h_sigma, m.h_pi);
-  if (t == 0 || t == 1) Fz = Fz + h * rx;
-  if (t == 0 || t == 2) Fz = Fz + h * ry;
+  c64 Fz = Z.w(true, 0, 0, 0) + Z.pick(t == 0, m.l_sigma, m.l_pi) * sl;
+  if (t == 0 || t == 1) Fz = Fz + Z.pick(t == 0, m.h_sigma, m.h_pi) * rx;
+  if (t == 0 || t == 2) Fz = Fz + Z.pick(t == 0, m.h_sigma, m.h_pi) * ry;
   const double Ev = m.omega_s * (s + 0.5) + m.omega_b * (x + y + 1.0) + m.omega_a * (a + 0.5);
   const c64 out = (o.E - Ev) * z0 - U - Fz;
   return t == 3 ? c64{0.0, 0.0} : out;

@@ -774,9 +774,26 @@ extern __shared__ __align__(16) char vdc_tile_lds[];
 // co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
 // of the neighbour components of w at s and the point's level-shift values;
 // in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
-// class's w at s - 1 .. s + 1.  A neighbour that is not in the basis reads
+// class's w at s - 1 .. s + 1; model coefficients picked as uniform values
+// (co2_pick: the march's loop would reload a per-lane choice after every
+// store of y).  A neighbour that is not in the basis reads
 // the centre, as in Co2Flat; the LDS is read at the own point then and the
 // value discarded.
+// A complex value in the march's LDS rings, read and written as one 16-byte
+// access (c64 itself is 8-byte aligned, so the compiler would split each
+// access into two of 8 bytes at a 16-byte lane stride: two-way bank
+// conflicts).  Every access to the rings goes through these.
+struct alignas(16) c64v {
+  double x, y;
+};
+
+__device__ inline c64 ld16(const c64* p) {
+  const c64v v = *reinterpret_cast<const c64v*>(p);
+  return c64{v.x, v.y};
+}
+
+__device__ inline void st16(c64* p, c64 v) { *reinterpret_cast<c64v*>(p) = c64v{v.x, v.y}; }
+
 struct Co2Ring {
   const c64* zm2;
   const c64* zp[3];
@@ -790,15 +807,17 @@ struct Co2Ring {
       if (ds == 0) return z0;
       if (ds == 1) return co2_sel(ok, z1, z0);
       if (ds == 2) return co2_sel(ok, z2, z0);
-      return co2_sel(ok, ds == -1 ? zp[0][j] : zm2[j], z0);
+      return co2_sel(ok, ld16((ds == -1 ? zp[0] : zm2) + j), z0);
     }
-    return co2_sel(ok, zp[1 + ds][ok ? j + dx * sx + dy : j], z0);
+    return co2_sel(ok, ld16(zp[1 + ds] + (ok ? j + dx * sx + dy : j)), z0);
   }
   __device__ c64 w(bool ok, int ds, int dx, int dy) const {
     if (dx == 0 && dy == 0) return co2_sel(ok, wc[1 + ds], wc[1]);
-    return co2_sel(ok, wn[ok ? j + dx * sx + dy : j], wc[1]);
+    return co2_sel(ok, ld16(wn + (ok ? j + dx * sx + dy : j)), wc[1]);
   }
-  __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return T[k]; }
+  __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return ld16(T + k); }
+  __device__ double pick(bool first, double a, double b) const { return co2_pick(first, a, b); }
+  __device__ double cls(const double* c2, int c) const { return co2_pick(c == 0, c2[0], c2[1]); }
 };
 
 // Doubles of sqrt(n/2) at the head of the march's dynamic LDS (even, so the
@@ -878,10 +897,10 @@ __global__ void __launch_bounds__(kThreads)
   c64 q1 = zat(3), q2 = zat(4);
   c64 zam = zna(alo, 0, -2), zap = zna(ahi, 0, 2);
   c64 wo0 = zero, wo1 = zero, yprev = zero;
-  for (int i = tid; i < ntp; i += blockDim.x) tl[i] = trow(0, i);
+  for (int i = tid; i < ntp; i += blockDim.x) st16(tl + i, trow(0, i));
   c64 tq = trow_ahead(1);
   // plane 0 and its w
-  if (live) zl[j] = z0;
+  if (live) st16(zl + j, z0);
   __syncthreads();
   {
     const Co2Ring R{zl, {zl, zl, zl}, wl, tl + trow_off, z0, z1, zero, {zero, zero}, {zero, zero, zero},
@@ -889,7 +908,7 @@ __global__ void __launch_bounds__(kThreads)
     c64 wa, wb;
     co2_point1(op, sq, R, Co2Point{0, ia, x, y, 0}, wa, wb);
     wo1 = co2_sel(t == 0, wa, wb);
-    if (live) wl[j] = co2_sel(t == 0, wb, wa);
+    if (live) st16(wl + j, co2_sel(t == 0, wb, wa));
   }
 #pragma unroll 1
   for (int s = 0; s < Ns; ++s) {
@@ -897,9 +916,9 @@ __global__ void __launch_bounds__(kThreads)
     c64* w1 = wl + ((s + 1) & 1) * NP;
     c64* t1 = tl + ((s + 1) & 1) * ntp;
     if (s + 1 < Ns) {
-      if (live) zs1[j] = z1;
-      if (tid < ntp) t1[tid] = tq;
-      for (int i = tid + blockDim.x; i < ntp; i += blockDim.x) t1[i] = trow(s + 1, i);
+      if (live) st16(zs1 + j, z1);
+      if (tid < ntp) st16(t1 + tid, tq);
+      for (int i = tid + blockDim.x; i < ntp; i += blockDim.x) st16(t1 + i, trow(s + 1, i));
     }
     const c64 tq2 = trow_ahead(s + 2);
     const c64 zam2 = zna(alo, s + 1, -2), zap2 = zna(ahi, s + 1, 2);
@@ -916,7 +935,7 @@ __global__ void __launch_bounds__(kThreads)
       c64 wa, wb;
       co2_point1(op, sq, R, Co2Point{s + 1, ia, x, y, 0}, wa, wb);
       wn1 = co2_sel(t == 0, wa, wb);
-      if (live) w1[j] = co2_sel(t == 0, wb, wa);
+      if (live) st16(w1 + j, co2_sel(t == 0, wb, wa));
     }
     {
       const Co2Ring R{zl + ((s + 2) & 3) * NP, {zl + ((s + 3) & 3) * NP, zl + (s & 3) * NP, zs1},
