@@ -21,6 +21,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
+import _oracle_pool as op
 from oracle import levelshift as ls
 from oracle import poly
 from oracle import precond as pc
@@ -118,6 +119,63 @@ def test_operator_matches_assembled_matrix(vdc, sizes, eps):
                                       for d2 in range(3)) for d1 in range(3)])
         bound = 1e-14 * (abs(A) @ ax) + np.abs(Fb_rows) + 1e-15
         assert np.all(np.abs(got - ref) <= bound), (px, py)
+
+
+def _operator_bound(A, Mb, n, full):
+    """1e-14 |A| |x| for the arithmetic plus the level-shift tables' rounding
+    bounds propagated through the sandwich, row block by row block."""
+    ax = np.abs(full)
+    Fb_rows = np.concatenate([sum(abs(Mb.F_block(d1, d2)) @ ax[d2 * n:(d2 + 1) * n]
+                                  for d2 in range(3)) for d1 in range(3)])
+    return 1e-14 * (abs(A) @ ax) + np.abs(Fb_rows) + 1e-15
+
+
+@pytest.mark.timeout(900)
+def test_operator_full_size_bench_launch(vdc):
+    """The operator entry point at the CO2-like workload's full size
+    (24 x 24 x 24 x 8) in the launch the bench times: 512 sector vectors,
+    sectors alternating, total energy 2.0 eV.  Eight of them, two per sector
+    and from both ends of the batch, are compared point by point with the
+    oracle's assembled matrix within the bound of the small-size test."""
+    import torch
+    cfg = inputs.co2like_jobs()
+    Pw, sizes = cfg["params"], cfg["sizes"]
+    E = 2.0
+    model = vdc.Co2Model(Pw, sizes)
+    n = model.npts
+    nv = 512
+    sectors = [(k % 2, (k // 2) % 2) for k in range(nv)]
+    rng = np.random.default_rng(11)
+    x = torch.empty((nv, n), dtype=torch.complex128)
+    idx_of = {sec: _sector_index_fast(sizes, *sec) for sec in set(sectors)}
+    for k in range(nv):
+        z = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        z[idx_of[sectors[k]] < 0] = 0
+        x[k] = torch.from_numpy(z)
+    y = vdc.co2_apply(model, E, x.cuda(), sectors, which=0).cpu().numpy()
+    xs = x.numpy()
+    A = poly.PolyModel(Pw, sizes, E, tables=op.unique_pair_tables).matrix().tocsr()
+    Mb = poly.PolyModel(Pw, sizes, E, tables=_bound_tables)
+    for k in (0, 1, 2, 3, 256, 257, 510, 511):
+        idx = idx_of[sectors[k]]
+        full = np.zeros(3 * n, dtype=complex)
+        full[idx[idx >= 0]] = xs[k][idx >= 0]
+        ref = A @ full
+        got = np.zeros_like(ref)
+        got[idx[idx >= 0]] = y[k][idx >= 0]
+        assert np.all(y[k][idx < 0] == 0), k
+        assert np.all(np.abs(got - ref) <= _operator_bound(A, Mb, n, full)), k
+
+
+def _sector_index_fast(sizes, px, py):
+    """_sector_index without the Python loops (the same order and values)."""
+    Ns, Nx, Ny, Na = (sizes[k] for k in ("s", "x", "y", "a"))
+    n = Ns * Nx * Ny * Na
+    s, a, x, y = np.meshgrid(np.arange(Ns), np.arange(Na), np.arange(Nx), np.arange(Ny),
+                             indexing="ij")
+    t = ((x + px) & 1) | (((y + py) & 1) << 1)
+    full = t * n + ((s * Nx + x) * Ny + y) * Na + a
+    return np.where(t != 3, full, -1).ravel()
 
 
 @pytest.mark.parametrize("sizes,eps", [(dict(s=3, x=6, y=6, a=2), 2.0), (dict(s=2, x=7, y=5, a=3), 0.9),
