@@ -759,8 +759,8 @@ __global__ void __launch_bounds__(kCo2Threads) co2_y_kernel(Co2OpsArgs a, int v0
 // the other class (w_B at sigma points, w_A at Pi points).  Every x value is
 // read from memory three times (own column, and as the n_a +- 2 neighbour of
 // two workgroups of the same vector), y written once, and no w leaves the
-// chip.  Loads run ahead: the own column three planes, the level-shift rows
-// one plane, z at n_a -+ 2 from the top of the step that uses it.
+// chip.  The loads a step needs (z of the own column at s + 2, z at n_a -+ 2,
+// the level-shift rows of s + 1) are issued at the top of the step before.
 // Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod
 // 8); the workgroups of one vector are numbered so that they share an XCD and
 // follow each other there, and their n_a +- 2 reads meet one L2.  The same
@@ -889,12 +889,12 @@ __global__ void __launch_bounds__(kThreads)
     if (tid < ntp && s < Ns) r = trow(s, tid);
     return r;
   };
-  // z(s), z(s + 1), z(s + 2) of the own column and z(s + 3), z(s + 4) in
-  // flight; z(s, n_a -+ 2); the own class's w(s - 1), w(s); the rows of plane
-  // s + 1 in flight.  The loads of a step are issued at its top and waited
-  // for at its end, where the registers move down.
+  // z(s), z(s + 1), z(s + 2) of the own column; z(s, n_a -+ 2); the own
+  // class's w(s - 1), w(s); the rows of plane s + 1 in flight.  The loads of a
+  // step are issued at its top and waited for at its end, where the registers
+  // move down (the wait there is for every load in flight, on this target's
+  // one in-order counter, so loading further ahead would only hold registers).
   c64 z0 = zat(0), z1 = zat(1), z2 = zat(2);
-  c64 q1 = zat(3), q2 = zat(4);
   c64 zam = zna(alo, 0, -2), zap = zna(ahi, 0, 2);
   c64 wo0 = zero, wo1 = zero, yprev = zero;
   for (int i = tid; i < ntp; i += blockDim.x) st16(tl + i, trow(0, i));
@@ -922,7 +922,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     const c64 tq2 = trow_ahead(s + 2);
     const c64 zam2 = zna(alo, s + 1, -2), zap2 = zna(ahi, s + 1, 2);
-    const c64 q3 = zat(s + 5);
+    const c64 z3 = zat(s + 3);
     // y of the previous step, stored after this step's loads: a store counts
     // with the loads, in order, so waiting for the loads then leaves it
     // outstanding
@@ -944,9 +944,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     z0 = z1;
     z1 = z2;
-    z2 = q1;
-    q1 = q2;
-    q2 = q3;
+    z2 = z3;
     zam = zam2;
     zap = zap2;
     tq = tq2;
