@@ -892,8 +892,8 @@ __global__ void __launch_bounds__(kThreads)
   // z(s), z(s + 1), z(s + 2) of the own column; z(s, n_a -+ 2); the own
   // class's w(s - 1), w(s); the rows of plane s + 1 in flight.  The loads of a
   // step are issued at its top and waited for at its end, where the registers
-  // move down (the wait there is for every load in flight, on this target's
-  // one in-order counter, so loading further ahead would only hold registers).
+  // move down; moving the freshest load waits for everything in flight, so in
+  // this rolled loop loading further ahead would only hold registers.
   c64 z0 = zat(0), z1 = zat(1), z2 = zat(2);
   c64 zam = zna(alo, 0, -2), zap = zna(ahi, 0, 2);
   c64 wo0 = zero, wo1 = zero, yprev = zero;
@@ -923,9 +923,10 @@ __global__ void __launch_bounds__(kThreads)
     const c64 tq2 = trow_ahead(s + 2);
     const c64 zam2 = zna(alo, s + 1, -2), zap2 = zna(ahi, s + 1, 2);
     const c64 z3 = zat(s + 3);
-    // y of the previous step, stored after this step's loads: a store counts
-    // with the loads, in order, so waiting for the loads then leaves it
-    // outstanding
+    // y of the previous step, stored at the top of this step: the wait at a
+    // step's end covers every memory operation in flight (stores count with
+    // the loads on this target), so a store issued just before it would be
+    // waited for at once
     if (live && s > 0) yv[(s - 1) * ss + j] = yprev;
     __syncthreads();
     c64 wn1 = zero;
