@@ -770,15 +770,6 @@ constexpr int kMarchMaxPlane = 1024;
 // The launch's dynamic LDS (the same array the solver kernels tile into).
 extern __shared__ __align__(16) char vdc_tile_lds[];
 
-// Neighbour accessor of the march for a centre at plane s (see co2_point1,
-// co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
-// of the neighbour components of w at s and the point's level-shift values;
-// in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
-// class's w at s - 1 .. s + 1; model coefficients picked as uniform values
-// (co2_pick: the march's loop would reload a per-lane choice after every
-// store of y).  A neighbour that is not in the basis reads
-// the centre, as in Co2Flat; the LDS is read at the own point then and the
-// value discarded.
 // A complex value in the march's LDS rings, read and written as one 16-byte
 // access (c64 itself is 8-byte aligned, so the compiler would split each
 // access into two of 8 bytes at a 16-byte lane stride: two-way bank
@@ -794,6 +785,14 @@ __device__ inline c64 ld16(const c64* p) {
 
 __device__ inline void st16(c64* p, c64 v) { *reinterpret_cast<c64v*>(p) = c64v{v.x, v.y}; }
 
+// Neighbour accessor of the march for a centre at plane s (see co2_point1,
+// co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
+// of the neighbour components of w at s and the point's level-shift values;
+// in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
+// class's w at s - 1 .. s + 1; model coefficients picked as uniform values
+// (co2_pick: the march's loop would reload a per-lane choice after every
+// store of y).  A neighbour that is not in the basis reads the centre, as in
+// Co2Flat; the LDS is read at the own point then and the value discarded.
 struct Co2Ring {
   const c64* zm2;
   const c64* zp[3];
