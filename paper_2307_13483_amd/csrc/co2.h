@@ -258,8 +258,7 @@ __device__ inline double co2_apply(const Co2Op& o, const double* sq, const c64* 
 // One job's block factor storage in bytes, for planes of n points and W1 =
 // 2 Ny + 1: L by columns (F) and by rows (G), complex FP16 [planes][n][W1];
 // 1/D, complex FP32 [planes][n]; the band staging of the factor kernel,
-// complex FP32 [planes][n][7]; 256 bytes of padding (the apply reads whole
-// 64-lane rows).
+// complex FP32 [planes][n][7]; 256 bytes of padding.
 struct Co2FacLayout {
   size_t F, G, Dinv, S, total;
 };

@@ -293,8 +293,8 @@ constexpr int kApplyQ = 15;
 // lanes 64 - kApplyQ .. 63 and are stored, and the starting lanes are
 // refilled (a value above them needs more than kApplyQ steps to reach the
 // band).  Factor rows are loaded kApplyQ steps ahead by all 64 lanes (the
-// lanes past the band read the next row and are masked; the job's storage
-// is padded for the last row).  Steps past the plane's end only touch
+// lanes outside the band read the row's entry 0, which the factor stores as
+// zero).  Steps past the plane's end only touch
 // values that are never stored.  Begins and ends with a barrier.
 __device__ __attribute__((always_inline)) inline void co2_block_apply(
     const Co2Model& m, const unsigned char* fac, const c64* v, double vs, c64* z) {
@@ -302,15 +302,19 @@ __device__ __attribute__((always_inline)) inline void co2_block_apply(
   constexpr int Q = kApplyQ;
   const int n = m.Nx * m.Ny, w = 2 * m.Ny, W1 = w + 1, planes = m.Ns * m.Na;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool band = lane >= 1 && lane <= w;
   const bool feed = lane > w && lane <= w + Q;   // refilled per chunk
   const int outq = lane - (64 - Q);              // the chunk step this lane holds at its end
+  // the lanes outside the band (lane 0 and lanes past w) read entry 0 of a
+  // factor row, which is zero, so their running values stay as they are
+  // without a per-step mask; the row is addressed as a uniform base plus the
+  // lane's byte offset
+  const unsigned loff = (unsigned)(lane >= 1 && lane <= w ? lane : 0) * (unsigned)sizeof(c16);
   const Co2FacLayout lay = co2_fac_layout(planes, n, W1);
   auto step = [&](c64& acc, c16& Lq, const c16* next_row) {
     const c64 x = rlane(acc, 0);
     const c16 Lh = Lq;
-    Lq = next_row[lane];
-    const double lx = band ? (double)(float)Lh.x : 0.0, ly = band ? (double)(float)Lh.y : 0.0;
+    Lq = *reinterpret_cast<const c16*>(reinterpret_cast<const char*>(next_row) + loff);
+    const double lx = (double)(float)Lh.x, ly = (double)(float)Lh.y;
     acc.x = fma(-lx, x.x, acc.x);
     acc.x = fma(ly, x.y, acc.x);
     acc.y = fma(-lx, x.y, acc.y);
@@ -326,7 +330,8 @@ __device__ __attribute__((always_inline)) inline void co2_block_apply(
     // forward: lane k starts with row k
     c16 Lr[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) Lr[q] = F[(size_t)min(q, n - 1) * W1 + lane];
+    for (int q = 0; q < Q; ++q)
+      Lr[q] = *reinterpret_cast<const c16*>(reinterpret_cast<const char*>(F + (size_t)min(q, n - 1) * W1) + loff);
     c64 acc = lane < n && lane <= w + Q ? vs * vp[lane] : c64{0.0, 0.0};
     for (int j0 = 0; j0 < n; j0 += Q) {
       const int e = j0 + Q + lane;   // starting values of the next chunk
@@ -339,7 +344,8 @@ __device__ __attribute__((always_inline)) inline void co2_block_apply(
     __threadfence_block();   // y, written above by several lanes, is read back below
     // backward: lane k starts with row n - 1 - k, D^{-1} y
 #pragma unroll
-    for (int q = 0; q < Q; ++q) Lr[q] = G[(size_t)max(n - 1 - q, 0) * W1 + lane];
+    for (int q = 0; q < Q; ++q)
+      Lr[q] = *reinterpret_cast<const c16*>(reinterpret_cast<const char*>(G + (size_t)max(n - 1 - q, 0) * W1) + loff);
     auto start = [&](int i) { return i >= 0 ? to64(Dinv[i]) * zp[i] : c64{0.0, 0.0}; };
     acc = lane <= w + Q ? start(n - 1 - lane) : c64{0.0, 0.0};
     for (int j1 = n - 1; j1 >= 0; j1 -= Q) {
