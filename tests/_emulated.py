@@ -165,3 +165,21 @@ def write_terms_case(path, desc, jobs, finals, opts):
                 row[q] = int(vq)
             f.write(struct.pack("<%di" % vdc.MAX_MODES, *row))
         f.write(bytes(opts.c()))
+
+
+def write_co2_solve_case(path, jobs, finals, opts):
+    """jobs: (eps_i, (n_s, n_x, n_y, n_a), mu_i); finals: 4-tuples."""
+    from paper_2307_13483_amd import vdc
+    with open(path, "wb") as f:
+        f.write(struct.pack("<i", len(jobs)))
+        for (e, v, mu) in jobs:
+            j = vdc.Co2Job()
+            j.eps_i = float(e)
+            for q in range(4):
+                j.v[q] = int(v[q])
+            j.mu_i = int(mu)
+            f.write(bytes(j))
+        f.write(struct.pack("<i", len(finals)))
+        for fv in finals:
+            f.write(struct.pack("<4i", *[int(c) for c in fv]))
+        f.write(bytes(opts.c()))

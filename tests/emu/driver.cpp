@@ -1,7 +1,8 @@
 // Runs one case through the library built for the CPU stand-in of HIP and
 // writes its results: "solve CASE OUT" (vdc_solve: two-state models),
-// "co2 DESC X N_VEC WHICH E OUT" (vdc_co2_apply on the vectors in X) and
-// "terms CASE DISPATCH OUT" (vdc_model_create + vdc_model_solve).  Case
+// "co2 DESC X N_VEC WHICH E OUT" (vdc_co2_apply on the vectors in X),
+// "co2solve DESC CASE OUT" (vdc_co2_solve) and "terms CASE DISPATCH OUT"
+// (vdc_model_create + vdc_model_solve).  Case
 // files hold the C structs of include/vdc.h as the tests write them.
 // Prints one line per job; exits non-zero when a call fails.
 #include <cstdio>
@@ -144,6 +145,62 @@ int run_co2(const char* path, const char* xpath, int n_vec, int which, double E,
   return 0;
 }
 
+// co2solve: desc; n_jobs, jobs (vdc_co2_job), n_final, finals [4], opts.
+// Writes T (complex [n_jobs][n_final][3]), sigma [n_jobs][n_final] and psi
+// (complex [n_jobs][npts]).
+int run_co2_solve(const char* dpath, const char* cpath, const char* out) {
+  vdc_co2_desc d;
+  FILE* f = fopen(dpath, "rb");
+  if (!f) return 2;
+  rd(f, &d, 1);
+  fclose(f);
+  vdc_co2_t m;
+  if (vdc_co2_create(&d, &m) != VDC_OK) {
+    printf("vdc_co2_create: %s\n", vdc_last_error());
+    return 3;
+  }
+  FILE* c = fopen(cpath, "rb");
+  if (!c) return 2;
+  int nj = 0, nf = 0;
+  rd(c, &nj, 1);
+  std::vector<vdc_co2_job> jobs(nj);
+  rd(c, jobs.data(), nj);
+  rd(c, &nf, 1);
+  std::vector<int> finals(4 * nf);
+  rd(c, finals.data(), 4 * nf);
+  vdc_solve_opts o;
+  rd(c, &o, 1);
+  fclose(c);
+  const size_t npts = (size_t)d.Ns * d.Nx * d.Ny * d.Na;
+  size_t ws = 0;
+  if (vdc_co2_workspace_size(m, &o, nj, jobs.data(), &ws) != VDC_OK) {
+    printf("vdc_co2_workspace_size: %s\n", vdc_last_error());
+    return 3;
+  }
+  void* w = dev_alloc(ws);
+  double* T = (double*)dev_alloc(sizeof(double) * 2 * nj * nf * 3);
+  double* sig = (double*)dev_alloc(sizeof(double) * nj * nf);
+  double* psi = (double*)dev_alloc(sizeof(double) * 2 * nj * npts);
+  std::vector<vdc_job_info> info(nj);
+  if (vdc_co2_solve(m, &o, nj, jobs.data(), nf, finals.data(), T, sig, psi, info.data(), w, ws,
+                    nullptr) != VDC_OK) {
+    printf("vdc_co2_solve: %s\n", vdc_last_error());
+    return 3;
+  }
+  report(info);
+  FILE* g = fopen(out, "wb");
+  put(g, T, sizeof(double) * 2 * nj * nf * 3);
+  put(g, sig, sizeof(double) * nj * nf);
+  put(g, psi, sizeof(double) * 2 * nj * npts);
+  fclose(g);
+  free(w);
+  free(T);
+  free(sig);
+  free(psi);
+  vdc_co2_destroy(m);
+  return 0;
+}
+
 // terms: D M P, omega[M], nbasis[M], e_state[D], n_u, uterms, n_v, vterms,
 // width[D P], K, X, n_jobs, jobs, n_final, finals [VDC_MAX_MODES], opts
 int run_terms(const char* path, int dispatch, const char* out) {
@@ -234,6 +291,7 @@ int main(int argc, char** argv) {
   if (cmd == "co2" && argc == 8)
     return run_co2(argv[2], argv[3], atoi(argv[4]), atoi(argv[5]), atof(argv[6]), argv[7]);
   if (cmd == "terms" && argc == 5) return run_terms(argv[2], atoi(argv[3]), argv[4]);
+  if (cmd == "co2solve" && argc == 5) return run_co2_solve(argv[2], argv[3], argv[4]);
   fprintf(stderr, "usage: solve CASE OUT | co2 DESC X N_VEC WHICH E OUT | terms CASE DISPATCH OUT\n");
   return 2;
 }

@@ -113,8 +113,19 @@ void run_grid(dim3 g, dim3 b, size_t shmem, const std::function<void()>& fn);
 extern thread_local char* emu_dyn_lds;   // the launch's dynamic LDS
 
 inline void __syncthreads() { emu::syncthreads(); }
-inline void __threadfence_block() { std::atomic_thread_fence(std::memory_order_seq_cst); }
-inline void __threadfence() { std::atomic_thread_fence(std::memory_order_seq_cst); }
+// The lanes of a wavefront execute a fence together on the GPU, so a fence
+// orders one lane's stores before other lanes' later loads of the same
+// wavefront (the library relies on this after its sweeps' stores); here a
+// fence also waits for the rest of the wavefront.  The library's fences are
+// reached by every lane of the wavefront.
+inline void __threadfence_block() {
+  emu::wave_sync();
+  std::atomic_thread_fence(std::memory_order_seq_cst);
+}
+inline void __threadfence() {
+  emu::wave_sync();
+  std::atomic_thread_fence(std::memory_order_seq_cst);
+}
 
 template <typename T>
 inline T __shfl_xor(T v, int mask, int width = 64) {

@@ -11,6 +11,7 @@ import math
 import os
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import _emulated as emu
@@ -123,7 +124,7 @@ def test_co2_operator_under_emulation(exe, tmp_path, sizes):
     """The CO2-like operator entry point (the march along n_s, or the two
     grid-wide passes for wide planes) on the four reflection sectors against
     the oracle's assembled matrix, and the bend-plane block factor and apply
-    on the same vectors (in bounds and finite)."""
+    on the same vectors against the oracle's block slices."""
     P = inputs.co2like_params()
     eps = 1.4
     E = poly.total_energy(P, eps, (0, 0, 0, 0))
@@ -148,6 +149,7 @@ def test_co2_operator_under_emulation(exe, tmp_path, sizes):
         y = np.fromfile(out, dtype=np.complex128).reshape(4, n)
         assert np.all(np.isfinite(y))
         if which == 1:
+            _check_block_apply(M, A, sizes, sectors, xs, y)
             continue
         for k, (px, py) in enumerate(sectors):
             idx = _co2_sector_index(sizes, px, py)
@@ -159,6 +161,28 @@ def test_co2_operator_under_emulation(exe, tmp_path, sizes):
             assert np.all(y[k][idx < 0] == 0)
             bound = 1e-12 * (abs(A) @ np.abs(full)) + 1e-13
             assert np.all(np.abs(got - ref) <= bound), k
+
+
+def _check_block_apply(M, A, sizes, sectors, xs, y):
+    """y = M^{-1} x for the bend-plane blocks: backward error against the
+    oracle's block-diagonal part of A, within the bound of the FP16/FP32
+    factor (as in the GPU test of the block preconditioner)."""
+    key = np.zeros(3 * M.n, dtype=np.int64)
+    for b, ii in enumerate(poly.bend_blocks(sizes)):
+        key[ii] = b
+    Ac = A.tocoo()
+    keep = key[Ac.row] == key[Ac.col]
+    B = sp.csr_matrix((Ac.data[keep], (Ac.row[keep], Ac.col[keep])), shape=A.shape)
+    normB = np.max(np.abs(B).sum(axis=1))
+    tol = 8 * (2 * 2.0 ** -11 + (2 * sizes["y"] + 2) * 2.0 ** -24)
+    for k, (px, py) in enumerate(sectors):
+        idx = _co2_sector_index(sizes, px, py)
+        full = np.zeros(3 * M.n, dtype=complex)
+        full[idx[idx >= 0]] = xs[k][idx >= 0]
+        yf = np.zeros(3 * M.n, dtype=complex)
+        yf[idx[idx >= 0]] = y[k][idx >= 0]
+        assert np.all(y[k][idx < 0] == 0), k
+        assert np.max(np.abs(B @ yf - full)) <= tol * normB * np.max(np.abs(yf)), k
 
 
 def test_term_list_solve_under_emulation(exe, tmp_path):
@@ -190,3 +214,51 @@ def test_term_list_solve_under_emulation(exe, tmp_path):
         assert np.linalg.norm(psi[k] - ref) <= 1e-8 * np.linalg.norm(ref)
         Tref = np.array([[tm.phi(vf, mf) @ ref for mf in range(P)] for vf in finals])
         assert np.max(np.abs(T[k] - Tref)) <= 1e-8 * np.max(np.abs(Tref))
+
+
+@pytest.mark.parametrize("method", ["gmres", "cocg"])
+def test_co2_solve_under_emulation(exe, tmp_path, method):
+    """The CO2-like solver kernels (the bend-plane factor, then GMRES or COCG
+    with the block preconditioner's apply and the operator inside one
+    persistent launch) on a small model, three partial waves and an excited
+    initial state, against the oracle's LU: true residual <= 1e-10 +
+    rounding, solution within 1e-8, amplitudes and cross sections."""
+    from paper_2307_13483_amd import vdc
+    P = inputs.co2like_params()
+    sizes = dict(s=3, x=4, y=5, a=2)
+    jobs = [(0.8, (0, 0, 0, 0), 0), (2.0, (0, 0, 0, 0), 1), (1.4, (1, 0, 0, 0), 2)]
+    finals = [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0)]
+    opts = vdc.Opts(restart=20, precision=vdc.FP64, precond=vdc.PREC_BLOCK, max_iter=5000,
+                    method=vdc.COCG if method == "cocg" else vdc.GMRES)
+    desc, case, out = (str(tmp_path / n) for n in ("co2.bin", "case.bin", "out.bin"))
+    emu.write_co2_desc(desc, P, sizes)
+    emu.write_co2_solve_case(case, jobs, finals, opts)
+    rc, text = emu.run(exe, ["co2solve", desc, case, out])
+    assert rc == 0, text[-3000:]
+    rows = emu.job_lines(text)
+    assert len(rows) == len(jobs) and all(r[0] == 0 for r in rows), text[-2000:]
+    nj, nf = len(jobs), len(finals)
+    n = sizes["s"] * sizes["x"] * sizes["y"] * sizes["a"]
+    raw = np.fromfile(out, dtype=np.float64)
+    T = raw[:2 * nj * nf * 3].view(np.complex128).reshape(nj, nf, 3)
+    sig = raw[2 * nj * nf * 3:2 * nj * nf * 3 + nj * nf].reshape(nj, nf)
+    psi = raw[2 * nj * nf * 3 + nj * nf:].view(np.complex128).reshape(nj, n)
+    for k, (eps, v, mu) in enumerate(jobs):
+        E = poly.total_energy(P, eps, v)
+        M = poly.PolyModel(P, sizes, E)
+        A = M.matrix().tocsr()
+        b = M.phi(v, poly.WAVES[mu])
+        x_lu = solvers.lu_solve(A, b)
+        px, py = vdc.co2_sector(v, mu)
+        idx = _co2_sector_index(sizes, px, py)
+        assert np.all(psi[k][idx < 0] == 0)
+        full = np.zeros(3 * n, dtype=complex)
+        full[idx[idx >= 0]] = psi[k][idx >= 0]
+        assert np.linalg.norm(b - A @ full) / np.linalg.norm(b) <= 1e-10 + 1e-13, k
+        assert np.linalg.norm(full - x_lu) <= 1e-8 * np.linalg.norm(x_lu), k
+        for f, vf in enumerate(finals):
+            for m_, muf in enumerate(poly.WAVES):
+                Tref = M.phi(vf, muf) @ x_lu
+                assert abs(T[k, f, m_] - Tref) <= 1e-7 * max(1e-300, np.max(np.abs(x_lu))), (k, f, m_)
+        pref = 2 * math.pi ** 3 / (eps / ls.HARTREE_EV)
+        assert np.allclose(sig[k], pref * np.sum(np.abs(T[k]) ** 2, axis=1), rtol=1e-12, atol=0)
