@@ -777,12 +777,10 @@ constexpr int kMarchMaxPlane = 1024;
 extern __shared__ __align__(16) char vdc_tile_lds[];
 
 // A complex value in the march's LDS rings, read and written as one 16-byte
-// access (c64 itself is 8-byte aligned, so the compiler would split each
-// access into two of 8 bytes at a 16-byte lane stride: two-way bank
+// vector access (c64 itself is 8-byte aligned, and a pair of doubles may be
+// split into two 8-byte accesses at a 16-byte lane stride: two-way bank
 // conflicts).  Every access to the rings goes through these.
-struct alignas(16) c64v {
-  double x, y;
-};
+typedef double c64v __attribute__((ext_vector_type(2)));
 
 __device__ inline c64 ld16(const c64* p) {
   const c64v v = *reinterpret_cast<const c64v*>(p);
@@ -797,8 +795,11 @@ __device__ inline void st16(c64* p, c64 v) { *reinterpret_cast<c64v*>(p) = c64v{
 // in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
 // class's w at s - 1 .. s + 1; model coefficients picked as uniform values
 // (co2_pick: the march's loop would reload a per-lane choice after every
-// store of y).  A neighbour that is not in the basis reads the centre, as in
-// Co2Flat; the LDS is read at the own point then and the value discarded.
+// store of y).  A neighbour that is not in the basis is not selected away:
+// every such term carries a zero weight (sqrt(0/2) of the basis edge), and the
+// value read there is finite for a finite input (the own point of the plane,
+// a zero plane past either end of n_s or n_a, or a w value), so the product
+// is zero without a select.
 struct Co2Ring {
   const c64* zm2;
   const c64* zp[3];
@@ -807,18 +808,18 @@ struct Co2Ring {
   c64 z0, z1, z2, za[2], wc[3];
   int j, sx;
   __device__ c64 z(bool ok, int ds, int da, int dx, int dy) const {
-    if (da != 0) return co2_sel(ok, za[da > 0 ? 1 : 0], z0);
+    if (da != 0) return za[da > 0 ? 1 : 0];
     if (dx == 0 && dy == 0) {
       if (ds == 0) return z0;
-      if (ds == 1) return co2_sel(ok, z1, z0);
-      if (ds == 2) return co2_sel(ok, z2, z0);
-      return co2_sel(ok, ld16((ds == -1 ? zp[0] : zm2) + j), z0);
+      if (ds == 1) return z1;
+      if (ds == 2) return z2;
+      return ld16((ds == -1 ? zp[0] : zm2) + j);
     }
-    return co2_sel(ok, ld16(zp[1 + ds] + (ok ? j + dx * sx + dy : j)), z0);
+    return ld16(zp[1 + ds] + (ok ? j + dx * sx + dy : j));
   }
   __device__ c64 w(bool ok, int ds, int dx, int dy) const {
-    if (dx == 0 && dy == 0) return co2_sel(ok, wc[1 + ds], wc[1]);
-    return co2_sel(ok, ld16(wn + (ok ? j + dx * sx + dy : j)), wc[1]);
+    if (dx == 0 && dy == 0) return wc[1 + ds];
+    return ld16(wn + (ok ? j + dx * sx + dy : j));
   }
   __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return ld16(T + k); }
   __device__ double pick(bool first, double a, double b) const { return co2_pick(first, a, b); }
@@ -864,7 +865,10 @@ __global__ void __launch_bounds__(kThreads)
   const bool live = tid < NP;
   const int j = live ? tid : 0;
   const int x = j / Ny, y = j - x * Ny;
-  const Co2Op op{model, tab, E, sectors[2 * v], sectors[2 * v + 1]};
+  // the model's fields read once, before the loop (read in the loop's
+  // branches, the compiler would load them again at every step)
+  const Co2Model mloc = md;
+  const Co2Op op{&mloc, tab, E, sectors[2 * v], sectors[2 * v + 1]};
   const int t = co2_type(x, y, op.px, op.py);
   const int trow_off = (x + y) * kNumF + (t == 0 || t == 3 ? 0 : 3);   // co2_tab's row and class
   const int ss = Na * NP;                     // stride of n_s
@@ -904,8 +908,12 @@ __global__ void __launch_bounds__(kThreads)
   c64 wo0 = zero, wo1 = zero, yprev = zero;
   for (int i = tid; i < ntp; i += blockDim.x) st16(tl + i, trow(0, i));
   c64 tq = trow_ahead(1);
-  // plane 0 and its w
-  if (live) st16(zl + j, z0);
+  // plane 0 and its w; the ring's planes -2 and -1 read as zeros
+  if (live) {
+    st16(zl + j, z0);
+    st16(zl + 2 * NP + j, zero);
+    st16(zl + 3 * NP + j, zero);
+  }
   __syncthreads();
   {
     const Co2Ring R{zl, {zl, zl, zl}, wl, tl + trow_off, z0, z1, zero, {zero, zero}, {zero, zero, zero},
