@@ -839,6 +839,52 @@ __host__ __device__ inline size_t co2_march_lds(int Ns, int Nx, int Ny, int Na) 
          ((size_t)6 * Nx * Ny + (size_t)2 * kNumF * (Nx + Ny - 1)) * sizeof(c64);
 }
 
+// The bend points of a plane that carry a state (types 0, 1, 2), in plane
+// order: a row with n_x + px even holds all Ny points, the others the ne
+// points with n_y + py even; the remaining points (type 3) carry none.
+__host__ __device__ inline int co2_row_even(int Ny, int py) { return (Ny + 1 - py) / 2; }
+
+__host__ __device__ inline int co2_live_count(int Nx, int Ny, int px, int py) {
+  const int full = (Nx + 1 - px) / 2;
+  return full * Ny + (Nx - full) * co2_row_even(Ny, py);
+}
+
+// The k-th point that carries a state (k < co2_live_count): rows come in
+// pairs of Ny + ne points, the full row first when px = 0.
+__host__ __device__ inline void co2_live_point(int k, int Ny, int px, int py, int& x, int& y) {
+  const int ne = co2_row_even(Ny, py);
+  const int n0 = px == 0 ? Ny : ne;   // points of the pair's first row, n_x = 2 q
+  const int q = k / (Ny + ne), r = k - q * (Ny + ne);
+  if (r < n0) {
+    x = 2 * q;
+    y = px == 0 ? r : 2 * r + py;
+  } else {
+    x = 2 * q + 1;
+    y = px == 0 ? 2 * (r - n0) + py : r - n0;
+  }
+}
+
+// The k-th point that carries none (k < Nx Ny - co2_live_count): n_x + px and
+// n_y + py both odd.
+__host__ __device__ inline void co2_dead_point(int k, int Ny, int px, int py, int& x, int& y) {
+  const int nd = Ny - co2_row_even(Ny, py);
+  const int h = k / nd;
+  x = 2 * h + 1 - px;
+  y = 2 * (k - h * nd) + 1 - py;
+}
+
+// Threads of a march workgroup: one per point that carries a state, and at
+// least as many as the points that carry none (each stores the zeros of one),
+// over the four sectors.
+inline int co2_march_threads(int Nx, int Ny) {
+  int n = 0;
+  for (int p = 0; p < 4; ++p) {
+    const int live = co2_live_count(Nx, Ny, p & 1, p >> 1);
+    n = max(n, max(live, Nx * Ny - live));
+  }
+  return (n + 63) / 64 * 64;
+}
+
 // The model, vectors and rows come as separate kernel arguments, none aliasing
 // another, so that the model's fields are read once into scalar registers
 // and no store of y orders the loads of x.
@@ -861,14 +907,21 @@ __global__ void __launch_bounds__(kThreads)
   c64* wl = zl + 4 * NP;                                                   // [2][NP]
   c64* tl = wl + 2 * NP;                                                   // [2][ntp]
   for (int n = tid; n < nsq; n += blockDim.x) sq[n] = sqrt(0.5 * n);
-  // lanes past the plane compute point 0 and store nothing
-  const bool live = tid < NP;
-  const int j = live ? tid : 0;
-  const int x = j / Ny, y = j - x * Ny;
+  // the rings start at zero: planes -2 and -1, and the points that carry no
+  // state, which are never stored
+  for (int i = tid; i < 6 * NP; i += blockDim.x) st16(zl + i, c64{0.0, 0.0});
+  const int px = sectors[2 * v] & 1, py = sectors[2 * v + 1] & 1;
+  // one lane per point that carries a state; lanes past them compute the
+  // first such point (or point 0 if there is none) and store nothing
+  const int n_live = co2_live_count(md.Nx, Ny, px, py), n_dead = NP - n_live;
+  const bool live = tid < n_live;
+  int x = 0, y = 0;
+  if (n_live > 0) co2_live_point(live ? tid : 0, Ny, px, py, x, y);
+  const int j = x * Ny + y;
   // the model's fields read once, before the loop (read in the loop's
   // branches, the compiler would load them again at every step)
   const Co2Model mloc = md;
-  const Co2Op op{&mloc, tab, E, sectors[2 * v], sectors[2 * v + 1]};
+  const Co2Op op{&mloc, tab, E, px, py};
   const int t = co2_type(x, y, op.px, op.py);
   const int trow_off = (x + y) * kNumF + (t == 0 || t == 3 ? 0 : 3);   // co2_tab's row and class
   const int ss = Na * NP;                     // stride of n_s
@@ -908,12 +961,9 @@ __global__ void __launch_bounds__(kThreads)
   c64 wo0 = zero, wo1 = zero, yprev = zero;
   for (int i = tid; i < ntp; i += blockDim.x) st16(tl + i, trow(0, i));
   c64 tq = trow_ahead(1);
-  // plane 0 and its w; the ring's planes -2 and -1 read as zeros
-  if (live) {
-    st16(zl + j, z0);
-    st16(zl + 2 * NP + j, zero);
-    st16(zl + 3 * NP + j, zero);
-  }
+  // plane 0 and its w
+  __syncthreads();
+  if (live) st16(zl + j, z0);
   __syncthreads();
   {
     const Co2Ring R{zl, {zl, zl, zl}, wl, tl + trow_off, z0, z1, zero, {zero, zero}, {zero, zero, zero},
@@ -966,6 +1016,12 @@ __global__ void __launch_bounds__(kThreads)
     wo1 = wn1;
   }
   if (live) yv[(Ns - 1) * ss + j] = yprev;
+  // y is zero at the points that carry no state
+  if (tid < n_dead) {
+    int xd, yd;
+    co2_dead_point(tid, Ny, px, py, xd, yd);
+    for (int sd = 0; sd < Ns; ++sd) yv[sd * ss + xd * Ny + yd] = zero;
+  }
 }
 
 // Whether the march takes a model: planes up to kMarchMaxPlane points and
@@ -979,11 +1035,11 @@ hipError_t launch_co2_march(const Co2OpsArgs& a, int Ns, int Nx, int Ny, int Na,
   if (a.n_vec == 0) return hipSuccess;
   const size_t groups = (size_t)8 * Na * ((a.n_vec + 7) / 8);
   if (!co2_march_fits(Ns, Nx, Ny, Na) || groups > 0x7fffffff) return hipErrorInvalidValue;
-  const int threads = (Nx * Ny + 63) / 64 * 64;
-  // planes up to 640 points (10 wavefronts, at most 3 per SIMD) may use 168
-  // VGPRs, wider ones 128
-  if (threads <= 640)
-    hipLaunchKernelGGL(co2_march_kernel<640>, dim3((unsigned)groups), dim3(threads),
+  const int threads = co2_march_threads(Nx, Ny);
+  // up to 512 threads (8 wavefronts, at most 2 per SIMD) the kernel may use
+  // 256 VGPRs, wider ones 128
+  if (threads <= 512)
+    hipLaunchKernelGGL(co2_march_kernel<512>, dim3((unsigned)groups), dim3(threads),
                        co2_march_lds(Ns, Nx, Ny, Na), s, a.model, a.tab, a.sectors, a.n_vec, a.E,
                        a.x, a.y);
   else
