@@ -789,56 +789,6 @@ __device__ inline c64 ld16(const c64* p) {
 
 __device__ inline void st16(c64* p, c64 v) { *reinterpret_cast<c64v*>(p) = c64v{v.x, v.y}; }
 
-// Neighbour accessor of the march for a centre at plane s (see co2_point1,
-// co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
-// of the neighbour components of w at s and the point's level-shift values;
-// in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
-// class's w at s - 1 .. s + 1; model coefficients picked as uniform values
-// (co2_pick: the march's loop would reload a per-lane choice after every
-// store of y).  A neighbour that is not in the basis is not selected away:
-// every such term carries a zero weight (sqrt(0/2) of the basis edge), and the
-// value read there is finite for a finite input (the own point of the plane,
-// a zero plane past either end of n_s or n_a, or a w value), so the product
-// is zero without a select.
-struct Co2Ring {
-  const c64* zm2;
-  const c64* zp[3];
-  const c64* wn;
-  const c64* T;
-  c64 z0, z1, z2, za[2], wc[3];
-  int j, sx;
-  __device__ c64 z(bool ok, int ds, int da, int dx, int dy) const {
-    if (da != 0) return za[da > 0 ? 1 : 0];
-    if (dx == 0 && dy == 0) {
-      if (ds == 0) return z0;
-      if (ds == 1) return z1;
-      if (ds == 2) return z2;
-      return ld16((ds == -1 ? zp[0] : zm2) + j);
-    }
-    return ld16(zp[1 + ds] + (ok ? j + dx * sx + dy : j));
-  }
-  __device__ c64 w(bool ok, int ds, int dx, int dy) const {
-    if (dx == 0 && dy == 0) return wc[1 + ds];
-    return ld16(wn + (ok ? j + dx * sx + dy : j));
-  }
-  __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return ld16(T + k); }
-  __device__ double pick(bool first, double a, double b) const { return co2_pick(first, a, b); }
-  __device__ double cls(const double* c2, int c) const { return co2_pick(c == 0, c2[0], c2[1]); }
-};
-
-// Doubles of sqrt(n/2) at the head of the march's dynamic LDS (even, so the
-// planes after them stay 16-byte aligned), and the whole dynamic LDS: sqrt
-// values, z ring [4][Nx Ny], w ring [2][Nx Ny], row ring [2][6 (Nx + Ny - 1)].
-__host__ __device__ inline int co2_march_sq(int Ns, int Nx, int Ny, int Na) {
-  const int nmax = max(max(Ns, Nx), max(Ny, Na));
-  return (nmax + 4) & ~1;
-}
-
-__host__ __device__ inline size_t co2_march_lds(int Ns, int Nx, int Ny, int Na) {
-  return (size_t)co2_march_sq(Ns, Nx, Ny, Na) * sizeof(double) +
-         ((size_t)6 * Nx * Ny + (size_t)2 * kNumF * (Nx + Ny - 1)) * sizeof(c64);
-}
-
 // The bend points of a plane that carry a state (types 0, 1, 2), in plane
 // order: a row with n_x + px even holds all Ny points, the others the ne
 // points with n_y + py even; the remaining points (type 3) carry none.
@@ -885,6 +835,83 @@ inline int co2_march_threads(int Nx, int Ny) {
   return (n + 63) / 64 * 64;
 }
 
+// The march's rings hold a plane's points that carry a state in the order
+// of co2_live_point, then one zero entry.  Co2Nbr: the ring indices of a
+// point's twelve bend neighbours (n_x, n_y offsets of co2_nbr_slot), the
+// zero entry for a neighbour outside the plane or one that carries no state.
+struct Co2Nbr {
+  int i[12];
+};
+
+__host__ __device__ constexpr int co2_nbr_slot(int dx, int dy) {
+  return dy == 0   ? (dx == -1 ? 0 : dx == 1 ? 1 : dx == -2 ? 4 : 5)
+         : dx == 0 ? (dy == -1 ? 2 : dy == 1 ? 3 : dy == -2 ? 6 : 7)
+                   : 8 + (dx > 0 ? 2 : 0) + (dy > 0 ? 1 : 0);
+}
+
+// Ring index of point (x, y) (the inverse of co2_live_point), or zslot.
+__host__ __device__ inline int co2_ring_index(int x, int y, int Nx, int Ny, int px, int py,
+                                              int zslot) {
+  if (x < 0 || x >= Nx || y < 0 || y >= Ny || (((x + px) & (y + py)) & 1)) return zslot;
+  const int ne = co2_row_even(Ny, py);
+  const int base = (x >> 1) * (Ny + ne);
+  const bool full = ((x + px) & 1) == 0;
+  const int first = px == 0 ? Ny : ne;   // points of the pair's first row
+  const int r = full ? y : (y - py) >> 1;
+  return base + ((x & 1) ? first : 0) + r;
+}
+
+// Neighbour accessor of the march for a centre at plane s (see co2_point1,
+// co2_point2): LDS planes of z at s - 2 (own column only) and s - 1 .. s + 1,
+// of the neighbour components of w at s and the point's level-shift values;
+// in registers the own column's z at s .. s + 2, z at n_a -+ 2 and the own
+// class's w at s - 1 .. s + 1; model coefficients picked as uniform values
+// (co2_pick: the march's loop would reload a per-lane choice after every
+// store of y).  A neighbour that is not in the basis is not selected away:
+// every such term carries a zero weight (sqrt(0/2) of the basis edge), and the
+// value read there is finite for a finite input (the own point of the plane,
+// a zero plane past either end of n_s or n_a, or a w value), so the product
+// is zero without a select.
+struct Co2Ring {
+  const c64* zm2;
+  const c64* zp[3];
+  const c64* wn;
+  const c64* T;
+  c64 z0, z1, z2, za[2], wc[3];
+  int k;                     // the point's ring index
+  Co2Nbr nb;                 // ring indices of its bend neighbours
+  __device__ c64 z(bool, int ds, int da, int dx, int dy) const {
+    if (da != 0) return za[da > 0 ? 1 : 0];
+    if (dx == 0 && dy == 0) {
+      if (ds == 0) return z0;
+      if (ds == 1) return z1;
+      if (ds == 2) return z2;
+      return ld16((ds == -1 ? zp[0] : zm2) + k);
+    }
+    return ld16(zp[1 + ds] + nb.i[co2_nbr_slot(dx, dy)]);
+  }
+  __device__ c64 w(bool, int ds, int dx, int dy) const {
+    if (dx == 0 && dy == 0) return wc[1 + ds];
+    return ld16(wn + nb.i[co2_nbr_slot(dx, dy)]);
+  }
+  __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return ld16(T + k); }
+  __device__ double pick(bool first, double a, double b) const { return co2_pick(first, a, b); }
+  __device__ double cls(const double* c2, int c) const { return co2_pick(c == 0, c2[0], c2[1]); }
+};
+
+// Doubles of sqrt(n/2) at the head of the march's dynamic LDS (even, so the
+// planes after them stay 16-byte aligned), and the whole dynamic LDS: sqrt
+// values, z ring [4][Nx Ny], w ring [2][Nx Ny], row ring [2][6 (Nx + Ny - 1)].
+__host__ __device__ inline int co2_march_sq(int Ns, int Nx, int Ny, int Na) {
+  const int nmax = max(max(Ns, Nx), max(Ny, Na));
+  return (nmax + 4) & ~1;
+}
+
+__host__ __device__ inline size_t co2_march_lds(int Ns, int Nx, int Ny, int Na) {
+  return (size_t)co2_march_sq(Ns, Nx, Ny, Na) * sizeof(double) +
+         ((size_t)6 * (Nx * Ny + 1) + (size_t)2 * kNumF * (Nx + Ny - 1)) * sizeof(c64);
+}
+
 // The model, vectors and rows come as separate kernel arguments, none aliasing
 // another, so that the model's fields are read once into scalar registers
 // and no store of y orders the loads of x.
@@ -903,13 +930,13 @@ __global__ void __launch_bounds__(kThreads)
   const int nsq = co2_march_sq(Ns, md.Nx, Ny, Na);
   const int ntp = kNumF * md.nb;              // level-shift values of one plane's rows
   double* sq = reinterpret_cast<double*>(vdc_tile_lds);
-  c64* zl = reinterpret_cast<c64*>(vdc_tile_lds + nsq * sizeof(double));   // [4][NP]
-  c64* wl = zl + 4 * NP;                                                   // [2][NP]
-  c64* tl = wl + 2 * NP;                                                   // [2][ntp]
+  const int PS = NP + 1;                      // ring plane: the points, one zero
+  c64* zl = reinterpret_cast<c64*>(vdc_tile_lds + nsq * sizeof(double));   // [4][PS]
+  c64* wl = zl + 4 * PS;                                                   // [2][PS]
+  c64* tl = wl + 2 * PS;                                                   // [2][ntp]
   for (int n = tid; n < nsq; n += blockDim.x) sq[n] = sqrt(0.5 * n);
-  // the rings start at zero: planes -2 and -1, and the points that carry no
-  // state, which are never stored
-  for (int i = tid; i < 6 * NP; i += blockDim.x) st16(zl + i, c64{0.0, 0.0});
+  // the rings start at zero: planes -2 and -1, and the zero entries
+  for (int i = tid; i < 6 * PS; i += blockDim.x) st16(zl + i, c64{0.0, 0.0});
   const int px = sectors[2 * v] & 1, py = sectors[2 * v + 1] & 1;
   // one lane per point that carries a state; lanes past them compute the
   // first such point (or point 0 if there is none) and store nothing
@@ -917,7 +944,15 @@ __global__ void __launch_bounds__(kThreads)
   const bool live = tid < n_live;
   int x = 0, y = 0;
   if (n_live > 0) co2_live_point(live ? tid : 0, Ny, px, py, x, y);
-  const int j = x * Ny + y;
+  const int j = x * Ny + y;                   // in the vector
+  const int k = live ? tid : 0;               // in the rings
+  Co2Nbr nb;
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const int dx = i < 8 ? (i < 4 ? (i < 2 ? 2 * i - 1 : 0) : (i < 6 ? 4 * i - 18 : 0)) : (i < 10 ? -1 : 1);
+    const int dy = i < 8 ? (i < 4 ? (i < 2 ? 0 : 2 * i - 5) : (i < 6 ? 0 : 4 * i - 26)) : ((i & 1) ? 1 : -1);
+    nb.i[i] = co2_ring_index(x + dx, y + dy, md.Nx, Ny, px, py, NP);
+  }
   // the model's fields read once, before the loop (read in the loop's
   // branches, the compiler would load them again at every step)
   const Co2Model mloc = md;
@@ -963,23 +998,23 @@ __global__ void __launch_bounds__(kThreads)
   c64 tq = trow_ahead(1);
   // plane 0 and its w
   __syncthreads();
-  if (live) st16(zl + j, z0);
+  if (live) st16(zl + k, z0);
   __syncthreads();
   {
     const Co2Ring R{zl, {zl, zl, zl}, wl, tl + trow_off, z0, z1, zero, {zero, zero}, {zero, zero, zero},
-                    j, Ny};
+                    k, nb};
     c64 wa, wb;
     co2_point1(op, sq, R, Co2Point{0, ia, x, y, 0}, wa, wb);
     wo1 = co2_sel(t == 0, wa, wb);
-    if (live) st16(wl + j, co2_sel(t == 0, wb, wa));
+    if (live) st16(wl + k, co2_sel(t == 0, wb, wa));
   }
 #pragma unroll 1
   for (int s = 0; s < Ns; ++s) {
-    c64* zs1 = zl + ((s + 1) & 3) * NP;
-    c64* w1 = wl + ((s + 1) & 1) * NP;
+    c64* zs1 = zl + ((s + 1) & 3) * PS;
+    c64* w1 = wl + ((s + 1) & 1) * PS;
     c64* t1 = tl + ((s + 1) & 1) * ntp;
     if (s + 1 < Ns) {
-      if (live) st16(zs1 + j, z1);
+      if (live) st16(zs1 + k, z1);
       if (tid < ntp) st16(t1 + tid, tq);
       for (int i = tid + blockDim.x; i < ntp; i += blockDim.x) st16(t1 + i, trow(s + 1, i));
     }
@@ -994,16 +1029,16 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
     c64 wn1 = zero;
     if (s + 1 < Ns) {
-      const Co2Ring R{zl, {zl + (s & 3) * NP, zs1, zs1}, w1, t1 + trow_off, z1, z2, zero, {zero, zero},
-                      {zero, zero, zero}, j, Ny};
+      const Co2Ring R{zl, {zl + (s & 3) * PS, zs1, zs1}, w1, t1 + trow_off, z1, z2, zero, {zero, zero},
+                      {zero, zero, zero}, k, nb};
       c64 wa, wb;
       co2_point1(op, sq, R, Co2Point{s + 1, ia, x, y, 0}, wa, wb);
       wn1 = co2_sel(t == 0, wa, wb);
-      if (live) st16(w1 + j, co2_sel(t == 0, wb, wa));
+      if (live) st16(w1 + k, co2_sel(t == 0, wb, wa));
     }
     {
-      const Co2Ring R{zl + ((s + 2) & 3) * NP, {zl + ((s + 3) & 3) * NP, zl + (s & 3) * NP, zs1},
-                      wl + (s & 1) * NP, tl, z0, z1, z2, {zam, zap}, {wo0, wo1, wn1}, j, Ny};
+      const Co2Ring R{zl + ((s + 2) & 3) * PS, {zl + ((s + 3) & 3) * PS, zl + (s & 3) * PS, zs1},
+                      wl + (s & 1) * PS, tl, z0, z1, z2, {zam, zap}, {wo0, wo1, wn1}, k, nb};
       yprev = co2_point2(op, sq, R, Co2Point{s, ia, x, y, 0});
     }
     z0 = z1;
