@@ -789,9 +789,11 @@ __device__ inline c64 ld16(const c64* p) {
 
 __device__ inline void st16(c64* p, c64 v) { *reinterpret_cast<c64v*>(p) = c64v{v.x, v.y}; }
 
-// The bend points of a plane that carry a state (types 0, 1, 2), in plane
-// order: a row with n_x + px even holds all Ny points, the others the ne
-// points with n_y + py even; the remaining points (type 3) carry none.
+// The bend points of a plane that carry a state (types 0, 1, 2), row by row:
+// a row with n_x + px even holds all Ny points, the ne with n_y + py even
+// first, then the others; a row with n_x + px odd only those ne points; the
+// remaining points (type 3) carry none.  Ordered so, the bend neighbours of
+// consecutive points are consecutive, or the one zero entry.
 __host__ __device__ inline int co2_row_even(int Ny, int py) { return (Ny + 1 - py) / 2; }
 
 __host__ __device__ inline int co2_live_count(int Nx, int Ny, int px, int py) {
@@ -804,14 +806,12 @@ __host__ __device__ inline int co2_live_count(int Nx, int Ny, int px, int py) {
 __host__ __device__ inline void co2_live_point(int k, int Ny, int px, int py, int& x, int& y) {
   const int ne = co2_row_even(Ny, py);
   const int n0 = px == 0 ? Ny : ne;   // points of the pair's first row, n_x = 2 q
-  const int q = k / (Ny + ne), r = k - q * (Ny + ne);
-  if (r < n0) {
-    x = 2 * q;
-    y = px == 0 ? r : 2 * r + py;
-  } else {
-    x = 2 * q + 1;
-    y = px == 0 ? 2 * (r - n0) + py : r - n0;
-  }
+  const int q = k / (Ny + ne), r0 = k - q * (Ny + ne);
+  const bool second = r0 >= n0;
+  const int r = second ? r0 - n0 : r0;  // in its row
+  x = 2 * q + (second ? 1 : 0);
+  // r < ne: n_y + py even; else (a full row's second part) odd
+  y = r < ne ? 2 * r + py : 2 * (r - ne) + 1 - py;
 }
 
 // The k-th point that carries none (k < Nx Ny - co2_live_count): n_x + px and
@@ -855,9 +855,8 @@ __host__ __device__ inline int co2_ring_index(int x, int y, int Nx, int Ny, int 
   if (x < 0 || x >= Nx || y < 0 || y >= Ny || (((x + px) & (y + py)) & 1)) return zslot;
   const int ne = co2_row_even(Ny, py);
   const int base = (x >> 1) * (Ny + ne);
-  const bool full = ((x + px) & 1) == 0;
   const int first = px == 0 ? Ny : ne;   // points of the pair's first row
-  const int r = full ? y : (y - py) >> 1;
+  const int r = ((y + py) & 1) ? ne + ((y + py - 1) >> 1) : (y - py) >> 1;
   return base + ((x & 1) ? first : 0) + r;
 }
 
