@@ -879,6 +879,7 @@ struct Co2Ring {
   c64 z0, z1, z2, za[2], wc[3];
   int k;                     // the point's ring index
   Co2Nbr nb;                 // ring indices of its bend neighbours
+  Co2BendW W;                // its bend-mode weights
   __device__ c64 z(bool, int ds, int da, int dx, int dy) const {
     if (da != 0) return za[da > 0 ? 1 : 0];
     if (dx == 0 && dy == 0) {
@@ -896,6 +897,7 @@ struct Co2Ring {
   __device__ c64 tab(const Co2Op&, const Co2Point&, int, int k) const { return ld16(T + k); }
   __device__ double pick(bool first, double a, double b) const { return co2_pick(first, a, b); }
   __device__ double cls(const double* c2, int c) const { return co2_pick(c == 0, c2[0], c2[1]); }
+  __device__ Co2BendW bend(const double*, const Co2Model&, const Co2Point&) const { return W; }
 };
 
 // Doubles of sqrt(n/2) at the head of the march's dynamic LDS (even, so the
@@ -997,11 +999,13 @@ __global__ void __launch_bounds__(kThreads)
   c64 tq = trow_ahead(1);
   // plane 0 and its w
   __syncthreads();
+  // the point's bend weights, held in registers for the march
+  const Co2BendW bw = co2_bend_w(sq, x, y, md.Nx, Ny);
   if (live) st16(zl + k, z0);
   __syncthreads();
   {
     const Co2Ring R{zl, {zl, zl, zl}, wl, tl + trow_off, z0, z1, zero, {zero, zero}, {zero, zero, zero},
-                    k, nb};
+                    k, nb, bw};
     c64 wa, wb;
     co2_point1(op, sq, R, Co2Point{0, ia, x, y, 0}, wa, wb);
     wo1 = co2_sel(t == 0, wa, wb);
@@ -1029,7 +1033,7 @@ __global__ void __launch_bounds__(kThreads)
     c64 wn1 = zero;
     if (s + 1 < Ns) {
       const Co2Ring R{zl, {zl + (s & 3) * PS, zs1, zs1}, w1, t1 + trow_off, z1, z2, zero, {zero, zero},
-                      {zero, zero, zero}, k, nb};
+                      {zero, zero, zero}, k, nb, bw};
       c64 wa, wb;
       co2_point1(op, sq, R, Co2Point{s + 1, ia, x, y, 0}, wa, wb);
       wn1 = co2_sel(t == 0, wa, wb);
@@ -1037,7 +1041,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     {
       const Co2Ring R{zl + ((s + 2) & 3) * PS, {zl + ((s + 3) & 3) * PS, zl + (s & 3) * PS, zs1},
-                      wl + (s & 1) * PS, tl, z0, z1, z2, {zam, zap}, {wo0, wo1, wn1}, k, nb};
+                      wl + (s & 1) * PS, tl, z0, z1, z2, {zam, zap}, {wo0, wo1, wn1}, k, nb, bw};
       yprev = co2_point2(op, sq, R, Co2Point{s, ia, x, y, 0});
     }
     z0 = z1;
