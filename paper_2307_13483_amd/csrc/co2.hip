@@ -789,11 +789,13 @@ __device__ inline c64 ld16(const c64* p) {
 
 __device__ inline void st16(c64* p, c64 v) { *reinterpret_cast<c64v*>(p) = c64v{v.x, v.y}; }
 
-// The bend points of a plane that carry a state (types 0, 1, 2), row by row:
-// a row with n_x + px even holds all Ny points, the ne with n_y + py even
-// first, then the others; a row with n_x + px odd only those ne points; the
-// remaining points (type 3) carry none.  Ordered so, the bend neighbours of
-// consecutive points are consecutive, or the one zero entry.
+// The bend points of a plane that carry a state (types 0, 1, 2): every row
+// holds the ne points with n_y + py even, a row with n_x + px even also the
+// Ny - ne others, and the remaining points (type 3) carry none.  They are
+// ordered in two parts: the points with n_y + py even, row by row (Nx ne),
+// then the others, row by row over the rows that hold them.  Ordered so, the
+// bend neighbours of a run of consecutive points in one row are consecutive
+// points of one row, or all the one zero entry.
 __host__ __device__ inline int co2_row_even(int Ny, int py) { return (Ny + 1 - py) / 2; }
 
 __host__ __device__ inline int co2_live_count(int Nx, int Ny, int px, int py) {
@@ -801,17 +803,18 @@ __host__ __device__ inline int co2_live_count(int Nx, int Ny, int px, int py) {
   return full * Ny + (Nx - full) * co2_row_even(Ny, py);
 }
 
-// The k-th point that carries a state (k < co2_live_count): rows come in
-// pairs of Ny + ne points, the full row first when px = 0.
-__host__ __device__ inline void co2_live_point(int k, int Ny, int px, int py, int& x, int& y) {
-  const int ne = co2_row_even(Ny, py);
-  const int n0 = px == 0 ? Ny : ne;   // points of the pair's first row, n_x = 2 q
-  const int q = k / (Ny + ne), r0 = k - q * (Ny + ne);
-  const bool second = r0 >= n0;
-  const int r = second ? r0 - n0 : r0;  // in its row
-  x = 2 * q + (second ? 1 : 0);
-  // r < ne: n_y + py even; else (a full row's second part) odd
-  y = r < ne ? 2 * r + py : 2 * (r - ne) + 1 - py;
+// The k-th point that carries a state (k < co2_live_count).
+__host__ __device__ inline void co2_live_point(int k, int Nx, int Ny, int px, int py, int& x,
+                                               int& y) {
+  const int ne = co2_row_even(Ny, py), no = Ny - ne;
+  if (k < Nx * ne) {
+    x = k / ne;
+    y = 2 * (k - x * ne) + py;
+  } else {
+    const int q = (k - Nx * ne) / no;
+    x = 2 * q + px;
+    y = 2 * (k - Nx * ne - q * no) + 1 - py;
+  }
 }
 
 // The k-th point that carries none (k < Nx Ny - co2_live_count): n_x + px and
@@ -854,10 +857,8 @@ __host__ __device__ inline int co2_ring_index(int x, int y, int Nx, int Ny, int 
                                               int zslot) {
   if (x < 0 || x >= Nx || y < 0 || y >= Ny || (((x + px) & (y + py)) & 1)) return zslot;
   const int ne = co2_row_even(Ny, py);
-  const int base = (x >> 1) * (Ny + ne);
-  const int first = px == 0 ? Ny : ne;   // points of the pair's first row
-  const int r = ((y + py) & 1) ? ne + ((y + py - 1) >> 1) : (y - py) >> 1;
-  return base + ((x & 1) ? first : 0) + r;
+  if (((y + py) & 1) == 0) return x * ne + ((y - py) >> 1);
+  return Nx * ne + (x >> 1) * (Ny - ne) + ((y + py - 1) >> 1);
 }
 
 // Neighbour accessor of the march for a centre at plane s (see co2_point1,
@@ -944,7 +945,7 @@ __global__ void __launch_bounds__(kThreads)
   const int n_live = co2_live_count(md.Nx, Ny, px, py), n_dead = NP - n_live;
   const bool live = tid < n_live;
   int x = 0, y = 0;
-  if (n_live > 0) co2_live_point(live ? tid : 0, Ny, px, py, x, y);
+  if (n_live > 0) co2_live_point(live ? tid : 0, md.Nx, Ny, px, py, x, y);
   const int j = x * Ny + y;                   // in the vector
   const int k = live ? tid : 0;               // in the rings
   Co2Nbr nb;
