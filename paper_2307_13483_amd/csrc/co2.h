@@ -87,29 +87,41 @@ __device__ inline double co2_pick(bool first, double a, double b) {
 // (q^2)_{n n} and (q^2)_{n, n+2} of the truncated product
 __device__ inline double q2_diag(int n, int N) { return 0.5 * n + (n + 1 < N ? 0.5 * (n + 1) : 0.0); }
 
-// The bend-mode weights of a point (n_x, n_y) = (x, y) from sq[n] = sqrt(n/2):
+// The bend-mode weights of a point (n_x, n_y) = (x, y), from sq[n] = sqrt(n/2):
 // of q_x at x - 1, x + 1 (xl, xh), of q_x^2 at x - 2, x + 2 (x2l, x2h) and
 // its diagonal x2d; the same along n_y.  Zero where the neighbour lies past
-// the basis edge.
-struct Co2BendW {
-  double xl, xh, yl, yh, x2l, x2h, y2l, y2h, x2d, y2d;
+// the basis edge.  Co2BendSq reads each from the table where it is used;
+// Co2BendW holds them (the march keeps them in registers).
+struct Co2BendSq {
+  const double* sq;
+  int x, y, Nx, Ny;
+  __device__ double xl() const { return sq[x > 0 ? x : 0]; }
+  __device__ double xh() const { return sq[x + 1 < Nx ? x + 1 : 0]; }
+  __device__ double yl() const { return sq[y > 0 ? y : 0]; }
+  __device__ double yh() const { return sq[y + 1 < Ny ? y + 1 : 0]; }
+  __device__ double x2l() const { return sq[x >= 2 ? x - 1 : 0] * sq[x >= 2 ? x : 0]; }
+  __device__ double x2h() const { return sq[x + 2 < Nx ? x + 1 : 0] * sq[x + 2 < Nx ? x + 2 : 0]; }
+  __device__ double y2l() const { return sq[y >= 2 ? y - 1 : 0] * sq[y >= 2 ? y : 0]; }
+  __device__ double y2h() const { return sq[y + 2 < Ny ? y + 1 : 0] * sq[y + 2 < Ny ? y + 2 : 0]; }
+  __device__ double x2d() const { return q2_diag(x, Nx); }
+  __device__ double y2d() const { return q2_diag(y, Ny); }
 };
 
-__device__ inline Co2BendW co2_bend_w(const double* sq, int x, int y, int Nx, int Ny) {
-  Co2BendW w;
-  w.xl = sq[x > 0 ? x : 0];
-  w.xh = sq[x + 1 < Nx ? x + 1 : 0];
-  w.yl = sq[y > 0 ? y : 0];
-  w.yh = sq[y + 1 < Ny ? y + 1 : 0];
-  const bool xl2 = x >= 2, xh2 = x + 2 < Nx, yl2 = y >= 2, yh2 = y + 2 < Ny;
-  w.x2l = sq[xl2 ? x - 1 : 0] * sq[xl2 ? x : 0];
-  w.x2h = sq[xh2 ? x + 1 : 0] * sq[xh2 ? x + 2 : 0];
-  w.y2l = sq[yl2 ? y - 1 : 0] * sq[yl2 ? y : 0];
-  w.y2h = sq[yh2 ? y + 1 : 0] * sq[yh2 ? y + 2 : 0];
-  w.x2d = q2_diag(x, Nx);
-  w.y2d = q2_diag(y, Ny);
-  return w;
-}
+struct Co2BendW {
+  double w[10];
+  __device__ explicit Co2BendW(const Co2BendSq& b)
+      : w{b.xl(), b.xh(), b.yl(), b.yh(), b.x2l(), b.x2h(), b.y2l(), b.y2h(), b.x2d(), b.y2d()} {}
+  __device__ double xl() const { return w[0]; }
+  __device__ double xh() const { return w[1]; }
+  __device__ double yl() const { return w[2]; }
+  __device__ double yh() const { return w[3]; }
+  __device__ double x2l() const { return w[4]; }
+  __device__ double x2h() const { return w[5]; }
+  __device__ double y2l() const { return w[6]; }
+  __device__ double y2h() const { return w[7]; }
+  __device__ double x2d() const { return w[8]; }
+  __device__ double y2d() const { return w[9]; }
+};
 
 struct Co2Point {
   int s, a, x, y, t;
@@ -157,8 +169,8 @@ __device__ inline c64 co2_tab(const Co2Op& o, int s, int x, int y, int a, int t,
 // point) at the offset point, else at the point itself; tab(o, p, t, k) the
 // level-shift value co2_tab at the point; pick(first, a, b) and cls(c2, c)
 // one of two model coefficients by the point's class; bend(sq, m, p) the
-// point's Co2BendW.  Co2Flat reads a whole vector and its w planes from
-// memory.
+// point's bend-mode weights (Co2BendSq or Co2BendW).  Co2Flat reads a whole
+// vector and its w planes from memory.
 struct Co2Flat {
   const c64* v;
   double vs;
@@ -175,8 +187,8 @@ struct Co2Flat {
   }
   __device__ double pick(bool first, double a, double b) const { return first ? a : b; }
   __device__ double cls(const double* c2, int c) const { return c2[c]; }
-  __device__ Co2BendW bend(const double* sq, const Co2Model& m, const Co2Point& p) const {
-    return co2_bend_w(sq, p.x, p.y, m.Nx, m.Ny);
+  __device__ Co2BendSq bend(const double* sq, const Co2Model& m, const Co2Point& p) const {
+    return Co2BendSq{sq, p.x, p.y, m.Nx, m.Ny};
   }
 };
 
@@ -190,11 +202,11 @@ __device__ inline void co2_point1(const Co2Op& o, const double* sq, const Acc& Z
   // sqrt(n/2) z(n - 1) + sqrt((n + 1)/2) z(n + 1) along one mode
   const bool slo = p.s > 0, shi = p.s + 1 < m.Ns, xlo = p.x > 0, xhi = p.x + 1 < m.Nx;
   const bool ylo = p.y > 0, yhi = p.y + 1 < m.Ny;
-  const Co2BendW W = Z.bend(sq, m, p);
+  const auto W = Z.bend(sq, m, p);
   const c64 z0 = Z.z(true, 0, 0, 0, 0);
   const c64 qs = sq[slo ? p.s : 0] * Z.z(slo, -1, 0, 0, 0) + sq[shi ? p.s + 1 : 0] * Z.z(shi, 1, 0, 0, 0);
-  const c64 qx = W.xl * Z.z(xlo, 0, 0, -1, 0) + W.xh * Z.z(xhi, 0, 0, 1, 0);
-  const c64 qy = W.yl * Z.z(ylo, 0, 0, 0, -1) + W.yh * Z.z(yhi, 0, 0, 0, 1);
+  const c64 qx = W.xl() * Z.z(xlo, 0, 0, -1, 0) + W.xh() * Z.z(xhi, 0, 0, 1, 0);
+  const c64 qy = W.yl() * Z.z(ylo, 0, 0, 0, -1) + W.yh() * Z.z(yhi, 0, 0, 0, 1);
   const int tt = t == 3 ? 0 : t;
   const c64 T0 = Z.tab(o, p, tt, 0);
   const c64 T1 = Z.tab(o, p, tt, 1);
@@ -225,16 +237,19 @@ __device__ inline c64 co2_point2(const Co2Op& o, const double* sq, const Acc& Z,
     return q2_diag(n, N) * z0 + (sq[lo ? n - 1 : 0] * sq[lo ? n : 0]) * Z.z(lo, -2 * us, -2 * ua, -2 * ux, -2 * uy) +
            (sq[hi ? n + 1 : 0] * sq[hi ? n + 2 : 0]) * Z.z(hi, 2 * us, 2 * ua, 2 * ux, 2 * uy);
   };
-  const Co2BendW W = Z.bend(sq, m, p);
-  const c64 q2x = W.x2d * z0 + W.x2l * Z.z(x >= 2, 0, 0, -2, 0) + W.x2h * Z.z(x + 2 < m.Nx, 0, 0, 2, 0);
-  const c64 q2y = W.y2d * z0 + W.y2l * Z.z(y >= 2, 0, 0, 0, -2) + W.y2h * Z.z(y + 2 < m.Ny, 0, 0, 0, 2);
+  // the same along a bend mode, with the point's bend weights
+  const auto W = Z.bend(sq, m, p);
+  auto q2b = [&](double d, double wl, double wh, bool lo, bool hi, int ux, int uy) {
+    return d * z0 + wl * Z.z(lo, 0, 0, -2 * ux, -2 * uy) + wh * Z.z(hi, 0, 0, 2 * ux, 2 * uy);
+  };
   const double gs = Z.cls(m.gs, c), gb = Z.cls(m.gb, c), ga = Z.cls(m.ga, c);
   c64 U = Z.pick(c == 0, m.E_sigma, m.E_pi) * z0 + Z.pick(c == 0, m.k_sigma, m.k_pi) * qs1 +
-          gs * q2(s, m.Ns, 1, 0, 0, 0) + (gb + rt) * q2x + (gb - rt) * q2y + ga * q2(a, m.Na, 0, 1, 0, 0);
+          gs * q2(s, m.Ns, 1, 0, 0, 0) + (gb + rt) * q2b(W.x2d(), W.x2l(), W.x2h(), x >= 2, x + 2 < m.Nx, 1, 0) +
+          (gb - rt) * q2b(W.y2d(), W.y2l(), W.y2h(), y >= 2, y + 2 < m.Ny, 0, 1) + ga * q2(a, m.Na, 0, 1, 0, 0);
   // sigma - Pi couplings c (1 + c' q_s) q_x and c (1 + c' q_s) q_y, at the
   // point's s - 1, s, s + 1
   const bool x_lo = x > 0, x_hi = x + 1 < m.Nx, y_lo = y > 0, y_hi = y + 1 < m.Ny;
-  const double wx_lo = W.xl, wx_hi = W.xh, wy_lo = W.yl, wy_hi = W.yh;
+  const double wx_lo = W.xl(), wx_hi = W.xh(), wy_lo = W.yl(), wy_hi = W.yh();
   auto qx_at = [&](bool ok, int ds) {
     return wx_lo * Z.z(ok && x_lo, ds, 0, -1, 0) + wx_hi * Z.z(ok && x_hi, ds, 0, 1, 0);
   };

@@ -1001,7 +1001,7 @@ __global__ void __launch_bounds__(kThreads)
   // plane 0 and its w
   __syncthreads();
   // the point's bend weights, held in registers for the march
-  const Co2BendW bw = co2_bend_w(sq, x, y, md.Nx, Ny);
+  const Co2BendW bw(Co2BendSq{sq, x, y, md.Nx, Ny});
   if (live) st16(zl + k, z0);
   __syncthreads();
   {
