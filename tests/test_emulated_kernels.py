@@ -116,7 +116,7 @@ def _co2_sector_index(sizes, px, py):
 # several wavefronts with a partial last one; a plane past the march's limit
 # (the two grid-wide passes)
 CO2_SIZES = [dict(s=3, x=5, y=4, a=2), dict(s=7, x=6, y=7, a=6), dict(s=5, x=9, y=11, a=5),
-             dict(s=2, x=35, y=30, a=1)]
+             dict(s=2, x=30, y=30, a=1), dict(s=2, x=35, y=30, a=1)]
 
 
 @pytest.mark.parametrize("sizes", CO2_SIZES, ids=lambda d: "x".join(str(d[k]) for k in "sxya"))

@@ -84,10 +84,11 @@ def _bound_tables(p, eps):
 
 # the march along n_s (planes up to 1024 points): n_a +- 2 neighbours on
 # one side or both, rings wrapping, planes of one or several wavefronts; a
-# single plane; and a plane past the march's limit (the split passes)
+# single plane; a plane of more than 512 points that carry a state (the
+# wider workgroup); and a plane past the march's limit (the split passes)
 @pytest.mark.parametrize("sizes,eps", [(dict(s=5, x=6, y=7, a=4), 1.7), (dict(s=3, x=9, y=4, a=3), 3.1),
                                        (dict(s=1, x=2, y=3, a=1), 0.6), (dict(s=7, x=9, y=11, a=6), 2.2),
-                                       (dict(s=2, x=35, y=30, a=1), 1.1)])
+                                       (dict(s=2, x=30, y=30, a=1), 1.3), (dict(s=2, x=35, y=30, a=1), 1.1)])
 def test_operator_matches_assembled_matrix(vdc, sizes, eps):
     E = poly.total_energy(P, eps, (0, 0, 0, 0))
     M = poly.PolyModel(P, sizes, E)
