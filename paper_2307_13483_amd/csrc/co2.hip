@@ -748,8 +748,8 @@ __global__ void __launch_bounds__(kCo2Threads) co2_y_kernel(Co2OpsArgs a, int v0
 
 // The operator on many sector vectors at once by marching along n_s
 // (vdc_co2_apply, which = 0, for bend planes of Nx Ny <= kMarchMaxPlane
-// points): one workgroup per (vector, n_a), one thread per bend point
-// j = n_x Ny + n_y.  Step s of the march
+// points): one workgroup per (vector, n_a), one thread per bend point that
+// carries a state (co2_live_point).  Step s of the march
 //   stores z and the level-shift rows of plane s + 1 into LDS rings (four
 //   z planes, two planes of rows),
 //   computes (w_A, w_B) at s + 1 (co2_point1; its bend neighbours from LDS),
@@ -764,8 +764,8 @@ __global__ void __launch_bounds__(kCo2Threads) co2_y_kernel(Co2OpsArgs a, int v0
 // other class or carries no state: each point stores only the component of
 // the other class (w_B at sigma points, w_A at Pi points).  Every x value is
 // read from memory three times (own column, and as the n_a +- 2 neighbour of
-// two workgroups of the same vector), y written once, and no w leaves the
-// chip.  The loads a step needs (z of the own column at s + 2, z at n_a -+ 2,
+// two workgroups of the same vector), y written once (its zeros at the
+// points that carry no state after the march), and no w leaves the chip.  The loads a step needs (z of the own column at s + 2, z at n_a -+ 2,
 // the level-shift rows of s + 1) are issued at the top of the step before.
 // Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b mod
 // 8); the workgroups of one vector are numbered so that they share an XCD and
@@ -869,9 +869,11 @@ __host__ __device__ inline int co2_ring_index(int x, int y, int Nx, int Ny, int 
 // (co2_pick: the march's loop would reload a per-lane choice after every
 // store of y).  A neighbour that is not in the basis is not selected away:
 // every such term carries a zero weight (sqrt(0/2) of the basis edge), and the
-// value read there is finite for a finite input (the own point of the plane,
-// a zero plane past either end of n_s or n_a, or a w value), so the product
-// is zero without a select.
+// value read there is finite for a finite input (the ring's zero entry, its
+// zero planes before the first n_s, an earlier plane of the input after the
+// last, or zeros past either end of n_a), so the product is zero without a
+// select.  A neighbour that carries no state reads the zero entry; the terms
+// that read one are those the point's type does not use.
 struct Co2Ring {
   const c64* zm2;
   const c64* zp[3];
