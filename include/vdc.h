@@ -473,8 +473,11 @@ vdc_status vdc_co2_solve(vdc_co2_t model, const vdc_solve_opts* opts, int n_jobs
 /* y = A x (which = 0) or y = M^{-1} x for the block preconditioner (which =
  * 1, the factor of vdc_co2_solve, Ny <= 24) at total energy E, on n_vec sector vectors (device complex
  * [n_vec][Ns*Na*Nx*Ny]), vector v in sector (sectors[2v], sectors[2v+1])
- * (host ints, 0/1).  x and y must not overlap.  Workspace:
- * vdc_co2_ops_workspace_size().  Synchronises the stream. */
+ * (host ints, 0/1).  For which = 0, entries of x at points that carry no
+ * state (n_x + px and n_y + py both odd) are ignored and y is zero there, and
+ * a non-finite entry of x may also reach y where its term carries a zero
+ * weight.  x and y must not overlap.  Workspace: vdc_co2_ops_workspace_size().  Synchronises the
+ * stream. */
 vdc_status vdc_co2_ops_workspace_size(vdc_co2_t model, int n_vec, int which, size_t* bytes);
 vdc_status vdc_co2_apply(vdc_co2_t model, double E, int which, int n_vec, const int* sectors,
                          const double* x, double* y, void* workspace, size_t ws_bytes,
